@@ -1,0 +1,283 @@
+"""CPU oracle (test infrastructure only).
+
+A plain, slow reference implementation of the stitching hot path, written
+from the paper (Section III.C, eq. (1), Code 1) and the readings listed in
+``oracle.c``'s header. Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package. It shares no code
+with the GPU library: the C source is built by ``oracle/build.py`` into
+``oracle/liboracle.so`` and called through ``ctypes`` with numpy arrays.
+
+Integer stages return int32 arrays; floating-point stages return float64.
+Flows are ``H x W x 2`` with (x, y) = (column, row) components.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+u8p = ctypes.POINTER(ctypes.c_uint8)
+i32p = ctypes.POINTER(ctypes.c_int32)
+f64p = ctypes.POINTER(ctypes.c_double)
+c_int, c_long, c_double = ctypes.c_int, ctypes.c_long, ctypes.c_double
+
+
+@dataclass(frozen=True)
+class Params:
+    """Parameters of the flow method and the blend (the paper publishes
+    none of their values; these are the adopted defaults)."""
+
+    levels: int = 6
+    patch: int = 2        # P: (2P+1)^2 patch
+    radius: int = 2       # R: search radius per level
+    radius_coarse: int = 4
+    prop_steps: int = 2   # T
+    median: int = 1       # M: (2M+1)^2 median
+    lk_patch: int = 2     # window (2P+1)^2
+    lk_iters: int = 2
+    lk_eps: float = 25.0
+    k_sharp: float = 10.0  # kSoftmaxSharpness
+    k_flowmag: float = 20.0  # kFlowMagCoef
+    blend_mode: int = 0   # 0 softmax (Code 1), 1 linear
+
+    @staticmethod
+    def lean(**kw) -> "Params":
+        d = dict(patch=1, radius=1, radius_coarse=3, prop_steps=1, lk_patch=1, lk_iters=1, lk_eps=9.0)
+        d.update(kw)
+        return Params(**d)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "orc_num_threads": (c_int, []),
+        "orc_luma": (None, [u8p, c_int, c_int, c_long, u8p]),
+        "orc_pyr_down": (None, [u8p, c_int, c_int, u8p]),
+        "orc_upsample": (None, [i32p, c_int, c_int, c_int, c_int, i32p]),
+        "orc_search": (None, [u8p, u8p, c_int, c_int, i32p, c_int, c_int, i32p, i32p]),
+        "orc_propagate": (None, [u8p, u8p, c_int, c_int, c_int, c_int, i32p, i32p]),
+        "orc_median": (None, [i32p, c_int, c_int, c_int, i32p]),
+        "orc_level_sizes": (None, [c_int, c_int, c_int, i32p, i32p]),
+        "orc_flow_int": (None, [u8p, u8p, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, i32p, i32p]),
+        "orc_refine": (None, [u8p, u8p, c_int, c_int, i32p, c_int, c_int, c_double, f64p]),
+        "orc_flow_bidirectional": (None, [u8p, u8p, c_int, c_int, c_long, c_long,
+                                          c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_double,
+                                          f64p, f64p, i32p, i32p, i32p, i32p]),
+        "orc_blend_coef": (c_double, [c_int, c_int, c_int, c_int, c_int]),
+        "orc_blend": (None, [f64p, f64p, f64p, f64p, f64p, c_int, c_int, c_int, c_double, c_double, c_int,
+                             f64p, u8p]),
+        "orc_energy": (c_double, [f64p, f64p, f64p, c_int, c_int, c_double, c_double, f64p, f64p, f64p]),
+        "orc_refine_gd": (None, [f64p, f64p, f64p, c_int, c_int, c_int, c_double, c_double, c_double,
+                                 c_double, f64p]),
+        "orc_blend_grad": (None, [f64p, f64p, f64p, f64p, f64p, c_int, c_int, c_int, c_double, c_double,
+                                  c_int, f64p, f64p, f64p, f64p, f64p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _p(a, typ):
+    if a is None:
+        return None
+    return a.ctypes.data_as(typ)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def level_sizes(H: int, W: int, N: int):
+    hs = np.zeros(N, np.int32)
+    ws = np.zeros(N, np.int32)
+    _load().orc_level_sizes(H, W, N, _p(hs, i32p), _p(ws, i32p))
+    return [(int(h), int(w)) for h, w in zip(hs, ws)]
+
+
+def luma(rgb: np.ndarray) -> np.ndarray:
+    rgb = _u8(rgb)
+    H, W, _ = rgb.shape
+    Y = np.empty((H, W), np.uint8)
+    _load().orc_luma(_p(rgb, u8p), H, W, W * 3, _p(Y, u8p))
+    return Y
+
+
+def pyr_down(Y: np.ndarray) -> np.ndarray:
+    Y = _u8(Y)
+    H, W = Y.shape
+    out = np.empty(((H + 1) // 2, (W + 1) // 2), np.uint8)
+    _load().orc_pyr_down(_p(Y, u8p), H, W, _p(out, u8p))
+    return out
+
+
+def pyramid(Y: np.ndarray, N: int):
+    levels = [_u8(Y)]
+    for _ in range(1, N):
+        levels.append(pyr_down(levels[-1]))
+    return levels
+
+
+def upsample(Dc: np.ndarray, H: int, W: int) -> np.ndarray:
+    Dc = _i32(Dc)
+    out = np.empty((H, W, 2), np.int32)
+    _load().orc_upsample(_p(Dc, i32p), Dc.shape[0], Dc.shape[1], H, W, _p(out, i32p))
+    return out
+
+
+def search(ref, tgt, centre=None, P=2, R=2):
+    ref, tgt = _u8(ref), _u8(tgt)
+    H, W = ref.shape
+    D = np.empty((H, W, 2), np.int32)
+    cost = np.empty((H, W), np.int32)
+    c = None if centre is None else _i32(centre)
+    _load().orc_search(_p(ref, u8p), _p(tgt, u8p), H, W, _p(c, i32p), P, R, _p(D, i32p), _p(cost, i32p))
+    return D, cost
+
+
+def propagate(ref, tgt, D, P=2, T=2):
+    ref, tgt, D = _u8(ref), _u8(tgt), _i32(D)
+    H, W = ref.shape
+    out = np.empty_like(D)
+    _load().orc_propagate(_p(ref, u8p), _p(tgt, u8p), H, W, P, T, _p(D, i32p), _p(out, i32p))
+    return out
+
+
+def median(D, M=1):
+    D = _i32(D)
+    H, W, _ = D.shape
+    out = np.empty_like(D)
+    _load().orc_median(_p(D, i32p), H, W, M, _p(out, i32p))
+    return out
+
+
+def _split_levels(flat, sizes):
+    out, off = [], 0
+    for h, w in sizes:
+        out.append(flat[off:off + h * w * 2].reshape(h, w, 2))
+        off += h * w * 2
+    return out
+
+
+def flow_int(yref, ytgt, params: Params = Params()):
+    """Integer coarse-to-fine chain of one direction. Returns two lists
+    (level 0 first): raw search results and final per-level flows."""
+    yref, ytgt = _u8(yref), _u8(ytgt)
+    H, W = yref.shape
+    sizes = level_sizes(H, W, params.levels)
+    tot = sum(h * w for h, w in sizes)
+    s = np.empty(tot * 2, np.int32)
+    f = np.empty(tot * 2, np.int32)
+    _load().orc_flow_int(_p(yref, u8p), _p(ytgt, u8p), H, W, params.levels, params.patch, params.radius,
+                         params.radius_coarse, params.prop_steps, params.median, _p(s, i32p), _p(f, i32p))
+    return _split_levels(s, sizes), _split_levels(f, sizes)
+
+
+def refine(A, B, D0, params: Params = Params()):
+    A, B, D0 = _u8(A), _u8(B), _i32(D0)
+    H, W = A.shape
+    u = np.empty((H, W, 2), np.float64)
+    _load().orc_refine(_p(A, u8p), _p(B, u8p), H, W, _p(D0, i32p), params.lk_patch, params.lk_iters,
+                       params.lk_eps, _p(u, f64p))
+    return u
+
+
+def flow_bidirectional(L, R, params: Params = Params(), levels_out: bool = False):
+    """Both flows of a strip. Returns (flow_lr, flow_rl) as float64, plus
+    a dict of the per-level integer results if ``levels_out``."""
+    L, R = _u8(L), _u8(R)
+    H, W, _ = L.shape
+    sizes = level_sizes(H, W, params.levels)
+    tot = sum(h * w for h, w in sizes)
+    flr = np.empty((H, W, 2), np.float64)
+    frl = np.empty((H, W, 2), np.float64)
+    bufs = [np.empty(tot * 2, np.int32) for _ in range(4)]
+    _load().orc_flow_bidirectional(_p(L, u8p), _p(R, u8p), H, W, W * 3, W * 3, params.levels, params.patch,
+                                   params.radius, params.radius_coarse, params.prop_steps, params.median,
+                                   params.lk_patch, params.lk_iters, params.lk_eps, _p(flr, f64p),
+                                   _p(frl, f64p), *[_p(b, i32p) for b in bufs])
+    if not levels_out:
+        return flr, frl
+    names = ["search_lr", "final_lr", "search_rl", "final_rl"]
+    return flr, frl, {n: _split_levels(b, sizes) for n, b in zip(names, bufs)}
+
+
+def blend_coef(H: int, W: int, axis: int = 0) -> np.ndarray:
+    lib = _load()
+    return np.array([[lib.orc_blend_coef(x, y, H, W, axis) for x in range(W)] for y in range(H)])
+
+
+def blend(L, R, flow_lr, flow_rl, blend=None, axis: int = 0, params: Params = Params()):
+    """Code 1 over a strip. Returns (F float64 H x W x 3, F uint8)."""
+    Ld, Rd = _f64(L), _f64(R)
+    H, W, _ = Ld.shape
+    flr, frl = _f64(flow_lr), _f64(flow_rl)
+    b = None if blend is None else _f64(blend)
+    F = np.empty((H, W, 3), np.float64)
+    F8 = np.empty((H, W, 3), np.uint8)
+    _load().orc_blend(_p(Ld, f64p), _p(Rd, f64p), _p(flr, f64p), _p(frl, f64p), _p(b, f64p), axis, H, W,
+                      params.k_sharp, params.k_flowmag, params.blend_mode, _p(F, f64p), _p(F8, u8p))
+    return F, F8
+
+
+def energy(Ref, Tgt, u, lam=0.05, eps=1e-3, grads: bool = True):
+    Ref, Tgt, u = _f64(Ref), _f64(Tgt), _f64(u)
+    H, W, _ = Ref.shape
+    if grads:
+        gu = np.empty((H, W, 2))
+        gr = np.empty((H, W, 3))
+        gt = np.empty((H, W, 3))
+    else:
+        gu = gr = gt = None
+    E = _load().orc_energy(_p(Ref, f64p), _p(Tgt, f64p), _p(u, f64p), H, W, lam, eps, _p(gu, f64p),
+                           _p(gr, f64p), _p(gt, f64p))
+    return (E, gu, gr, gt) if grads else E
+
+
+def refine_gd(Ref, Tgt, u, steps=50, eta=0.5, lam=0.05, eps=1e-3, clip=0.25):
+    Ref, Tgt = _f64(Ref), _f64(Tgt)
+    u = _f64(u).copy()
+    H, W, _ = Ref.shape
+    hist = np.empty(steps + 1)
+    _load().orc_refine_gd(_p(Ref, f64p), _p(Tgt, f64p), _p(u, f64p), H, W, steps, eta, lam, eps, clip,
+                          _p(hist, f64p))
+    return u, hist
+
+
+def blend_grad(L, R, flow_lr, flow_rl, g_F, blend=None, axis: int = 0, params: Params = Params()):
+    """Adjoint of Code 1. Returns (g_flow_lr, g_flow_rl, g_L, g_R)."""
+    Ld, Rd = _f64(L), _f64(R)
+    H, W, _ = Ld.shape
+    flr, frl, gF = _f64(flow_lr), _f64(flow_rl), _f64(g_F)
+    b = None if blend is None else _f64(blend)
+    out = [np.empty((H, W, 2)), np.empty((H, W, 2)), np.empty((H, W, 3)), np.empty((H, W, 3))]
+    _load().orc_blend_grad(_p(Ld, f64p), _p(Rd, f64p), _p(flr, f64p), _p(frl, f64p), _p(b, f64p), axis, H, W,
+                           params.k_sharp, params.k_flowmag, params.blend_mode, _p(gF, f64p),
+                           *[_p(o, f64p) for o in out])
+    return tuple(out)

@@ -1,0 +1,336 @@
+"""Seeded synthetic overlap strips (inputs only).
+
+The paper evaluates on twenty photo sets that are not available, so every
+input here is synthetic, with the paper's panorama shape (9000 x 4000,
+Section IV) and the structure of a coarsely registered overlap strip: an
+analytic texture seen through a smooth, bounded disparity field, an
+optional occluding band at its own disparity, a residual exposure gain and
+sensor noise.
+
+This module holds none of the stitching method's arithmetic (no luma, no
+pyramid, no search, no warp-and-blend). It is shared by the tests, the
+benchmark and the CPU oracle's test harness purely as input plumbing.
+
+Coordinates: ``x`` is the column, ``y`` the row. A strip is ``H`` rows by
+``W`` columns. The ground-truth flow of direction "R to L" satisfies
+``R(p) ~ L(p + u_rl(p))`` and the "L to R" flow ``L(q) ~ R(q + u_lr(q))``.
+"""
+from __future__ import annotations
+
+import os
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy import ndimage
+
+SEED_ROOT = (2006, 1201)
+SIZE_DRAW = 99  # the "strip" slot of the seed used for strip-size draws
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def rng_for(cfg: int, pano: int, strip: int) -> np.random.Generator:
+    """The one seeding rule: SeedSequence([2006, 1201, cfg, pano, strip])."""
+    return np.random.default_rng(np.random.SeedSequence([*SEED_ROOT, cfg, pano, strip]))
+
+
+class Texture:
+    """Analytic RGB texture evaluated at real coordinates.
+
+    128 + sum of 8 oriented sinusoids (per-channel phase) + 20 additive
+    axis-aligned rectangles. Amplitudes U[8, 20], frequencies U[1/80, 1/6]
+    cycles/px, orientations U[0, pi), phases U[0, 2 pi); rectangle corners
+    uniform over the ``H x W`` frame, sides U[0.05, 0.4] of the frame
+    dimensions, per-channel offsets U[-50, 50].
+    """
+
+    def __init__(self, rng: np.random.Generator, H: int, W: int, n_sin: int = 8, n_rect: int = 20):
+        self.amp = rng.uniform(8.0, 20.0, n_sin)
+        self.freq = rng.uniform(1.0 / 80.0, 1.0 / 6.0, n_sin)
+        self.theta = rng.uniform(0.0, np.pi, n_sin)
+        self.phase = rng.uniform(0.0, 2.0 * np.pi, (n_sin, 3))
+        rx0 = rng.uniform(0.0, W, n_rect)
+        ry0 = rng.uniform(0.0, H, n_rect)
+        rw = rng.uniform(0.05, 0.4, n_rect) * W
+        rh = rng.uniform(0.05, 0.4, n_rect) * H
+        self.rects = np.stack([rx0, ry0, rx0 + rw, ry0 + rh], axis=1)
+        self.offset = rng.uniform(-50.0, 50.0, (n_rect, 3))
+
+    def __call__(self, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        x, y = np.broadcast_arrays(x, y)
+        if x.ndim >= 1 and x.size > (1 << 18):
+            parts = parallel_rows(lambda r0, r1: self._eval(x[r0:r1], y[r0:r1]), x.shape[0])
+            return np.concatenate(parts, axis=0)
+        return self._eval(x, y)
+
+    def _eval(self, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+        out = np.full(x.shape + (3,), 128.0)
+        cph, sph = np.cos(self.phase), np.sin(self.phase)
+        for k in range(len(self.amp)):
+            arg = (2.0 * np.pi * self.freq[k]) * (x * np.cos(self.theta[k]) + y * np.sin(self.theta[k]))
+            s, c = np.sin(arg), np.cos(arg)
+            for ch in range(3):
+                # sin(arg + phase) by the angle-sum identity, so the two
+                # transcendental evaluations are shared by the channels
+                out[..., ch] += self.amp[k] * (s * cph[k, ch] + c * sph[k, ch])
+        for r in range(len(self.rects)):
+            x0, y0, x1, y1 = self.rects[r]
+            m = (x >= x0) & (x < x1) & (y >= y0) & (y < y1)
+            out[m] += self.offset[r]
+        return out
+
+
+def smooth_field(rng: np.random.Generator, H: int, W: int, sigma: float, max_abs: float) -> np.ndarray:
+    """White noise low-passed by a Gaussian of std ``sigma`` px (in the
+    Fourier domain, periodic), rescaled so that max |f| = ``max_abs``."""
+    noise = rng.standard_normal((H, W))
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.rfftfreq(W)[None, :]
+    g = np.exp(-2.0 * np.pi ** 2 * sigma ** 2 * (fx ** 2 + fy ** 2))
+    f = np.fft.irfft2(np.fft.rfft2(noise) * g, s=(H, W))
+    m = np.abs(f).max()
+    return f * (max_abs / m) if m > 0 else f
+
+
+def bilinear_field(f: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Sample a 2-D field at real coordinates, bilinear, clamp to edge."""
+    H, W = f.shape
+    xc = np.clip(x, 0.0, W - 1.0)
+    yc = np.clip(y, 0.0, H - 1.0)
+    return ndimage.map_coordinates(f, [yc.ravel(), xc.ravel()], order=1, mode="nearest").reshape(x.shape)
+
+
+def _row_blocks(H: int, n: int):
+    step = max(16, -(-H // n))
+    return [(r, min(H, r + step)) for r in range(0, H, step)]
+
+
+def parallel_rows(fn, H: int):
+    """Run ``fn(r0, r1)`` over row blocks on a thread pool (numpy and
+    scipy release the GIL in the bulk work) and return the results in
+    block order."""
+    blocks = _row_blocks(H, 4 * _WORKERS)
+    with ThreadPoolExecutor(_WORKERS) as ex:
+        return list(ex.map(lambda b: fn(*b), blocks))
+
+
+def invert_field(ux: np.ndarray, uy: np.ndarray, iters: int = 20, tol: float = 1e-6):
+    """Fixed-point inverse v(q) = -u(q + v(q)) on the pixel grid."""
+    H, W = ux.shape
+
+    def block(r0, r1):
+        yy, xx = np.mgrid[r0:r1, 0:W].astype(np.float64)
+        vx, vy = -ux[r0:r1].copy(), -uy[r0:r1].copy()
+        for _ in range(iters):
+            nx = -bilinear_field(ux, xx + vx, yy + vy)
+            ny = -bilinear_field(uy, xx + vx, yy + vy)
+            delta = max(np.abs(nx - vx).max(initial=0.0), np.abs(ny - vy).max(initial=0.0))
+            vx, vy = nx, ny
+            if delta < tol:
+                break
+        return vx, vy
+
+    parts = parallel_rows(block, H)
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
+@dataclass
+class Strip:
+    """One overlap strip: L and R images (H x W x 3) plus ground truth."""
+
+    L: np.ndarray
+    R: np.ndarray
+    axis: int  # 0: Area1 (only L) is left of the strip; 1: Area1 is above
+    flow_rl_gt: np.ndarray  # H x W x 2 (x, y), R(p) ~ L(p + u)
+    flow_lr_gt: np.ndarray  # H x W x 2 (x, y), L(q) ~ R(q + v)
+    valid_rl: np.ndarray  # bool H x W: correspondence visible and inside
+    valid_lr: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def H(self) -> int:
+        return self.L.shape[0]
+
+    @property
+    def W(self) -> int:
+        return self.L.shape[1]
+
+
+def _quantise(v: np.ndarray) -> np.ndarray:
+    return np.clip(np.rint(v), 0, 255).astype(np.uint8)
+
+
+def _inside_mask(x, y, H, W):
+    return (x >= 0) & (x <= W - 1) & (y >= 0) & (y <= H - 1)
+
+
+def _strip_axis0(rng, H, W, *, field_kind, max_ux, max_uy, noise_l, noise_r,
+                 gain_range=None, occluder=False, float_out=False,
+                 frame=None, x_off=0, field_params=None):
+    """Generate one strip whose seam runs vertically (disparity mostly along x).
+
+    Draw order (fixed): background texture, flow field, occluder
+    (width, position, disparity, texture), gain, noise on L, noise on R.
+    """
+    fH, fW = frame if frame is not None else (H, W)
+    tex = Texture(rng, fH, fW)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    if field_kind == "sinusoid":
+        # (3, 0) + separable sinusoids with amplitude <= 2 px and
+        # wavelengths U[96, 256] px
+        ax, ay = rng.uniform(1.0, 2.0, 2)
+        lam = rng.uniform(96.0, 256.0, 4)
+        ph = rng.uniform(0.0, 2.0 * np.pi, 4)
+        gx = xx + x_off
+        ux = max_ux + ax * np.sin(2 * np.pi * gx / lam[0] + ph[0]) * np.sin(2 * np.pi * yy / lam[1] + ph[1])
+        uy = ay * np.sin(2 * np.pi * gx / lam[2] + ph[2]) * np.sin(2 * np.pi * yy / lam[3] + ph[3])
+    else:
+        sigma = field_params.get("sigma") if field_params else None
+        if sigma is None:
+            sigma = max(128.0, 0.15 * min(H, W))
+        ux = smooth_field(rng, H, W, sigma, max_ux)
+        uy = smooth_field(rng, H, W, sigma, max_uy)
+    band = None
+    if occluder:
+        wb = int(rng.integers(64, 129))
+        xb = float(rng.uniform(0.25 * W, 0.6 * W))
+        dob = float(rng.uniform(30.0, 40.0))
+        tex_o = Texture(rng, fH, fW)
+        band = (xb, xb + wb, dob, tex_o)
+    gain = float(rng.uniform(*gain_range)) if gain_range else 1.0
+
+    # L(p) = T(p); R(p) = g * T(p + u(p))
+    Lf = tex(xx + x_off, yy)
+    Rf = gain * tex(xx + x_off + ux, yy + uy)
+    u_rl = np.stack([ux, uy], axis=-1)
+    vx, vy = invert_field(ux, uy)
+    u_lr = np.stack([vx, vy], axis=-1)
+    valid_rl = _inside_mask(xx + ux, yy + uy, H, W)
+    valid_lr = _inside_mask(xx + vx, yy + vy, H, W)
+    if band is not None:
+        b0, b1, dob, tex_o = band
+        in_l = (xx >= b0) & (xx < b1)
+        Lf[in_l] = tex_o(xx[in_l] + x_off, yy[in_l])
+        in_r = (xx + dob >= b0) & (xx + dob < b1)
+        Rf[in_r] = gain * tex_o(xx[in_r] + dob + x_off, yy[in_r])
+        # background R pixels whose match falls on L's band are occluded
+        mx = xx + ux
+        valid_rl &= ~((mx >= b0) & (mx < b1) & ~in_r)
+        u_rl[in_r] = (dob, 0.0)
+        valid_rl[in_r] = _inside_mask(xx[in_r] + dob, yy[in_r], H, W)
+        # background L pixels whose match falls on R's band are occluded
+        mx = xx + vx
+        valid_lr &= ~((mx + dob >= b0) & (mx + dob < b1) & ~in_l)
+        u_lr[in_l] = (-dob, 0.0)
+        valid_lr[in_l] = _inside_mask(xx[in_l] - dob, yy[in_l], H, W)
+    if noise_l:
+        Lf = Lf + rng.normal(0.0, noise_l, Lf.shape)
+    if noise_r:
+        Rf = Rf + rng.normal(0.0, noise_r, Rf.shape)
+    if float_out:
+        L = (Lf / 255.0).astype(np.float32)
+        R = (Rf / 255.0).astype(np.float32)
+    else:
+        L, R = _quantise(Lf), _quantise(Rf)
+    meta = {"gain": gain}
+    if band is not None:
+        meta.update(band_x0=band[0], band_x1=band[1], band_disp=band[2])
+    return L, R, u_rl, u_lr, valid_rl, valid_lr, meta
+
+
+def make_strip(rng, H, W, axis=0, **kw) -> Strip:
+    """One strip of ``H x W``. For ``axis == 1`` (seam runs horizontally,
+    disparity mostly along y) the strip is generated in the transposed
+    frame and transposed back, so ``max_ux`` is then the bound across the
+    seam (vertical) and ``max_uy`` the bound along it."""
+    if axis == 0:
+        L, R, u_rl, u_lr, v_rl, v_lr, meta = _strip_axis0(rng, H, W, **kw)
+    else:
+        L, R, u_rl, u_lr, v_rl, v_lr, meta = _strip_axis0(rng, W, H, **kw)
+        L = np.ascontiguousarray(L.transpose(1, 0, 2))
+        R = np.ascontiguousarray(R.transpose(1, 0, 2))
+        u_rl = np.ascontiguousarray(u_rl.transpose(1, 0, 2)[..., ::-1])
+        u_lr = np.ascontiguousarray(u_lr.transpose(1, 0, 2)[..., ::-1])
+        v_rl, v_lr = v_rl.T.copy(), v_lr.T.copy()
+    return Strip(L=L, R=R, axis=axis, flow_rl_gt=u_rl.astype(np.float32),
+                 flow_lr_gt=u_lr.astype(np.float32), valid_rl=v_rl, valid_lr=v_lr, meta=meta)
+
+
+# ---------------------------------------------------------------------------
+# the five workloads
+
+#: pyramid levels per workload (parameters of the flow method, listed here
+#: only so that every caller uses the same value for the same workload)
+LEVELS = {0: 3, 1: 6, 2: 6, 3: 6, 4: 6}
+
+
+def strip_shapes(cfg: int, pano: int = 0):
+    """List of (H, W, axis) for one panorama of workload ``cfg``."""
+    if cfg == 0:
+        return [(256, 64, 0)]
+    if cfg == 1:
+        return [(4000, 768, 0)]
+    if cfg == 2:
+        r = rng_for(2, pano, SIZE_DRAW)
+        ws = r.integers(480, 961, size=6)
+        return [(4000, int(w), 0) for w in ws] + [(600, 9000, 1)]
+    if cfg == 3:
+        return [(2048, 512, 0)]
+    if cfg == 4:
+        r = rng_for(4, pano, SIZE_DRAW)
+        hs = r.integers(2000, 4001, size=6)
+        ws = r.integers(480, 961, size=6)
+        tw = int(r.integers(4500, 9001))
+        th = int(r.integers(300, 601))
+        return [(int(h), int(w), 0) for h, w in zip(hs, ws)] + [(th, tw, 1)]
+    raise ValueError(f"unknown workload {cfg}")
+
+
+def make_config_strip(cfg: int, pano: int, strip: int) -> Strip:
+    shapes = strip_shapes(cfg, pano)
+    H, W, axis = shapes[strip]
+    rng = rng_for(cfg, pano, strip)
+    if cfg == 0:
+        # 256 x 256 images; the strip is columns [96, 160)
+        return make_strip(rng, H, W, axis, field_kind="sinusoid", max_ux=3.0, max_uy=0.0,
+                          noise_l=0.0, noise_r=2.0, frame=(256, 256), x_off=96)
+    if cfg == 1:
+        return make_strip(rng, H, W, axis, field_kind="smooth", max_ux=40.0, max_uy=8.0,
+                          noise_l=3.0, noise_r=3.0, occluder=True)
+    if cfg in (2, 4):
+        return make_strip(rng, H, W, axis, field_kind="smooth", max_ux=40.0, max_uy=8.0,
+                          noise_l=2.0, noise_r=2.0, occluder=True, gain_range=(0.9, 1.1))
+    if cfg == 3:
+        return make_strip(rng, H, W, axis, field_kind="smooth", max_ux=40.0, max_uy=8.0,
+                          noise_l=2.0, noise_r=2.0, float_out=True)
+    raise ValueError(f"unknown workload {cfg}")
+
+
+def make_config(cfg: int, pano: int = 0):
+    return [make_config_strip(cfg, pano, s) for s in range(len(strip_shapes(cfg, pano)))]
+
+
+def make_random(seed: int, H: int, W: int, axis: int = 0, max_ux: float = 6.0, max_uy: float = 2.0,
+                noise: float = 2.0, sigma: float | None = None, occluder: bool = False,
+                float_out: bool = False) -> Strip:
+    """A strip of any size for parity tests (seed slot cfg = 100)."""
+    rng = rng_for(100, seed, 0)
+    if sigma is None:
+        sigma = max(8.0, 0.15 * min(H, W))
+    return make_strip(rng, H, W, axis, field_kind="smooth", max_ux=max_ux, max_uy=max_uy,
+                      noise_l=noise, noise_r=noise, occluder=occluder, float_out=float_out,
+                      field_params={"sigma": sigma})
+
+
+def random_bytes(seed: int, shape) -> np.ndarray:
+    """Uniform random uint8 array (tie-rich when drawn from few levels)."""
+    return rng_for(101, seed, 0).integers(0, 256, size=shape, dtype=np.uint8)
+
+
+def random_levels(seed: int, shape, levels: int) -> np.ndarray:
+    """uint8 array drawn from ``levels`` distinct values (many ties)."""
+    r = rng_for(102, seed, 0)
+    vals = np.linspace(0, 255, levels).round().astype(np.uint8)
+    return vals[r.integers(0, levels, size=shape)]
