@@ -1,0 +1,229 @@
+/*
+ * abf.h - C ABI of libabf: asymmetric bidirectional optical flow and
+ * asymmetric blending of panorama overlap strips on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Meng & Liu, "High-quality Panorama Stitching based on Asymmetric
+ * Bidirectional Optical Flow" (arXiv 2006.01201), Section III.C:
+ *   - III.C.1: two dense flows per overlap strip, FlowRtoL (OverlappedR
+ *     relative to OverlappedL) and FlowLtoR, by a coarse-to-fine pyramid
+ *     method;
+ *   - III.C.2, eq. (1): the global blending coefficient Blend;
+ *   - III.C.3, Code 1: per-pixel warp of L by FlowRtoL * Blend and of R by
+ *     FlowLtoR * (1 - Blend), then a softmax composite into F.
+ *
+ * Conventions shared by every call:
+ *   - A strip is H rows x W columns and is the whole of Area3 (the
+ *     overlap); L and R are its two crops, OverlappedL and OverlappedR.
+ *   - Images are RGB uint8, interleaved (HWC), rows `pitch` bytes apart
+ *     (pitch >= 3 W). Flows are float32 H x W x 2, contiguous, (x, y) =
+ *     (column, row) components.
+ *   - Flow sense: Ref(p) ~ Tgt(p + u(p)). FlowRtoL has Ref = R and Tgt = L
+ *     (R(p) ~ L(p + FlowRtoL(p))); FlowLtoR has Ref = L and Tgt = R.
+ *   - axis 0: Area1 (only L) lies left of the strip and Area2 right of it;
+ *     axis 1: Area1 above, Area2 below.
+ *   - All pointers named as device pointers point to device memory owned
+ *     by the caller. The library never allocates device memory on the hot
+ *     path: scratch comes from one caller-provided workspace.
+ *   - Calls are asynchronous on the given HIP stream (NULL = the default
+ *     stream); a kernel fault surfaces at the next synchronisation.
+ *   - A plan is bound to the device current at creation, and is not
+ *     thread-safe: use one plan per stream.
+ *   - Errors are returned as abf_status; no C++ exception crosses the ABI.
+ *     abf_last_error() gives the text of the last failure of a plan.
+ */
+#ifndef ABF_H
+#define ABF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum abf_status {
+    ABF_OK = 0,
+    ABF_E_INVALID = 1,     /* null pointer, bad parameter value */
+    ABF_E_SHAPE = 2,       /* sizes inconsistent or beyond the plan's limits */
+    ABF_E_WORKSPACE = 3,   /* no workspace bound, or too small */
+    ABF_E_DEVICE = 4,      /* a HIP runtime error (text in abf_last_error) */
+    ABF_E_UNSUPPORTED = 5, /* no device, not gfx950, or a parameter value the kernels do not implement */
+    ABF_E_CAPTURE = 6      /* hipGraph capture or instantiation failed */
+} abf_status;
+
+/* Parameters that change results. The paper publishes no values for its
+ * flow method or for kSoftmaxSharpness / kFlowMagCoef (Section III.C.3);
+ * abf_default_params() fills the adopted defaults. */
+typedef struct abf_params {
+    int32_t levels;        /* pyramid levels N, 1..12 */
+    int32_t patch;         /* P: (2P+1)^2 patch for the integer search; 1 or 2 */
+    int32_t radius;        /* R: search radius at every level but the coarsest; 1..4 */
+    int32_t radius_coarse; /* search radius at the coarsest level; 1..4 */
+    int32_t prop_steps;    /* T: Jacobi propagation steps per level; 0..4 */
+    int32_t median;        /* M: (2M+1)^2 component-wise median per level; 0 or 1 */
+    int32_t lk_patch;      /* (2P+1)^2 window of the level-0 Lucas-Kanade refinement; 1..3 */
+    int32_t lk_iters;      /* Gauss-Newton iterations; 0..8 */
+    float lk_eps;          /* Tikhonov term added to the window-summed normal matrix; > 0 */
+    float k_sharp;         /* kSoftmaxSharpness of Code 1 */
+    float k_flowmag;       /* kFlowMagCoef of Code 1 (flow magnitude is divided by the strip
+                              extent across the seam: W for axis 0, H for axis 1) */
+    int32_t blend_mode;    /* 0: softmax composite of Code 1; 1: linear weights (SoftmaxR = Blend) */
+} abf_params;
+
+typedef struct abf_plan abf_plan;
+
+/* One strip of a batch for abf_stitch_strips. Inputs: L, R, blend
+ * (nullable: eq. (1) ramp). Outputs: both flows and F; F_f32 (nullable)
+ * receives the unrounded composite, float32 H x W x 3 contiguous. */
+typedef struct abf_strip {
+    const uint8_t *L;
+    const uint8_t *R;
+    int32_t H, W;
+    int32_t pitch_L, pitch_R;
+    int32_t axis;
+    const float *blend;
+    float *flow_LtoR;
+    float *flow_RtoL;
+    uint8_t *F;
+    int32_t pitch_F;
+    float *F_f32;
+} abf_strip;
+
+/* Fills the adopted defaults: N = 6, P = 2, R = 2, Rc = 4, T = 2, M = 1,
+ * lk window 5 x 5, 2 iterations, eps 25, kSoftmaxSharpness 10,
+ * kFlowMagCoef 20, softmax blend. */
+void abf_default_params(abf_params *p);
+
+/* Creates a plan for batches of at most max_strips strips whose level-0
+ * pixel counts sum to at most max_pixels, each strip at most max_H x max_W.
+ * Checks the parameters (ABF_E_INVALID / ABF_E_UNSUPPORTED) and the device
+ * (ABF_E_UNSUPPORTED without a gfx950 device). *out receives the plan. */
+abf_status abf_create_plan(const abf_params *params, int32_t max_strips, int64_t max_pixels,
+                           int32_t max_H, int32_t max_W, abf_plan **out);
+
+/* Device bytes the workspace must hold for the plan's limits. */
+size_t abf_workspace_bytes(const abf_plan *plan);
+
+/* Binds caller-owned device memory (at least abf_workspace_bytes, 256-byte
+ * aligned) as the plan's workspace: image pyramids, integer flows of every
+ * level and the batch descriptor tables. The memory must stay valid while
+ * the plan uses it; rebinding replaces it. */
+abf_status abf_bind_workspace(abf_plan *plan, void *dev_ptr, size_t bytes);
+
+/* Section III.C.1: FlowLtoR and FlowRtoL of one strip. Device pointers:
+ * L, R (inputs), flow_LtoR, flow_RtoL (outputs, float32 H x W x 2).
+ * Pipeline: luma, binomial pyramid, per level from coarse to fine an
+ * integer patch-cost search around the upsampled coarser flow, Jacobi
+ * propagation and a median, then Lucas-Kanade refinement at level 0.
+ * ABF_E_SHAPE if the coarsest level would be smaller than 1 x 1 or the
+ * strip exceeds the plan. */
+abf_status abf_flow_bidirectional(abf_plan *plan, const uint8_t *L, const uint8_t *R, int32_t H,
+                                  int32_t W, int32_t pitch_L, int32_t pitch_R, float *flow_LtoR,
+                                  float *flow_RtoL, void *hip_stream);
+
+/* Code 1 with eq. (1) over one strip. Device pointers: L, R, flow_LtoR,
+ * flow_RtoL, blend (nullable: eq. (1) for a rectangular strip,
+ * Blend = (x+1)/(W+1) for axis 0, (y+1)/(H+1) for axis 1; otherwise a
+ * float32 H x W array of Blend values); F (output, uint8 RGB with pitch_F,
+ * round half up, clamped); F_f32 (nullable output, float32 H x W x 3). A
+ * non-finite flow component is used as 0. */
+abf_status abf_blend_asymmetric(abf_plan *plan, const uint8_t *L, const uint8_t *R,
+                                const float *flow_LtoR, const float *flow_RtoL, const float *blend,
+                                int32_t axis, int32_t H, int32_t W, int32_t pitch_L, int32_t pitch_R,
+                                uint8_t *F, int32_t pitch_F, float *F_f32, void *hip_stream);
+
+/* Both flows and the blend for a batch of n strips (host array of
+ * descriptors; the pointers inside are device pointers), with one launch
+ * per pyramid level and stage covering all strips. Results equal those of
+ * per-strip abf_flow_bidirectional + abf_blend_asymmetric bit for bit.
+ * use_graph != 0 captures the launch sequence in a hipGraph per batch
+ * shape and replays it (ABF_E_CAPTURE if capture fails). */
+abf_status abf_stitch_strips(abf_plan *plan, const abf_strip *strips, int32_t n, int32_t use_graph,
+                             void *hip_stream);
+
+/* Destroys a plan (host state only; the workspace stays the caller's). */
+abf_status abf_destroy(abf_plan *plan);
+
+const char *abf_status_string(abf_status s);
+const char *abf_last_error(const abf_plan *plan);
+
+/* ------------------------------------------------------------------ */
+/* Introspection of the workspace after a call, for tests: a device
+ * pointer to one intermediate of strip `strip` (0-based position in the
+ * last call's batch; 0 for the single-strip calls), level `level`,
+ * direction `dir` (0: LtoR, Ref = L; 1: RtoL, Ref = R).
+ *   kind 0: luma of the Ref image of `dir` at `level`, uint8, row pitch *pitch bytes;
+ *   kind 1: raw search result, int16 pairs (x, y), row pitch *pitch pairs;
+ *   kind 2: final flow of the level (after propagation and median), same layout.
+ * *H and *W receive the level size. */
+abf_status abf_workspace_view(const abf_plan *plan, int32_t kind, int32_t strip, int32_t level,
+                              int32_t dir, void **dev_ptr, int32_t *H, int32_t *W, int32_t *pitch);
+
+/* ------------------------------------------------------------------ */
+/* Flow refinement by gradient descent (an extension; not in the paper).
+ * Energy of a flow u (float32 H x W x 2) between float32 RGB images Ref
+ * and Tgt (H x W x 3, contiguous):
+ *   E = sum_p sum_c rho(Tgt~_c(p + u(p)) - Ref_c(p))
+ *     + lambda * sum_p sum_m sqrt((dx u_m)^2 + (dy u_m)^2 + eps^2),
+ * rho(r) = sqrt(r^2 + eps^2), Tgt~ bilinear with clamped indices, forward
+ * differences that are 0 at the last column / row.
+ * abf_energy writes E (one float, device) and, where non-null, dE/du,
+ * dE/dRef, dE/dTgt (device, same shapes as u, Ref, Tgt; overwritten). The
+ * derivative at an integer sample position is the right-hand one.
+ * deterministic != 0 computes dE/dTgt by a gather that fixes the
+ * summation order; otherwise atomics are used. */
+abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H,
+                      int32_t W, float lambda, float eps, float *E_dev, float *g_u, float *g_Ref,
+                      float *g_Tgt, int32_t deterministic, void *hip_stream);
+
+/* steps times u <- u - clip(eta * dE/du, -clip_px, clip_px) in place. */
+abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, float *u, int32_t H,
+                           int32_t W, int32_t steps, float eta, float lambda, float eps, float clip_px,
+                           void *hip_stream);
+
+/* Adjoint of Code 1 over float32 RGB images L, R (H x W x 3, contiguous;
+ * any value scale): given g_F (float32 H x W x 3), writes the gradients
+ * with respect to flow_LtoR, flow_RtoL (H x W x 2) and L, R (H x W x 3),
+ * each nullable and overwritten. d|f|/df = f/|f| for f != 0 and 0 at 0;
+ * a non-finite flow component is used as 0 and receives gradient 0. */
+abf_status abf_blend_backward(abf_plan *plan, const float *L, const float *R, const float *flow_LtoR,
+                              const float *flow_RtoL, const float *blend, int32_t axis, int32_t H,
+                              int32_t W, const float *g_F, float *g_flow_LtoR, float *g_flow_RtoL,
+                              float *g_L, float *g_R, void *hip_stream);
+
+/* Code 1 forward over float32 RGB images (the differentiable variant of
+ * abf_blend_asymmetric): F (float32 H x W x 3). */
+abf_status abf_blend_asymmetric_f32(abf_plan *plan, const float *L, const float *R,
+                                    const float *flow_LtoR, const float *flow_RtoL, const float *blend,
+                                    int32_t axis, int32_t H, int32_t W, float *F, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Autotuning of launch shapes (never of results): times the candidate
+ * tile heights and persistent grid sizes of each stage on the batch
+ * `strips` and keeps the fastest per (stage, level-size class). Writes
+ * the choice to the JSON file named by the ABF_TUNE_CACHE environment
+ * variable if set. Runs synchronously. */
+abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hip_stream);
+
+/* Current launch choice, for tests: stage 0..5 (luma, pyramid, search,
+ * propagation, refine, blend), level-size class 0..3; *tile_h and *grid
+ * receive the tile height and persistent workgroups per CU (0 = one
+ * workgroup per tile). abf_set_launch overrides it. */
+abf_status abf_get_launch(const abf_plan *plan, int32_t stage, int32_t size_class, int32_t *tile_h,
+                          int32_t *grid);
+abf_status abf_set_launch(abf_plan *plan, int32_t stage, int32_t size_class, int32_t tile_h, int32_t grid);
+
+/* Timing of the batched launch sequence (for benchmarks and profiles):
+ * runs abf_stitch_strips' launches `reps` times without a graph, with a
+ * hipEvent pair around every launch on `hip_stream`, and writes the mean
+ * milliseconds per launch to ms_out[stage * 12 + level] (stage numbering
+ * of abf_get_launch; 6 * 12 floats, host memory). Synchronous. */
+abf_status abf_profile(abf_plan *plan, const abf_strip *strips, int32_t n, int32_t reps, float *ms_out,
+                       void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABF_H */

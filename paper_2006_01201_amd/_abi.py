@@ -1,0 +1,193 @@
+"""ctypes binding of libabf.so (include/abf.h), one Python function per C
+entry point with the same name minus the ``abf_`` prefix. Arguments are
+plain integers (device pointers, sizes, stream handles); no computation
+happens here. Importing this module does not load the library; the first
+call does, and fails loudly if the HIP build is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabf.so")
+
+OK, E_INVALID, E_SHAPE, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED, E_CAPTURE = range(7)
+
+c_i32, c_i64, c_f32, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
+
+
+class AbfParams(ctypes.Structure):
+    _fields_ = [
+        ("levels", c_i32), ("patch", c_i32), ("radius", c_i32), ("radius_coarse", c_i32),
+        ("prop_steps", c_i32), ("median", c_i32), ("lk_patch", c_i32), ("lk_iters", c_i32),
+        ("lk_eps", c_f32), ("k_sharp", c_f32), ("k_flowmag", c_f32), ("blend_mode", c_i32),
+    ]
+
+
+class AbfStrip(ctypes.Structure):
+    _fields_ = [
+        ("L", c_vp), ("R", c_vp), ("H", c_i32), ("W", c_i32), ("pitch_L", c_i32), ("pitch_R", c_i32),
+        ("axis", c_i32), ("blend", c_vp), ("flow_LtoR", c_vp), ("flow_RtoL", c_vp), ("F", c_vp),
+        ("pitch_F", c_i32), ("F_f32", c_vp),
+    ]
+
+
+_SIGS = {
+    "abf_default_params": (None, [ctypes.POINTER(AbfParams)]),
+    "abf_create_plan": (c_i32, [ctypes.POINTER(AbfParams), c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_vp)]),
+    "abf_workspace_bytes": (c_sz, [c_vp]),
+    "abf_bind_workspace": (c_i32, [c_vp, c_vp, c_sz]),
+    "abf_flow_bidirectional": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp]),
+    "abf_blend_asymmetric": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32,
+                                     c_vp, c_i32, c_vp, c_vp]),
+    "abf_stitch_strips": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_i32, c_vp]),
+    "abf_destroy": (c_i32, [c_vp]),
+    "abf_status_string": (ctypes.c_char_p, [c_i32]),
+    "abf_last_error": (ctypes.c_char_p, [c_vp]),
+    "abf_workspace_view": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_vp),
+                                   ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+    "abf_energy": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp, c_i32,
+                           c_vp]),
+    "abf_refine_flow": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_f32, c_vp]),
+    "abf_blend_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp,
+                                   c_vp, c_vp, c_vp]),
+    "abf_blend_asymmetric_f32": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
+    "abf_tune": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_vp]),
+    "abf_get_launch": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+    "abf_set_launch": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32]),
+    "abf_profile": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_i32, ctypes.POINTER(c_f32), c_vp]),
+}
+
+MAX_LEVELS = 12
+N_STAGES = 6
+
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libabf.so (built by ``paper_2006_01201_amd/build.py``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libabf.so is not built ({LIB_PATH}); run paper_2006_01201_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class AbfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+def check(status: int, plan=None, what: str = "") -> None:
+    if status == OK:
+        return
+    lib = load()
+    text = lib.abf_status_string(status).decode()
+    detail = lib.abf_last_error(plan).decode() if plan else ""
+    msg = f"{what}: {text}" + (f" ({detail})" if detail else "")
+    if status in (E_INVALID, E_SHAPE):
+        raise ValueError(msg)
+    raise AbfError(status, msg)
+
+
+# thin wrappers with the C names ------------------------------------------
+def default_params() -> AbfParams:
+    p = AbfParams()
+    load().abf_default_params(ctypes.byref(p))
+    return p
+
+
+def create_plan(params: AbfParams, max_strips: int, max_pixels: int, max_H: int, max_W: int):
+    out = c_vp()
+    st = load().abf_create_plan(ctypes.byref(params), max_strips, max_pixels, max_H, max_W, ctypes.byref(out))
+    return st, out.value
+
+
+def workspace_bytes(plan) -> int:
+    return load().abf_workspace_bytes(plan)
+
+
+def bind_workspace(plan, ptr: int, nbytes: int) -> int:
+    return load().abf_bind_workspace(plan, ptr, nbytes)
+
+
+def flow_bidirectional(plan, L, R, H, W, pitch_L, pitch_R, flow_LtoR, flow_RtoL, stream) -> int:
+    return load().abf_flow_bidirectional(plan, L, R, H, W, pitch_L, pitch_R, flow_LtoR, flow_RtoL, stream)
+
+
+def blend_asymmetric(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, pitch_L, pitch_R, F, pitch_F, F_f32,
+                     stream) -> int:
+    return load().abf_blend_asymmetric(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, pitch_L, pitch_R, F,
+                                       pitch_F, F_f32, stream)
+
+
+def stitch_strips(plan, strips, n, use_graph, stream) -> int:
+    return load().abf_stitch_strips(plan, strips, n, use_graph, stream)
+
+
+def destroy(plan) -> int:
+    return load().abf_destroy(plan)
+
+
+def status_string(status: int) -> str:
+    return load().abf_status_string(status).decode()
+
+
+def last_error(plan) -> str:
+    return load().abf_last_error(plan).decode()
+
+
+def workspace_view(plan, kind, strip, level, direction):
+    ptr, H, W, pitch = c_vp(), c_i32(), c_i32(), c_i32()
+    st = load().abf_workspace_view(plan, kind, strip, level, direction, ctypes.byref(ptr), ctypes.byref(H),
+                                   ctypes.byref(W), ctypes.byref(pitch))
+    return st, ptr.value, H.value, W.value, pitch.value
+
+
+def energy(plan, Ref, Tgt, u, H, W, lam, eps, E, g_u, g_ref, g_tgt, deterministic, stream) -> int:
+    return load().abf_energy(plan, Ref, Tgt, u, H, W, lam, eps, E, g_u, g_ref, g_tgt, deterministic, stream)
+
+
+def refine_flow(plan, Ref, Tgt, u, H, W, steps, eta, lam, eps, clip_px, stream) -> int:
+    return load().abf_refine_flow(plan, Ref, Tgt, u, H, W, steps, eta, lam, eps, clip_px, stream)
+
+
+def blend_backward(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, g_F, g_flr, g_frl, g_L, g_R, stream) -> int:
+    return load().abf_blend_backward(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, g_F, g_flr, g_frl, g_L,
+                                     g_R, stream)
+
+
+def blend_asymmetric_f32(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, F, stream) -> int:
+    return load().abf_blend_asymmetric_f32(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, F, stream)
+
+
+def tune(plan, strips, n, stream) -> int:
+    return load().abf_tune(plan, strips, n, stream)
+
+
+def get_launch(plan, stage, size_class):
+    th, g = c_i32(), c_i32()
+    st = load().abf_get_launch(plan, stage, size_class, ctypes.byref(th), ctypes.byref(g))
+    return st, th.value, g.value
+
+
+def set_launch(plan, stage, size_class, tile_h, grid) -> int:
+    return load().abf_set_launch(plan, stage, size_class, tile_h, grid)
+
+
+def profile(plan, strips, n, reps, stream):
+    out = (c_f32 * (N_STAGES * MAX_LEVELS))()
+    st = load().abf_profile(plan, strips, n, reps, out, stream)
+    return st, [[out[s * MAX_LEVELS + k] for k in range(MAX_LEVELS)] for s in range(N_STAGES)]

@@ -1,0 +1,207 @@
+"""Torch-facing wrapper of libabf: tensors in, tensors out.
+
+PyTorch supplies device memory (the workspace and the outputs are
+``torch.empty`` tensors) and the stream (the current stream); every step of
+the computation runs in libabf's HIP kernels. Shape and dtype checks and
+argument marshalling are all this module does.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, fields
+
+import torch
+
+from . import _abi
+
+STAGES = ("luma", "pyramid", "search", "propagation", "refine", "blend")
+
+
+@dataclass(frozen=True)
+class Params:
+    """Mirror of ``abf_params`` (include/abf.h) with the adopted defaults."""
+
+    levels: int = 6
+    patch: int = 2
+    radius: int = 2
+    radius_coarse: int = 4
+    prop_steps: int = 2
+    median: int = 1
+    lk_patch: int = 2
+    lk_iters: int = 2
+    lk_eps: float = 25.0
+    k_sharp: float = 10.0
+    k_flowmag: float = 20.0
+    blend_mode: int = 0
+
+    def to_c(self) -> _abi.AbfParams:
+        p = _abi.AbfParams()
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+    @staticmethod
+    def lean(**kw) -> "Params":
+        d = dict(patch=1, radius=1, radius_coarse=3, prop_steps=1, lk_patch=1, lk_iters=1, lk_eps=9.0)
+        d.update(kw)
+        return Params(**d)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _img_u8(t: torch.Tensor, name: str):
+    if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != 3 or not t.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA uint8 tensor of shape (H, W, 3), got {t.dtype} {tuple(t.shape)}")
+    if t.stride(2) != 1 or t.stride(1) != 3:
+        raise ValueError(f"{name}: pixels must be interleaved RGB (strides (pitch, 3, 1)), got {t.stride()}")
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+def _f32(t: torch.Tensor, shape, name: str):
+    if t.dtype != torch.float32 or tuple(t.shape) != tuple(shape) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous CUDA float32 tensor {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+class Batch:
+    """Strip descriptors plus their output tensors, reusable across calls."""
+
+    def __init__(self, strips, outputs, arr):
+        self.strips = strips
+        self.outputs = outputs
+        self.arr = arr
+        self.n = len(strips)
+
+
+class Plan:
+    """An abf_plan with its workspace."""
+
+    def __init__(self, params: Params = Params(), max_strips: int = 1, max_pixels: int | None = None,
+                 max_H: int = 4096, max_W: int = 4096):
+        if max_pixels is None:
+            max_pixels = max_strips * max_H * max_W
+        self.params = params
+        st, h = _abi.create_plan(params.to_c(), max_strips, max_pixels, max_H, max_W)
+        _abi.check(st, None, "abf_create_plan")
+        self.h = h
+        nbytes = _abi.workspace_bytes(h)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        self._ws_off = (-base) % 256
+        _abi.check(_abi.bind_workspace(h, base + self._ws_off, nbytes), h, "abf_bind_workspace")
+        self.workspace_bytes = nbytes
+
+    def close(self):
+        if getattr(self, "h", None):
+            _abi.destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the paper's calls ---------------------------------------------
+    def flow_bidirectional(self, L: torch.Tensor, R: torch.Tensor, out=None):
+        """FlowLtoR and FlowRtoL (float32 H x W x 2) of one strip."""
+        H, W, pl = _img_u8(L, "L")
+        H2, W2, pr = _img_u8(R, "R")
+        if (H, W) != (H2, W2):
+            raise ValueError("L and R differ in size")
+        if out is None:
+            flr = torch.empty((H, W, 2), dtype=torch.float32, device=L.device)
+            frl = torch.empty((H, W, 2), dtype=torch.float32, device=L.device)
+        else:
+            flr, frl = out
+        st = _abi.flow_bidirectional(self.h, L.data_ptr(), R.data_ptr(), H, W, pl, pr,
+                                     _f32(flr, (H, W, 2), "flow_LtoR"), _f32(frl, (H, W, 2), "flow_RtoL"), _stream())
+        _abi.check(st, self.h, "abf_flow_bidirectional")
+        return flr, frl
+
+    def blend_asymmetric(self, L, R, flow_lr, flow_rl, blend=None, axis: int = 0, f32: bool = False, out=None):
+        """Code 1 over one strip; returns F (uint8 H x W x 3) and, if
+        ``f32``, the unrounded composite (float32 H x W x 3)."""
+        H, W, pl = _img_u8(L, "L")
+        _, _, pr = _img_u8(R, "R")
+        if out is None:
+            F = torch.empty((H, W, 3), dtype=torch.uint8, device=L.device)
+        else:
+            F = out
+        _, _, pf = _img_u8(F, "F")
+        Ff = torch.empty((H, W, 3), dtype=torch.float32, device=L.device) if f32 else None
+        bp = _f32(blend, (H, W), "blend") if blend is not None else None
+        st = _abi.blend_asymmetric(self.h, L.data_ptr(), R.data_ptr(), _f32(flow_lr, (H, W, 2), "flow_LtoR"),
+                                   _f32(flow_rl, (H, W, 2), "flow_RtoL"), bp, axis, H, W, pl, pr, F.data_ptr(), pf,
+                                   Ff.data_ptr() if Ff is not None else None, _stream())
+        _abi.check(st, self.h, "abf_blend_asymmetric")
+        return (F, Ff) if f32 else F
+
+    def make_batch(self, strips, f32: bool = False) -> Batch:
+        """strips: sequence of (L, R, axis) or (L, R, axis, blend). Allocates
+        the outputs once; ``stitch`` can then be called repeatedly."""
+        arr = (_abi.AbfStrip * len(strips))()
+        outs = []
+        keep = []
+        for i, s in enumerate(strips):
+            L, R, axis = s[0], s[1], s[2]
+            blend = s[3] if len(s) > 3 else None
+            H, W, pl = _img_u8(L, "L")
+            _, _, pr = _img_u8(R, "R")
+            o = {
+                "flow_lr": torch.empty((H, W, 2), dtype=torch.float32, device=L.device),
+                "flow_rl": torch.empty((H, W, 2), dtype=torch.float32, device=L.device),
+                "F": torch.empty((H, W, 3), dtype=torch.uint8, device=L.device),
+                "F_f32": torch.empty((H, W, 3), dtype=torch.float32, device=L.device) if f32 else None,
+            }
+            d = arr[i]
+            d.L, d.R, d.H, d.W, d.pitch_L, d.pitch_R, d.axis = L.data_ptr(), R.data_ptr(), H, W, pl, pr, axis
+            d.blend = _f32(blend, (H, W), "blend") if blend is not None else None
+            d.flow_LtoR, d.flow_RtoL = o["flow_lr"].data_ptr(), o["flow_rl"].data_ptr()
+            d.F, d.pitch_F = o["F"].data_ptr(), 3 * W
+            d.F_f32 = o["F_f32"].data_ptr() if f32 else None
+            outs.append(o)
+            keep.append(s)
+        return Batch(keep, outs, arr)
+
+    def stitch(self, batch: Batch, use_graph: bool = True):
+        st = _abi.stitch_strips(self.h, batch.arr, batch.n, int(use_graph), _stream())
+        _abi.check(st, self.h, "abf_stitch_strips")
+        return batch.outputs
+
+    def stitch_strips(self, strips, use_graph: bool = True, f32: bool = False):
+        return self.stitch(self.make_batch(strips, f32), use_graph)
+
+    def tune(self, batch: Batch):
+        _abi.check(_abi.tune(self.h, batch.arr, batch.n, _stream()), self.h, "abf_tune")
+
+    def profile(self, batch: Batch, reps: int = 5):
+        """Mean ms per launch, indexed [stage][level] (eager launches
+        bracketed by HIP events on the current stream)."""
+        st, ms = _abi.profile(self.h, batch.arr, batch.n, reps, _stream())
+        _abi.check(st, self.h, "abf_profile")
+        return ms
+
+    def get_launch(self, stage: int, size_class: int):
+        st, th, g = _abi.get_launch(self.h, stage, size_class)
+        _abi.check(st, self.h, "abf_get_launch")
+        return th, g
+
+    def set_launch(self, stage: int, size_class: int, tile_h: int, grid: int):
+        _abi.check(_abi.set_launch(self.h, stage, size_class, tile_h, grid), self.h, "abf_set_launch")
+
+    # -- inspection ------------------------------------------------------
+    def view(self, kind: int, strip: int, level: int, direction: int) -> torch.Tensor:
+        """A copy of one intermediate of the last flow call: kind 0 luma
+        (uint8 H x W), 1 raw search / 2 final integer flow (int16 H x W x 2)."""
+        st, ptr, H, W, pitch = _abi.workspace_view(self.h, kind, strip, level, direction)
+        _abi.check(st, self.h, "abf_workspace_view")
+        off = ptr - self._ws.data_ptr()
+        if kind == 0:
+            t = self._ws[off:off + H * pitch].view(H, pitch)[:, :W]
+        else:
+            t = self._ws[off:off + H * pitch * 4].view(torch.int16).view(H, pitch, 2)[:, :W]
+        return t.clone()

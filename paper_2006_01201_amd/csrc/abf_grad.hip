@@ -1,0 +1,396 @@
+// Differentiable path of libabf (an extension of the paper's method):
+//   - the photometric Charbonnier + TV energy of a flow between two float
+//     RGB images, with its gradients with respect to the flow and both
+//     images, and a fused gradient-descent step on the flow;
+//   - Code 1 over float RGB images and its adjoint with respect to both
+//     flows and both images.
+// One thread per pixel. Bilinear samples split the displacement into
+// floor + fraction (the derivative at an integer position is the
+// right-hand one). Scatters into image gradients use float atomics, or,
+// in deterministic mode, 64-bit fixed-point integer atomics (exactly
+// order-independent) converted to float afterwards.
+#include <hip/hip_runtime.h>
+
+#include "abf_internal.h"
+
+namespace abf {
+
+namespace {
+
+__device__ __forceinline__ int clampg(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+constexpr double kFixScale = 1099511627776.0;  // 2^40
+
+__device__ __forceinline__ void scatter_add(float *g, unsigned long long *gfix, size_t i, float v)
+{
+    if (gfix)
+        atomicAdd(gfix + i, (unsigned long long)(long long)llrint((double)v * kFixScale));
+    else
+        atomicAdd(g + i, v);
+}
+
+struct Bil {
+    int xa, xb, ya, yb;
+    float fx, fy;
+};
+
+__device__ __forceinline__ Bil bil_at(int x, int y, float ux, float uy, int H, int W)
+{
+    const float fux = floorf(ux), fuy = floorf(uy);
+    const int x0 = x + (int)fux, y0 = y + (int)fuy;
+    Bil b;
+    b.fx = ux - fux;
+    b.fy = uy - fuy;
+    b.xa = clampg(x0, 0, W - 1);
+    b.xb = clampg(x0 + 1, 0, W - 1);
+    b.ya = clampg(y0, 0, H - 1);
+    b.yb = clampg(y0 + 1, 0, H - 1);
+    return b;
+}
+
+// value and position derivatives of channel c of a float HWC image
+__device__ __forceinline__ void bil_eval(const float *img, int W, const Bil &b, int c, float &v, float &dX, float &dY)
+{
+    const float v00 = img[3 * ((size_t)b.ya * W + b.xa) + c], v01 = img[3 * ((size_t)b.ya * W + b.xb) + c];
+    const float v10 = img[3 * ((size_t)b.yb * W + b.xa) + c], v11 = img[3 * ((size_t)b.yb * W + b.xb) + c];
+    const float top = v00 + b.fx * (v01 - v00), bot = v10 + b.fx * (v11 - v10);
+    v = top + b.fy * (bot - top);
+    dX = (1.f - b.fy) * (v01 - v00) + b.fy * (v11 - v10);
+    dY = (1.f - b.fx) * (v10 - v00) + b.fx * (v11 - v01);
+}
+
+__device__ __forceinline__ void bil_scatter(float *g, unsigned long long *gfix, int W, const Bil &b, int c, float w)
+{
+    scatter_add(g, gfix, 3 * ((size_t)b.ya * W + b.xa) + c, w * (1.f - b.fy) * (1.f - b.fx));
+    scatter_add(g, gfix, 3 * ((size_t)b.ya * W + b.xb) + c, w * (1.f - b.fy) * b.fx);
+    scatter_add(g, gfix, 3 * ((size_t)b.yb * W + b.xa) + c, w * b.fy * (1.f - b.fx));
+    scatter_add(g, gfix, 3 * ((size_t)b.yb * W + b.xb) + c, w * b.fy * b.fx);
+}
+
+// TV term at q for component m: s(q) and the forward differences
+__device__ __forceinline__ float tv_s(const float *u, int H, int W, int x, int y, int m, float eps, float &dx,
+                                      float &dy)
+{
+    const size_t q = (size_t)y * W + x;
+    const float c = u[2 * q + m];
+    dx = x < W - 1 ? u[2 * (q + 1) + m] - c : 0.f;
+    dy = y < H - 1 ? u[2 * (q + W) + m] - c : 0.f;
+    return sqrtf(dx * dx + dy * dy + eps * eps);
+}
+
+// dE/du at p (photometric + lambda * TV); also returns the pixel's energy
+__device__ __forceinline__ void grad_u_at(const float *Ref, const float *Tgt, const float *u, int H, int W, int x,
+                                          int y, float lambda, float eps, float &gx, float &gy, double &e)
+{
+    const size_t p = (size_t)y * W + x;
+    const float ux = u[2 * p], uy = u[2 * p + 1];
+    const Bil b = bil_at(x, y, ux, uy, H, W);
+    gx = gy = 0.f;
+    e = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float v, dX, dY;
+        bil_eval(Tgt, W, b, c, v, dX, dY);
+        const float r = v - Ref[3 * p + c];
+        const float rho = sqrtf(r * r + eps * eps);
+        const float d = r / rho;
+        e += rho;
+        gx = fmaf(d, dX, gx);
+        gy = fmaf(d, dY, gy);
+    }
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        float dx, dy;
+        const float s = tv_s(u, H, W, x, y, m, eps, dx, dy);
+        e += (double)lambda * s;
+        float g = -(dx + dy) / s;
+        if (x > 0) {
+            float ddx, ddy;
+            const float sl = tv_s(u, H, W, x - 1, y, m, eps, ddx, ddy);
+            g += ddx / sl;
+        }
+        if (y > 0) {
+            float ddx, ddy;
+            const float su = tv_s(u, H, W, x, y - 1, m, eps, ddx, ddy);
+            g += ddy / su;
+        }
+        if (m == 0) gx = fmaf(lambda, g, gx);
+        else gy = fmaf(lambda, g, gy);
+    }
+}
+
+constexpr int kEB = 256;
+
+__global__ __launch_bounds__(kEB) void k_energy(const float *__restrict__ Ref, const float *__restrict__ Tgt,
+                                                const float *__restrict__ u, int H, int W, float lambda, float eps,
+                                                double *__restrict__ partials, float *__restrict__ g_u,
+                                                float *__restrict__ g_ref, float *g_tgt, unsigned long long *g_fix)
+{
+    __shared__ double red[kEB];
+    const int64_t n = (int64_t)H * W;
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * kEB + threadIdx.x; p < n; p += (int64_t)gridDim.x * kEB) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        float gx, gy;
+        double e;
+        grad_u_at(Ref, Tgt, u, H, W, x, y, lambda, eps, gx, gy, e);
+        acc += e;
+        if (g_u) {
+            g_u[2 * p] = gx;
+            g_u[2 * p + 1] = gy;
+        }
+        if (g_ref || g_tgt || g_fix) {
+            const Bil b = bil_at(x, y, u[2 * p], u[2 * p + 1], H, W);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                float v, dX, dY;
+                bil_eval(Tgt, W, b, c, v, dX, dY);
+                const float r = v - Ref[3 * p + c];
+                const float d = r / sqrtf(r * r + eps * eps);
+                if (g_ref) g_ref[3 * p + c] = -d;
+                if (g_tgt || g_fix) bil_scatter(g_tgt, g_fix, W, b, c, d);
+            }
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kEB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kEB) void k_sum_partials(const double *__restrict__ partials, int n, float *E)
+{
+    __shared__ double red[kEB];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kEB) acc += partials[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kEB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *E = (float)red[0];
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(float *a, unsigned long long *b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (a) a[i] = 0.f;
+        if (b) b[i] = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fix_to_float(const unsigned long long *__restrict__ b, float *a, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        a[i] = (float)((double)(long long)b[i] / kFixScale);
+}
+
+__global__ __launch_bounds__(256) void k_energy_step(const float *__restrict__ Ref, const float *__restrict__ Tgt,
+                                                     const float *__restrict__ u_in, float *__restrict__ u_out, int H,
+                                                     int W, float eta, float lambda, float eps, float clip)
+{
+    const int64_t n = (int64_t)H * W;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        float gx, gy;
+        double e;
+        grad_u_at(Ref, Tgt, u_in, H, W, x, y, lambda, eps, gx, gy, e);
+        const float sx = fminf(fmaxf(eta * gx, -clip), clip), sy = fminf(fmaxf(eta * gy, -clip), clip);
+        u_out[2 * p] = u_in[2 * p] - sx;
+        u_out[2 * p + 1] = u_in[2 * p + 1] - sy;
+    }
+}
+
+// --- Code 1 on float images ------------------------------------------
+struct Setup {
+    Bil bl, br;
+    double t, nrl, nlr;
+    float rl[2], lr[2];
+    bool okrl[2], oklr[2];
+    float sL;
+};
+
+__device__ __forceinline__ Setup code1_setup(int x, int y, int H, int W, int axis, const float *blend,
+                                             const float *flr, const float *frl, BlendParams bp)
+{
+    Setup s;
+    const size_t p = (size_t)y * W + x;
+    s.t = blend ? (double)blend[p] : (axis == 0 ? (x + 1.0) / (W + 1.0) : (y + 1.0) / (H + 1.0));
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const float a = frl[2 * p + k], b = flr[2 * p + k];
+        s.okrl[k] = isfinite(a);
+        s.oklr[k] = isfinite(b);
+        s.rl[k] = s.okrl[k] ? a : 0.f;
+        s.lr[k] = s.oklr[k] ? b : 0.f;
+    }
+    const double ax = s.rl[0] * s.t, ay = s.rl[1] * s.t, bx = s.lr[0] * (1.0 - s.t), by = s.lr[1] * (1.0 - s.t);
+    const double fax = floor(ax), fay = floor(ay), fbx = floor(bx), fby = floor(by);
+    auto mk = [&](int x0, int y0, float fx, float fy) {
+        Bil b;
+        b.fx = fx;
+        b.fy = fy;
+        b.xa = clampg(x0, 0, W - 1);
+        b.xb = clampg(x0 + 1, 0, W - 1);
+        b.ya = clampg(y0, 0, H - 1);
+        b.yb = clampg(y0 + 1, 0, H - 1);
+        return b;
+    };
+    s.bl = mk(x + (int)fax, y + (int)fay, (float)(ax - fax), (float)(ay - fay));
+    s.br = mk(x + (int)fbx, y + (int)fby, (float)(bx - fbx), (float)(by - fby));
+    s.nrl = sqrt((double)s.rl[0] * s.rl[0] + (double)s.rl[1] * s.rl[1]);
+    s.nlr = sqrt((double)s.lr[0] * s.lr[0] + (double)s.lr[1] * s.lr[1]);
+    if (bp.mode == 1) {
+        s.sL = (float)(1.0 - s.t);
+    } else {
+        const double S = axis == 0 ? (double)W : (double)H;
+        const double zL = (double)bp.k_sharp * (1.0 - s.t) * (1.0 + (double)bp.k_flowmag * s.nrl / S);
+        const double zR = (double)bp.k_sharp * s.t * (1.0 + (double)bp.k_flowmag * s.nlr / S);
+        s.sL = 1.0f / (1.0f + expf((float)(zR - zL)));
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_blend_f32(const float *__restrict__ L, const float *__restrict__ R,
+                                                   const float *__restrict__ flr, const float *__restrict__ frl,
+                                                   const float *__restrict__ blend, int axis, int H, int W,
+                                                   BlendParams bp, float *__restrict__ F)
+{
+    const int64_t n = (int64_t)H * W;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const Setup s = code1_setup(x, y, H, W, axis, blend, flr, frl, bp);
+        const float sR = 1.f - s.sL;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float cl, cr, d0, d1;
+            bil_eval(L, W, s.bl, c, cl, d0, d1);
+            bil_eval(R, W, s.br, c, cr, d0, d1);
+            F[3 * p + c] = s.sL * cl + sR * cr;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_blend_bwd(const float *__restrict__ L, const float *__restrict__ R,
+                                                   const float *__restrict__ flr, const float *__restrict__ frl,
+                                                   const float *__restrict__ blend, int axis, int H, int W,
+                                                   BlendParams bp, const float *__restrict__ gF,
+                                                   float *__restrict__ g_flr, float *__restrict__ g_frl, float *g_L,
+                                                   float *g_R, unsigned long long *fixL, unsigned long long *fixR)
+{
+    const int64_t n = (int64_t)H * W;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const Setup s = code1_setup(x, y, H, W, axis, blend, flr, frl, bp);
+        const float sL = s.sL, sR = 1.f - s.sL;
+        float gs = 0.f, gLx = 0.f, gLy = 0.f, gRx = 0.f, gRy = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float cl, cr, lX, lY, rX, rY;
+            bil_eval(L, W, s.bl, c, cl, lX, lY);
+            bil_eval(R, W, s.br, c, cr, rX, rY);
+            const float g = gF[3 * p + c];
+            gs = fmaf(g, cl - cr, gs);
+            gLx = fmaf(g * sL, lX, gLx);
+            gLy = fmaf(g * sL, lY, gLy);
+            gRx = fmaf(g * sR, rX, gRx);
+            gRy = fmaf(g * sR, rY, gRy);
+            if (g_L || fixL) bil_scatter(g_L, fixL, W, s.bl, c, g * sL);
+            if (g_R || fixR) bil_scatter(g_R, fixR, W, s.br, c, g * sR);
+        }
+        const float t = (float)s.t;
+        float grl_x = t * gLx, grl_y = t * gLy, glr_x = (1.f - t) * gRx, glr_y = (1.f - t) * gRy;
+        if (bp.mode != 1) {
+            const double S = axis == 0 ? (double)W : (double)H;
+            const double dz = (double)gs * (double)sL * (double)sR;
+            if (s.nrl > 0) {
+                const double k = dz * bp.k_sharp * (1.0 - s.t) * bp.k_flowmag / S / s.nrl;
+                grl_x += (float)(k * s.rl[0]);
+                grl_y += (float)(k * s.rl[1]);
+            }
+            if (s.nlr > 0) {
+                const double k = -dz * bp.k_sharp * s.t * bp.k_flowmag / S / s.nlr;
+                glr_x += (float)(k * s.lr[0]);
+                glr_y += (float)(k * s.lr[1]);
+            }
+        }
+        if (g_frl) {
+            g_frl[2 * p] = s.okrl[0] ? grl_x : 0.f;
+            g_frl[2 * p + 1] = s.okrl[1] ? grl_y : 0.f;
+        }
+        if (g_flr) {
+            g_flr[2 * p] = s.oklr[0] ? glr_x : 0.f;
+            g_flr[2 * p + 1] = s.oklr[1] ? glr_y : 0.f;
+        }
+    }
+}
+
+inline int blocks_for(int64_t n, int per = 256, int cap = 65536)
+{
+    int64_t b = (n + per - 1) / per;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+int energy_blocks(int H, int W) { return blocks_for((int64_t)H * W, kEB, 4096); }
+
+// partials: energy_blocks doubles; fix: 3 H W uint64 (deterministic only)
+hipError_t launch_energy_full(const float *Ref, const float *Tgt, const float *u, int H, int W, float lambda,
+                              float eps, double *partials, float *E, float *g_u, float *g_ref, float *g_tgt,
+                              unsigned long long *fix, hipStream_t s)
+{
+    const int64_t n3 = (int64_t)H * W * 3;
+    const int nb = energy_blocks(H, W);
+    if (g_tgt) {
+        hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, fix ? nullptr : g_tgt, fix, n3);
+    }
+    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kEB), 0, s, Ref, Tgt, u, H, W, lambda, eps, partials, g_u, g_ref,
+                       fix ? nullptr : g_tgt, g_tgt ? fix : nullptr);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kEB), 0, s, partials, nb, E);
+    if (g_tgt && fix) hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fix, g_tgt, n3);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_step(const float *Ref, const float *Tgt, const float *u_in, float *u_out, int H, int W,
+                              float eta, float lambda, float eps, float clip, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_step, dim3(blocks_for((int64_t)H * W)), dim3(256), 0, s, Ref, Tgt, u_in, u_out, H,
+                       W, eta, lambda, eps, clip);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t s)
+{
+    return hipMemcpyAsync(dst, src, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t launch_blend_f32(const float *L, const float *R, const float *flr, const float *frl, const float *blend,
+                            int axis, int H, int W, BlendParams bp, float *F, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_blend_f32, dim3(blocks_for((int64_t)H * W)), dim3(256), 0, s, L, R, flr, frl, blend, axis,
+                       H, W, bp, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *flr, const float *frl,
+                                 const float *blend, int axis, int H, int W, BlendParams bp, const float *gF,
+                                 float *g_flr, float *g_frl, float *g_L, float *g_R, unsigned long long *fixL,
+                                 unsigned long long *fixR, hipStream_t s)
+{
+    const int64_t n3 = (int64_t)H * W * 3;
+    if (g_L) hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, fixL ? nullptr : g_L, fixL, n3);
+    if (g_R) hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, fixR ? nullptr : g_R, fixR, n3);
+    hipLaunchKernelGGL(k_blend_bwd, dim3(blocks_for((int64_t)H * W)), dim3(256), 0, s, L, R, flr, frl, blend, axis,
+                       H, W, bp, gF, g_flr, g_frl, fixL ? nullptr : g_L, fixR ? nullptr : g_R, g_L ? fixL : nullptr,
+                       g_R ? fixR : nullptr);
+    if (g_L && fixL) hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fixL, g_L, n3);
+    if (g_R && fixR) hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fixR, g_R, n3);
+    return hipGetLastError();
+}
+
+}  // namespace abf

@@ -1,0 +1,113 @@
+// Internal definitions shared by the HIP kernels and the host runtime of
+// libabf. Nothing here is part of the public ABI (include/abf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace abf {
+
+constexpr int kMaxLevels = 12;
+constexpr int kStages = 6;       // luma, pyramid, search, propagation, refine, blend
+constexpr int kSizeClasses = 4;  // by pixel count of one level over the batch
+
+enum Stage { ST_LUMA = 0, ST_PYR = 1, ST_SEARCH = 2, ST_PROP = 3, ST_REFINE = 4, ST_BLEND = 5 };
+
+// One strip at one pyramid level, as the kernels see it. Direction d uses
+// y[d] as Ref and y[1 - d] as Tgt (d = 0: LtoR, d = 1: RtoL). Integer
+// flows are int16 pairs packed in one uint32 (x low, y high).
+struct StripLv {
+    uint8_t *y[2];          // luma of L and R at this level (pitch ypitch bytes)
+    uint32_t *ds[2];        // raw search result per direction (pitch fpitch)
+    uint32_t *df[2];        // final flow of the level per direction
+    const uint32_t *dc[2];  // final flow of the next coarser level (null at the coarsest)
+    const uint8_t *yfine[2];// luma of the next finer level (pyramid input; null at level 0)
+    int32_t H, W, ypitch, fpitch;
+    int32_t Hc, Wc, fpitch_c;
+    int32_t Hf, Wf, ypitch_f;  // finer level geometry (pyramid input)
+    int32_t radius;
+    int32_t pad_;
+};
+
+// The caller's buffers of one strip.
+struct StripIO {
+    const uint8_t *L, *R;
+    const float *blend;
+    float *flow[2];  // [0] = FlowLtoR, [1] = FlowRtoL
+    uint8_t *F;
+    float *Ff32;
+    int32_t pitchL, pitchR, pitchF;
+    int32_t H, W, axis;
+};
+
+// Launch of one stage over a batch: the strip table, per-strip tile
+// prefix sums (n + 1 entries, device) and the total tile count.
+struct Work {
+    const int32_t *prefix;  // device
+    int32_t n;              // strips
+    int32_t total;          // tiles over all strips
+};
+
+// Float parameters the kernels take by value.
+struct LkParams {
+    int32_t patch, iters;
+    float eps;
+};
+
+struct BlendParams {
+    float k_sharp, k_flowmag;
+    int32_t mode;
+};
+
+// Tile geometry per stage, shared by host and device (tiles per strip are
+// computed identically on both sides).
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// search / propagation / refine tiles: 64 x TH (search, refine) and
+// 32 x TH (propagation); luma / blend: 256 pixels of one row; pyramid:
+// 64 x 4 output pixels.
+constexpr int kSearchTW = 64;
+constexpr int kPropTW = 32;
+constexpr int kRefineTW = 64;
+constexpr int kRowTW = 256;
+constexpr int kPyrTW = 64;
+constexpr int kPyrTH = 4;
+
+// ---------------------------------------------------------------------
+// Kernel launchers (defined in abf_kernels.hip). Each returns the HIP
+// error of the launch. `grid` = 0 launches one workgroup per tile;
+// otherwise that many persistent workgroups loop over the tiles.
+hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s);
+hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s);
+hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int th, int grid, hipStream_t s);
+hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid,
+                       hipStream_t s);
+hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid,
+                         hipStream_t s);
+hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s);
+
+// differentiable path (float images); `fix` buffers (3 H W uint64) select
+// the deterministic fixed-point scatter, null selects float atomics
+int energy_blocks(int H, int W);
+hipError_t launch_energy_full(const float *Ref, const float *Tgt, const float *u, int H, int W, float lambda,
+                              float eps, double *partials, float *E, float *g_u, float *g_ref, float *g_tgt,
+                              unsigned long long *fix, hipStream_t s);
+hipError_t launch_energy_step(const float *Ref, const float *Tgt, const float *u_in, float *u_out, int H, int W,
+                              float eta, float lambda, float eps, float clip, hipStream_t s);
+hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_blend_f32(const float *L, const float *R, const float *flr, const float *frl, const float *blend,
+                            int axis, int H, int W, BlendParams bp, float *F, hipStream_t s);
+hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *flr, const float *frl,
+                                 const float *blend, int axis, int H, int W, BlendParams bp, const float *gF,
+                                 float *g_flr, float *g_frl, float *g_L, float *g_R, unsigned long long *fixL,
+                                 unsigned long long *fixR, hipStream_t s);
+
+// tiles of one strip for a stage (both directions where the stage has two)
+__host__ __device__ inline int tiles_luma(int H, int W) { return H * ceil_div(W, kRowTW); }
+__host__ __device__ inline int tiles_pyr(int H, int W) { return ceil_div(H, kPyrTH) * ceil_div(W, kPyrTW); }
+__host__ __device__ inline int tiles_search(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kSearchTW); }
+__host__ __device__ inline int tiles_prop(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kPropTW); }
+__host__ __device__ inline int tiles_refine(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kRefineTW); }
+__host__ __device__ inline int tiles_blend(int H, int W) { return H * ceil_div(W, kRowTW); }
+
+}  // namespace abf

@@ -1,0 +1,914 @@
+// Host runtime and C ABI of libabf (declared in include/abf.h).
+//
+// A plan owns host state only: parameters, the bound workspace, a small
+// ring of pinned host buffers for the batch descriptor tables, the launch
+// table chosen by the autotuner and a cache of instantiated hipGraphs.
+// Every call lays the batch out in the workspace (pyramids and integer
+// flows of every level of every strip), writes the descriptor tables
+// (strip buffers, per-level geometry, per-stage tile prefix sums) to the
+// head of the workspace and enqueues one launch per stage and level for
+// the whole batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/abf.h"
+#include "abf_internal.h"
+
+using namespace abf;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kSlots = 4;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Launch {
+    int tile_h;
+    int grid;  // persistent workgroups per CU; 0 = one workgroup per tile
+};
+
+// Byte layout of one batch in the workspace.
+struct Layout {
+    int n = 0, N = 0;
+    std::vector<int> H, W;                // per strip
+    std::vector<std::vector<int>> hk, wk;  // [strip][level]
+    size_t hdr_io = 0, hdr_lv = 0, hdr_prefix = 0, hdr_bytes = 0;
+    size_t data_bytes = 0;
+};
+
+}  // namespace
+
+struct abf_plan {
+    abf_params p{};
+    int max_strips = 0;
+    int64_t max_pixels = 0;
+    int max_H = 0, max_W = 0;
+    int device = 0, n_cu = 0;
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t hdr_cap = 0;  // bytes reserved at the head of the workspace for descriptor tables
+    std::string err;
+    Launch launch[kStages][kSizeClasses];
+    // pinned staging for descriptor uploads
+    uint8_t *pinned[kSlots] = {};
+    hipEvent_t ev[kSlots] = {};
+    bool ev_used[kSlots] = {};
+    int slot = 0;
+    std::vector<uint8_t> last_upload;
+    // last batch, for workspace views
+    std::vector<StripLv> lv_host;  // [level * n + strip]
+    int last_n = 0;
+    // graphs
+    std::map<std::string, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+abf_status fail(abf_plan *pl, abf_status st, const char *fmt, ...)
+{
+    if (pl) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        pl->err = buf;
+    }
+    return st;
+}
+
+abf_status hip_fail(abf_plan *pl, hipError_t e, const char *what)
+{
+    return fail(pl, ABF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(pl, expr)                                   \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(pl, e_, #expr); \
+    } while (0)
+
+int size_class(int64_t px)
+{
+    if (px < (1 << 16)) return 0;
+    if (px < (1 << 20)) return 1;
+    if (px < (1 << 23)) return 2;
+    return 3;
+}
+
+void default_launch(abf_plan *pl)
+{
+    for (int s = 0; s < kStages; s++)
+        for (int c = 0; c < kSizeClasses; c++) pl->launch[s][c] = {4, 0};
+    for (int c = 0; c < kSizeClasses; c++) {
+        pl->launch[ST_PROP][c].tile_h = 8;
+        pl->launch[ST_REFINE][c].tile_h = 4;
+    }
+}
+
+bool valid_th(int stage, int th)
+{
+    switch (stage) {
+    case ST_SEARCH: return th == 2 || th == 4 || th == 8;
+    case ST_PROP: return th == 4 || th == 8;
+    case ST_REFINE: return th == 2 || th == 4;
+    default: return th == 4;
+    }
+}
+
+abf_status check_params(const abf_params *p)
+{
+    if (p->levels < 1 || p->levels > kMaxLevels) return ABF_E_INVALID;
+    if (p->patch < 1 || p->radius < 1 || p->radius_coarse < 1 || p->prop_steps < 0 || p->median < 0 ||
+        p->lk_patch < 1 || p->lk_iters < 0)
+        return ABF_E_INVALID;
+    if (!(p->lk_eps > 0.f) || !std::isfinite(p->lk_eps) || !std::isfinite(p->k_sharp) ||
+        !std::isfinite(p->k_flowmag))
+        return ABF_E_INVALID;
+    if (p->blend_mode != 0 && p->blend_mode != 1) return ABF_E_INVALID;
+    if (p->patch > 2 || p->radius > 4 || p->radius_coarse > 4 || p->prop_steps > 4 || p->median > 1 ||
+        p->prop_steps + p->median > 5 || p->lk_patch > 3 || p->lk_iters > 8)
+        return ABF_E_UNSUPPORTED;
+    return ABF_OK;
+}
+
+inline int ypitch_of(int w) { return (int)align_up((size_t)w, 64); }
+inline int fpitch_of(int w) { return (int)align_up((size_t)w, 16); }
+
+// Data bytes of one strip (pyramids of both images, raw and final integer
+// flows of both directions at every level).
+size_t strip_bytes(int H, int W, int N)
+{
+    size_t b = 0;
+    for (int k = 0; k < N; k++) {
+        b += 2 * align_up((size_t)ypitch_of(W) * H, kAlign);
+        b += 4 * align_up((size_t)fpitch_of(W) * 4 * H, kAlign);
+        H = (H + 1) / 2;
+        W = (W + 1) / 2;
+    }
+    return b;
+}
+
+size_t header_bytes(int n, int N)
+{
+    size_t b = align_up(sizeof(StripIO) * n, kAlign);
+    b += align_up(sizeof(StripLv) * n * N, kAlign);
+    b += align_up(sizeof(int32_t) * (n + 1) * (size_t)(kStages * N), kAlign);
+    return b;
+}
+
+// Upper bound of the data bytes of any batch within the plan's limits.
+size_t data_bound(const abf_plan *pl)
+{
+    const int N = pl->p.levels;
+    // per level: y <= (W/2^k + 64)(H/2^k + 1) + 256, flows <= (4W/2^k + 64)(H/2^k + 1) + 256
+    double b = 0;
+    const double mp = (double)pl->max_pixels, S = pl->max_strips, Hm = pl->max_H, Wm = pl->max_W;
+    for (int k = 0; k < N; k++) {
+        const double f = std::ldexp(1.0, -k);
+        b += 2 * (mp * f * f + S * (Wm * f + 64 * Hm * f + 64 + 256));
+        b += 4 * (4 * mp * f * f + S * (4 * Wm * f + 64 * Hm * f + 64 + 256));
+    }
+    return align_up((size_t)b + 4096, kAlign);
+}
+
+void level_sizes(int H, int W, int N, std::vector<int> &hs, std::vector<int> &ws)
+{
+    hs.resize(N);
+    ws.resize(N);
+    for (int k = 0; k < N; k++) {
+        hs[k] = H;
+        ws[k] = W;
+        H = (H + 1) / 2;
+        W = (W + 1) / 2;
+    }
+}
+
+// Tiles of one strip at one level for a stage.
+int stage_tiles(const abf_plan *pl, int stage, int cls, int H, int W)
+{
+    const int th = pl->launch[stage][cls].tile_h;
+    switch (stage) {
+    case ST_LUMA: return tiles_luma(H, W);
+    case ST_PYR: return 2 * tiles_pyr(H, W);
+    case ST_SEARCH: return tiles_search(H, W, th);
+    case ST_PROP: return tiles_prop(H, W, th);
+    case ST_REFINE: return tiles_refine(H, W, th);
+    default: return tiles_blend(H, W);
+    }
+}
+
+struct Batch {
+    Layout lay;
+    std::vector<StripIO> io;
+    std::vector<StripLv> lv;              // [k * n + s]
+    std::vector<int32_t> prefix;          // [(stage * N + k) * (n + 1) + s]
+    std::vector<int> cls;                 // [k] size class of level k over the batch
+    std::vector<int64_t> level_px;        // [k]
+};
+
+abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, bool blend, Batch &b)
+{
+    const int N = pl->p.levels;
+    Layout &L = b.lay;
+    L.n = n;
+    L.N = N;
+    L.H.resize(n);
+    L.W.resize(n);
+    L.hk.resize(n);
+    L.wk.resize(n);
+    int64_t px = 0;
+    for (int s = 0; s < n; s++) {
+        const abf_strip &x = st[s];
+        if (!x.L || !x.R || (blend && !x.F) || !x.flow_LtoR || !x.flow_RtoL)
+            return fail(pl, ABF_E_INVALID, "strip %d: null pointer", s);
+        if (x.H < 1 || x.W < 1) return fail(pl, ABF_E_SHAPE, "strip %d: size %d x %d", s, x.H, x.W);
+        if (x.H > pl->max_H || x.W > pl->max_W)
+            return fail(pl, ABF_E_SHAPE, "strip %d: %d x %d exceeds the plan's %d x %d", s, x.H, x.W, pl->max_H,
+                        pl->max_W);
+        if (x.pitch_L < 3 * x.W || x.pitch_R < 3 * x.W || (blend && x.pitch_F < 3 * x.W))
+            return fail(pl, ABF_E_SHAPE, "strip %d: pitch smaller than 3 W", s);
+        if (x.axis != 0 && x.axis != 1) return fail(pl, ABF_E_INVALID, "strip %d: axis %d", s, x.axis);
+        L.H[s] = x.H;
+        L.W[s] = x.W;
+        level_sizes(x.H, x.W, N, L.hk[s], L.wk[s]);
+        px += (int64_t)x.H * x.W;
+    }
+    if (n > pl->max_strips) return fail(pl, ABF_E_SHAPE, "%d strips exceed the plan's %d", n, pl->max_strips);
+    if (px > pl->max_pixels)
+        return fail(pl, ABF_E_SHAPE, "%lld pixels exceed the plan's %lld", (long long)px, (long long)pl->max_pixels);
+    if (!pl->ws) return fail(pl, ABF_E_WORKSPACE, "no workspace bound");
+
+    // header: io, lv, prefix
+    L.hdr_io = 0;
+    L.hdr_lv = align_up(sizeof(StripIO) * n, kAlign);
+    L.hdr_prefix = L.hdr_lv + align_up(sizeof(StripLv) * n * N, kAlign);
+    L.hdr_bytes = L.hdr_prefix + align_up(sizeof(int32_t) * (n + 1) * (size_t)(kStages * N), kAlign);
+    if (L.hdr_bytes > pl->hdr_cap) return fail(pl, ABF_E_WORKSPACE, "descriptor tables exceed the reserved head");
+
+    b.io.resize(n);
+    b.lv.assign((size_t)n * N, StripLv{});
+    b.level_px.assign(N, 0);
+    for (int s = 0; s < n; s++)
+        for (int k = 0; k < N; k++) b.level_px[k] += (int64_t)L.hk[s][k] * L.wk[s][k];
+    b.cls.resize(N);
+    for (int k = 0; k < N; k++) b.cls[k] = size_class(b.level_px[k]);
+
+    size_t off = pl->hdr_cap;
+    for (int s = 0; s < n; s++) {
+        const abf_strip &x = st[s];
+        StripIO &io = b.io[s];
+        io.L = x.L;
+        io.R = x.R;
+        io.blend = x.blend;
+        io.flow[0] = x.flow_LtoR;
+        io.flow[1] = x.flow_RtoL;
+        io.F = x.F;
+        io.Ff32 = x.F_f32;
+        io.pitchL = x.pitch_L;
+        io.pitchR = x.pitch_R;
+        io.pitchF = x.pitch_F;
+        io.H = x.H;
+        io.W = x.W;
+        io.axis = x.axis;
+        if (!flows) continue;
+        for (int k = 0; k < N; k++) {
+            StripLv &v = b.lv[(size_t)k * n + s];
+            v.H = L.hk[s][k];
+            v.W = L.wk[s][k];
+            v.ypitch = ypitch_of(v.W);
+            v.fpitch = fpitch_of(v.W);
+            for (int d = 0; d < 2; d++) {
+                v.y[d] = pl->ws + off;
+                off += align_up((size_t)v.ypitch * v.H, kAlign);
+            }
+            for (int d = 0; d < 2; d++) {
+                v.ds[d] = reinterpret_cast<uint32_t *>(pl->ws + off);
+                off += align_up((size_t)v.fpitch * 4 * v.H, kAlign);
+                v.df[d] = reinterpret_cast<uint32_t *>(pl->ws + off);
+                off += align_up((size_t)v.fpitch * 4 * v.H, kAlign);
+            }
+            v.radius = k == N - 1 ? pl->p.radius_coarse : pl->p.radius;
+        }
+        for (int k = 0; k < N; k++) {
+            StripLv &v = b.lv[(size_t)k * n + s];
+            if (k + 1 < N) {
+                const StripLv &c = b.lv[(size_t)(k + 1) * n + s];
+                v.dc[0] = c.df[0];
+                v.dc[1] = c.df[1];
+                v.Hc = c.H;
+                v.Wc = c.W;
+                v.fpitch_c = c.fpitch;
+            }
+            if (k > 0) {
+                const StripLv &f = b.lv[(size_t)(k - 1) * n + s];
+                v.yfine[0] = f.y[0];
+                v.yfine[1] = f.y[1];
+                v.Hf = f.H;
+                v.Wf = f.W;
+                v.ypitch_f = f.ypitch;
+            }
+        }
+    }
+    L.data_bytes = off - pl->hdr_cap;
+    if (off > pl->ws_bytes)
+        return fail(pl, ABF_E_WORKSPACE, "batch needs %zu workspace bytes, %zu bound", off, pl->ws_bytes);
+
+    // tile prefix sums per stage and level
+    b.prefix.assign((size_t)(n + 1) * kStages * N, 0);
+    for (int stg = 0; stg < kStages; stg++)
+        for (int k = 0; k < N; k++) {
+            int32_t *pre = &b.prefix[((size_t)stg * N + k) * (n + 1)];
+            int64_t acc = 0;
+            for (int s = 0; s < n; s++) {
+                pre[s] = (int32_t)acc;
+                acc += stage_tiles(pl, stg, b.cls[k], L.hk[s][k], L.wk[s][k]);
+            }
+            pre[n] = (int32_t)acc;
+            if (acc > 0x7fffffff) return fail(pl, ABF_E_SHAPE, "too many tiles");
+        }
+    return ABF_OK;
+}
+
+// Copies the descriptor tables to the head of the workspace (stream
+// ordered), through a pinned slot whose previous copy has completed.
+abf_status upload(abf_plan *pl, const Batch &b, hipStream_t s)
+{
+    const Layout &L = b.lay;
+    std::vector<uint8_t> host(L.hdr_bytes, 0);
+    memcpy(host.data() + L.hdr_io, b.io.data(), sizeof(StripIO) * L.n);
+    memcpy(host.data() + L.hdr_lv, b.lv.data(), sizeof(StripLv) * b.lv.size());
+    memcpy(host.data() + L.hdr_prefix, b.prefix.data(), sizeof(int32_t) * b.prefix.size());
+    if (host == pl->last_upload) return ABF_OK;
+    const int k = pl->slot;
+    pl->slot = (pl->slot + 1) % kSlots;
+    if (pl->ev_used[k]) HIP_TRY(pl, hipEventSynchronize(pl->ev[k]));
+    memcpy(pl->pinned[k], host.data(), host.size());
+    HIP_TRY(pl, hipMemcpyAsync(pl->ws, pl->pinned[k], host.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(pl, hipEventRecord(pl->ev[k], s));
+    pl->ev_used[k] = true;
+    pl->last_upload.swap(host);
+    return ABF_OK;
+}
+
+int grid_of(const abf_plan *pl, int stage, int cls)
+{
+    const int g = pl->launch[stage][cls].grid;
+    return g > 0 ? g * pl->n_cu : 0;
+}
+
+// Optional per-launch timing: when `prof` is set, an event pair brackets
+// every launch and the elapsed times are added to prof->ms[stage][level].
+struct Prof {
+    std::vector<hipEvent_t> ev;
+    std::vector<std::pair<int, int>> tag;  // (stage, level) per event pair
+};
+
+// Enqueues the launch sequence of a batch whose tables are in place.
+abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStream_t s, Prof *prof = nullptr)
+{
+    const Layout &L = b.lay;
+    const int n = L.n, N = L.N;
+    const StripIO *io = reinterpret_cast<const StripIO *>(pl->ws + L.hdr_io);
+    const StripLv *lv = reinterpret_cast<const StripLv *>(pl->ws + L.hdr_lv);
+    const int32_t *pre = reinterpret_cast<const int32_t *>(pl->ws + L.hdr_prefix);
+    auto work = [&](int stg, int k) {
+        Work w;
+        const size_t o = ((size_t)stg * N + k) * (n + 1);
+        w.prefix = pre + o;
+        w.n = n;
+        w.total = b.prefix[o + n];
+        return w;
+    };
+    const abf_params &p = pl->p;
+    auto mark = [&](int stg, int k) -> hipError_t {
+        if (!prof) return hipSuccess;
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        prof->ev.push_back(e);
+        if (prof->ev.size() % 2 == 1) prof->tag.emplace_back(stg, k);
+        return hipEventRecord(e, s);
+    };
+#define TIMED(stg, k, call)              \
+    do {                                 \
+        HIP_TRY(pl, mark(stg, k));       \
+        HIP_TRY(pl, call);               \
+        HIP_TRY(pl, mark(stg, k));       \
+    } while (0)
+    if (flows) {
+        TIMED(ST_LUMA, 0, launch_luma(io, lv, work(ST_LUMA, 0), grid_of(pl, ST_LUMA, b.cls[0]), s));
+        for (int k = 1; k < N; k++)
+            TIMED(ST_PYR, k, launch_pyr(lv + (size_t)k * n, work(ST_PYR, k), grid_of(pl, ST_PYR, b.cls[k]), s));
+        for (int k = N - 1; k >= 0; k--) {
+            const int c = b.cls[k];
+            const int r = k == N - 1 ? p.radius_coarse : p.radius;
+            TIMED(ST_SEARCH, k,
+                  launch_search(lv + (size_t)k * n, work(ST_SEARCH, k), p.patch, r, pl->launch[ST_SEARCH][c].tile_h,
+                                grid_of(pl, ST_SEARCH, c), s));
+            TIMED(ST_PROP, k,
+                  launch_prop(lv + (size_t)k * n, work(ST_PROP, k), p.patch, p.prop_steps, p.median,
+                              pl->launch[ST_PROP][c].tile_h, grid_of(pl, ST_PROP, c), s));
+        }
+        LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
+        TIMED(ST_REFINE, 0,
+              launch_refine(lv, io, work(ST_REFINE, 0), lk, pl->launch[ST_REFINE][b.cls[0]].tile_h,
+                            grid_of(pl, ST_REFINE, b.cls[0]), s));
+    }
+    if (blend) {
+        BlendParams bp{p.k_sharp, p.k_flowmag, p.blend_mode};
+        TIMED(ST_BLEND, 0, launch_blend(io, work(ST_BLEND, 0), bp, grid_of(pl, ST_BLEND, b.cls[0]), s));
+    }
+#undef TIMED
+    return ABF_OK;
+}
+
+std::string graph_key(const abf_plan *pl, const Batch &b, bool flows, bool blend)
+{
+    std::string k;
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%d:%d:%d|", b.lay.n, (int)flows, (int)blend);
+    k += buf;
+    for (int s = 0; s < b.lay.n; s++) {
+        snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d;", b.lay.H[s], b.lay.W[s], b.io[s].axis, b.io[s].blend != nullptr,
+                 b.io[s].Ff32 != nullptr);
+        k += buf;
+    }
+    for (int s = 0; s < kStages; s++)
+        for (int c = 0; c < kSizeClasses; c++) {
+            snprintf(buf, sizeof(buf), "%d/%d,", pl->launch[s][c].tile_h, pl->launch[s][c].grid);
+            k += buf;
+        }
+    return k;
+}
+
+void clear_graphs(abf_plan *pl)
+{
+    for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+    pl->graphs.clear();
+}
+
+abf_status run(abf_plan *pl, const abf_strip *st, int n, bool flows, bool blend, bool use_graph, hipStream_t s)
+{
+    Batch b;
+    abf_status rc = build_batch(pl, st, n, flows, blend, b);
+    if (rc != ABF_OK) return rc;
+    rc = upload(pl, b, s);
+    if (rc != ABF_OK) return rc;
+    if (flows) {
+        pl->lv_host = b.lv;
+        pl->last_n = n;
+    }
+    if (!use_graph) return enqueue(pl, b, flows, blend, s);
+
+    const std::string key = graph_key(pl, b, flows, blend);
+    auto it = pl->graphs.find(key);
+    if (it == pl->graphs.end()) {
+        if (!pl->cap_stream) HIP_TRY(pl, hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+        // the tables were uploaded on `s`; the capture stream only records
+        HIP_TRY(pl, hipStreamSynchronize(s));
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(pl, ABF_E_CAPTURE, "hipStreamBeginCapture failed");
+        abf_status er = enqueue(pl, b, flows, blend, pl->cap_stream);
+        hipError_t ee = hipStreamEndCapture(pl->cap_stream, &g);
+        if (er != ABF_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return er;
+        }
+        if (ee != hipSuccess || !g) return fail(pl, ABF_E_CAPTURE, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+        hipGraphExec_t ex = nullptr;
+        hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(pl, ABF_E_CAPTURE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        it = pl->graphs.emplace(key, ex).first;
+    }
+    HIP_TRY(pl, hipGraphLaunch(it->second, s));
+    return ABF_OK;
+}
+
+}  // namespace
+
+// =====================================================================
+// C ABI
+
+extern "C" {
+
+void abf_default_params(abf_params *p)
+{
+    if (!p) return;
+    p->levels = 6;
+    p->patch = 2;
+    p->radius = 2;
+    p->radius_coarse = 4;
+    p->prop_steps = 2;
+    p->median = 1;
+    p->lk_patch = 2;
+    p->lk_iters = 2;
+    p->lk_eps = 25.0f;
+    p->k_sharp = 10.0f;
+    p->k_flowmag = 20.0f;
+    p->blend_mode = 0;
+}
+
+const char *abf_status_string(abf_status s)
+{
+    switch (s) {
+    case ABF_OK: return "ABF_OK";
+    case ABF_E_INVALID: return "ABF_E_INVALID: invalid argument";
+    case ABF_E_SHAPE: return "ABF_E_SHAPE: inconsistent or out-of-range sizes";
+    case ABF_E_WORKSPACE: return "ABF_E_WORKSPACE: workspace missing or too small";
+    case ABF_E_DEVICE: return "ABF_E_DEVICE: HIP runtime error";
+    case ABF_E_UNSUPPORTED: return "ABF_E_UNSUPPORTED: no gfx950 device or unsupported parameter";
+    case ABF_E_CAPTURE: return "ABF_E_CAPTURE: hipGraph capture failed";
+    }
+    return "unknown abf_status";
+}
+
+const char *abf_last_error(const abf_plan *plan) { return plan ? plan->err.c_str() : "null plan"; }
+
+abf_status abf_create_plan(const abf_params *params, int32_t max_strips, int64_t max_pixels, int32_t max_H,
+                           int32_t max_W, abf_plan **out)
+{
+    if (!params || !out) return ABF_E_INVALID;
+    *out = nullptr;
+    abf_status rc = check_params(params);
+    if (rc != ABF_OK) return rc;
+    if (max_strips < 1 || max_pixels < 1 || max_H < 1 || max_W < 1) return ABF_E_INVALID;
+    if ((int64_t)max_H * max_W > max_pixels) max_pixels = (int64_t)max_H * max_W;
+    int dev = 0, count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return ABF_E_UNSUPPORTED;
+    if (hipGetDevice(&dev) != hipSuccess) return ABF_E_UNSUPPORTED;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return ABF_E_UNSUPPORTED;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ABF_E_UNSUPPORTED;
+
+    abf_plan *pl = new abf_plan();
+    pl->p = *params;
+    pl->max_strips = max_strips;
+    pl->max_pixels = max_pixels;
+    pl->max_H = max_H;
+    pl->max_W = max_W;
+    pl->device = dev;
+    pl->n_cu = prop.multiProcessorCount;
+    pl->hdr_cap = header_bytes(max_strips, params->levels);
+    default_launch(pl);
+    for (int k = 0; k < kSlots; k++) {
+        if (hipHostMalloc((void **)&pl->pinned[k], pl->hdr_cap, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&pl->ev[k], hipEventDisableTiming) != hipSuccess) {
+            abf_destroy(pl);
+            return ABF_E_DEVICE;
+        }
+    }
+    const char *cache = getenv("ABF_TUNE_CACHE");
+    if (cache) {
+        FILE *f = fopen(cache, "r");
+        if (f) {
+            char arch[64] = {0};
+            if (fscanf(f, " { \"arch\" : \"%63[^\"]\" , \"launch\" : [", arch) == 1 &&
+                strncmp(arch, prop.gcnArchName, 6) == 0) {
+                Launch tmp[kStages][kSizeClasses];
+                bool ok = true;
+                for (int s = 0; s < kStages && ok; s++)
+                    for (int c = 0; c < kSizeClasses && ok; c++)
+                        ok = fscanf(f, " [ %d , %d ]%*[, ]", &tmp[s][c].tile_h, &tmp[s][c].grid) == 2 &&
+                             valid_th(s, tmp[s][c].tile_h) && tmp[s][c].grid >= 0 && tmp[s][c].grid <= 64;
+                if (ok) memcpy(pl->launch, tmp, sizeof(tmp));
+            }
+            fclose(f);
+        }
+    }
+    *out = pl;
+    return ABF_OK;
+}
+
+size_t abf_workspace_bytes(const abf_plan *plan)
+{
+    if (!plan) return 0;
+    return plan->hdr_cap + data_bound(plan);
+}
+
+abf_status abf_bind_workspace(abf_plan *plan, void *dev_ptr, size_t bytes)
+{
+    if (!plan || !dev_ptr) return fail(plan, ABF_E_INVALID, "null workspace");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign != 0)
+        return fail(plan, ABF_E_INVALID, "workspace not %zu-byte aligned", kAlign);
+    if (bytes < abf_workspace_bytes(plan))
+        return fail(plan, ABF_E_WORKSPACE, "workspace of %zu bytes, %zu needed", bytes, abf_workspace_bytes(plan));
+    plan->ws = static_cast<uint8_t *>(dev_ptr);
+    plan->ws_bytes = bytes;
+    plan->last_upload.clear();
+    clear_graphs(plan);
+    return ABF_OK;
+}
+
+abf_status abf_flow_bidirectional(abf_plan *plan, const uint8_t *L, const uint8_t *R, int32_t H, int32_t W,
+                                  int32_t pitch_L, int32_t pitch_R, float *flow_LtoR, float *flow_RtoL,
+                                  void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    abf_strip st{};
+    st.L = L;
+    st.R = R;
+    st.H = H;
+    st.W = W;
+    st.pitch_L = pitch_L;
+    st.pitch_R = pitch_R;
+    st.flow_LtoR = flow_LtoR;
+    st.flow_RtoL = flow_RtoL;
+    return run(plan, &st, 1, true, false, false, static_cast<hipStream_t>(hip_stream));
+}
+
+abf_status abf_blend_asymmetric(abf_plan *plan, const uint8_t *L, const uint8_t *R, const float *flow_LtoR,
+                                const float *flow_RtoL, const float *blend, int32_t axis, int32_t H, int32_t W,
+                                int32_t pitch_L, int32_t pitch_R, uint8_t *F, int32_t pitch_F, float *F_f32,
+                                void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!flow_LtoR || !flow_RtoL) return fail(plan, ABF_E_INVALID, "null flow");
+    abf_strip st{};
+    st.L = L;
+    st.R = R;
+    st.H = H;
+    st.W = W;
+    st.pitch_L = pitch_L;
+    st.pitch_R = pitch_R;
+    st.axis = axis;
+    st.blend = blend;
+    st.flow_LtoR = const_cast<float *>(flow_LtoR);
+    st.flow_RtoL = const_cast<float *>(flow_RtoL);
+    st.F = F;
+    st.pitch_F = pitch_F;
+    st.F_f32 = F_f32;
+    return run(plan, &st, 1, false, true, false, static_cast<hipStream_t>(hip_stream));
+}
+
+abf_status abf_stitch_strips(abf_plan *plan, const abf_strip *strips, int32_t n, int32_t use_graph,
+                             void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!strips || n < 1) return fail(plan, ABF_E_INVALID, "no strips");
+    return run(plan, strips, n, true, true, use_graph != 0, static_cast<hipStream_t>(hip_stream));
+}
+
+abf_status abf_destroy(abf_plan *plan)
+{
+    if (!plan) return ABF_E_INVALID;
+    clear_graphs(plan);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    for (int k = 0; k < kSlots; k++) {
+        if (plan->ev[k]) {
+            if (plan->ev_used[k]) (void)hipEventSynchronize(plan->ev[k]);
+            (void)hipEventDestroy(plan->ev[k]);
+        }
+        if (plan->pinned[k]) (void)hipHostFree(plan->pinned[k]);
+    }
+    delete plan;
+    return ABF_OK;
+}
+
+abf_status abf_workspace_view(const abf_plan *plan, int32_t kind, int32_t strip, int32_t level, int32_t dir,
+                              void **dev_ptr, int32_t *H, int32_t *W, int32_t *pitch)
+{
+    if (!plan || !dev_ptr || !H || !W || !pitch) return ABF_E_INVALID;
+    if (strip < 0 || strip >= plan->last_n || level < 0 || level >= plan->p.levels || dir < 0 || dir > 1)
+        return ABF_E_SHAPE;
+    const StripLv &v = plan->lv_host[(size_t)level * plan->last_n + strip];
+    *H = v.H;
+    *W = v.W;
+    switch (kind) {
+    case 0:
+        *dev_ptr = v.y[dir];
+        *pitch = v.ypitch;
+        return ABF_OK;
+    case 1:
+        *dev_ptr = v.ds[dir];
+        *pitch = v.fpitch;
+        return ABF_OK;
+    case 2:
+        *dev_ptr = v.df[dir];
+        *pitch = v.fpitch;
+        return ABF_OK;
+    }
+    return ABF_E_INVALID;
+}
+
+abf_status abf_get_launch(const abf_plan *plan, int32_t stage, int32_t size_class, int32_t *tile_h, int32_t *grid)
+{
+    if (!plan || !tile_h || !grid || stage < 0 || stage >= kStages || size_class < 0 || size_class >= kSizeClasses)
+        return ABF_E_INVALID;
+    *tile_h = plan->launch[stage][size_class].tile_h;
+    *grid = plan->launch[stage][size_class].grid;
+    return ABF_OK;
+}
+
+abf_status abf_set_launch(abf_plan *plan, int32_t stage, int32_t size_class, int32_t tile_h, int32_t grid)
+{
+    if (!plan || stage < 0 || stage >= kStages || size_class < 0 || size_class >= kSizeClasses)
+        return ABF_E_INVALID;
+    if (!valid_th(stage, tile_h) || grid < 0 || grid > 64)
+        return fail(plan, ABF_E_INVALID, "tile height %d / grid %d not available for stage %d", tile_h, grid, stage);
+    plan->launch[stage][size_class] = {tile_h, grid};
+    return ABF_OK;
+}
+
+abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hip_stream)
+{
+    if (!plan || !strips || n < 1) return ABF_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(plan, hipEventCreate(&e0));
+    HIP_TRY(plan, hipEventCreate(&e1));
+    auto timed = [&](float &ms) -> abf_status {
+        abf_status rc = run(plan, strips, n, true, true, false, s);  // warm
+        if (rc != ABF_OK) return rc;
+        float best = 1e30f;
+        for (int r = 0; r < 3; r++) {
+            HIP_TRY(plan, hipEventRecord(e0, s));
+            rc = run(plan, strips, n, true, true, false, s);
+            if (rc != ABF_OK) return rc;
+            HIP_TRY(plan, hipEventRecord(e1, s));
+            HIP_TRY(plan, hipEventSynchronize(e1));
+            float t = 0;
+            HIP_TRY(plan, hipEventElapsedTime(&t, e0, e1));
+            best = std::min(best, t);
+        }
+        ms = best;
+        return ABF_OK;
+    };
+    static const int grids[] = {0, 1, 2, 4, 8};
+    abf_status rc = ABF_OK;
+    for (int stage = 0; stage < kStages && rc == ABF_OK; stage++)
+        for (int c = 0; c < kSizeClasses && rc == ABF_OK; c++) {
+            std::vector<int> ths;
+            for (int th : {2, 4, 8})
+                if (valid_th(stage, th)) ths.push_back(th);
+            Launch best = plan->launch[stage][c];
+            float best_ms = 1e30f;
+            for (int th : ths)
+                for (int g : grids) {
+                    plan->launch[stage][c] = {th, g};
+                    float ms = 0;
+                    rc = timed(ms);
+                    if (rc != ABF_OK) break;
+                    if (ms < best_ms * 0.99f) {
+                        best_ms = ms;
+                        best = plan->launch[stage][c];
+                    }
+                }
+            plan->launch[stage][c] = best;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ABF_OK) return rc;
+    const char *cache = getenv("ABF_TUNE_CACHE");
+    if (cache) {
+        FILE *f = fopen(cache, "w");
+        if (f) {
+            hipDeviceProp_t prop;
+            (void)hipGetDeviceProperties(&prop, plan->device);
+            fprintf(f, "{\"arch\": \"%s\", \"launch\": [", prop.gcnArchName);
+            for (int st = 0; st < kStages; st++)
+                for (int c = 0; c < kSizeClasses; c++)
+                    fprintf(f, "%s[%d, %d]", st + c ? ", " : "", plan->launch[st][c].tile_h,
+                            plan->launch[st][c].grid);
+            fprintf(f, "]}\n");
+            fclose(f);
+        }
+    }
+    return ABF_OK;
+}
+
+// ------------------------------------------------------------------
+// differentiable path: scratch (energy partials, fixed-point scatter
+// buffers, the other half of the descent ping-pong) comes from the
+// workspace's data region.
+
+static abf_status grad_scratch(abf_plan *plan, size_t need, uint8_t **out)
+{
+    if (!plan->ws) return fail(plan, ABF_E_WORKSPACE, "no workspace bound");
+    if (plan->hdr_cap + need > plan->ws_bytes)
+        return fail(plan, ABF_E_WORKSPACE, "needs %zu scratch bytes, workspace holds %zu", need,
+                    plan->ws_bytes - plan->hdr_cap);
+    *out = plan->ws + plan->hdr_cap;
+    return ABF_OK;
+}
+
+abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H, int32_t W,
+                      float lambda, float eps, float *E_dev, float *g_u, float *g_Ref, float *g_Tgt,
+                      int32_t deterministic, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!Ref || !Tgt || !u || !E_dev) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (!(eps > 0.f) || !(lambda >= 0.f)) return fail(plan, ABF_E_INVALID, "eps must be > 0, lambda >= 0");
+    const size_t npart = align_up(sizeof(double) * energy_blocks(H, W), kAlign);
+    const size_t nfix = (deterministic && g_Tgt) ? align_up(sizeof(uint64_t) * 3 * (size_t)H * W, kAlign) : 0;
+    uint8_t *scr = nullptr;
+    abf_status rc = grad_scratch(plan, npart + nfix, &scr);
+    if (rc != ABF_OK) return rc;
+    HIP_TRY(plan, launch_energy_full(Ref, Tgt, u, H, W, lambda, eps, reinterpret_cast<double *>(scr), E_dev, g_u,
+                                     g_Ref, g_Tgt, nfix ? reinterpret_cast<unsigned long long *>(scr + npart) : nullptr,
+                                     static_cast<hipStream_t>(hip_stream)));
+    return ABF_OK;
+}
+
+abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, float *u, int32_t H, int32_t W,
+                           int32_t steps, float eta, float lambda, float eps, float clip_px, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!Ref || !Tgt || !u) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (H < 1 || W < 1 || steps < 0) return fail(plan, ABF_E_SHAPE, "size %d x %d, %d steps", H, W, steps);
+    if (!(eps > 0.f) || !(lambda >= 0.f) || !(clip_px >= 0.f)) return fail(plan, ABF_E_INVALID, "bad parameter");
+    uint8_t *scr = nullptr;
+    abf_status rc = grad_scratch(plan, sizeof(float) * 2 * (size_t)H * W, &scr);
+    if (rc != ABF_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    float *bufs[2] = {u, reinterpret_cast<float *>(scr)};
+    for (int k = 0; k < steps; k++)
+        HIP_TRY(plan, launch_energy_step(Ref, Tgt, bufs[k & 1], bufs[(k + 1) & 1], H, W, eta, lambda, eps, clip_px, s));
+    if (steps & 1) HIP_TRY(plan, launch_copy_f32(bufs[1], u, 2 * (int64_t)H * W, s));
+    return ABF_OK;
+}
+
+abf_status abf_blend_asymmetric_f32(abf_plan *plan, const float *L, const float *R, const float *flow_LtoR,
+                                    const float *flow_RtoL, const float *blend, int32_t axis, int32_t H, int32_t W,
+                                    float *F, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!L || !R || !flow_LtoR || !flow_RtoL || !F) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (axis != 0 && axis != 1) return fail(plan, ABF_E_INVALID, "axis %d", axis);
+    BlendParams bp{plan->p.k_sharp, plan->p.k_flowmag, plan->p.blend_mode};
+    HIP_TRY(plan, launch_blend_f32(L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, bp, F,
+                                   static_cast<hipStream_t>(hip_stream)));
+    return ABF_OK;
+}
+
+abf_status abf_blend_backward(abf_plan *plan, const float *L, const float *R, const float *flow_LtoR,
+                              const float *flow_RtoL, const float *blend, int32_t axis, int32_t H, int32_t W,
+                              const float *g_F, float *g_flow_LtoR, float *g_flow_RtoL, float *g_L, float *g_R,
+                              void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!L || !R || !flow_LtoR || !flow_RtoL || !g_F) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (axis != 0 && axis != 1) return fail(plan, ABF_E_INVALID, "axis %d", axis);
+    const bool det = getenv("ABF_DETERMINISTIC") && atoi(getenv("ABF_DETERMINISTIC")) != 0;
+    const size_t nfix = align_up(sizeof(uint64_t) * 3 * (size_t)H * W, kAlign);
+    uint8_t *scr = nullptr;
+    if (det) {
+        abf_status rc = grad_scratch(plan, 2 * nfix, &scr);
+        if (rc != ABF_OK) return rc;
+    }
+    BlendParams bp{plan->p.k_sharp, plan->p.k_flowmag, plan->p.blend_mode};
+    HIP_TRY(plan, launch_blend_bwd_full(L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, bp, g_F, g_flow_LtoR,
+                                        g_flow_RtoL, g_L, g_R,
+                                        det ? reinterpret_cast<unsigned long long *>(scr) : nullptr,
+                                        det ? reinterpret_cast<unsigned long long *>(scr + nfix) : nullptr,
+                                        static_cast<hipStream_t>(hip_stream)));
+    return ABF_OK;
+}
+
+abf_status abf_profile(abf_plan *plan, const abf_strip *strips, int32_t n, int32_t reps, float *ms_out,
+                       void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!strips || n < 1 || reps < 1 || !ms_out) return fail(plan, ABF_E_INVALID, "bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Batch b;
+    abf_status rc = build_batch(plan, strips, n, true, true, b);
+    if (rc != ABF_OK) return rc;
+    for (int i = 0; i < kStages * kMaxLevels; i++) ms_out[i] = 0.f;
+    for (int r = 0; r < reps; r++) {
+        rc = upload(plan, b, s);
+        if (rc != ABF_OK) return rc;
+        Prof prof;
+        rc = enqueue(plan, b, true, true, s, &prof);
+        hipError_t e = hipStreamSynchronize(s);
+        for (size_t i = 0; i + 1 < prof.ev.size(); i += 2) {
+            float t = 0.f;
+            if (rc == ABF_OK && e == hipSuccess && hipEventElapsedTime(&t, prof.ev[i], prof.ev[i + 1]) == hipSuccess)
+                ms_out[prof.tag[i / 2].first * kMaxLevels + prof.tag[i / 2].second] += t / reps;
+        }
+        for (hipEvent_t ev : prof.ev) (void)hipEventDestroy(ev);
+        if (rc != ABF_OK) return rc;
+        if (e != hipSuccess) return hip_fail(plan, e, "hipStreamSynchronize");
+    }
+    plan->lv_host = b.lv;
+    plan->last_n = n;
+    return ABF_OK;
+}
+
+}  // extern "C"

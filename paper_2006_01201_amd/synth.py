@@ -35,24 +35,30 @@ def rng_for(cfg: int, pano: int, strip: int) -> np.random.Generator:
 
 
 class Texture:
-    """Analytic RGB texture evaluated at real coordinates.
+    """Analytic multi-scale RGB texture evaluated at real coordinates.
 
-    128 + sum of 8 oriented sinusoids (per-channel phase) + 20 additive
-    axis-aligned rectangles. Amplitudes U[8, 20], frequencies U[1/80, 1/6]
-    cycles/px, orientations U[0, pi), phases U[0, 2 pi); rectangle corners
-    uniform over the ``H x W`` frame, sides U[0.05, 0.4] of the frame
-    dimensions, per-channel offsets U[-50, 50].
+    128 + 24 oriented sinusoids (per-channel phase) + 60 additive
+    axis-aligned rectangles. Sinusoid amplitudes U[6, 14], frequencies
+    log-uniform in [1/400, 1/5] cycles/px, orientations U[0, pi), phases
+    U[0, 2 pi). Rectangle corners uniform over the ``H x W`` frame, widths
+    log-uniform in [0.02, 0.4] W and heights in [0.005, 0.4] H, per-channel
+    offsets U[-50, 50]. Content at every scale (as in natural images) keeps
+    the coarse pyramid levels textured.
     """
 
-    def __init__(self, rng: np.random.Generator, H: int, W: int, n_sin: int = 8, n_rect: int = 20):
-        self.amp = rng.uniform(8.0, 20.0, n_sin)
-        self.freq = rng.uniform(1.0 / 80.0, 1.0 / 6.0, n_sin)
+    N_SIN = 24
+    N_RECT = 60
+
+    def __init__(self, rng: np.random.Generator, H: int, W: int):
+        n_sin, n_rect = self.N_SIN, self.N_RECT
+        self.amp = rng.uniform(6.0, 14.0, n_sin)
+        self.freq = np.exp(rng.uniform(np.log(1.0 / 400.0), np.log(1.0 / 5.0), n_sin))
         self.theta = rng.uniform(0.0, np.pi, n_sin)
         self.phase = rng.uniform(0.0, 2.0 * np.pi, (n_sin, 3))
         rx0 = rng.uniform(0.0, W, n_rect)
         ry0 = rng.uniform(0.0, H, n_rect)
-        rw = rng.uniform(0.05, 0.4, n_rect) * W
-        rh = rng.uniform(0.05, 0.4, n_rect) * H
+        rw = np.exp(rng.uniform(np.log(0.02), np.log(0.4), n_rect)) * W
+        rh = np.exp(rng.uniform(np.log(0.005), np.log(0.4), n_rect)) * H
         self.rects = np.stack([rx0, ry0, rx0 + rw, ry0 + rh], axis=1)
         self.offset = rng.uniform(-50.0, 50.0, (n_rect, 3))
 
@@ -60,25 +66,34 @@ class Texture:
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
         x, y = np.broadcast_arrays(x, y)
-        if x.ndim >= 1 and x.size > (1 << 18):
+        if x.ndim >= 1 and x.size > (1 << 16):
             parts = parallel_rows(lambda r0, r1: self._eval(x[r0:r1], y[r0:r1]), x.shape[0])
             return np.concatenate(parts, axis=0)
         return self._eval(x, y)
 
     def _eval(self, x: np.ndarray, y: np.ndarray) -> np.ndarray:
-        out = np.full(x.shape + (3,), 128.0)
-        cph, sph = np.cos(self.phase), np.sin(self.phase)
+        out = np.full(x.shape + (3,), 128.0, dtype=np.float32)
+        cph = np.cos(self.phase).astype(np.float32)
+        sph = np.sin(self.phase).astype(np.float32)
+        two_pi = 2.0 * np.pi
         for k in range(len(self.amp)):
-            arg = (2.0 * np.pi * self.freq[k]) * (x * np.cos(self.theta[k]) + y * np.sin(self.theta[k]))
+            arg = (two_pi * self.freq[k]) * (x * np.cos(self.theta[k]) + y * np.sin(self.theta[k]))
+            # range-reduce in double, then evaluate the two transcendental
+            # functions once in float32; the angle-sum identity gives every
+            # channel's phase from them
+            arg = (arg - two_pi * np.rint(arg / two_pi)).astype(np.float32)
             s, c = np.sin(arg), np.cos(arg)
+            a = np.float32(self.amp[k])
             for ch in range(3):
-                # sin(arg + phase) by the angle-sum identity, so the two
-                # transcendental evaluations are shared by the channels
-                out[..., ch] += self.amp[k] * (s * cph[k, ch] + c * sph[k, ch])
-        for r in range(len(self.rects)):
-            x0, y0, x1, y1 = self.rects[r]
-            m = (x >= x0) & (x < x1) & (y >= y0) & (y < y1)
-            out[m] += self.offset[r]
+                out[..., ch] += a * (s * cph[k, ch] + c * sph[k, ch])
+        if x.size:
+            xlo, xhi, ylo, yhi = x.min(), x.max(), y.min(), y.max()
+            for r in range(len(self.rects)):
+                x0, y0, x1, y1 = self.rects[r]
+                if x1 <= xlo or x0 > xhi or y1 <= ylo or y0 > yhi:
+                    continue
+                m = (x >= x0) & (x < x1) & (y >= y0) & (y < y1)
+                out[m] += self.offset[r].astype(np.float32)
         return out
 
 
@@ -309,7 +324,12 @@ def make_config_strip(cfg: int, pano: int, strip: int) -> Strip:
 
 
 def make_config(cfg: int, pano: int = 0):
-    return [make_config_strip(cfg, pano, s) for s in range(len(strip_shapes(cfg, pano)))]
+    """All strips of one panorama of workload ``cfg`` (generated in
+    parallel; each strip has its own seed, so the result does not depend
+    on the order)."""
+    n = len(strip_shapes(cfg, pano))
+    with ThreadPoolExecutor(min(n, 4)) as ex:
+        return list(ex.map(lambda s: make_config_strip(cfg, pano, s), range(n)))
 
 
 def make_random(seed: int, H: int, W: int, axis: int = 0, max_ux: float = 6.0, max_uy: float = 2.0,

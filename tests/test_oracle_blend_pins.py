@@ -257,10 +257,11 @@ def test_blend_adjoint_matches_central_differences(orc):
                     fd = (f(L, R, flr, ap) - f(L, R, flr, am)) / (2 * h)
                 assert abs(fd - g[y, x, m]) <= 1e-6 * max(1.0, abs(fd))
         for c in range(3):
+            # F is linear in the image values: a unit step is exact
             for img, g, which in ((L, gL, 0), (R, gR, 1)):
                 ip, im = img.copy(), img.copy()
-                ip[y, x, c] += h
-                im[y, x, c] -= h
-                fd = (f(ip, R, flr, frl) - f(im, R, flr, frl)) / (2 * h) if which == 0 else \
-                    (f(L, ip, flr, frl) - f(L, im, flr, frl)) / (2 * h)
-                assert abs(fd - g[y, x, c]) <= 1e-6 * max(1.0, abs(fd))
+                ip[y, x, c] += 1.0
+                im[y, x, c] -= 1.0
+                fd = (f(ip, R, flr, frl) - f(im, R, flr, frl)) / 2.0 if which == 0 else \
+                    (f(L, ip, flr, frl) - f(L, im, flr, frl)) / 2.0
+                assert abs(fd - g[y, x, c]) <= 1e-9 * max(1.0, abs(fd))
