@@ -69,6 +69,10 @@ typedef struct abf_params {
     float k_flowmag;       /* kFlowMagCoef of Code 1 (flow magnitude is divided by the strip
                               extent across the seam: W for axis 0, H for axis 1) */
     int32_t blend_mode;    /* 0: softmax composite of Code 1; 1: linear weights (SoftmaxR = Blend) */
+    int32_t gain_comp;     /* 1: before the pyramid, scale R's intensity by the ratio of the two
+                              strips' intensity sums (16-bit fixed point: a = floor(2^16 sum(YL) /
+                              sum(YR)), YR' = min(255, (YR a + 2^15) >> 16)) to remove a residual
+                              exposure gain left by pre-processing (Section III.B); 0: off */
 } abf_params;
 
 typedef struct abf_plan abf_plan;
@@ -92,7 +96,7 @@ typedef struct abf_strip {
 
 /* Fills the adopted defaults: N = 6, P = 2, R = 2, Rc = 4, T = 2, M = 1,
  * lk window 5 x 5, 2 iterations, eps 25, kSoftmaxSharpness 10,
- * kFlowMagCoef 20, softmax blend. */
+ * kFlowMagCoef 20, softmax blend, exposure compensation on. */
 void abf_default_params(abf_params *p);
 
 /* Creates a plan for batches of at most max_strips strips whose level-0

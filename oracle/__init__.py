@@ -45,6 +45,7 @@ class Params:
     k_sharp: float = 10.0  # kSoftmaxSharpness
     k_flowmag: float = 20.0  # kFlowMagCoef
     blend_mode: int = 0   # 0 softmax (Code 1), 1 linear
+    gain_comp: int = 1    # compensate R's intensity by the ratio of intensity sums
 
     @staticmethod
     def lean(**kw) -> "Params":
@@ -72,8 +73,9 @@ def _load():
         "orc_level_sizes": (None, [c_int, c_int, c_int, i32p, i32p]),
         "orc_flow_int": (None, [u8p, u8p, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, i32p, i32p]),
         "orc_refine": (None, [u8p, u8p, c_int, c_int, i32p, c_int, c_int, c_double, f64p]),
+        "orc_gain_comp": (None, [u8p, u8p, c_long]),
         "orc_flow_bidirectional": (None, [u8p, u8p, c_int, c_int, c_long, c_long,
-                                          c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_double,
+                                          c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_double, c_int,
                                           f64p, f64p, i32p, i32p, i32p, i32p]),
         "orc_blend_coef": (c_double, [c_int, c_int, c_int, c_int, c_int]),
         "orc_blend": (None, [f64p, f64p, f64p, f64p, f64p, c_int, c_int, c_int, c_double, c_double, c_int,
@@ -127,6 +129,14 @@ def luma(rgb: np.ndarray) -> np.ndarray:
     Y = np.empty((H, W), np.uint8)
     _load().orc_luma(_p(rgb, u8p), H, W, W * 3, _p(Y, u8p))
     return Y
+
+
+def gain_comp(yl: np.ndarray, yr: np.ndarray) -> np.ndarray:
+    """R's intensity after exposure compensation (a new array)."""
+    yl = _u8(yl)
+    out = _u8(yr).copy()
+    _load().orc_gain_comp(_p(yl, u8p), _p(out, u8p), out.size)
+    return out
 
 
 def pyr_down(Y: np.ndarray) -> np.ndarray:
@@ -220,7 +230,7 @@ def flow_bidirectional(L, R, params: Params = Params(), levels_out: bool = False
     bufs = [np.empty(tot * 2, np.int32) for _ in range(4)]
     _load().orc_flow_bidirectional(_p(L, u8p), _p(R, u8p), H, W, W * 3, W * 3, params.levels, params.patch,
                                    params.radius, params.radius_coarse, params.prop_steps, params.median,
-                                   params.lk_patch, params.lk_iters, params.lk_eps, _p(flr, f64p),
+                                   params.lk_patch, params.lk_iters, params.lk_eps, params.gain_comp, _p(flr, f64p),
                                    _p(frl, f64p), *[_p(b, i32p) for b in bufs])
     if not levels_out:
         return flr, frl

@@ -63,6 +63,27 @@ void orc_luma(const uint8_t *rgb, int H, int W, long pitch, uint8_t *Y)
         }
 }
 
+/* Flow, step 1b: exposure compensation of R's intensity. The paper's
+ * pre-processing corrects chromaticity between cameras (Section III.B);
+ * the flow stage removes a residual global gain by scaling R's intensity
+ * with the ratio of the two strips' intensity sums, in 16-bit fixed point:
+ * a = floor(2^16 sum(YL) / sum(YR)), YR' = min(255, (YR a + 2^15) >> 16).
+ * (An all-zero YR is left as it is.) */
+void orc_gain_comp(const uint8_t *yl, uint8_t *yr, long n)
+{
+    long long sl = 0, sr = 0;
+    for (long i = 0; i < n; i++) {
+        sl += yl[i];
+        sr += yr[i];
+    }
+    if (sr == 0) return;
+    long long a = (sl << 16) / sr;
+    for (long i = 0; i < n; i++) {
+        long long v = ((long long)yr[i] * a + (1LL << 15)) >> 16;
+        yr[i] = (uint8_t)(v > 255 ? 255 : v);
+    }
+}
+
 /* Flow, step 2: one pyramid reduction. 5x5 binomial filter (weights
  * 1 4 6 4 1 in each direction, total 256), sampled at even positions,
  * borders clamped, one rounding. Output is ceil(H/2) x ceil(W/2). */
@@ -342,10 +363,11 @@ void orc_refine(const uint8_t *A, const uint8_t *B, int H, int W, const int32_t 
 }
 
 /* Both flows of one strip (Section III.C.1). FlowLtoR: Ref = L, Tgt = R.
- * FlowRtoL: Ref = R, Tgt = L. Optional integer outputs: per-level search
+ * FlowRtoL: Ref = R, Tgt = L; with `gain`, R's intensity is compensated
+ * first (step 1b) and both directions use it. Optional integer outputs: per-level search
  * results and final flows for each direction (layout of orc_flow_int). */
 void orc_flow_bidirectional(const uint8_t *L, const uint8_t *R, int H, int W, long pitchL, long pitchR,
-                            int N, int P, int Rs, int Rc, int T, int M, int Plk, int Klk, double eps,
+                            int N, int P, int Rs, int Rc, int T, int M, int Plk, int Klk, double eps, int gain,
                             double *flow_lr, double *flow_rl,
                             int32_t *search_lr, int32_t *final_lr, int32_t *search_rl, int32_t *final_rl)
 {
@@ -356,6 +378,7 @@ void orc_flow_bidirectional(const uint8_t *L, const uint8_t *R, int H, int W, lo
     uint8_t *yl = (uint8_t *)malloc(n), *yr = (uint8_t *)malloc(n);
     orc_luma(L, H, W, pitchL, yl);
     orc_luma(R, H, W, pitchR, yr);
+    if (gain) orc_gain_comp(yl, yr, n);
     int32_t *s1 = search_lr ? search_lr : (int32_t *)malloc(sizeof(int32_t) * 2 * tot);
     int32_t *f1 = final_lr ? final_lr : (int32_t *)malloc(sizeof(int32_t) * 2 * tot);
     int32_t *s2 = search_rl ? search_rl : (int32_t *)malloc(sizeof(int32_t) * 2 * tot);

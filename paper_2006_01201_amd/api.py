@@ -33,6 +33,7 @@ class Params:
     k_sharp: float = 10.0
     k_flowmag: float = 20.0
     blend_mode: int = 0
+    gain_comp: int = 1
 
     def to_c(self) -> _abi.AbfParams:
         p = _abi.AbfParams()

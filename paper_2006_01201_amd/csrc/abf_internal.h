@@ -8,6 +8,10 @@
 namespace abf {
 
 constexpr int kMaxLevels = 12;
+// Luma planes carry a border of kPad replicated pixels on every side, so a
+// window that leaves the image by up to kPad pixels reads exactly the
+// clamp-to-edge values without per-access clamping.
+constexpr int kPad = 64;
 constexpr int kStages = 6;       // luma, pyramid, search, propagation, refine, blend
 constexpr int kSizeClasses = 4;  // by pixel count of one level over the batch
 
@@ -32,6 +36,7 @@ struct StripLv {
 // The caller's buffers of one strip.
 struct StripIO {
     const uint8_t *L, *R;
+    unsigned long long *sums;  // device: intensity sums of L and R (exposure step)
     const float *blend;
     float *flow[2];  // [0] = FlowLtoR, [1] = FlowRtoL
     uint8_t *F;
@@ -50,6 +55,7 @@ struct Work {
 
 // Float parameters the kernels take by value.
 struct LkParams {
+    // (Lucas-Kanade refinement)
     int32_t patch, iters;
     float eps;
 };
@@ -63,10 +69,11 @@ struct BlendParams {
 // computed identically on both sides).
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// search / propagation / refine tiles: 64 x TH (search, refine) and
-// 32 x TH (propagation); luma / blend: 256 pixels of one row; pyramid:
-// 64 x 4 output pixels.
-constexpr int kSearchTW = 64;
+// search tiles: 128 x TH pixels (64 threads per row, two pixels each);
+// refine: 64 x TH; propagation: 32 x TH; luma, exposure step and blend:
+// 256 pixels of one row; pyramid: 64 x 4 output pixels. Luma, exposure
+// and pyramid tiles cover the padded planes.
+constexpr int kSearchTW = 128;
 constexpr int kPropTW = 32;
 constexpr int kRefineTW = 64;
 constexpr int kRowTW = 256;
@@ -78,6 +85,8 @@ constexpr int kPyrTH = 4;
 // error of the launch. `grid` = 0 launches one workgroup per tile;
 // otherwise that many persistent workgroups loop over the tiles.
 hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s);
+hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s);
+hipError_t launch_gain(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s);
 hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s);
 hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int th, int grid, hipStream_t s);
 hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid,
@@ -103,8 +112,11 @@ hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *fl
                                  unsigned long long *fixR, hipStream_t s);
 
 // tiles of one strip for a stage (both directions where the stage has two)
-__host__ __device__ inline int tiles_luma(int H, int W) { return H * ceil_div(W, kRowTW); }
-__host__ __device__ inline int tiles_pyr(int H, int W) { return ceil_div(H, kPyrTH) * ceil_div(W, kPyrTW); }
+__host__ __device__ inline int tiles_luma(int H, int W) { return (H + 2 * kPad) * ceil_div(W + 2 * kPad, kRowTW); }
+__host__ __device__ inline int tiles_pyr(int H, int W)
+{
+    return ceil_div(H + 2 * kPad, kPyrTH) * ceil_div(W + 2 * kPad, kPyrTW);
+}
 __host__ __device__ inline int tiles_search(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kSearchTW); }
 __host__ __device__ inline int tiles_prop(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kPropTW); }
 __host__ __device__ inline int tiles_refine(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kRefineTW); }

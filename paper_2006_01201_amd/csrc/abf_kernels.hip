@@ -9,12 +9,16 @@
 // land on one XCD (dispatch is round-robin over the 8 XCDs) take
 // neighbouring tiles and share that XCD's L2.
 //
+// Memory: luma planes carry a kPad-pixel replicated border, so the
+// windows of the search, the propagation and the refinement are read
+// straight from global memory (L1/L2) with aligned dword loads and
+// byte-alignment shifts; only a window that leaves the image by more than
+// kPad pixels takes a per-byte clamped path. Nothing depends on how far
+// the flows of neighbouring pixels differ.
+//
 // The integer stages are bit-exact by construction (integer arithmetic,
-// fixed candidate order, Jacobi updates into separate buffers). The
-// patch costs use v_sad_u8 on byte-packed dwords read from LDS tables in
-// which entry (y, x) holds bytes x..x+3 of row y ("H") or rows y..y+3 of
-// column x ("V"), so any 4-byte run of a row or column is one aligned
-// 32-bit LDS read.
+// fixed candidate order, Jacobi updates into separate buffers). Patch
+// costs use v_sad_u8 on byte-packed dwords.
 #include "abf_internal.h"
 
 namespace abf {
@@ -43,12 +47,62 @@ __device__ __forceinline__ int xcd_block(int b, int G)
     return x * per + min(x, rem) + i;
 }
 
+#define TILE_LOOP(total) for (int t = xcd_block(blockIdx.x, gridDim.x); t < (total); t += gridDim.x)
+
 __device__ __forceinline__ uint32_t pack16(int x, int y)
 {
     return (uint32_t)(uint16_t)(int16_t)x | ((uint32_t)(uint16_t)(int16_t)y << 16);
 }
 __device__ __forceinline__ int unpack_x(uint32_t v) { return (int)(int16_t)(v & 0xffffu); }
 __device__ __forceinline__ int unpack_y(uint32_t v) { return (int)(int16_t)(v >> 16); }
+
+// Bytes c .. c+NB-1 of a padded luma row, normalised so that out[k] holds
+// bytes c+4k .. c+4k+3. The row must hold those bytes (|c| <= kPad away).
+template <int NB>
+__device__ __forceinline__ void load_row(const uint8_t *__restrict__ row, int c, uint32_t (&out)[(NB + 3) / 4])
+{
+    constexpr int NO = (NB + 3) / 4;
+    constexpr int ND = (NB + 6) / 4;  // dwords covering NB bytes at any alignment
+    const int a = c & ~3;             // floor to a multiple of 4 (two's complement)
+    const int s = c - a;
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(row + a);
+    uint32_t w[ND + 1];
+#pragma unroll
+    for (int k = 0; k < ND; k++) w[k] = p[k];
+    w[ND] = 0;
+#pragma unroll
+    for (int k = 0; k < NO; k++) out[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], s);
+}
+
+// The same bytes with every index clamped to the image (for windows that
+// leave the padded border); `img` points at pixel (0, 0).
+template <int NB>
+__device__ void load_row_clamped(const uint8_t *__restrict__ img, int H, int W, int pitch, int r, int c,
+                                 uint32_t (&out)[(NB + 3) / 4])
+{
+    const uint8_t *row = img + (ptrdiff_t)clampi(r, 0, H - 1) * pitch;
+#pragma unroll
+    for (int k = 0; k < (NB + 3) / 4; k++) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if (4 * k + b < NB) v |= (uint32_t)row[clampi(c + 4 * k + b, 0, W - 1)] << (8 * b);
+        out[k] = v;
+    }
+}
+
+// dword of bytes o .. o+3 and byte o of a normalised row (o compile-time)
+template <int NO>
+__device__ __forceinline__ uint32_t dword_at(const uint32_t (&t)[NO], int o)
+{
+    const int q = o >> 2, sh = o & 3;
+    return sh == 0 ? t[q] : __builtin_amdgcn_alignbyte(t[q + 1], t[q], sh);
+}
+template <int NO>
+__device__ __forceinline__ uint32_t byte_at(const uint32_t (&t)[NO], int o)
+{
+    return (t[o >> 2] >> (8 * (o & 3))) & 0xffu;
+}
 
 template <int NT>
 __device__ __forceinline__ void wg_minmax4(int &a0, int &a1, int &a2, int &a3, int *red)
@@ -84,139 +138,100 @@ __device__ __forceinline__ void wg_minmax4(int &a0, int &a1, int &a2, int &a3, i
     __syncthreads();
 }
 
-// Stage the box [bx0, bx0 + bw) x [by0, by0 + bh) of a uint8 image
-// (coordinates clamped to the image) as H and V tables of row stride
-// STRIDE entries. `raw` holds (bh + 3) rows of RAWQ dwords. Ends with a
-// barrier.
-template <int STRIDE, int RAWQ, int NT>
-__device__ void stage_tables(const uint8_t *__restrict__ img, int H, int W, int pitch, int bx0, int by0,
-                             int bw, int bh, uint32_t *raw, uint32_t *tabH, uint32_t *tabV, bool needV)
-{
-    const int ax0 = bx0 & ~3;  // floor to a multiple of 4 (two's complement)
-    const int sh = bx0 - ax0;
-    const int nq = ((sh + bw + 2) >> 2) + 2;
-    const int rows = bh + 3;
-    for (int e = threadIdx.x; e < rows * nq; e += NT) {
-        int r = e / nq, q = e - r * nq;
-        int gy = clampi(by0 + r, 0, H - 1);
-        int gx = ax0 + 4 * q;
-        const uint8_t *row = img + (size_t)gy * pitch;
-        uint32_t v;
-        if (gx >= 0 && gx + 3 <= W - 1) {
-            v = *reinterpret_cast<const uint32_t *>(row + gx);
-        } else {
-            v = (uint32_t)row[clampi(gx, 0, W - 1)] | ((uint32_t)row[clampi(gx + 1, 0, W - 1)] << 8) |
-                ((uint32_t)row[clampi(gx + 2, 0, W - 1)] << 16) | ((uint32_t)row[clampi(gx + 3, 0, W - 1)] << 24);
-        }
-        raw[r * RAWQ + q] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < bh * bw; e += NT) {
-        int r = e / bw, c = e - r * bw;
-        int xo = c + sh, q = xo >> 2, b = xo & 3;
-        uint32_t lo = raw[r * RAWQ + q], hi = raw[r * RAWQ + q + 1];
-        tabH[r * STRIDE + c] = __builtin_amdgcn_alignbyte(hi, lo, b);
-        if (needV) {
-            int s = 8 * b;
-            uint32_t b0 = (raw[r * RAWQ + q] >> s) & 0xffu;
-            uint32_t b1 = (raw[(r + 1) * RAWQ + q] >> s) & 0xffu;
-            uint32_t b2 = (raw[(r + 2) * RAWQ + q] >> s) & 0xffu;
-            uint32_t b3 = (raw[(r + 3) * RAWQ + q] >> s) & 0xffu;
-            tabV[r * STRIDE + c] = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
-        }
-    }
-    __syncthreads();
-}
-
-// Patch cost from tables. Ref values of the pixel are preloaded: rr[r] =
-// row r bytes 0..3 (P = 2) or 0..2 (P = 1, byte 3 zero), rv = column 4
-// rows 0..3, rs = byte (4, 4). `th`, `tv` point at the window's top-left
-// entry in the Tgt tables.
-template <int P, int STRIDE>
-__device__ __forceinline__ uint32_t sad_tab(const uint32_t (&rr)[2 * P + 1], uint32_t rv, uint32_t rs,
-                                            const uint32_t *th, const uint32_t *tv)
-{
-    uint32_t s = 0;
-    if constexpr (P == 2) {
-#pragma unroll
-        for (int r = 0; r < 5; r++) s = __builtin_amdgcn_sad_u8(rr[r], th[r * STRIDE], s);
-        s = __builtin_amdgcn_sad_u8(rv, tv[4], s);
-        s = __builtin_amdgcn_sad_u8(rs, tv[STRIDE + 4] >> 24, s);
-    } else {
-#pragma unroll
-        for (int r = 0; r < 3; r++) s = __builtin_amdgcn_sad_u8(rr[r], th[r * STRIDE] & 0x00ffffffu, s);
-    }
-    return s;
-}
-
-template <int P, int STRIDE>
-__device__ __forceinline__ void load_ref(const uint32_t *rh, const uint32_t *rvt, uint32_t (&rr)[2 * P + 1],
-                                         uint32_t &rv, uint32_t &rs)
-{
-#pragma unroll
-    for (int r = 0; r < 2 * P + 1; r++) rr[r] = rh[r * STRIDE];
-    if constexpr (P == 2) {
-        rv = rvt[4];
-        rs = rvt[STRIDE + 4] >> 24;
-    } else {
-#pragma unroll
-        for (int r = 0; r < 3; r++) rr[r] &= 0x00ffffffu;
-        rv = rs = 0;
-    }
-}
-
-// Patch cost straight from global memory (fallback when a tile's target
-// footprint does not fit the LDS tables).
-template <int P>
-__device__ uint32_t sad_global(const uint8_t *__restrict__ ref, const uint8_t *__restrict__ tgt, int H, int W,
-                               int pitch, int x, int y, int dx, int dy)
-{
-    uint32_t s = 0;
-    for (int j = -P; j <= P; j++) {
-        const uint8_t *rrow = ref + (size_t)clampi(y + j, 0, H - 1) * pitch;
-        const uint8_t *trow = tgt + (size_t)clampi(y + j + dy, 0, H - 1) * pitch;
-        for (int i = -P; i <= P; i++) {
-            int a = rrow[clampi(x + i, 0, W - 1)], b = trow[clampi(x + i + dx, 0, W - 1)];
-            s += (uint32_t)abs(a - b);
-        }
-    }
-    return s;
-}
-
-#define TILE_LOOP(total, grid_is_persistent)                                           \
-    for (int t = xcd_block(blockIdx.x, gridDim.x); t < (total); t += gridDim.x)
-
 // ------------------------------------------------------------------ luma
-// Y = (77 R + 150 G + 29 B + 128) >> 8 for both images of every strip.
+// Y = (77 R + 150 G + 29 B + 128) >> 8 for both images of every strip,
+// written over the padded planes (a border pixel takes the value of the
+// nearest image pixel). The intensity sums over the image (for the
+// exposure step) are accumulated with 64-bit integer atomics, so they do
+// not depend on the order of the additions.
+__global__ __launch_bounds__(256) void k_zero_sums(const StripIO *__restrict__ io, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < 2 * n) io[i >> 1].sums[i & 1] = 0ull;
+}
+
 __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
                                               const int32_t *__restrict__ prefix, int n, int total)
 {
-    TILE_LOOP(total, 0)
+    __shared__ unsigned long long red[2][4];
+    TILE_LOOP(total)
+    {
+        const int s = find_strip(prefix, n, t);
+        const int local = t - prefix[s];
+        const int W = lv[s].W, H = lv[s].H;
+        const int segs = ceil_div(W + 2 * kPad, kRowTW);
+        const int py = local / segs;
+        const int px = (local - py * segs) * kRowTW + (int)threadIdx.x;
+        const int y = py - kPad, x = px - kPad;
+        unsigned long long sl = 0, sr = 0;
+        if (px < W + 2 * kPad) {
+            const int cx = clampi(x, 0, W - 1), cy = clampi(y, 0, H - 1);
+            const uint8_t *pl = io[s].L + (size_t)cy * io[s].pitchL + 3 * cx;
+            const uint8_t *pr = io[s].R + (size_t)cy * io[s].pitchR + 3 * cx;
+            const int yl = (77 * pl[0] + 150 * pl[1] + 29 * pl[2] + 128) >> 8;
+            const int yr = (77 * pr[0] + 150 * pr[1] + 29 * pr[2] + 128) >> 8;
+            const ptrdiff_t o = (ptrdiff_t)y * lv[s].ypitch + x;
+            lv[s].y[0][o] = (uint8_t)yl;
+            lv[s].y[1][o] = (uint8_t)yr;
+            if (x == cx && y == cy) {
+                sl = (unsigned long long)yl;
+                sr = (unsigned long long)yr;
+            }
+        }
+        // workgroup sum, one atomic per image
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            sl += __shfl_xor(sl, m, 64);
+            sr += __shfl_xor(sr, m, 64);
+        }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[0][w] = sl;
+            red[1][w] = sr;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+            const unsigned long long b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+            if (a) atomicAdd(&io[s].sums[0], a);
+            if (b) atomicAdd(&io[s].sums[1], b);
+        }
+        __syncthreads();
+    }
+}
+
+// Exposure step: R's padded luma plane scaled by a = floor(2^16 sum(YL) /
+// sum(YR)): YR' = min(255, (YR a + 2^15) >> 16); all-zero YR is kept.
+__global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
+                                              const int32_t *__restrict__ prefix, int n, int total)
+{
+    TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         const int local = t - prefix[s];
         const int W = lv[s].W;
-        const int segs = ceil_div(W, kRowTW);
-        const int y = local / segs;
-        const int x = (local - y * segs) * kRowTW + threadIdx.x;
-        if (x < W) {
-            const uint8_t *pl = io[s].L + (size_t)y * io[s].pitchL + 3 * x;
-            const uint8_t *pr = io[s].R + (size_t)y * io[s].pitchR + 3 * x;
-            const int yp = lv[s].ypitch;
-            lv[s].y[0][(size_t)y * yp + x] = (uint8_t)((77 * pl[0] + 150 * pl[1] + 29 * pl[2] + 128) >> 8);
-            lv[s].y[1][(size_t)y * yp + x] = (uint8_t)((77 * pr[0] + 150 * pr[1] + 29 * pr[2] + 128) >> 8);
-        }
+        const int segs = ceil_div(W + 2 * kPad, kRowTW);
+        const int py = local / segs;
+        const int px = (local - py * segs) * kRowTW + (int)threadIdx.x;
+        const unsigned long long sl = io[s].sums[0], sr = io[s].sums[1];
+        if (sr == 0 || px >= W + 2 * kPad) continue;
+        const unsigned long long a = (sl << 16) / sr;
+        uint8_t *p = lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch + (px - kPad);
+        const unsigned long long v = ((unsigned long long)*p * a + (1ull << 15)) >> 16;
+        *p = (uint8_t)(v > 255ull ? 255ull : v);
     }
 }
 
 // --------------------------------------------------------------- pyramid
 // One reduction, both images: 5x5 binomial (1 4 6 4 1)^2 / 256 sampled at
-// even positions, clamped borders, rounding (s + 128) >> 8.
+// even positions, clamped borders, rounding (s + 128) >> 8. Outputs cover
+// the padded plane (a border pixel takes the value at the nearest image
+// pixel); the taps of an image pixel stay inside the finer plane's border.
 __global__ __launch_bounds__(256) void k_pyr(const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix,
                                              int n, int total)
 {
     constexpr int w5[5] = {1, 4, 6, 4, 1};
-    TILE_LOOP(total, 0)
+    TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         int local = t - prefix[s];
@@ -224,111 +239,137 @@ __global__ __launch_bounds__(256) void k_pyr(const StripLv *__restrict__ lv, con
         const int per_img = tiles_pyr(L.H, L.W);
         const int img = local / per_img;
         local -= img * per_img;
-        const int tx = ceil_div(L.W, kPyrTW);
+        const int tx = ceil_div(L.W + 2 * kPad, kPyrTW);
         const int ty = local / tx;
-        const int x = (local - ty * tx) * kPyrTW + (threadIdx.x & (kPyrTW - 1));
-        const int y = ty * kPyrTH + (threadIdx.x / kPyrTW);
-        if (x < L.W && y < L.H) {
+        const int px = (local - ty * tx) * kPyrTW + (int)(threadIdx.x & (kPyrTW - 1));
+        const int py = ty * kPyrTH + (int)(threadIdx.x / kPyrTW);
+        if (px < L.W + 2 * kPad && py < L.H + 2 * kPad) {
+            const int x = clampi(px - kPad, 0, L.W - 1), y = clampi(py - kPad, 0, L.H - 1);
             const uint8_t *src = L.yfine[img];
-            const int Hf = L.Hf, Wf = L.Wf, pf = L.ypitch_f;
-            int cx[5];
-#pragma unroll
-            for (int i = 0; i < 5; i++) cx[i] = clampi(2 * x + i - 2, 0, Wf - 1);
+            const int pf = L.ypitch_f;
             int acc = 0;
 #pragma unroll
             for (int j = 0; j < 5; j++) {
-                const uint8_t *row = src + (size_t)clampi(2 * y + j - 2, 0, Hf - 1) * pf;
+                const uint8_t *row = src + (ptrdiff_t)(2 * y + j - 2) * pf + (2 * x - 2);
                 int h = 0;
 #pragma unroll
-                for (int i = 0; i < 5; i++) h += w5[i] * row[cx[i]];
+                for (int i = 0; i < 5; i++) h += w5[i] * row[i];
                 acc += w5[j] * h;
             }
-            L.y[img][(size_t)y * L.ypitch + x] = (uint8_t)((acc + 128) >> 8);
+            L.y[img][(ptrdiff_t)(py - kPad) * L.ypitch + (px - kPad)] = (uint8_t)((acc + 128) >> 8);
         }
     }
 }
 
 // ---------------------------------------------------------------- search
 // Integer patch-cost search around the upsampled coarser flow, both
-// directions. Tile: 64 x TH pixels, one pixel per thread. Key of a
-// candidate: (cost << 11) | (L1 offset << 7) | enumeration index, so one
-// unsigned min gives the lexicographic winner.
-constexpr int kTgtBW = 128;  // Tgt table row stride (entries)
-
+// directions. A thread takes two horizontally adjacent pixels (x even):
+// they share the centre (the coarser flow is upsampled by replication),
+// so one set of target rows serves both and, for P = 2, the middle four
+// columns of every row cost are shared. Key of a candidate:
+// (cost << 11) | (L1 offset << 7) | enumeration index, so one unsigned min
+// gives the lexicographic winner.
 template <int P, int R, int TH>
 __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ lv,
                                                     const int32_t *__restrict__ prefix, int n, int total)
 {
-    constexpr int NT = 64 * TH;
-    constexpr int TW = kSearchTW;
-    constexpr int S = R + P;
-    constexpr int RBW = TW + 2 * P, RBH = TH + 2 * P;
-    constexpr int TBH = TH + 16;  // Tgt table rows: 2S + vertical centre spread must fit
-    constexpr int RAWQ = (kTgtBW + 8) / 4 + 2;
-    constexpr int NC = 2 * R + 1;
-    __shared__ uint32_t raw[(TBH + 3) * RAWQ];
-    __shared__ uint32_t refH[RBH * RBW], refV[RBH * RBW];
-    __shared__ uint32_t tgtH[TBH * kTgtBW], tgtV[TBH * kTgtBW];
-    __shared__ int red[4 * (NT / 64)];
-
+    constexpr int NC = 2 * R + 1;          // candidates per axis
+    constexpr int NR = 2 * R + 2 * P + 1;  // target rows
+    constexpr int NB = 2 * R + 2 * P + 2;  // target bytes per row (both pixels)
+    constexpr int NBO = (NB + 3) / 4;
+    constexpr int RB = 2 * P + 2;          // reference bytes per row (both pixels)
     const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
-    TILE_LOOP(total, 0)
+    TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         int local = t - prefix[s];
         const StripLv &L = lv[s];
         const int H = L.H, W = L.W, yp = L.ypitch;
-        const int ntx = ceil_div(W, TW), per_dir = ntx * ceil_div(H, TH);
+        const int ntx = ceil_div(W, kSearchTW), per_dir = ntx * ceil_div(H, TH);
         const int dir = local / per_dir;
         local -= dir * per_dir;
         const int tyi = local / ntx;
-        const int x0 = (local - tyi * ntx) * TW, y0 = tyi * TH;
-        const int x = x0 + lane, y = y0 + wrow;
+        const int x = (local - tyi * ntx) * kSearchTW + 2 * lane, y = tyi * TH + wrow;
+        if (x >= W || y >= H) continue;  // no barrier in this kernel
         const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
-
         int cx = 0, cy = 0;
         if (L.dc[dir]) {
-            const uint32_t v = L.dc[dir][(size_t)min(min(y, H - 1) >> 1, L.Hc - 1) * L.fpitch_c +
-                                         min(min(x, W - 1) >> 1, L.Wc - 1)];
+            const uint32_t v = L.dc[dir][(size_t)min(y >> 1, L.Hc - 1) * L.fpitch_c + min(x >> 1, L.Wc - 1)];
             cx = 2 * unpack_x(v);
             cy = 2 * unpack_y(v);
         }
-        int cxmin = cx, cymin = cy, cxmax = cx, cymax = cy;
-        wg_minmax4<NT>(cxmin, cymin, cxmax, cymax, red);
-        const int tbw = TW + 2 * S + (cxmax - cxmin), tbh = TH + 2 * S + (cymax - cymin);
-        const bool fast = tbw <= kTgtBW && tbh <= TBH;
-
-        uint32_t best = 0xffffffffu;
-        if (fast) {
-            stage_tables<RBW, RAWQ, NT>(ref, H, W, yp, x0 - P, y0 - P, RBW, RBH, raw, refH, refV, P == 2);
-            uint32_t rr[2 * P + 1], rv, rs;
-            load_ref<P, RBW>(refH + wrow * RBW + lane, refV + wrow * RBW + lane, rr, rv, rs);
-            stage_tables<kTgtBW, RAWQ, NT>(tgt, H, W, yp, x0 + cxmin - S, y0 + cymin - S, tbw, tbh, raw, tgtH,
-                                           tgtV, P == 2);
-            const int off = (wrow + cy - cymin) * kTgtBW + lane + (cx - cxmin);
-            const uint32_t *th = tgtH + off, *tv = tgtV + off;
+        // reference rows y-P .. y+P, columns x-P .. x+1+P
+        uint32_t rr[2 * P + 1][(RB + 3) / 4];
+#pragma unroll
+        for (int r = 0; r < 2 * P + 1; r++) load_row<RB>(ref + (ptrdiff_t)(y - P + r) * yp, x - P, rr[r]);
+        // target rows, columns x+cx-R-P .. x+cx+R+P+1
+        const int c0 = x + cx - R - P, r0 = y + cy - R - P;
+        const bool inpad = c0 >= -kPad && c0 + NB - 1 <= W - 1 + kPad && r0 >= -kPad && r0 + NR - 1 <= H - 1 + kPad;
+        uint32_t tt[NR][NBO];
+        if (inpad) {
+#pragma unroll
+            for (int k = 0; k < NR; k++) load_row<NB>(tgt + (ptrdiff_t)(r0 + k) * yp, c0, tt[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NR; k++) load_row_clamped<NB>(tgt, H, W, yp, r0 + k, c0, tt[k]);
+        }
+        uint32_t best0 = 0xffffffffu, best1 = 0xffffffffu;
+        if constexpr (P == 2) {
+            uint32_t rm[5], rl[5], rh[5];
+#pragma unroll
+            for (int r = 0; r < 5; r++) {
+                rm[r] = dword_at(rr[r], 1);
+                rl[r] = byte_at(rr[r], 0);
+                rh[r] = byte_at(rr[r], 5);
+            }
 #pragma unroll
             for (int j = 0; j < NC; j++)
 #pragma unroll
                 for (int i = 0; i < NC; i++) {
-                    const uint32_t c = sad_tab<P, kTgtBW>(rr, rv, rs, th + j * kTgtBW + i, tv + j * kTgtBW + i);
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int r = 0; r < 5; r++) m = __builtin_amdgcn_sad_u8(rm[r], dword_at(tt[j + r], i + 1), m);
+                    uint32_t s0 = m, s1 = m;
+#pragma unroll
+                    for (int r = 0; r < 5; r++) {
+                        s0 = __builtin_amdgcn_sad_u8(rl[r], byte_at(tt[j + r], i), s0);
+                        s1 = __builtin_amdgcn_sad_u8(rh[r], byte_at(tt[j + r], i + 5), s1);
+                    }
                     const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
-                    best = min(best, (c << 11) + K);
+                    best0 = min(best0, (s0 << 11) + K);
+                    best1 = min(best1, (s1 << 11) + K);
                 }
         } else {
+            uint32_t r0m[3], r1m[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                r0m[r] = rr[r][0] & 0x00ffffffu;
+                r1m[r] = rr[r][0] >> 8;
+            }
+#pragma unroll
             for (int j = 0; j < NC; j++)
+#pragma unroll
                 for (int i = 0; i < NC; i++) {
-                    const uint32_t c = sad_global<P>(ref, tgt, H, W, yp, x, y, cx + i - R, cy + j - R);
+                    uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+                    for (int r = 0; r < 3; r++) {
+                        s0 = __builtin_amdgcn_sad_u8(r0m[r], dword_at(tt[j + r], i) & 0x00ffffffu, s0);
+                        s1 = __builtin_amdgcn_sad_u8(r1m[r], dword_at(tt[j + r], i + 1) & 0x00ffffffu, s1);
+                    }
                     const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
-                    best = min(best, (c << 11) + K);
+                    best0 = min(best0, (s0 << 11) + K);
+                    best1 = min(best1, (s1 << 11) + K);
                 }
         }
-        if (x < W && y < H) {
-            const int idx = (int)(best & 127u);
-            const int j = idx / NC, i = idx - j * NC;
-            L.ds[dir][(size_t)y * L.fpitch + x] = pack16(cx + i - R, cy + j - R);
+        uint32_t *out = L.ds[dir] + (size_t)y * L.fpitch + x;
+        {
+            const int idx = (int)(best0 & 127u), j = idx / NC, i = idx - j * NC;
+            out[0] = pack16(cx + i - R, cy + j - R);
         }
-        __syncthreads();
+        if (x + 1 < W) {
+            const int idx = (int)(best1 & 127u), j = idx / NC, i = idx - j * NC;
+            out[1] = pack16(cx + i - R, cy + j - R);
+        }
     }
 }
 
@@ -337,10 +378,34 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
 // iterate; lower cost wins, earlier candidate on ties; neighbours outside
 // the image skipped) and a (2M+1)^2 component-wise median with clamped
 // indices, fused per 32 x TH tile by recomputing a halo of T + M pixels.
+// The flows live in LDS; patches are read from the padded luma planes.
 constexpr int kHaloMax = 5;
-constexpr int kPropTgtBW = 96;
 
 __device__ __forceinline__ int med3i(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+
+template <int P>
+__device__ __forceinline__ uint32_t patch_cost(const uint32_t (&rr)[2 * P + 1][(2 * P + 4) / 4],
+                                               const uint8_t *__restrict__ tgt,
+                                               int H, int W, int yp, int px, int py, int dx, int dy)
+{
+    constexpr int NB = 2 * P + 1;
+    const int c0 = px + dx - P, r0 = py + dy - P;
+    const bool inpad = c0 >= -kPad && c0 + NB - 1 <= W - 1 + kPad && r0 >= -kPad && r0 + NB - 1 <= H - 1 + kPad;
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < NB; r++) {
+        uint32_t t[(NB + 3) / 4];
+        if (inpad) load_row<NB>(tgt + (ptrdiff_t)(r0 + r) * yp, c0, t);
+        else load_row_clamped<NB>(tgt, H, W, yp, r0 + r, c0, t);
+        if constexpr (P == 2) {
+            s = __builtin_amdgcn_sad_u8(rr[r][0], t[0], s);
+            s = __builtin_amdgcn_sad_u8(rr[r][1], t[1] & 0xffu, s);
+        } else {
+            s = __builtin_amdgcn_sad_u8(rr[r][0], t[0] & 0x00ffffffu, s);
+        }
+    }
+    return s;
+}
 
 template <int P, int TH>
 __global__ __launch_bounds__(256) void k_prop(const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix,
@@ -349,18 +414,10 @@ __global__ __launch_bounds__(256) void k_prop(const StripLv *__restrict__ lv, co
     constexpr int NT = 256;
     constexpr int TW = kPropTW;
     constexpr int DW = TW + 2 * kHaloMax, DH = TH + 2 * kHaloMax;
-    constexpr int RBW = TW + 2 * (kHaloMax - 1) + 2 * P;  // ref tables cover step-1 region + P
-    constexpr int RBH = TH + 2 * (kHaloMax - 1) + 2 * P;
-    constexpr int TBH = RBH + 8;
-    constexpr int RAWQ = (kPropTgtBW + 8) / 4 + 2;
     __shared__ uint32_t dbuf[2][DH * DW];
-    __shared__ uint32_t raw[(TBH + 3) * RAWQ];
-    __shared__ uint32_t refH[RBH * RBW], refV[RBH * RBW];
-    __shared__ uint32_t tgtH[TBH * kPropTgtBW], tgtV[TBH * kPropTgtBW];
-    __shared__ int red[16];
 
     const int h = T + M;
-    TILE_LOOP(total, 0)
+    TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         int local = t - prefix[s];
@@ -375,91 +432,67 @@ __global__ __launch_bounds__(256) void k_prop(const StripLv *__restrict__ lv, co
         const uint32_t *dsrc = L.ds[dir];
         // frame of the D buffers: (x0 - kHaloMax, y0 - kHaloMax)
         const int fx0 = x0 - kHaloMax, fy0 = y0 - kHaloMax;
-
-        int dxmin = 1 << 20, dymin = 1 << 20, dxmax = -(1 << 20), dymax = -(1 << 20);
         for (int e = threadIdx.x; e < DH * DW; e += NT) {
             const int ry = e / DW, rx = e - ry * DW;
             const int gx = fx0 + rx, gy = fy0 + ry;
             uint32_t v = 0;
             if (gx >= 0 && gx < W && gy >= 0 && gy < H && gx >= x0 - h && gx < x0 + TW + h && gy >= y0 - h &&
-                gy < y0 + TH + h) {
+                gy < y0 + TH + h)
                 v = dsrc[(size_t)gy * L.fpitch + gx];
-                const int vx = unpack_x(v), vy = unpack_y(v);
-                dxmin = min(dxmin, vx);
-                dxmax = max(dxmax, vx);
-                dymin = min(dymin, vy);
-                dymax = max(dymax, vy);
-            }
             dbuf[0][e] = v;
         }
-        wg_minmax4<NT>(dxmin, dymin, dxmax, dymax, red);
+        __syncthreads();
         int cur = 0;
-        if (T > 0) {
-            // step-1 region: tile +- (h - 1); its patches and displaced patches
-            const int g = h - 1;
-            const int rbx0 = x0 - g - P, rby0 = y0 - g - P;
-            const int tbx0 = rbx0 + dxmin, tby0 = rby0 + dymin;
-            const int tbw = TW + 2 * g + 2 * P + (dxmax - dxmin), tbh = TH + 2 * g + 2 * P + (dymax - dymin);
-            const bool fast = dxmin <= dxmax && tbw <= kPropTgtBW && tbh <= TBH;
-            if (fast) {
-                stage_tables<RBW, RAWQ, NT>(ref, H, W, yp, rbx0, rby0, TW + 2 * g + 2 * P, TH + 2 * g + 2 * P, raw,
-                                            refH, refV, P == 2);
-                stage_tables<kPropTgtBW, RAWQ, NT>(tgt, H, W, yp, tbx0, tby0, tbw, tbh, raw, tgtH, tgtV, P == 2);
-            }
-            for (int step = 1; step <= T; step++) {
-                const int gg = h - step;  // region of this step: tile +- gg
-                const int rw = TW + 2 * gg, rh = TH + 2 * gg;
-                const uint32_t *prev = dbuf[cur];
-                uint32_t *next = dbuf[cur ^ 1];
-                for (int e = threadIdx.x; e < rw * rh; e += NT) {
-                    const int ly = e / rw, lx = e - ly * rw;
-                    const int px = x0 - gg + lx, py = y0 - gg + ly;
-                    const int fi = (py - fy0) * DW + (px - fx0);
-                    if (px < 0 || px >= W || py < 0 || py >= H) {
-                        next[fi] = 0;
-                        continue;
-                    }
-                    uint32_t cand[5];
-                    bool ok[5];
-                    cand[0] = prev[fi];
-                    ok[0] = true;
-                    cand[1] = prev[fi - 1];
-                    ok[1] = px > 0;
-                    cand[2] = prev[fi + 1];
-                    ok[2] = px < W - 1;
-                    cand[3] = prev[fi - DW];
-                    ok[3] = py > 0;
-                    cand[4] = prev[fi + DW];
-                    ok[4] = py < H - 1;
-                    uint32_t rr[2 * P + 1], rv = 0, rs = 0;
-                    const int qx = px - rbx0 - P, qy = py - rby0 - P;  // window top-left in ref tables
-                    if (fast) load_ref<P, RBW>(refH + qy * RBW + qx, refV + qy * RBW + qx, rr, rv, rs);
-                    uint32_t bestc = 0xffffffffu, bestv = cand[0];
-#pragma unroll
-                    for (int k = 0; k < 5; k++) {
-                        if (!ok[k]) continue;
-                        bool dup = false;
-#pragma unroll
-                        for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
-                        if (dup) continue;  // an earlier equal candidate already has this cost
-                        const int dx = unpack_x(cand[k]), dy = unpack_y(cand[k]);
-                        uint32_t c;
-                        if (fast) {
-                            const int o = (qy + dy - dymin) * kPropTgtBW + (qx + dx - dxmin);
-                            c = sad_tab<P, kPropTgtBW>(rr, rv, rs, tgtH + o, tgtV + o);
-                        } else {
-                            c = sad_global<P>(ref, tgt, H, W, yp, px, py, dx, dy);
-                        }
-                        if (c < bestc) {
-                            bestc = c;
-                            bestv = cand[k];
-                        }
-                    }
-                    next[fi] = bestv;
+        for (int step = 1; step <= T; step++) {
+            const int gg = h - step;  // region of this step: tile +- gg
+            const int rw = TW + 2 * gg, rh = TH + 2 * gg;
+            const uint32_t *prev = dbuf[cur];
+            uint32_t *next = dbuf[cur ^ 1];
+            for (int e = threadIdx.x; e < rw * rh; e += NT) {
+                const int ly = e / rw, lx = e - ly * rw;
+                const int px = x0 - gg + lx, py = y0 - gg + ly;
+                const int fi = (py - fy0) * DW + (px - fx0);
+                if (px < 0 || px >= W || py < 0 || py >= H) {
+                    next[fi] = 0;
+                    continue;
                 }
-                __syncthreads();
-                cur ^= 1;
+                uint32_t cand[5];
+                bool ok[5];
+                cand[0] = prev[fi];
+                ok[0] = true;
+                cand[1] = prev[fi - 1];
+                ok[1] = px > 0;
+                cand[2] = prev[fi + 1];
+                ok[2] = px < W - 1;
+                cand[3] = prev[fi - DW];
+                ok[3] = py > 0;
+                cand[4] = prev[fi + DW];
+                ok[4] = py < H - 1;
+                uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
+#pragma unroll
+                for (int r = 0; r < 2 * P + 1; r++) {
+                    load_row<2 * P + 1>(ref + (ptrdiff_t)(py - P + r) * yp, px - P, rr[r]);
+                    if constexpr (P == 2) rr[r][1] &= 0xffu;
+                    else rr[r][0] &= 0x00ffffffu;
+                }
+                uint32_t bestc = 0xffffffffu, bestv = cand[0];
+#pragma unroll
+                for (int k = 0; k < 5; k++) {
+                    if (!ok[k]) continue;
+                    bool dup = false;
+#pragma unroll
+                    for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
+                    if (dup) continue;  // an earlier equal candidate already has this cost
+                    const uint32_t c = patch_cost<P>(rr, tgt, H, W, yp, px, py, unpack_x(cand[k]), unpack_y(cand[k]));
+                    if (c < bestc) {
+                        bestc = c;
+                        bestv = cand[k];
+                    }
+                }
+                next[fi] = bestv;
             }
+            __syncthreads();
+            cur ^= 1;
         }
         // median (or copy) over the tile
         const uint32_t *fin = dbuf[cur];
@@ -515,26 +548,20 @@ __global__ __launch_bounds__(256) void k_prop(const StripLv *__restrict__ lv, co
 // Gauss-Newton steps from the integer flow with bilinear Tgt samples; each
 // component clamped to within 1 px of the integer flow. The displacement
 // is split into floor + fraction so no FP32 coordinate is ever formed.
-constexpr int kRefTgtBW = 192;
-
+// A pixel whose window lies inside the image reads its Ref rows and its
+// (WN+1)^2 Tgt block straight from the padded planes; a pixel near the
+// border (its window positions are clamped, so they repeat) evaluates
+// every window position on its own.
 template <int LP, int TH>
 __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
                                                     const int32_t *__restrict__ prefix, int n, int total, int iters,
                                                     float eps)
 {
-    constexpr int NT = 64 * TH;
     constexpr int TW = kRefineTW;
-    constexpr int AW = TW + 2 * LP + 2, AH = TH + 2 * LP + 2;  // Ref box: tile +- (LP + 1)
-    constexpr int GW = TW + 2 * LP, GH = TH + 2 * LP;          // gradient box: tile +- LP
-    constexpr int BBH = TH + 2 * LP + 2 + 24;                  // Tgt box rows (vertical spread <= 24)
     constexpr int WN = 2 * LP + 1;
-    __shared__ uint8_t abox[AH * AW];
-    __shared__ uint32_t gbox[GH * GW];
-    __shared__ uint8_t bbox[BBH * kRefTgtBW];
-    __shared__ int red[4 * (NT / 64)];
-
+    constexpr int AB = WN + 2;  // Ref bytes per row (window + gradient taps)
     const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
-    TILE_LOOP(total, 0)
+    TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         int local = t - prefix[s];
@@ -544,76 +571,68 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
         const int dir = local / per_dir;
         local -= dir * per_dir;
         const int tyi = local / ntx;
-        const int x0 = (local - tyi * ntx) * TW, y0 = tyi * TH;
-        const int x = x0 + lane, y = y0 + wrow;
+        const int x = (local - tyi * ntx) * TW + lane, y = tyi * TH + wrow;
+        if (x >= W || y >= H) continue;  // no barrier in this kernel
         const uint8_t *A = L.y[dir], *B = L.y[1 - dir];
-
-        // Ref box and gradients
-        const int ax0 = x0 - LP - 1, ay0 = y0 - LP - 1;
-        for (int e = threadIdx.x; e < AW * AH; e += NT) {
-            const int r = e / AW, c = e - r * AW;
-            abox[e] = A[(size_t)clampi(ay0 + r, 0, H - 1) * yp + clampi(ax0 + c, 0, W - 1)];
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < GW * GH; e += NT) {
-            const int r = e / GW, c = e - r * GW;
-            // gradient at image position q = (x0 - LP + c, y0 - LP + r), clamped to the image
-            const int qx = clampi(x0 - LP + c, 0, W - 1), qy = clampi(y0 - LP + r, 0, H - 1);
-            const int bx = qx - ax0, by = qy - ay0;
-            const int xm = clampi(qx - 1, 0, W - 1) - ax0, xp = clampi(qx + 1, 0, W - 1) - ax0;
-            const int ym = clampi(qy - 1, 0, H - 1) - ay0, yq = clampi(qy + 1, 0, H - 1) - ay0;
-            const int gx2 = (int)abox[by * AW + xp] - (int)abox[by * AW + xm];
-            const int gy2 = (int)abox[yq * AW + bx] - (int)abox[ym * AW + bx];
-            gbox[e] = pack16(gx2, gy2);
-        }
-        // integer flow and Tgt footprint
-        const bool inside = x < W && y < H;
-        const uint32_t d0 = L.df[dir][(size_t)min(y, H - 1) * L.fpitch + min(x, W - 1)];
+        const uint32_t d0 = L.df[dir][(size_t)y * L.fpitch + x];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
-        int dxmin = d0x, dymin = d0y, dxmax = d0x, dymax = d0y;
-        wg_minmax4<NT>(dxmin, dymin, dxmax, dymax, red);
-        const int bx0 = x0 - LP + dxmin - 1, by0 = y0 - LP + dymin - 1;
-        const int bw = TW + 2 * LP + (dxmax - dxmin) + 3, bh = TH + 2 * LP + (dymax - dymin) + 3;
-        const bool fast = bw <= kRefTgtBW && bh <= BBH;
-        if (fast) {
-            for (int e = threadIdx.x; e < bw * bh; e += NT) {
-                const int r = e / bw, c = e - r * bw;
-                bbox[r * kRefTgtBW + c] = B[(size_t)clampi(by0 + r, 0, H - 1) * yp + clampi(bx0 + c, 0, W - 1)];
-            }
-        }
-        __syncthreads();
+        const bool interior = x - LP >= 0 && x + LP <= W - 1 && y - LP >= 0 && y + LP <= H - 1;
 
-        // normal matrix (times 4, exact)
+        // window: Ref value and doubled gradient at each (clamped) position
+        int av[WN][WN], gx[WN][WN], gy[WN][WN];
+        if (interior) {
+            uint32_t ar[WN + 2][(AB + 3) / 4];
+#pragma unroll
+            for (int r = 0; r < WN + 2; r++) load_row<AB>(A + (ptrdiff_t)(y - LP - 1 + r) * yp, x - LP - 1, ar[r]);
+#pragma unroll
+            for (int j = 0; j < WN; j++)
+#pragma unroll
+                for (int i = 0; i < WN; i++) {
+                    av[j][i] = (int)byte_at(ar[j + 1], i + 1);
+                    gx[j][i] = (int)byte_at(ar[j + 1], i + 2) - (int)byte_at(ar[j + 1], i);
+                    gy[j][i] = (int)byte_at(ar[j + 2], i + 1) - (int)byte_at(ar[j], i + 1);
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < WN; j++)
+#pragma unroll
+                for (int i = 0; i < WN; i++) {
+                    const int qx = clampi(x + i - LP, 0, W - 1), qy = clampi(y + j - LP, 0, H - 1);
+                    const uint8_t *rw = A + (ptrdiff_t)qy * yp;  // q +- 1 stays inside the border
+                    av[j][i] = rw[qx];
+                    gx[j][i] = (int)rw[qx + 1] - (int)rw[qx - 1];
+                    gy[j][i] = (int)rw[qx + yp] - (int)rw[qx - yp];
+                }
+        }
         int hxx = 0, hxy = 0, hyy = 0;
-        for (int j = -LP; j <= LP; j++)
-            for (int i = -LP; i <= LP; i++) {
-                const int qx = clampi(x + i, 0, W - 1), qy = clampi(y + j, 0, H - 1);
-                const uint32_t g = gbox[(qy - (y0 - LP)) * GW + (qx - (x0 - LP))];
-                const int gx = unpack_x(g), gy = unpack_y(g);
-                hxx += gx * gx;
-                hxy += gx * gy;
-                hyy += gy * gy;
+#pragma unroll
+        for (int j = 0; j < WN; j++)
+#pragma unroll
+            for (int i = 0; i < WN; i++) {
+                hxx += gx[j][i] * gx[j][i];
+                hxy += gx[j][i] * gy[j][i];
+                hyy += gy[j][i] * gy[j][i];
             }
         const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
         const double det = Hxx * Hyy - Hxy * Hxy;
         float ux = (float)d0x, uy = (float)d0y;
-        const bool interior = x - LP >= 0 && x + LP <= W - 1 && y - LP >= 0 && y + LP <= H - 1;
         for (int it = 0; it < iters; it++) {
             const float fux = floorf(ux), fuy = floorf(uy);
             const float fx = ux - fux, fy = uy - fuy;
             const int iux = (int)fux, iuy = (int)fuy;
             float bxs = 0.f, bys = 0.f;
-            if (fast && interior) {
-                // window of Tgt samples on a (WN+1)^2 block with shared weights
-                const int ox = x - LP + iux - bx0, oy = y - LP + iuy - by0;
+            const int c0 = x - LP + iux, r0 = y - LP + iuy;
+            if (interior && c0 >= -kPad && c0 + WN <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
+                // (WN+1)^2 block of Tgt with shared bilinear weights
                 float hrow[WN + 1][WN];
 #pragma unroll
                 for (int r = 0; r <= WN; r++) {
-                    const uint8_t *br = bbox + (oy + r) * kRefTgtBW + ox;
-                    float prev = (float)br[0];
+                    uint32_t br[(WN + 1 + 3) / 4];
+                    load_row<WN + 1>(B + (ptrdiff_t)(r0 + r) * yp, c0, br);
+                    float prev = (float)byte_at(br, 0);
 #pragma unroll
                     for (int c = 0; c < WN; c++) {
-                        const float nx = (float)br[c + 1];
+                        const float nx = (float)byte_at(br, c + 1);
                         hrow[r][c] = prev + fx * (nx - prev);
                         prev = nx;
                     }
@@ -623,44 +642,25 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
 #pragma unroll
                     for (int i = 0; i < WN; i++) {
                         const float bs = hrow[j][i] + fy * (hrow[j + 1][i] - hrow[j][i]);
-                        const int qx = x - LP + i, qy = y - LP + j;
-                        const float e = bs - (float)abox[(qy - ay0) * AW + (qx - ax0)];
-                        const uint32_t g = gbox[(qy - (y0 - LP)) * GW + (qx - (x0 - LP))];
-                        bxs = fmaf(0.5f * (float)unpack_x(g), e, bxs);
-                        bys = fmaf(0.5f * (float)unpack_y(g), e, bys);
+                        const float e = bs - (float)av[j][i];
+                        bxs = fmaf(0.5f * (float)gx[j][i], e, bxs);
+                        bys = fmaf(0.5f * (float)gy[j][i], e, bys);
                     }
             } else {
-                for (int j = -LP; j <= LP; j++)
-                    for (int i = -LP; i <= LP; i++) {
-                        const int qx = clampi(x + i, 0, W - 1), qy = clampi(y + j, 0, H - 1);
+#pragma unroll
+                for (int j = 0; j < WN; j++)
+#pragma unroll
+                    for (int i = 0; i < WN; i++) {
+                        const int qx = clampi(x + i - LP, 0, W - 1), qy = clampi(y + j - LP, 0, H - 1);
                         const int sx = qx + iux, sy = qy + iuy;
-                        float v00, v01, v10, v11;
-                        if (fast) {
-                            // the box holds B at clamped coordinates, indexed by the
-                            // unclamped position (which always lies inside the box;
-                            // the clamped one need not when the box starts beyond
-                            // an image edge)
-                            const int cxa = sx - bx0, cxb = cxa + 1;
-                            const int cya = sy - by0, cyb = cya + 1;
-                            v00 = bbox[cya * kRefTgtBW + cxa];
-                            v01 = bbox[cya * kRefTgtBW + cxb];
-                            v10 = bbox[cyb * kRefTgtBW + cxa];
-                            v11 = bbox[cyb * kRefTgtBW + cxb];
-                        } else {
-                            const uint8_t *ra = B + (size_t)clampi(sy, 0, H - 1) * yp;
-                            const uint8_t *rb = B + (size_t)clampi(sy + 1, 0, H - 1) * yp;
-                            const int cxa = clampi(sx, 0, W - 1), cxb = clampi(sx + 1, 0, W - 1);
-                            v00 = ra[cxa];
-                            v01 = ra[cxb];
-                            v10 = rb[cxa];
-                            v11 = rb[cxb];
-                        }
+                        const uint8_t *ra = B + (ptrdiff_t)clampi(sy, 0, H - 1) * yp;
+                        const uint8_t *rb = B + (ptrdiff_t)clampi(sy + 1, 0, H - 1) * yp;
+                        const int xa = clampi(sx, 0, W - 1), xb = clampi(sx + 1, 0, W - 1);
+                        const float v00 = ra[xa], v01 = ra[xb], v10 = rb[xa], v11 = rb[xb];
                         const float top = v00 + fx * (v01 - v00), bot = v10 + fx * (v11 - v10);
-                        const float bs = top + fy * (bot - top);
-                        const float e = bs - (float)abox[(qy - ay0) * AW + (qx - ax0)];
-                        const uint32_t g = gbox[(qy - (y0 - LP)) * GW + (qx - (x0 - LP))];
-                        bxs = fmaf(0.5f * (float)unpack_x(g), e, bxs);
-                        bys = fmaf(0.5f * (float)unpack_y(g), e, bys);
+                        const float e = top + fy * (bot - top) - (float)av[j][i];
+                        bxs = fmaf(0.5f * (float)gx[j][i], e, bxs);
+                        bys = fmaf(0.5f * (float)gy[j][i], e, bys);
                     }
             }
             const double dx = -(Hyy * (double)bxs - Hxy * (double)bys) / det;
@@ -668,11 +668,8 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
             ux = fminf(fmaxf((float)((double)ux + dx), (float)(d0x - 1)), (float)(d0x + 1));
             uy = fminf(fmaxf((float)((double)uy + dy), (float)(d0y - 1)), (float)(d0y + 1));
         }
-        if (inside) {
-            float2 *out = reinterpret_cast<float2 *>(io[s].flow[dir]);
-            out[(size_t)y * W + x] = make_float2(ux, uy);
-        }
-        __syncthreads();
+        float2 *out = reinterpret_cast<float2 *>(io[s].flow[dir]);
+        out[(size_t)y * W + x] = make_float2(ux, uy);
     }
 }
 
@@ -737,7 +734,7 @@ __device__ __forceinline__ void sample_u8(const uint8_t *img, int pitch, int H, 
 __global__ __launch_bounds__(256) void k_blend(const StripIO *__restrict__ io, const int32_t *__restrict__ prefix,
                                                int n, int total, BlendParams bp)
 {
-    TILE_LOOP(total, 0)
+    TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         const int local = t - prefix[s];
@@ -776,6 +773,18 @@ hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, 
     return hipGetLastError();
 }
 
+hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_sums, dim3(ceil_div(2 * n, 256)), dim3(256), 0, s, io, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gain(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gain, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n, w.total);
+    return hipGetLastError();
+}
+
 hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pyr, dim3(grid_for(w.total, grid)), dim3(256), 0, s, lv, w.prefix, w.n, w.total);
@@ -787,6 +796,7 @@ static hipError_t search_th(const StripLv *lv, Work w, int th, int grid, hipStre
 {
     const int g = grid_for(w.total, grid);
     switch (th) {
+    case 1: hipLaunchKernelGGL((k_search<P, R, 1>), dim3(g), dim3(64), 0, s, lv, w.prefix, w.n, w.total); break;
     case 2: hipLaunchKernelGGL((k_search<P, R, 2>), dim3(g), dim3(128), 0, s, lv, w.prefix, w.n, w.total); break;
     case 8: hipLaunchKernelGGL((k_search<P, R, 8>), dim3(g), dim3(512), 0, s, lv, w.prefix, w.n, w.total); break;
     default: hipLaunchKernelGGL((k_search<P, R, 4>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total); break;

@@ -120,7 +120,7 @@ void default_launch(abf_plan *pl)
 bool valid_th(int stage, int th)
 {
     switch (stage) {
-    case ST_SEARCH: return th == 2 || th == 4 || th == 8;
+    case ST_SEARCH: return th == 1 || th == 2 || th == 4 || th == 8;
     case ST_PROP: return th == 4 || th == 8;
     case ST_REFINE: return th == 2 || th == 4;
     default: return th == 4;
@@ -137,28 +137,19 @@ abf_status check_params(const abf_params *p)
         !std::isfinite(p->k_flowmag))
         return ABF_E_INVALID;
     if (p->blend_mode != 0 && p->blend_mode != 1) return ABF_E_INVALID;
+    if (p->gain_comp != 0 && p->gain_comp != 1) return ABF_E_INVALID;
     if (p->patch > 2 || p->radius > 4 || p->radius_coarse > 4 || p->prop_steps > 4 || p->median > 1 ||
         p->prop_steps + p->median > 5 || p->lk_patch > 3 || p->lk_iters > 8)
         return ABF_E_UNSUPPORTED;
     return ABF_OK;
 }
 
-inline int ypitch_of(int w) { return (int)align_up((size_t)w, 64); }
+// Padded luma planes: kPad replicated pixels on every side, 64-byte
+// aligned rows, plus 64 bytes of slack before and after (the aligned
+// row loads may read a few bytes past the last padded row).
+inline int ypitch_of(int w) { return (int)align_up((size_t)w + 2 * kPad, 64); }
+inline size_t plane_bytes(int H, int W) { return align_up(64 + (size_t)ypitch_of(W) * (H + 2 * kPad) + 64, kAlign); }
 inline int fpitch_of(int w) { return (int)align_up((size_t)w, 16); }
-
-// Data bytes of one strip (pyramids of both images, raw and final integer
-// flows of both directions at every level).
-size_t strip_bytes(int H, int W, int N)
-{
-    size_t b = 0;
-    for (int k = 0; k < N; k++) {
-        b += 2 * align_up((size_t)ypitch_of(W) * H, kAlign);
-        b += 4 * align_up((size_t)fpitch_of(W) * 4 * H, kAlign);
-        H = (H + 1) / 2;
-        W = (W + 1) / 2;
-    }
-    return b;
-}
 
 size_t header_bytes(int n, int N)
 {
@@ -172,14 +163,18 @@ size_t header_bytes(int n, int N)
 size_t data_bound(const abf_plan *pl)
 {
     const int N = pl->p.levels;
-    // per level: y <= (W/2^k + 64)(H/2^k + 1) + 256, flows <= (4W/2^k + 64)(H/2^k + 1) + 256
+    // per level and strip: a padded plane <= (w + 2 kPad + 64)(h + 2 kPad)
+    // + 384 with w <= W/2^k + 1, h <= H/2^k + 1; a flow buffer <= (4 w + 64)
+    // h + 256. Summed over strips with sum(H W) <= max_pixels.
     double b = 0;
     const double mp = (double)pl->max_pixels, S = pl->max_strips, Hm = pl->max_H, Wm = pl->max_W;
+    const double pd = 2 * kPad + 1;
     for (int k = 0; k < N; k++) {
         const double f = std::ldexp(1.0, -k);
-        b += 2 * (mp * f * f + S * (Wm * f + 64 * Hm * f + 64 + 256));
-        b += 4 * (4 * mp * f * f + S * (4 * Wm * f + 64 * Hm * f + 64 + 256));
+        b += 2 * (mp * f * f + S * ((Wm * f) * pd + (64 + pd) * (Hm * f + pd) + 384));
+        b += 4 * (4 * mp * f * f + S * (4 * Wm * f + 64 * Hm * f + 68 + 256));
     }
+    b += S * kAlign;  // exposure sums
     return align_up((size_t)b + 4096, kAlign);
 }
 
@@ -283,6 +278,8 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
         io.W = x.W;
         io.axis = x.axis;
         if (!flows) continue;
+        io.sums = reinterpret_cast<unsigned long long *>(pl->ws + off);
+        off += kAlign;
         for (int k = 0; k < N; k++) {
             StripLv &v = b.lv[(size_t)k * n + s];
             v.H = L.hk[s][k];
@@ -290,8 +287,8 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
             v.ypitch = ypitch_of(v.W);
             v.fpitch = fpitch_of(v.W);
             for (int d = 0; d < 2; d++) {
-                v.y[d] = pl->ws + off;
-                off += align_up((size_t)v.ypitch * v.H, kAlign);
+                v.y[d] = pl->ws + off + 64 + (size_t)v.ypitch * kPad + kPad;
+                off += plane_bytes(v.H, v.W);
             }
             for (int d = 0; d < 2; d++) {
                 v.ds[d] = reinterpret_cast<uint32_t *>(pl->ws + off);
@@ -408,7 +405,10 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
         HIP_TRY(pl, mark(stg, k));       \
     } while (0)
     if (flows) {
+        HIP_TRY(pl, launch_zero_sums(io, n, s));
         TIMED(ST_LUMA, 0, launch_luma(io, lv, work(ST_LUMA, 0), grid_of(pl, ST_LUMA, b.cls[0]), s));
+        if (p.gain_comp)
+            TIMED(ST_LUMA, 1, launch_gain(io, lv, work(ST_LUMA, 0), grid_of(pl, ST_LUMA, b.cls[0]), s));
         for (int k = 1; k < N; k++)
             TIMED(ST_PYR, k, launch_pyr(lv + (size_t)k * n, work(ST_PYR, k), grid_of(pl, ST_PYR, b.cls[k]), s));
         for (int k = N - 1; k >= 0; k--) {
@@ -520,6 +520,7 @@ void abf_default_params(abf_params *p)
     p->k_sharp = 10.0f;
     p->k_flowmag = 20.0f;
     p->blend_mode = 0;
+    p->gain_comp = 1;
 }
 
 const char *abf_status_string(abf_status s)

@@ -41,6 +41,7 @@ def test_default_params(lib):
     p = _abi.default_params()
     assert (p.levels, p.patch, p.radius, p.radius_coarse, p.prop_steps, p.median) == (6, 2, 2, 4, 2, 1)
     assert (p.lk_patch, p.lk_iters, p.lk_eps, p.k_sharp, p.k_flowmag, p.blend_mode) == (2, 2, 25.0, 10.0, 20.0, 0)
+    assert p.gain_comp == 1
 
 
 def test_defaults_match_oracle_and_api():
@@ -49,13 +50,14 @@ def test_defaults_match_oracle_and_api():
 
     o, a = oracle.Params(), api.Params()
     for f in ("levels", "patch", "radius", "radius_coarse", "prop_steps", "median", "lk_patch", "lk_iters",
-              "lk_eps", "k_sharp", "k_flowmag", "blend_mode"):
+              "lk_eps", "k_sharp", "k_flowmag", "blend_mode", "gain_comp"):
         assert getattr(o, f) == getattr(a, f), f
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("levels", 0, _abi.E_INVALID), ("levels", 13, _abi.E_INVALID), ("patch", 0, _abi.E_INVALID),
     ("lk_eps", 0.0, _abi.E_INVALID), ("lk_eps", float("nan"), _abi.E_INVALID), ("blend_mode", 2, _abi.E_INVALID),
+    ("gain_comp", 2, _abi.E_INVALID),
     ("patch", 3, _abi.E_UNSUPPORTED), ("radius", 5, _abi.E_UNSUPPORTED), ("median", 2, _abi.E_UNSUPPORTED),
 ])
 def test_create_plan_rejects_parameters(lib, field, value, status):
@@ -96,4 +98,4 @@ def test_strip_struct_layout():
     S = _abi.AbfStrip
     assert S.H.offset == 16 and S.pitch_L.offset == 24 and S.blend.offset == 40
     assert S.F_f32.offset == 80 and ctypes.sizeof(S) == 88
-    assert ctypes.sizeof(_abi.AbfParams) == 48
+    assert ctypes.sizeof(_abi.AbfParams) == 52

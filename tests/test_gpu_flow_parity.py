@@ -91,8 +91,11 @@ def test_flow_parity(api, name):
     L, R, axis, p, g_lr, g_rl, views = run_case(api, name)
     op = o_params(p)
     o_lr, o_rl, lv = oracle.flow_bidirectional(L, R, op, levels_out=True)
-    pyrL = oracle.pyramid(oracle.luma(L), p.levels)
-    pyrR = oracle.pyramid(oracle.luma(R), p.levels)
+    yl, yr = oracle.luma(L), oracle.luma(R)
+    if p.gain_comp:
+        yr = oracle.gain_comp(yl, yr)
+    pyrL = oracle.pyramid(yl, p.levels)
+    pyrR = oracle.pyramid(yr, p.levels)
     for k in range(p.levels):
         assert np.array_equal(views[(0, k, 0)], pyrL[k]), f"luma pyramid L level {k}"
         assert np.array_equal(views[(0, k, 1)], pyrR[k]), f"luma pyramid R level {k}"

@@ -196,7 +196,8 @@ def _shifted_pair(seed, H, W, sx, sy, pad=24):
 def test_integer_shift_is_recovered_exactly(orc, s):
     H, W = 96, 128
     L, R = _shifted_pair(11, H, W, *s)
-    p = orc.Params(levels=3)
+    # the exposure step would rescale R (its border content differs from L's)
+    p = orc.Params(levels=3, gain_comp=0)
     flr, frl, lv = orc.flow_bidirectional(L, R, p, levels_out=True)
     m = max(abs(s[0]), abs(s[1])) + p.patch + p.prop_steps + p.median + 2
     inner = (slice(m, H - m), slice(m, W - m))
@@ -299,3 +300,42 @@ def test_refine_subpixel_sinusoid(orc):
     u = orc.refine(A, B, np.zeros((H, W, 2), np.int32), orc.Params())
     inner = (slice(6, H - 6), slice(6, W - 6))
     assert np.median(np.abs(u[inner][..., 0] - s)) < 0.05
+
+
+# ------------------------------------------------- exposure compensation
+def test_gain_comp_unit_gain_is_identity(orc):
+    y = synth.random_bytes(20, (31, 47))
+    assert np.array_equal(orc.gain_comp(y, y), y)
+
+
+def test_gain_comp_recovers_exact_gain(orc):
+    # R = L scaled by a known gain (mid-range values, no clipping): the
+    # compensated R is L up to the two roundings (within 1 gray level)
+    r = synth.rng_for(121, 0, 0)
+    yl = r.integers(60, 180, size=(40, 50)).astype(np.uint8)
+    for g in (0.9, 0.93, 1.07, 1.1):
+        yr = np.clip(np.rint(yl * g), 0, 255).astype(np.uint8)
+        out = orc.gain_comp(yl, yr)
+        assert np.abs(out.astype(int) - yl.astype(int)).max() <= 1
+
+
+def test_gain_comp_fixed_point_formula(orc):
+    yl = np.array([[10, 20, 30, 255]], np.uint8)
+    yr = np.array([[5, 10, 15, 200]], np.uint8)
+    a = (int(yl.sum()) << 16) // int(yr.sum())
+    expect = np.minimum(255, (yr.astype(np.int64) * a + (1 << 15)) >> 16)
+    assert np.array_equal(orc.gain_comp(yl, yr), expect.astype(np.uint8))
+    z = np.zeros((2, 3), np.uint8)
+    assert np.array_equal(orc.gain_comp(yl[:, :3].repeat(2, 0), z), z)
+
+
+def test_gain_compensated_flow_is_accurate_under_exposure_gain(orc):
+    st = synth.make_random(21, 96, 160, max_ux=6, max_uy=2)
+    R = np.clip(np.rint(st.R.astype(float) * 0.9), 0, 255).astype(np.uint8)
+    m = 12
+    sl = (slice(m, -m), slice(m, -m))
+    for gain, bound in ((1, 0.5), (0, None)):
+        _, frl = orc.flow_bidirectional(st.L, R, orc.Params(levels=3, gain_comp=gain))
+        e = np.hypot(*(frl - st.flow_rl_gt).transpose(2, 0, 1))[sl][st.valid_rl[sl]]
+        if bound is not None:
+            assert np.median(e) < bound
