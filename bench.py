@@ -42,10 +42,22 @@ def level_sizes(H, W, N):
     return out
 
 
+def kernel_name(stage, level, p):
+    if stage == 0:
+        return "k_luma level 0" if level == 0 else "k_gain level 0"
+    if stage == 3:
+        return f"k_prop_step x{p.prop_steps} + k_median level {level}"
+    return f"{KERNELS[stage]} level {level}"
+
+
 def algorithmic(stage, level, shapes, p):
-    """(bound, amount per launch, unit, peak) of one launch."""
+    """(bound, amount per launch, unit, peak) of one launch (of the
+    launches of a stage and level, for the propagation)."""
     px = sum(lh * lw for (H, W, _) in shapes for (lh, lw) in [level_sizes(H, W, p.levels)[level]])
     win = (2 * p.patch + 1) ** 2
+    if stage == 0 and level == 1:  # exposure step: R's level-0 plane read and written
+        px0 = sum(H * W for (H, W, _) in shapes)
+        return "hbm", px0 * 2.0, "GB/s", HBM_PEAK_GBS
     if stage == 0:  # RGB of L and R in, two luma planes out
         return "hbm", px * 8.0, "GB/s", HBM_PEAK_GBS
     if stage == 1:  # two finer planes in (4 px per output), two planes out
@@ -77,6 +89,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the workload, copy a MIB-mebibyte device buffer once (a kernel of known "
+                         "traffic, for scaling hardware byte counters)")
+    ap.add_argument("--refine", action="store_true",
+                    help="also time 50 gradient-descent refinement steps on the 2048 x 512 float strip")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -93,6 +110,14 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = src.clone()
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration} MiB done")
+        del src, dst
 
     cfg = 2
     shapes = synth.strip_shapes(cfg, args.pano)
@@ -164,14 +189,30 @@ def main():
     achieved = rate(amount, dom_ms, unit)
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": f"{KERNELS[dom_st]} level {dom_k}", "launch_ms": round(dom_ms, 4),
+                "kernel": kernel_name(dom_st, dom_k, p), "launch_ms": round(dom_ms, 4),
                 "work_per_launch": amount}
     per_launch = []
     for ms, st, k in sorted(launches, reverse=True)[:8]:
         b, a, u, pk = algorithmic(st, k, shapes, p)
-        per_launch.append({"kernel": f"{KERNELS[st]} level {k}", "ms": round(ms, 4), "bound": b,
+        per_launch.append({"kernel": kernel_name(st, k, p), "ms": round(ms, 4), "bound": b,
                            "achieved": round(rate(a, ms, u), 3), "unit": u, "frac": round(rate(a, ms, u) / pk, 4)})
     log(f"dominant launch {roofline['kernel']}: {dom_ms:.4f} ms, {achieved:.2f} {unit} of {peak:.1f}")
+
+    refine = None
+    if args.refine:
+        st3 = synth.make_config_strip(3, 0, 0)
+        H3, W3 = st3.H, st3.W
+        plan3 = api.Plan(p, max_strips=1, max_H=H3, max_W=W3)
+        ref3 = torch.from_numpy(st3.R).cuda()
+        tgt3 = torch.from_numpy(st3.L).cuda()
+        u0 = torch.from_numpy(np.rint(st3.flow_rl_gt)).float().cuda()
+        u = u0.clone()
+        plan3.refine_flow(ref3, tgt3, u, steps=5)
+        ms_r, _ = timed(lambda: (u.copy_(u0), plan3.refine_flow(ref3, tgt3, u, steps=50)), 3)
+        refine = {"workload": "2048 x 512 float RGB strip, 50 gradient-descent steps (energy gradient + step, "
+                              "fused per step)", "ms": round(ms_r, 4),
+                  "mpix_steps_s": round(H3 * W3 * 50 / ms_r / 1e3, 1)}
+        log(f"refine 50 steps: {ms_r:.3f} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -218,6 +259,7 @@ def main():
         "stage_ms": stage_ms,
         "top_launches": per_launch,
         "roofline": roofline,
+        "refine_flow": refine,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

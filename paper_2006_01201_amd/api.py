@@ -194,6 +194,57 @@ class Plan:
     def set_launch(self, stage: int, size_class: int, tile_h: int, grid: int):
         _abi.check(_abi.set_launch(self.h, stage, size_class, tile_h, grid), self.h, "abf_set_launch")
 
+    # -- differentiable path (float images) ------------------------------
+    def energy(self, ref, tgt, u, lam: float = 0.05, eps: float = 1e-3, grads: bool = True,
+               deterministic: bool = False):
+        """Photometric Charbonnier + lam * TV energy of flow ``u`` (float32
+        H x W x 2) between float32 RGB images (H x W x 3). Returns E (a
+        1-element tensor) and, if ``grads``, dE/du, dE/dref, dE/dtgt."""
+        H, W = u.shape[0], u.shape[1]
+        E = torch.empty(1, dtype=torch.float32, device=u.device)
+        gu = torch.empty_like(u) if grads else None
+        gr = torch.empty_like(ref) if grads else None
+        gt = torch.empty_like(tgt) if grads else None
+        st = _abi.energy(self.h, _f32(ref, (H, W, 3), "ref"), _f32(tgt, (H, W, 3), "tgt"), _f32(u, (H, W, 2), "u"),
+                         H, W, lam, eps, E.data_ptr(), gu.data_ptr() if grads else None,
+                         gr.data_ptr() if grads else None, gt.data_ptr() if grads else None, int(deterministic),
+                         _stream())
+        _abi.check(st, self.h, "abf_energy")
+        return (E, gu, gr, gt) if grads else E
+
+    def refine_flow(self, ref, tgt, u, steps: int = 50, eta: float = 0.5, lam: float = 0.05, eps: float = 1e-3,
+                    clip: float = 0.25):
+        """``steps`` gradient-descent steps on the energy, in place on ``u``."""
+        H, W = u.shape[0], u.shape[1]
+        st = _abi.refine_flow(self.h, _f32(ref, (H, W, 3), "ref"), _f32(tgt, (H, W, 3), "tgt"),
+                              _f32(u, (H, W, 2), "u"), H, W, steps, eta, lam, eps, clip, _stream())
+        _abi.check(st, self.h, "abf_refine_flow")
+        return u
+
+    def blend_f32(self, L, R, flow_lr, flow_rl, blend=None, axis: int = 0):
+        """Code 1 over float32 RGB images; returns F (float32 H x W x 3)."""
+        H, W = L.shape[0], L.shape[1]
+        F = torch.empty((H, W, 3), dtype=torch.float32, device=L.device)
+        st = _abi.blend_asymmetric_f32(self.h, _f32(L, (H, W, 3), "L"), _f32(R, (H, W, 3), "R"),
+                                       _f32(flow_lr, (H, W, 2), "flow_LtoR"), _f32(flow_rl, (H, W, 2), "flow_RtoL"),
+                                       _f32(blend, (H, W), "blend") if blend is not None else None, axis, H, W,
+                                       F.data_ptr(), _stream())
+        _abi.check(st, self.h, "abf_blend_asymmetric_f32")
+        return F
+
+    def blend_backward(self, L, R, flow_lr, flow_rl, g_F, blend=None, axis: int = 0):
+        """Adjoint of Code 1: (dF/dflow_LtoR, dF/dflow_RtoL, dF/dL, dF/dR)
+        contracted with g_F."""
+        H, W = L.shape[0], L.shape[1]
+        out = [torch.empty((H, W, 2), dtype=torch.float32, device=L.device) for _ in range(2)]
+        out += [torch.empty((H, W, 3), dtype=torch.float32, device=L.device) for _ in range(2)]
+        st = _abi.blend_backward(self.h, _f32(L, (H, W, 3), "L"), _f32(R, (H, W, 3), "R"),
+                                 _f32(flow_lr, (H, W, 2), "flow_LtoR"), _f32(flow_rl, (H, W, 2), "flow_RtoL"),
+                                 _f32(blend, (H, W), "blend") if blend is not None else None, axis, H, W,
+                                 _f32(g_F, (H, W, 3), "g_F"), *[o.data_ptr() for o in out], _stream())
+        _abi.check(st, self.h, "abf_blend_backward")
+        return tuple(out)
+
     # -- inspection ------------------------------------------------------
     def view(self, kind: int, strip: int, level: int, direction: int) -> torch.Tensor:
         """A copy of one intermediate of the last flow call: kind 0 luma

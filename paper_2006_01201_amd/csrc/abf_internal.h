@@ -23,6 +23,9 @@ enum Stage { ST_LUMA = 0, ST_PYR = 1, ST_SEARCH = 2, ST_PROP = 3, ST_REFINE = 4,
 struct StripLv {
     uint8_t *y[2];          // luma of L and R at this level (pitch ypitch bytes)
     uint32_t *ds[2];        // raw search result per direction (pitch fpitch)
+    uint16_t *cs[2];        // its patch cost
+    uint32_t *dt[2][2];     // propagation iterates (ping-pong) per direction
+    uint16_t *ct[2][2];     // their patch costs
     uint32_t *df[2];        // final flow of the level per direction
     const uint32_t *dc[2];  // final flow of the next coarser level (null at the coarsest)
     const uint8_t *yfine[2];// luma of the next finer level (pyramid input; null at level 0)
@@ -70,11 +73,11 @@ struct BlendParams {
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // search tiles: 128 x TH pixels (64 threads per row, two pixels each);
-// refine: 64 x TH; propagation: 32 x TH; luma, exposure step and blend:
+// refine and propagation: 64 x TH; luma, exposure step and blend:
 // 256 pixels of one row; pyramid: 64 x 4 output pixels. Luma, exposure
 // and pyramid tiles cover the padded planes.
 constexpr int kSearchTW = 128;
-constexpr int kPropTW = 32;
+constexpr int kPropTW = 64;
 constexpr int kRefineTW = 64;
 constexpr int kRowTW = 256;
 constexpr int kPyrTW = 64;
@@ -89,7 +92,8 @@ hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s);
 hipError_t launch_gain(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s);
 hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s);
 hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int th, int grid, hipStream_t s);
-hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid,
+// one Jacobi propagation step (step = 1..T) or the median (step = 0)
+hipError_t launch_prop(const StripLv *lv, Work w, int patch, int step, int steps, int median, int th, int grid,
                        hipStream_t s);
 hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid,
                          hipStream_t s);
@@ -112,14 +116,38 @@ hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *fl
                                  unsigned long long *fixR, hipStream_t s);
 
 // tiles of one strip for a stage (both directions where the stage has two)
-__host__ __device__ inline int tiles_luma(int H, int W) { return (H + 2 * kPad) * ceil_div(W + 2 * kPad, kRowTW); }
+// luma and exposure: 4 pixels per thread over the padded rows
+constexpr int kLumaTW = 4 * kRowTW;
+__host__ __device__ inline int tiles_luma(int H, int W) { return (H + 2 * kPad) * ceil_div(W + 2 * kPad, kLumaTW); }
 __host__ __device__ inline int tiles_pyr(int H, int W)
 {
     return ceil_div(H + 2 * kPad, kPyrTH) * ceil_div(W + 2 * kPad, kPyrTW);
 }
 __host__ __device__ inline int tiles_search(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kSearchTW); }
 __host__ __device__ inline int tiles_prop(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kPropTW); }
-__host__ __device__ inline int tiles_refine(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kRefineTW); }
+// refine: interior tiles (window inside the image) then border tiles of
+// 64 th pixels enumerated along the border band, per direction
+struct RefineSplit {
+    int ylo, yhi, xlo, xhi;  // interior rows [ylo, yhi), columns [xlo, xhi)
+    int nint, nbord, nbp;    // interior tiles, border tiles, border pixels
+};
+__host__ __device__ inline RefineSplit refine_split(int H, int W, int th, int lp)
+{
+    RefineSplit r;
+    r.ylo = H < lp ? H : lp;
+    r.yhi = H - lp > r.ylo ? H - lp : r.ylo;
+    r.xlo = W < lp ? W : lp;
+    r.xhi = W - lp > r.xlo ? W - lp : r.xlo;
+    r.nint = ceil_div(r.yhi - r.ylo, th) * ceil_div(r.xhi - r.xlo, kRefineTW);
+    r.nbp = H * W - (r.yhi - r.ylo) * (r.xhi - r.xlo);
+    r.nbord = ceil_div(r.nbp, kRefineTW * th);
+    return r;
+}
+__host__ __device__ inline int tiles_refine(int H, int W, int th, int lp)
+{
+    const RefineSplit r = refine_split(H, W, th, lp);
+    return 2 * (r.nint + r.nbord);
+}
 __host__ __device__ inline int tiles_blend(int H, int W) { return H * ceil_div(W, kRowTW); }
 
 }  // namespace abf

@@ -150,6 +150,8 @@ __global__ __launch_bounds__(256) void k_zero_sums(const StripIO *__restrict__ i
     if (i < 2 * n) io[i >> 1].sums[i & 1] = 0ull;
 }
 
+__device__ __forceinline__ int luma_of(uint32_t r, uint32_t g, uint32_t b) { return (77 * r + 150 * g + 29 * b + 128) >> 8; }
+
 __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
                                               const int32_t *__restrict__ prefix, int n, int total)
 {
@@ -159,23 +161,49 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
         const int s = find_strip(prefix, n, t);
         const int local = t - prefix[s];
         const int W = lv[s].W, H = lv[s].H;
-        const int segs = ceil_div(W + 2 * kPad, kRowTW);
+        const int segs = ceil_div(W + 2 * kPad, kLumaTW);
         const int py = local / segs;
-        const int px = (local - py * segs) * kRowTW + (int)threadIdx.x;
+        const int px = (local - py * segs) * kLumaTW + 4 * (int)threadIdx.x;  // first of 4 padded columns
         const int y = py - kPad, x = px - kPad;
+        const int cy = clampi(y, 0, H - 1);
         unsigned long long sl = 0, sr = 0;
         if (px < W + 2 * kPad) {
-            const int cx = clampi(x, 0, W - 1), cy = clampi(y, 0, H - 1);
-            const uint8_t *pl = io[s].L + (size_t)cy * io[s].pitchL + 3 * cx;
-            const uint8_t *pr = io[s].R + (size_t)cy * io[s].pitchR + 3 * cx;
-            const int yl = (77 * pl[0] + 150 * pl[1] + 29 * pl[2] + 128) >> 8;
-            const int yr = (77 * pr[0] + 150 * pr[1] + 29 * pr[2] + 128) >> 8;
-            const ptrdiff_t o = (ptrdiff_t)y * lv[s].ypitch + x;
-            lv[s].y[0][o] = (uint8_t)yl;
-            lv[s].y[1][o] = (uint8_t)yr;
-            if (x == cx && y == cy) {
-                sl = (unsigned long long)yl;
-                sr = (unsigned long long)yr;
+            const uint8_t *rl = io[s].L + (size_t)cy * io[s].pitchL;
+            const uint8_t *rr = io[s].R + (size_t)cy * io[s].pitchR;
+            int yl[4], yr[4];
+            // four image pixels from 12-byte aligned runs when possible
+            if (x >= 0 && x + 3 <= W - 1 && ((reinterpret_cast<uintptr_t>(rl + 3 * x) | reinterpret_cast<uintptr_t>(rr + 3 * x)) & 3) == 0) {
+                const uint32_t *ql = reinterpret_cast<const uint32_t *>(rl + 3 * x);
+                const uint32_t *qr = reinterpret_cast<const uint32_t *>(rr + 3 * x);
+                const uint32_t a0 = ql[0], a1 = ql[1], a2 = ql[2], b0 = qr[0], b1 = qr[1], b2 = qr[2];
+                yl[0] = luma_of(a0 & 0xff, (a0 >> 8) & 0xff, (a0 >> 16) & 0xff);
+                yl[1] = luma_of(a0 >> 24, a1 & 0xff, (a1 >> 8) & 0xff);
+                yl[2] = luma_of((a1 >> 16) & 0xff, a1 >> 24, a2 & 0xff);
+                yl[3] = luma_of((a2 >> 8) & 0xff, (a2 >> 16) & 0xff, a2 >> 24);
+                yr[0] = luma_of(b0 & 0xff, (b0 >> 8) & 0xff, (b0 >> 16) & 0xff);
+                yr[1] = luma_of(b0 >> 24, b1 & 0xff, (b1 >> 8) & 0xff);
+                yr[2] = luma_of((b1 >> 16) & 0xff, b1 >> 24, b2 & 0xff);
+                yr[3] = luma_of((b2 >> 8) & 0xff, (b2 >> 16) & 0xff, b2 >> 24);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int cx = clampi(x + k, 0, W - 1);
+                    yl[k] = luma_of(rl[3 * cx], rl[3 * cx + 1], rl[3 * cx + 2]);
+                    yr[k] = luma_of(rr[3 * cx], rr[3 * cx + 1], rr[3 * cx + 2]);
+                }
+            }
+            const ptrdiff_t o = (ptrdiff_t)y * lv[s].ypitch + x;  // 4-byte aligned (padded rows are)
+            *reinterpret_cast<uint32_t *>(lv[s].y[0] + o) =
+                (uint32_t)yl[0] | ((uint32_t)yl[1] << 8) | ((uint32_t)yl[2] << 16) | ((uint32_t)yl[3] << 24);
+            *reinterpret_cast<uint32_t *>(lv[s].y[1] + o) =
+                (uint32_t)yr[0] | ((uint32_t)yr[1] << 8) | ((uint32_t)yr[2] << 16) | ((uint32_t)yr[3] << 24);
+            if (y == cy) {
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    if (x + k >= 0 && x + k < W) {
+                        sl += (unsigned long long)yl[k];
+                        sr += (unsigned long long)yr[k];
+                    }
             }
         }
         // workgroup sum, one atomic per image
@@ -210,15 +238,21 @@ __global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, co
         const int s = find_strip(prefix, n, t);
         const int local = t - prefix[s];
         const int W = lv[s].W;
-        const int segs = ceil_div(W + 2 * kPad, kRowTW);
+        const int segs = ceil_div(W + 2 * kPad, kLumaTW);
         const int py = local / segs;
-        const int px = (local - py * segs) * kRowTW + (int)threadIdx.x;
+        const int px = (local - py * segs) * kLumaTW + 4 * (int)threadIdx.x;
         const unsigned long long sl = io[s].sums[0], sr = io[s].sums[1];
         if (sr == 0 || px >= W + 2 * kPad) continue;
         const unsigned long long a = (sl << 16) / sr;
-        uint8_t *p = lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch + (px - kPad);
-        const unsigned long long v = ((unsigned long long)*p * a + (1ull << 15)) >> 16;
-        *p = (uint8_t)(v > 255ull ? 255ull : v);
+        uint32_t *p = reinterpret_cast<uint32_t *>(lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch + (px - kPad));
+        const uint32_t v = *p;
+        uint32_t o = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const unsigned long long g = ((unsigned long long)((v >> (8 * k)) & 0xffu) * a + (1ull << 15)) >> 16;
+            o |= (uint32_t)(g > 255ull ? 255ull : g) << (8 * k);
+        }
+        *p = o;
     }
 }
 
@@ -362,31 +396,35 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                 }
         }
         uint32_t *out = L.ds[dir] + (size_t)y * L.fpitch + x;
+        uint16_t *cst = L.cs[dir] + (size_t)y * L.fpitch + x;
         {
             const int idx = (int)(best0 & 127u), j = idx / NC, i = idx - j * NC;
             out[0] = pack16(cx + i - R, cy + j - R);
+            cst[0] = (uint16_t)(best0 >> 11);
         }
         if (x + 1 < W) {
             const int idx = (int)(best1 & 127u), j = idx / NC, i = idx - j * NC;
             out[1] = pack16(cx + i - R, cy + j - R);
+            cst[1] = (uint16_t)(best1 >> 11);
         }
     }
 }
 
 // ----------------------------------------------------------- propagation
-// T Jacobi steps (candidates self, left, right, up, down of the previous
-// iterate; lower cost wins, earlier candidate on ties; neighbours outside
-// the image skipped) and a (2M+1)^2 component-wise median with clamped
-// indices, fused per 32 x TH tile by recomputing a halo of T + M pixels.
-// The flows live in LDS; patches are read from the padded luma planes.
-constexpr int kHaloMax = 5;
-
+// One Jacobi step per launch: each pixel keeps the lowest-cost vector among
+// its own and those of its left, right, upper and lower neighbours in the
+// previous iterate (neighbours outside the image skipped; on equal cost
+// the earlier candidate in that order wins). The cost of a pixel's own
+// vector is carried from the search / previous step, and a neighbour whose
+// vector equals an earlier candidate's is skipped (same cost, loses the
+// tie), so a pixel in a region of uniform flow evaluates no patch at all.
+// A separate launch applies the (2M+1)^2 component-wise median.
 __device__ __forceinline__ int med3i(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
 
 template <int P>
 __device__ __forceinline__ uint32_t patch_cost(const uint32_t (&rr)[2 * P + 1][(2 * P + 4) / 4],
-                                               const uint8_t *__restrict__ tgt,
-                                               int H, int W, int yp, int px, int py, int dx, int dy)
+                                               const uint8_t *__restrict__ tgt, int H, int W, int yp, int px, int py,
+                                               int dx, int dy)
 {
     constexpr int NB = 2 * P + 1;
     const int c0 = px + dx - P, r0 = py + dy - P;
@@ -407,138 +445,143 @@ __device__ __forceinline__ uint32_t patch_cost(const uint32_t (&rr)[2 * P + 1][(
     return s;
 }
 
-template <int P, int TH>
-__global__ __launch_bounds__(256) void k_prop(const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix,
-                                              int n, int total, int T, int M)
+// buffers of propagation step `step` (1-based) of T: input, output
+__device__ __forceinline__ void prop_bufs(const StripLv &L, int dir, int step, int T, int M, const uint32_t *&din,
+                                          const uint16_t *&cin, uint32_t *&dout, uint16_t *&cout)
 {
-    constexpr int NT = 256;
-    constexpr int TW = kPropTW;
-    constexpr int DW = TW + 2 * kHaloMax, DH = TH + 2 * kHaloMax;
-    __shared__ uint32_t dbuf[2][DH * DW];
+    din = step == 1 ? L.ds[dir] : L.dt[dir][(step - 2) & 1];
+    cin = step == 1 ? L.cs[dir] : L.ct[dir][(step - 2) & 1];
+    dout = (step == T && M == 0) ? L.df[dir] : L.dt[dir][(step - 1) & 1];
+    cout = L.ct[dir][(step - 1) & 1];
+}
 
-    const int h = T + M;
+template <int P, int TH>
+__global__ __launch_bounds__(64 * TH) void k_prop_step(const StripLv *__restrict__ lv,
+                                                       const int32_t *__restrict__ prefix, int n, int total, int step,
+                                                       int T, int M)
+{
+    const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         int local = t - prefix[s];
         const StripLv &L = lv[s];
-        const int H = L.H, W = L.W, yp = L.ypitch;
-        const int ntx = ceil_div(W, TW), per_dir = ntx * ceil_div(H, TH);
+        const int H = L.H, W = L.W, yp = L.ypitch, fp = L.fpitch;
+        const int ntx = ceil_div(W, kPropTW), per_dir = ntx * ceil_div(H, TH);
         const int dir = local / per_dir;
         local -= dir * per_dir;
         const int tyi = local / ntx;
-        const int x0 = (local - tyi * ntx) * TW, y0 = tyi * TH;
-        const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
-        const uint32_t *dsrc = L.ds[dir];
-        // frame of the D buffers: (x0 - kHaloMax, y0 - kHaloMax)
-        const int fx0 = x0 - kHaloMax, fy0 = y0 - kHaloMax;
-        for (int e = threadIdx.x; e < DH * DW; e += NT) {
-            const int ry = e / DW, rx = e - ry * DW;
-            const int gx = fx0 + rx, gy = fy0 + ry;
-            uint32_t v = 0;
-            if (gx >= 0 && gx < W && gy >= 0 && gy < H && gx >= x0 - h && gx < x0 + TW + h && gy >= y0 - h &&
-                gy < y0 + TH + h)
-                v = dsrc[(size_t)gy * L.fpitch + gx];
-            dbuf[0][e] = v;
+        const int x = (local - tyi * ntx) * kPropTW + lane, y = tyi * TH + wrow;
+        if (x >= W || y >= H) continue;  // no barrier in this kernel
+        const uint32_t *din;
+        const uint16_t *cin;
+        uint32_t *dout;
+        uint16_t *cout;
+        prop_bufs(L, dir, step, T, M, din, cin, dout, cout);
+        const size_t p = (size_t)y * fp + x;
+        uint32_t cand[5];
+        bool ok[5];
+        cand[0] = din[p];
+        ok[0] = true;
+        cand[1] = x > 0 ? din[p - 1] : 0u;
+        ok[1] = x > 0;
+        cand[2] = x < W - 1 ? din[p + 1] : 0u;
+        ok[2] = x < W - 1;
+        cand[3] = y > 0 ? din[p - fp] : 0u;
+        ok[3] = y > 0;
+        cand[4] = y < H - 1 ? din[p + fp] : 0u;
+        ok[4] = y < H - 1;
+        bool need[5];
+        bool any = false;
+#pragma unroll
+        for (int k = 1; k < 5; k++) {
+            bool dup = !ok[k];
+#pragma unroll
+            for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
+            need[k] = !dup;
+            any |= need[k];
         }
-        __syncthreads();
-        int cur = 0;
-        for (int step = 1; step <= T; step++) {
-            const int gg = h - step;  // region of this step: tile +- gg
-            const int rw = TW + 2 * gg, rh = TH + 2 * gg;
-            const uint32_t *prev = dbuf[cur];
-            uint32_t *next = dbuf[cur ^ 1];
-            for (int e = threadIdx.x; e < rw * rh; e += NT) {
-                const int ly = e / rw, lx = e - ly * rw;
-                const int px = x0 - gg + lx, py = y0 - gg + ly;
-                const int fi = (py - fy0) * DW + (px - fx0);
-                if (px < 0 || px >= W || py < 0 || py >= H) {
-                    next[fi] = 0;
-                    continue;
-                }
-                uint32_t cand[5];
-                bool ok[5];
-                cand[0] = prev[fi];
-                ok[0] = true;
-                cand[1] = prev[fi - 1];
-                ok[1] = px > 0;
-                cand[2] = prev[fi + 1];
-                ok[2] = px < W - 1;
-                cand[3] = prev[fi - DW];
-                ok[3] = py > 0;
-                cand[4] = prev[fi + DW];
-                ok[4] = py < H - 1;
-                uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
+        uint32_t bestv = cand[0], bestc = cin[p];
+        if (any) {
+            const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
+            uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
 #pragma unroll
-                for (int r = 0; r < 2 * P + 1; r++) {
-                    load_row<2 * P + 1>(ref + (ptrdiff_t)(py - P + r) * yp, px - P, rr[r]);
-                    if constexpr (P == 2) rr[r][1] &= 0xffu;
-                    else rr[r][0] &= 0x00ffffffu;
-                }
-                uint32_t bestc = 0xffffffffu, bestv = cand[0];
-#pragma unroll
-                for (int k = 0; k < 5; k++) {
-                    if (!ok[k]) continue;
-                    bool dup = false;
-#pragma unroll
-                    for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
-                    if (dup) continue;  // an earlier equal candidate already has this cost
-                    const uint32_t c = patch_cost<P>(rr, tgt, H, W, yp, px, py, unpack_x(cand[k]), unpack_y(cand[k]));
-                    if (c < bestc) {
-                        bestc = c;
-                        bestv = cand[k];
-                    }
-                }
-                next[fi] = bestv;
+            for (int r = 0; r < 2 * P + 1; r++) {
+                load_row<2 * P + 1>(ref + (ptrdiff_t)(y - P + r) * yp, x - P, rr[r]);
+                if constexpr (P == 2) rr[r][1] &= 0xffu;
+                else rr[r][0] &= 0x00ffffffu;
             }
-            __syncthreads();
-            cur ^= 1;
-        }
-        // median (or copy) over the tile
-        const uint32_t *fin = dbuf[cur];
-        for (int e = threadIdx.x; e < TW * TH; e += NT) {
-            const int ly = e / TW, lx = e - ly * TW;
-            const int px = x0 + lx, py = y0 + ly;
-            if (px >= W || py >= H) continue;
-            uint32_t outv;
-            if (M == 0) {
-                outv = fin[(py - fy0) * DW + (px - fx0)];
-            } else {
-                int vx[9], vy[9];
 #pragma unroll
-                for (int j = 0; j < 3; j++)
-#pragma unroll
-                    for (int i = 0; i < 3; i++) {
-                        const int qx = clampi(px + i - 1, 0, W - 1), qy = clampi(py + j - 1, 0, H - 1);
-                        const uint32_t v = fin[(qy - fy0) * DW + (qx - fx0)];
-                        vx[3 * j + i] = unpack_x(v);
-                        vy[3 * j + i] = unpack_y(v);
-                    }
-                // median of 9 = med3(max of row minima, med3 of row medians, min of row maxima)
-                int mx, my;
-                {
-                    int lo0 = min(min(vx[0], vx[1]), vx[2]), lo1 = min(min(vx[3], vx[4]), vx[5]),
-                        lo2 = min(min(vx[6], vx[7]), vx[8]);
-                    int hi0 = max(max(vx[0], vx[1]), vx[2]), hi1 = max(max(vx[3], vx[4]), vx[5]),
-                        hi2 = max(max(vx[6], vx[7]), vx[8]);
-                    int md0 = med3i(vx[0], vx[1], vx[2]), md1 = med3i(vx[3], vx[4], vx[5]),
-                        md2 = med3i(vx[6], vx[7], vx[8]);
-                    mx = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
+            for (int k = 1; k < 5; k++) {
+                if (!need[k]) continue;
+                const uint32_t c = patch_cost<P>(rr, tgt, H, W, yp, x, y, unpack_x(cand[k]), unpack_y(cand[k]));
+                if (c < bestc) {
+                    bestc = c;
+                    bestv = cand[k];
                 }
-                {
-                    int lo0 = min(min(vy[0], vy[1]), vy[2]), lo1 = min(min(vy[3], vy[4]), vy[5]),
-                        lo2 = min(min(vy[6], vy[7]), vy[8]);
-                    int hi0 = max(max(vy[0], vy[1]), vy[2]), hi1 = max(max(vy[3], vy[4]), vy[5]),
-                        hi2 = max(max(vy[6], vy[7]), vy[8]);
-                    int md0 = med3i(vy[0], vy[1], vy[2]), md1 = med3i(vy[3], vy[4], vy[5]),
-                        md2 = med3i(vy[6], vy[7], vy[8]);
-                    my = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
-                }
-                outv = pack16(mx, my);
             }
-            L.df[dir][(size_t)py * L.fpitch + px] = outv;
         }
-        __syncthreads();
+        dout[p] = bestv;
+        cout[p] = (uint16_t)bestc;
+    }
+}
+
+template <int TH>
+__global__ __launch_bounds__(64 * TH) void k_median(const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix,
+                                                    int n, int total, int T, int M)
+{
+    const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
+    TILE_LOOP(total)
+    {
+        const int s = find_strip(prefix, n, t);
+        int local = t - prefix[s];
+        const StripLv &L = lv[s];
+        const int H = L.H, W = L.W, fp = L.fpitch;
+        const int ntx = ceil_div(W, kPropTW), per_dir = ntx * ceil_div(H, TH);
+        const int dir = local / per_dir;
+        local -= dir * per_dir;
+        const int tyi = local / ntx;
+        const int x = (local - tyi * ntx) * kPropTW + lane, y = tyi * TH + wrow;
+        if (x >= W || y >= H) continue;
+        const uint32_t *fin = T == 0 ? L.ds[dir] : L.dt[dir][(T - 1) & 1];
+        uint32_t outv;
+        if (M == 0) {
+            outv = fin[(size_t)y * fp + x];
+        } else {
+            int vx[9], vy[9];
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const uint32_t *row = fin + (size_t)clampi(y + j - 1, 0, H - 1) * fp;
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    const uint32_t v = row[clampi(x + i - 1, 0, W - 1)];
+                    vx[3 * j + i] = unpack_x(v);
+                    vy[3 * j + i] = unpack_y(v);
+                }
+            }
+            // median of 9 = med3(max of row minima, med3 of row medians, min of row maxima)
+            int mx, my;
+            {
+                int lo0 = min(min(vx[0], vx[1]), vx[2]), lo1 = min(min(vx[3], vx[4]), vx[5]),
+                    lo2 = min(min(vx[6], vx[7]), vx[8]);
+                int hi0 = max(max(vx[0], vx[1]), vx[2]), hi1 = max(max(vx[3], vx[4]), vx[5]),
+                    hi2 = max(max(vx[6], vx[7]), vx[8]);
+                int md0 = med3i(vx[0], vx[1], vx[2]), md1 = med3i(vx[3], vx[4], vx[5]),
+                    md2 = med3i(vx[6], vx[7], vx[8]);
+                mx = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
+            }
+            {
+                int lo0 = min(min(vy[0], vy[1]), vy[2]), lo1 = min(min(vy[3], vy[4]), vy[5]),
+                    lo2 = min(min(vy[6], vy[7]), vy[8]);
+                int hi0 = max(max(vy[0], vy[1]), vy[2]), hi1 = max(max(vy[3], vy[4]), vy[5]),
+                    hi2 = max(max(vy[6], vy[7]), vy[8]);
+                int md0 = med3i(vy[0], vy[1], vy[2]), md1 = med3i(vy[3], vy[4], vy[5]),
+                    md2 = med3i(vy[6], vy[7], vy[8]);
+                my = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
+            }
+            outv = pack16(mx, my);
+        }
+        L.df[dir][(size_t)y * fp + x] = outv;
     }
 }
 
@@ -567,16 +610,42 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
         int local = t - prefix[s];
         const StripLv &L = lv[s];
         const int H = L.H, W = L.W, yp = L.ypitch;
-        const int ntx = ceil_div(W, TW), per_dir = ntx * ceil_div(H, TH);
+        const RefineSplit sp = refine_split(H, W, TH, LP);
+        const int per_dir = sp.nint + sp.nbord;
         const int dir = local / per_dir;
         local -= dir * per_dir;
-        const int tyi = local / ntx;
-        const int x = (local - tyi * ntx) * TW + lane, y = tyi * TH + wrow;
-        if (x >= W || y >= H) continue;  // no barrier in this kernel
+        int x, y;
+        bool interior;
+        if (local < sp.nint) {  // a tile of the interior rectangle
+            const int ntx = ceil_div(sp.xhi - sp.xlo, TW);
+            const int tyi = local / ntx;
+            x = sp.xlo + (local - tyi * ntx) * TW + lane;
+            y = sp.ylo + tyi * TH + wrow;
+            if (x >= sp.xhi || y >= sp.yhi) continue;  // no barrier in this kernel
+            interior = true;
+        } else {  // border band: rows above and below, then columns left and right
+            int b = (local - sp.nint) * TW * TH + (int)threadIdx.x;
+            if (b >= sp.nbp) continue;
+            const int top = sp.ylo * W, bot = (H - sp.yhi) * W;
+            if (b < top) {
+                y = b / W;
+                x = b - y * W;
+            } else if (b < top + bot) {
+                b -= top;
+                y = sp.yhi + b / W;
+                x = b - (b / W) * W;
+            } else {
+                b -= top + bot;
+                const int k = sp.xlo + W - sp.xhi;
+                y = sp.ylo + b / k;
+                const int c = b - (b / k) * k;
+                x = c < sp.xlo ? c : sp.xhi + (c - sp.xlo);
+            }
+            interior = false;
+        }
         const uint8_t *A = L.y[dir], *B = L.y[1 - dir];
         const uint32_t d0 = L.df[dir][(size_t)y * L.fpitch + x];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
-        const bool interior = x - LP >= 0 && x + LP <= W - 1 && y - LP >= 0 && y + LP <= H - 1;
 
         // window: Ref value and doubled gradient at each (clamped) position
         int av[WN][WN], gx[WN][WN], gy[WN][WN];
@@ -622,7 +691,21 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
             const int iux = (int)fux, iuy = (int)fuy;
             float bxs = 0.f, bys = 0.f;
             const int c0 = x - LP + iux, r0 = y - LP + iuy;
-            if (interior && c0 >= -kPad && c0 + WN <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
+            if (it == 0 && interior && c0 >= -kPad && c0 + WN <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
+                // the first step starts from the integer flow: the samples are
+                // pixels (zero fractions), no interpolation
+#pragma unroll
+                for (int j = 0; j < WN; j++) {
+                    uint32_t br[(WN + 3) / 4];
+                    load_row<WN>(B + (ptrdiff_t)(r0 + j) * yp, c0, br);
+#pragma unroll
+                    for (int i = 0; i < WN; i++) {
+                        const float e = (float)byte_at(br, i) - (float)av[j][i];
+                        bxs = fmaf(0.5f * (float)gx[j][i], e, bxs);
+                        bys = fmaf(0.5f * (float)gy[j][i], e, bys);
+                    }
+                }
+            } else if (interior && c0 >= -kPad && c0 + WN <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
                 // (WN+1)^2 block of Tgt with shared bilinear weights
                 float hrow[WN + 1][WN];
 #pragma unroll
@@ -824,22 +907,37 @@ hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int t
 }
 
 template <int P>
-static hipError_t prop_th(const StripLv *lv, Work w, int steps, int median, int th, int grid, hipStream_t s)
+static hipError_t prop_th(const StripLv *lv, Work w, int step, int steps, int median, int th, int grid,
+                          hipStream_t s)
 {
     const int g = grid_for(w.total, grid);
-    if (th == 4)
-        hipLaunchKernelGGL((k_prop<P, 4>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total, steps, median);
-    else
-        hipLaunchKernelGGL((k_prop<P, 8>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total, steps, median);
+    if (step == 0) {
+        switch (th) {
+        case 1: hipLaunchKernelGGL((k_median<1>), dim3(g), dim3(64), 0, s, lv, w.prefix, w.n, w.total, steps, median); break;
+        case 2: hipLaunchKernelGGL((k_median<2>), dim3(g), dim3(128), 0, s, lv, w.prefix, w.n, w.total, steps, median); break;
+        default: hipLaunchKernelGGL((k_median<4>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total, steps, median); break;
+        }
+        return hipGetLastError();
+    }
+    switch (th) {
+    case 1:
+        hipLaunchKernelGGL((k_prop_step<P, 1>), dim3(g), dim3(64), 0, s, lv, w.prefix, w.n, w.total, step, steps, median);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_prop_step<P, 2>), dim3(g), dim3(128), 0, s, lv, w.prefix, w.n, w.total, step, steps, median);
+        break;
+    default:
+        hipLaunchKernelGGL((k_prop_step<P, 4>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total, step, steps, median);
+        break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid,
+hipError_t launch_prop(const StripLv *lv, Work w, int patch, int step, int steps, int median, int th, int grid,
                        hipStream_t s)
 {
-    if (steps + median > kHaloMax) return hipErrorInvalidValue;
-    if (patch == 1) return prop_th<1>(lv, w, steps, median, th, grid, s);
-    if (patch == 2) return prop_th<2>(lv, w, steps, median, th, grid, s);
+    if (patch == 1) return prop_th<1>(lv, w, step, steps, median, th, grid, s);
+    if (patch == 2) return prop_th<2>(lv, w, step, steps, median, th, grid, s);
     return hipErrorInvalidValue;
 }
 
