@@ -74,6 +74,47 @@ def algorithmic(stage, level, shapes, p):
     return "hbm", px * 25.0, "GB/s", HBM_PEAK_GBS
 
 
+def run_stream(n_pano, p, timed, log):
+    """The cfg4 stream: n_pano panoramas of 7 strips of drawn sizes; flow +
+    blend batched per chunk of 4 panoramas (graph replays), then 20
+    descent steps on every strip's FlowRtoL, batched per chunk. Inputs
+    (uint8 and their float copies) are generated on the GPU beforehand."""
+    import torch
+
+    from paper_2006_01201_amd import api, synth
+
+    chunk = 4
+    t0 = time.time()
+    panos = [[synth.make_config_strip_device(4, k, s) for s in range(7)] for k in range(n_pano)]
+    floats = [[(R.float().div_(255.0), L.float().div_(255.0)) for (L, R, _) in pano] for pano in panos]
+    torch.cuda.synchronize()
+    total_px = sum(L.shape[0] * L.shape[1] for pano in panos for (L, _, _) in pano)
+    log(f"stream: {n_pano} panoramas, {total_px / 1e6:.1f} Mpx generated in {time.time() - t0:.1f} s")
+    groups = [sum(panos[i:i + chunk], []) for i in range(0, n_pano, chunk)]
+    fgroups = [sum(floats[i:i + chunk], []) for i in range(0, n_pano, chunk)]
+    max_px = max(sum(L.shape[0] * L.shape[1] for (L, _, _) in g) for g in groups)
+    plan = api.Plan(p, max_strips=7 * chunk, max_pixels=max_px, max_H=4000, max_W=9000)
+    batches = [plan.make_batch(g) for g in groups]
+    items = [[(ref, tgt, b.outputs[i]["flow_rl"]) for i, (ref, tgt) in enumerate(fg)] for b, fg in zip(batches, fgroups)]
+
+    def flows():
+        for b in batches:
+            plan.stitch(b, use_graph=True)
+
+    def refine():
+        for it in items:
+            plan.refine_strips(it, steps=20)
+
+    flows()  # captures one graph per chunk shape
+    ms_f, _ = timed(flows, 2)
+    ms_r, _ = timed(refine, 1)
+    log(f"stream: flow + blend {ms_f:.2f} ms, 20 refinement steps {ms_r:.2f} ms")
+    return {"workload": f"{n_pano} panoramas (cfg4) x 7 strips, sizes drawn per panorama, 6 levels",
+            "overlap_mpix": round(total_px / 1e6, 2), "ms_flow_blend": round(ms_f, 3),
+            "mpix_s_flow_blend": round(total_px / ms_f / 1e3, 1), "ms_refine_20_steps": round(ms_r, 3),
+            "mpix_s_with_refine": round(total_px / (ms_f + ms_r) / 1e3, 1)}
+
+
 def rate(amount, ms, unit):
     s = ms / 1e3
     return amount / s / (1e9 if unit == "GB/s" else 1e12)
@@ -94,6 +135,9 @@ def main():
                          "traffic, for scaling hardware byte counters)")
     ap.add_argument("--refine", action="store_true",
                     help="also time 50 gradient-descent refinement steps on the 2048 x 512 float strip")
+    ap.add_argument("--stream", type=int, default=0, metavar="PANORAMAS",
+                    help="also time a stream of this many panoramas of the cfg4 workload (7 strips of drawn "
+                         "sizes each; flow + blend batched per 4 panoramas, then 20 batched refinement steps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -214,6 +258,10 @@ def main():
                   "mpix_steps_s": round(H3 * W3 * 50 / ms_r / 1e3, 1)}
         log(f"refine 50 steps: {ms_r:.3f} ms")
 
+    stream = None
+    if args.stream:
+        stream = run_stream(args.stream, p, timed, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -260,6 +308,7 @@ def main():
         "top_launches": per_launch,
         "roofline": roofline,
         "refine_flow": refine,
+        "stream": stream,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -175,8 +175,11 @@ abf_status abf_workspace_view(const abf_plan *plan, int32_t kind, int32_t strip,
  * abf_energy writes E (one float, device) and, where non-null, dE/du,
  * dE/dRef, dE/dTgt (device, same shapes as u, Ref, Tgt; overwritten). The
  * derivative at an integer sample position is the right-hand one.
- * deterministic != 0 computes dE/dTgt by a gather that fixes the
- * summation order; otherwise atomics are used. */
+ * dE/dTgt is a bilinear scatter: with deterministic != 0 it is summed with
+ * 64-bit fixed-point integer atomics (resolution 2^-40, |sums| < 2^23), so
+ * the result does not depend on the order of the additions; otherwise with
+ * float atomics. Scratch: 8 bytes per energy block and, if deterministic,
+ * 24 bytes per pixel of the bound workspace (ABF_E_WORKSPACE if short). */
 abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H,
                       int32_t W, float lambda, float eps, float *E_dev, float *g_u, float *g_Ref,
                       float *g_Tgt, int32_t deterministic, void *hip_stream);
@@ -186,11 +189,31 @@ abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, f
                            int32_t W, int32_t steps, float eta, float lambda, float eps, float clip_px,
                            void *hip_stream);
 
+/* One strip of a batched refinement (device pointers): float32 RGB Ref and
+ * Tgt (H x W x 3) and the flow u (H x W x 2), refined in place. */
+typedef struct abf_refine_strip {
+    const float *Ref;
+    const float *Tgt;
+    float *u;
+    int32_t H, W;
+} abf_refine_strip;
+
+/* abf_refine_flow over n strips at once (host array of descriptors): one
+ * launch per descent step covers every strip. Results equal per-strip
+ * abf_refine_flow calls bit for bit. Scratch: 8 bytes per pixel of the
+ * workspace. */
+abf_status abf_refine_strips(abf_plan *plan, const abf_refine_strip *strips, int32_t n, int32_t steps,
+                             float eta, float lambda, float eps, float clip_px, void *hip_stream);
+
 /* Adjoint of Code 1 over float32 RGB images L, R (H x W x 3, contiguous;
  * any value scale): given g_F (float32 H x W x 3), writes the gradients
  * with respect to flow_LtoR, flow_RtoL (H x W x 2) and L, R (H x W x 3),
  * each nullable and overwritten. d|f|/df = f/|f| for f != 0 and 0 at 0;
- * a non-finite flow component is used as 0 and receives gradient 0. */
+ * a non-finite flow component is used as 0 and receives gradient 0. The
+ * image gradients are bilinear scatters, summed with float atomics, or,
+ * when the environment variable ABF_DETERMINISTIC is a non-zero integer,
+ * with the order-independent fixed-point atomics of abf_energy (scratch:
+ * 48 bytes per pixel of the workspace). */
 abf_status abf_blend_backward(abf_plan *plan, const float *L, const float *R, const float *flow_LtoR,
                               const float *flow_RtoL, const float *blend, int32_t axis, int32_t H,
                               int32_t W, const float *g_F, float *g_flow_LtoR, float *g_flow_RtoL,

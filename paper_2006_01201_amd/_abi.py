@@ -34,6 +34,10 @@ class AbfStrip(ctypes.Structure):
     ]
 
 
+class AbfRefineStrip(ctypes.Structure):
+    _fields_ = [("Ref", c_vp), ("Tgt", c_vp), ("u", c_vp), ("H", c_i32), ("W", c_i32)]
+
+
 _SIGS = {
     "abf_default_params": (None, [ctypes.POINTER(AbfParams)]),
     "abf_create_plan": (c_i32, [ctypes.POINTER(AbfParams), c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_vp)]),
@@ -57,6 +61,8 @@ _SIGS = {
     "abf_tune": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_vp]),
     "abf_get_launch": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "abf_set_launch": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32]),
+    "abf_refine_strips": (c_i32, [c_vp, ctypes.POINTER(AbfRefineStrip), c_i32, c_i32, c_f32, c_f32, c_f32, c_f32,
+                                  c_vp]),
     "abf_profile": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_i32, ctypes.POINTER(c_f32), c_vp]),
 }
 
@@ -192,3 +198,7 @@ def profile(plan, strips, n, reps, stream):
     out = (c_f32 * (N_STAGES * MAX_LEVELS))()
     st = load().abf_profile(plan, strips, n, reps, out, stream)
     return st, [[out[s * MAX_LEVELS + k] for k in range(MAX_LEVELS)] for s in range(N_STAGES)]
+
+
+def refine_strips(plan, strips, n, steps, eta, lam, eps, clip_px, stream) -> int:
+    return load().abf_refine_strips(plan, strips, n, steps, eta, lam, eps, clip_px, stream)

@@ -221,6 +221,21 @@ class Plan:
         _abi.check(st, self.h, "abf_refine_flow")
         return u
 
+    def refine_strips(self, items, steps: int = 20, eta: float = 0.5, lam: float = 0.05, eps: float = 1e-3,
+                      clip: float = 0.25):
+        """Batched ``refine_flow``: items are (ref, tgt, u) triples; every u
+        is refined in place, one launch per step for all of them."""
+        arr = (_abi.AbfRefineStrip * len(items))()
+        for i, (ref, tgt, u) in enumerate(items):
+            H, W = u.shape[0], u.shape[1]
+            arr[i].Ref = _f32(ref, (H, W, 3), "ref")
+            arr[i].Tgt = _f32(tgt, (H, W, 3), "tgt")
+            arr[i].u = _f32(u, (H, W, 2), "u")
+            arr[i].H, arr[i].W = H, W
+        st = _abi.refine_strips(self.h, arr, len(items), steps, eta, lam, eps, clip, _stream())
+        _abi.check(st, self.h, "abf_refine_strips")
+        return [it[2] for it in items]
+
     def blend_f32(self, L, R, flow_lr, flow_rl, blend=None, axis: int = 0):
         """Code 1 over float32 RGB images; returns F (float32 H x W x 3)."""
         H, W = L.shape[0], L.shape[1]

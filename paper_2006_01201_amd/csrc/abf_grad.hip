@@ -329,6 +329,53 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const float *__restrict__ L, 
     }
 }
 
+// Batched descent step over many strips: one launch per step, a flat list
+// of 256-pixel tiles over all strips (prefix sums per strip); u[in] is
+// read, u[1 - in] written.
+__global__ __launch_bounds__(256) void k_energy_step_batch(const RefineDesc *__restrict__ d,
+                                                           const int32_t *__restrict__ prefix, int n, int total,
+                                                           int in, float eta, float lambda, float eps, float clip)
+{
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const RefineDesc &r = d[lo];
+        const int64_t p = (int64_t)(t - prefix[lo]) * 256 + threadIdx.x;
+        if (p >= (int64_t)r.H * r.W) continue;
+        const int y = (int)(p / r.W), x = (int)(p - (int64_t)y * r.W);
+        const float *u_in = r.u[in];
+        float *u_out = r.u[1 - in];
+        float gx, gy;
+        double e;
+        grad_u_at(r.Ref, r.Tgt, u_in, r.H, r.W, x, y, lambda, eps, gx, gy, e);
+        const float sx = fminf(fmaxf(eta * gx, -clip), clip), sy = fminf(fmaxf(eta * gy, -clip), clip);
+        u_out[2 * p] = u_in[2 * p] - sx;
+        u_out[2 * p + 1] = u_in[2 * p + 1] - sy;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_back_batch(const RefineDesc *__restrict__ d,
+                                                         const int32_t *__restrict__ prefix, int n, int total)
+{
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const RefineDesc &r = d[lo];
+        const int64_t p = (int64_t)(t - prefix[lo]) * 256 + threadIdx.x;
+        if (p >= (int64_t)r.H * r.W) continue;
+        r.u[0][2 * p] = r.u[1][2 * p];
+        r.u[0][2 * p + 1] = r.u[1][2 * p + 1];
+    }
+}
+
 inline int blocks_for(int64_t n, int per = 256, int cap = 65536)
 {
     int64_t b = (n + per - 1) / per;
@@ -361,6 +408,17 @@ hipError_t launch_energy_step(const float *Ref, const float *Tgt, const float *u
 {
     hipLaunchKernelGGL(k_energy_step, dim3(blocks_for((int64_t)H * W)), dim3(256), 0, s, Ref, Tgt, u_in, u_out, H,
                        W, eta, lambda, eps, clip);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_batch(const RefineDesc *d, const int32_t *prefix, int n, int total, int steps, float eta,
+                               float lambda, float eps, float clip, hipStream_t s)
+{
+    const int g = total < 65536 ? (total > 0 ? total : 1) : 65536;
+    for (int k = 0; k < steps; k++)
+        hipLaunchKernelGGL(k_energy_step_batch, dim3(g), dim3(256), 0, s, d, prefix, n, total, k & 1, eta, lambda,
+                           eps, clip);
+    if (steps & 1) hipLaunchKernelGGL(k_copy_back_batch, dim3(g), dim3(256), 0, s, d, prefix, n, total);
     return hipGetLastError();
 }
 

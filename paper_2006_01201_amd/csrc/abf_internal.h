@@ -99,6 +99,16 @@ hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams
                          hipStream_t s);
 hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s);
 
+// One strip of a batched refinement: u[0] is the caller's flow, u[1] the
+// other half of the descent ping-pong (workspace).
+struct RefineDesc {
+    const float *Ref, *Tgt;
+    float *u[2];
+    int32_t H, W;
+};
+hipError_t launch_refine_batch(const RefineDesc *d, const int32_t *prefix, int n, int total, int steps, float eta,
+                               float lambda, float eps, float clip, hipStream_t s);
+
 // differentiable path (float images); `fix` buffers (3 H W uint64) select
 // the deterministic fixed-point scatter, null selects float atomics
 int energy_blocks(int H, int W);

@@ -455,11 +455,21 @@ __device__ __forceinline__ void prop_bufs(const StripLv &L, int dir, int step, i
     cout = L.ct[dir][(step - 1) & 1];
 }
 
+// Work per workgroup: every pixel lists the neighbour vectors it must
+// cost (on average well under one per pixel), the lists are packed into
+// one LDS job array, the threads share the jobs evenly, and each pixel
+// then picks its winner from its own cost slots in the fixed candidate
+// order, so the result does not depend on the packing order.
 template <int P, int TH>
 __global__ __launch_bounds__(64 * TH) void k_prop_step(const StripLv *__restrict__ lv,
                                                        const int32_t *__restrict__ prefix, int n, int total, int step,
                                                        int T, int M)
 {
+    constexpr int NT = 64 * TH;
+    __shared__ uint32_t jvec[4 * NT];    // candidate vector of a job
+    __shared__ uint16_t jslot[4 * NT];   // owner thread * 4 + candidate - 1
+    __shared__ uint32_t jcost[4 * NT];   // cost, indexed by slot
+    __shared__ int njobs;
     const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
     TILE_LOOP(total)
     {
@@ -471,58 +481,81 @@ __global__ __launch_bounds__(64 * TH) void k_prop_step(const StripLv *__restrict
         const int dir = local / per_dir;
         local -= dir * per_dir;
         const int tyi = local / ntx;
-        const int x = (local - tyi * ntx) * kPropTW + lane, y = tyi * TH + wrow;
-        if (x >= W || y >= H) continue;  // no barrier in this kernel
+        const int x0 = (local - tyi * ntx) * kPropTW, y0 = tyi * TH;
+        const int x = x0 + lane, y = y0 + wrow;
+        const bool valid = x < W && y < H;
         const uint32_t *din;
         const uint16_t *cin;
         uint32_t *dout;
         uint16_t *cout;
         prop_bufs(L, dir, step, T, M, din, cin, dout, cout);
+        if (threadIdx.x == 0) njobs = 0;
+        __syncthreads();
         const size_t p = (size_t)y * fp + x;
         uint32_t cand[5];
-        bool ok[5];
-        cand[0] = din[p];
-        ok[0] = true;
-        cand[1] = x > 0 ? din[p - 1] : 0u;
-        ok[1] = x > 0;
-        cand[2] = x < W - 1 ? din[p + 1] : 0u;
-        ok[2] = x < W - 1;
-        cand[3] = y > 0 ? din[p - fp] : 0u;
-        ok[3] = y > 0;
-        cand[4] = y < H - 1 ? din[p + fp] : 0u;
-        ok[4] = y < H - 1;
         bool need[5];
-        bool any = false;
+        need[0] = false;
+        if (valid) {
+            bool ok[5];
+            cand[0] = din[p];
+            ok[0] = true;
+            cand[1] = x > 0 ? din[p - 1] : 0u;
+            ok[1] = x > 0;
+            cand[2] = x < W - 1 ? din[p + 1] : 0u;
+            ok[2] = x < W - 1;
+            cand[3] = y > 0 ? din[p - fp] : 0u;
+            ok[3] = y > 0;
+            cand[4] = y < H - 1 ? din[p + fp] : 0u;
+            ok[4] = y < H - 1;
 #pragma unroll
-        for (int k = 1; k < 5; k++) {
-            bool dup = !ok[k];
+            for (int k = 1; k < 5; k++) {
+                bool dup = !ok[k];
 #pragma unroll
-            for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
-            need[k] = !dup;
-            any |= need[k];
+                for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
+                need[k] = !dup;
+                if (need[k]) {
+                    const int j = atomicAdd(&njobs, 1);
+                    jvec[j] = cand[k];
+                    jslot[j] = (uint16_t)(threadIdx.x * 4 + k - 1);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 1; k < 5; k++) need[k] = false;
         }
-        uint32_t bestv = cand[0], bestc = cin[p];
-        if (any) {
-            const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
+        __syncthreads();
+        const int nj = njobs;
+        const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
+        for (int j = threadIdx.x; j < nj; j += NT) {
+            const int slot = jslot[j];
+            const int owner = slot >> 2;
+            const int px = x0 + (owner & 63), py = y0 + (owner >> 6);
             uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
 #pragma unroll
             for (int r = 0; r < 2 * P + 1; r++) {
-                load_row<2 * P + 1>(ref + (ptrdiff_t)(y - P + r) * yp, x - P, rr[r]);
+                load_row<2 * P + 1>(ref + (ptrdiff_t)(py - P + r) * yp, px - P, rr[r]);
                 if constexpr (P == 2) rr[r][1] &= 0xffu;
                 else rr[r][0] &= 0x00ffffffu;
             }
+            const uint32_t v = jvec[j];
+            jcost[slot] = patch_cost<P>(rr, tgt, H, W, yp, px, py, unpack_x(v), unpack_y(v));
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t bestv = cand[0], bestc = cin[p];
 #pragma unroll
             for (int k = 1; k < 5; k++) {
                 if (!need[k]) continue;
-                const uint32_t c = patch_cost<P>(rr, tgt, H, W, yp, x, y, unpack_x(cand[k]), unpack_y(cand[k]));
+                const uint32_t c = jcost[threadIdx.x * 4 + k - 1];
                 if (c < bestc) {
                     bestc = c;
                     bestv = cand[k];
                 }
             }
+            dout[p] = bestv;
+            cout[p] = (uint16_t)bestc;
         }
-        dout[p] = bestv;
-        cout[p] = (uint16_t)bestc;
+        __syncthreads();
     }
 }
 

@@ -350,15 +350,12 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
     return ABF_OK;
 }
 
-// Copies the descriptor tables to the head of the workspace (stream
-// ordered), through a pinned slot whose previous copy has completed.
-abf_status upload(abf_plan *pl, const Batch &b, hipStream_t s)
+// Copies descriptor bytes to the head of the workspace (stream ordered),
+// through a pinned slot whose previous copy has completed; skipped when
+// the head already holds exactly these bytes.
+abf_status upload_bytes(abf_plan *pl, std::vector<uint8_t> &host, hipStream_t s)
 {
-    const Layout &L = b.lay;
-    std::vector<uint8_t> host(L.hdr_bytes, 0);
-    memcpy(host.data() + L.hdr_io, b.io.data(), sizeof(StripIO) * L.n);
-    memcpy(host.data() + L.hdr_lv, b.lv.data(), sizeof(StripLv) * b.lv.size());
-    memcpy(host.data() + L.hdr_prefix, b.prefix.data(), sizeof(int32_t) * b.prefix.size());
+    if (host.size() > pl->hdr_cap) return fail(pl, ABF_E_WORKSPACE, "descriptor tables exceed the reserved head");
     if (host == pl->last_upload) return ABF_OK;
     const int k = pl->slot;
     pl->slot = (pl->slot + 1) % kSlots;
@@ -369,6 +366,16 @@ abf_status upload(abf_plan *pl, const Batch &b, hipStream_t s)
     pl->ev_used[k] = true;
     pl->last_upload.swap(host);
     return ABF_OK;
+}
+
+abf_status upload(abf_plan *pl, const Batch &b, hipStream_t s)
+{
+    const Layout &L = b.lay;
+    std::vector<uint8_t> host(L.hdr_bytes, 0);
+    memcpy(host.data() + L.hdr_io, b.io.data(), sizeof(StripIO) * L.n);
+    memcpy(host.data() + L.hdr_lv, b.lv.data(), sizeof(StripLv) * b.lv.size());
+    memcpy(host.data() + L.hdr_prefix, b.prefix.data(), sizeof(int32_t) * b.prefix.size());
+    return upload_bytes(pl, host, s);
 }
 
 int grid_of(const abf_plan *pl, int stage, int cls)
@@ -926,6 +933,49 @@ abf_status abf_profile(abf_plan *plan, const abf_strip *strips, int32_t n, int32
     }
     plan->lv_host = b.lv;
     plan->last_n = n;
+    return ABF_OK;
+}
+
+abf_status abf_refine_strips(abf_plan *plan, const abf_refine_strip *strips, int32_t n, int32_t steps, float eta,
+                             float lambda, float eps, float clip_px, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!strips || n < 1 || steps < 0) return fail(plan, ABF_E_INVALID, "bad arguments");
+    if (n > plan->max_strips) return fail(plan, ABF_E_SHAPE, "%d strips exceed the plan's %d", n, plan->max_strips);
+    if (!(eps > 0.f) || !(lambda >= 0.f) || !(clip_px >= 0.f)) return fail(plan, ABF_E_INVALID, "bad parameter");
+    if (!plan->ws) return fail(plan, ABF_E_WORKSPACE, "no workspace bound");
+    std::vector<RefineDesc> d(n);
+    std::vector<int32_t> prefix(n + 1);
+    size_t off = plan->hdr_cap;
+    int64_t acc = 0;
+    for (int i = 0; i < n; i++) {
+        const abf_refine_strip &x = strips[i];
+        if (!x.Ref || !x.Tgt || !x.u) return fail(plan, ABF_E_INVALID, "strip %d: null pointer", i);
+        if (x.H < 1 || x.W < 1) return fail(plan, ABF_E_SHAPE, "strip %d: size %d x %d", i, x.H, x.W);
+        d[i].Ref = x.Ref;
+        d[i].Tgt = x.Tgt;
+        d[i].u[0] = x.u;
+        d[i].u[1] = reinterpret_cast<float *>(plan->ws + off);
+        d[i].H = x.H;
+        d[i].W = x.W;
+        off += align_up(sizeof(float) * 2 * (size_t)x.H * x.W, kAlign);
+        prefix[i] = (int32_t)acc;
+        acc += ceil_div(x.H * x.W, 256);
+    }
+    prefix[n] = (int32_t)acc;
+    if (off > plan->ws_bytes)
+        return fail(plan, ABF_E_WORKSPACE, "batch needs %zu workspace bytes, %zu bound", off, plan->ws_bytes);
+    if (acc > 0x7fffffff) return fail(plan, ABF_E_SHAPE, "too many tiles");
+    const size_t dbytes = align_up(sizeof(RefineDesc) * n, kAlign);
+    std::vector<uint8_t> host(dbytes + sizeof(int32_t) * (n + 1), 0);
+    memcpy(host.data(), d.data(), sizeof(RefineDesc) * n);
+    memcpy(host.data() + dbytes, prefix.data(), sizeof(int32_t) * (n + 1));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    abf_status rc = upload_bytes(plan, host, s);
+    if (rc != ABF_OK) return rc;
+    HIP_TRY(plan, launch_refine_batch(reinterpret_cast<const RefineDesc *>(plan->ws),
+                                      reinterpret_cast<const int32_t *>(plan->ws + dbytes), n, (int)acc, steps, eta,
+                                      lambda, eps, clip_px, s));
     return ABF_OK;
 }
 

@@ -354,3 +354,83 @@ def random_levels(seed: int, shape, levels: int) -> np.ndarray:
     r = rng_for(102, seed, 0)
     vals = np.linspace(0, 255, levels).round().astype(np.uint8)
     return vals[r.integers(0, levels, size=shape)]
+
+
+# ---------------------------------------------------------------------------
+# Device-side evaluation for large streams (the 32-panorama workload): the
+# same recipe and the same parameter draws as ``make_config_strip``, with
+# the per-pixel work (texture, smoothing of the flow noise, warp, sensor
+# noise) evaluated by torch on the GPU. Sensor noise comes from a torch
+# generator seeded from the strip's generator, so the images are not bit
+# for bit those of the CPU path; they are used for throughput runs, not for
+# parity.
+
+def _texture_torch(tex: Texture, x, y):
+    import torch
+
+    out = torch.full(x.shape + (3,), 128.0, dtype=torch.float32, device=x.device)
+    two_pi = 2.0 * np.pi
+    cph = torch.tensor(np.cos(tex.phase), dtype=torch.float32, device=x.device)
+    sph = torch.tensor(np.sin(tex.phase), dtype=torch.float32, device=x.device)
+    for k in range(len(tex.amp)):
+        arg = (two_pi * tex.freq[k]) * (x * np.cos(tex.theta[k]) + y * np.sin(tex.theta[k]))
+        arg = (arg - two_pi * torch.round(arg / two_pi)).float()
+        s, c = torch.sin(arg), torch.cos(arg)
+        for ch in range(3):
+            out[..., ch] += float(tex.amp[k]) * (s * cph[k, ch] + c * sph[k, ch])
+    for r in range(len(tex.rects)):
+        x0, y0, x1, y1 = tex.rects[r]
+        m = (x >= x0) & (x < x1) & (y >= y0) & (y < y1)
+        out[m] += torch.tensor(tex.offset[r], dtype=torch.float32, device=x.device)
+    return out
+
+
+def _smooth_field_torch(rng, H, W, sigma, max_abs, device):
+    import torch
+
+    noise = torch.from_numpy(rng.standard_normal((H, W))).to(device)
+    fy = torch.fft.fftfreq(H, device=device, dtype=torch.float64)[:, None]
+    fx = torch.fft.rfftfreq(W, device=device, dtype=torch.float64)[None, :]
+    g = torch.exp(-2.0 * np.pi ** 2 * sigma ** 2 * (fx ** 2 + fy ** 2))
+    f = torch.fft.irfft2(torch.fft.rfft2(noise) * g, s=(H, W))
+    m = f.abs().max()
+    return f * (max_abs / m) if float(m) > 0 else f
+
+
+def make_config_strip_device(cfg: int, pano: int, strip: int, device="cuda"):
+    """(L, R, axis) as uint8 tensors on ``device`` for the panorama
+    workloads (cfg 2 and 4); see the section comment."""
+    import torch
+
+    if cfg not in (2, 4):
+        raise ValueError("device generation covers the panorama workloads (2, 4)")
+    H, W, axis = strip_shapes(cfg, pano)[strip]
+    rng = rng_for(cfg, pano, strip)
+    h, w = (H, W) if axis == 0 else (W, H)  # generated in the frame where the seam runs vertically
+    tex = Texture(rng, h, w)
+    sigma = max(128.0, 0.15 * min(h, w))
+    ux = _smooth_field_torch(rng, h, w, sigma, 40.0, device)
+    uy = _smooth_field_torch(rng, h, w, sigma, 8.0, device)
+    wb = int(rng.integers(64, 129))
+    xb = float(rng.uniform(0.25 * w, 0.6 * w))
+    dob = float(rng.uniform(30.0, 40.0))
+    tex_o = Texture(rng, h, w)
+    gain = float(rng.uniform(0.9, 1.1))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(0, 2 ** 62)))
+    yy, xx = torch.meshgrid(torch.arange(h, device=device, dtype=torch.float64),
+                            torch.arange(w, device=device, dtype=torch.float64), indexing="ij")
+    Lf = _texture_torch(tex, xx, yy)
+    Rf = gain * _texture_torch(tex, xx + ux, yy + uy)
+    in_l = (xx >= xb) & (xx < xb + wb)
+    Lf[in_l] = _texture_torch(tex_o, xx[in_l], yy[in_l])
+    in_r = (xx + dob >= xb) & (xx + dob < xb + wb)
+    Rf[in_r] = gain * _texture_torch(tex_o, xx[in_r] + dob, yy[in_r])
+    Lf += 2.0 * torch.randn(Lf.shape, generator=gen, device=device)
+    Rf += 2.0 * torch.randn(Rf.shape, generator=gen, device=device)
+    L = Lf.round_().clamp_(0, 255).to(torch.uint8)
+    R = Rf.round_().clamp_(0, 255).to(torch.uint8)
+    if axis == 1:
+        L = L.transpose(0, 1).contiguous()
+        R = R.transpose(0, 1).contiguous()
+    return L, R, axis

@@ -191,3 +191,23 @@ def test_autograd_functions(api, cfg3):
     direct = plan.blend_backward(L.detach(), R.detach(), flr.detach(), frl.detach(), gF)
     for a, b in zip(grads, direct):
         assert torch.allclose(a, b, rtol=1e-5, atol=1e-5)
+
+
+def test_refine_strips_equals_per_strip_calls(api, cfg3):
+    # uneven crops refined together, against one refine_flow call each
+    crops = [(slice(0, 200), slice(0, 300)), (slice(300, 420), slice(100, 377)), (slice(1000, 1003), slice(5, 9))]
+    items, ref = [], []
+    plan = api.Plan(api.Params(), max_strips=4, max_H=512, max_W=512)
+    print("[gpu] refine_strips", flush=True)
+    for steps in (3, 4):
+        items, ref = [], []
+        for rows, cols in crops:
+            R_, T_, u0 = cfg3.R[rows, cols], cfg3.L[rows, cols], np.rint(cfg3.flow_rl_gt[rows, cols])
+            items.append((dev(R_), dev(T_), dev(u0)))
+            ua = dev(u0)
+            plan.refine_flow(dev(R_), dev(T_), ua, steps=steps)
+            ref.append(ua)
+        plan.refine_strips(items, steps=steps)
+        torch.cuda.synchronize()
+        for (_, _, u), r in zip(items, ref):
+            assert torch.equal(u, r)
