@@ -46,7 +46,7 @@ def kernel_name(stage, level, p):
     if stage == 0:
         return "k_luma level 0" if level == 0 else "k_gain level 0"
     if stage == 3:
-        return f"k_prop_step x{p.prop_steps} + k_median level {level}"
+        return f"k_prop ({p.prop_steps} steps + median) level {level}"
     return f"{KERNELS[stage]} level {level}"
 
 
@@ -85,7 +85,11 @@ def run_stream(n_pano, p, timed, log):
 
     chunk = 4
     t0 = time.time()
-    panos = [[synth.make_config_strip_device(4, k, s) for s in range(7)] for k in range(n_pano)]
+    panos = []
+    for k in range(n_pano):
+        panos.append([synth.make_config_strip_device(4, k, s) for s in range(7)])
+        torch.cuda.synchronize()
+        log(f"stream: panorama {k} generated ({time.time() - t0:.1f} s)")
     floats = [[(R.float().div_(255.0), L.float().div_(255.0)) for (L, R, _) in pano] for pano in panos]
     torch.cuda.synchronize()
     total_px = sum(L.shape[0] * L.shape[1] for pano in panos for (L, _, _) in pano)
@@ -128,7 +132,7 @@ def main():
     ap.add_argument("--pano", type=int, default=0, help="panorama seed index of the workload")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the workload, copy a MIB-mebibyte device buffer once (a kernel of known "
@@ -268,21 +272,24 @@ def main():
 
         op = oracle.Params(levels=p.levels)
         used, px_done, t_cpu = [], 0, 0.0
-        for i, s in enumerate(strips[:-1]):
-            t0 = time.perf_counter()
-            o_lr, o_rl = oracle.flow_bidirectional(s.L, s.R, op)
-            oracle.blend(s.L, s.R, o_lr, o_rl, axis=s.axis, params=op)
-            t_cpu += time.perf_counter() - t0
-            px_done += s.H * s.W
-            used.append(i)
-            log(f"cpu oracle strip {i}: {t_cpu:.1f} s so far")
-            if t_cpu >= args.cpu_seconds:
-                break
+        # side strips of the panorama in turn (the top seam is the one shape
+        # left out), repeated until the time budget is spent
+        while t_cpu < args.cpu_seconds:
+            for i, s in enumerate(strips[:-1]):
+                t0 = time.perf_counter()
+                o_lr, o_rl = oracle.flow_bidirectional(s.L, s.R, op)
+                oracle.blend(s.L, s.R, o_lr, o_rl, axis=s.axis, params=op)
+                t_cpu += time.perf_counter() - t0
+                px_done += s.H * s.W
+                used.append(i)
+                log(f"cpu oracle strip {i}: {t_cpu:.1f} s so far")
+                if t_cpu >= args.cpu_seconds:
+                    break
         cpu = {"value": round(px_done / t_cpu / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": f"side strips {used} of the same panorama ({px_done / 1e6:.2f} Mpx): flow both "
-                         f"directions + Code 1 blend, C/OpenMP oracle (int32 search, FP64 refine and blend), "
-                         f"{t_cpu:.1f} s"}
+               "sample": f"side strips {used} of the same panorama, in turn ({px_done / 1e6:.2f} Mpx): flow "
+                         f"both directions + Code 1 blend, C/OpenMP oracle (int32 search, FP64 refine and "
+                         f"blend), {t_cpu:.1f} s"}
 
     out = {
         "metric": METRIC,

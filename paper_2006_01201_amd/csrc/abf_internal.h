@@ -24,8 +24,6 @@ struct StripLv {
     uint8_t *y[2];          // luma of L and R at this level (pitch ypitch bytes)
     uint32_t *ds[2];        // raw search result per direction (pitch fpitch)
     uint16_t *cs[2];        // its patch cost
-    uint32_t *dt[2][2];     // propagation iterates (ping-pong) per direction
-    uint16_t *ct[2][2];     // their patch costs
     uint32_t *df[2];        // final flow of the level per direction
     const uint32_t *dc[2];  // final flow of the next coarser level (null at the coarsest)
     const uint8_t *yfine[2];// luma of the next finer level (pyramid input; null at level 0)
@@ -73,11 +71,10 @@ struct BlendParams {
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // search tiles: 128 x TH pixels (64 threads per row, two pixels each);
-// refine and propagation: 64 x TH; luma, exposure step and blend:
+// refine: 64 x TH; propagation: (64 - 2h) x TH outputs, TH = 8 or 16; luma, exposure step and blend:
 // 256 pixels of one row; pyramid: 64 x 4 output pixels. Luma, exposure
 // and pyramid tiles cover the padded planes.
 constexpr int kSearchTW = 128;
-constexpr int kPropTW = 64;
 constexpr int kRefineTW = 64;
 constexpr int kRowTW = 256;
 constexpr int kPyrTW = 64;
@@ -92,9 +89,8 @@ hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s);
 hipError_t launch_gain(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s);
 hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s);
 hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int th, int grid, hipStream_t s);
-// one Jacobi propagation step (step = 1..T) or the median (step = 0)
-hipError_t launch_prop(const StripLv *lv, Work w, int patch, int step, int steps, int median, int th, int grid,
-                       hipStream_t s);
+// the T propagation steps and the median of one level (one launch)
+hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid, hipStream_t s);
 hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid,
                          hipStream_t s);
 hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s);
@@ -134,7 +130,17 @@ __host__ __device__ inline int tiles_pyr(int H, int W)
     return ceil_div(H + 2 * kPad, kPyrTH) * ceil_div(W + 2 * kPad, kPyrTW);
 }
 __host__ __device__ inline int tiles_search(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kSearchTW); }
-__host__ __device__ inline int tiles_prop(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kPropTW); }
+// fused propagation (T steps + median, halo h = T + M): 256 threads per
+// tile of (kPropRW - 2h) x th outputs over a kPropRW x (th + 2h) region;
+// LDS per region pixel: two iterates (4 B) and their costs (2 B), four
+// candidate costs and up to four jobs (2 B each), plus the job counter
+constexpr int kPropThreads = 256;
+constexpr int kPropRW = 64;
+__host__ __device__ inline int tiles_prop(int H, int W, int th, int h)
+{
+    return 2 * ceil_div(H, th) * ceil_div(W, kPropRW - 2 * h);
+}
+__host__ __device__ inline size_t prop_lds_bytes(int h, int th) { return (size_t)kPropRW * (th + 2 * h) * 28 + 16; }
 // refine: interior tiles (window inside the image) then border tiles of
 // 64 th pixels enumerated along the border band, per direction
 struct RefineSplit {

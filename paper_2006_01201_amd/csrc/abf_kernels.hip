@@ -56,6 +56,22 @@ __device__ __forceinline__ uint32_t pack16(int x, int y)
 __device__ __forceinline__ int unpack_x(uint32_t v) { return (int)(int16_t)(v & 0xffffu); }
 __device__ __forceinline__ int unpack_y(uint32_t v) { return (int)(int16_t)(v >> 16); }
 
+typedef const __attribute__((address_space(1))) uint32_t gu32;
+
+// The buffers are plain device memory: accessing them through global
+// (rather than generic) pointers makes the loads count on vmcnt only, so
+// waits for them do not also wait for LDS traffic and vice versa.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gld(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)(const void *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p)
+{
+    return (__attribute__((address_space(1))) T *)(void *)p;
+}
+
 // Bytes c .. c+NB-1 of a padded luma row, normalised so that out[k] holds
 // bytes c+4k .. c+4k+3. The row must hold those bytes (|c| <= kPad away).
 template <int NB>
@@ -65,13 +81,41 @@ __device__ __forceinline__ void load_row(const uint8_t *__restrict__ row, int c,
     constexpr int ND = (NB + 6) / 4;  // dwords covering NB bytes at any alignment
     const int a = c & ~3;             // floor to a multiple of 4 (two's complement)
     const int s = c - a;
-    const uint32_t *p = reinterpret_cast<const uint32_t *>(row + a);
+    // global address space: the loads count on vmcnt only and return in
+    // order, so a use waits for its own row and not for every load in flight
+    const gu32 *p = (const gu32 *)(const void *)(row + a);
     uint32_t w[ND + 1];
 #pragma unroll
     for (int k = 0; k < ND; k++) w[k] = p[k];
     w[ND] = 0;
 #pragma unroll
     for (int k = 0; k < NO; k++) out[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], s);
+}
+
+// NR consecutive rows of the same columns (row r at base + r * pitch): all
+// loads are issued before the first row is normalised, so the rows are in
+// flight together rather than one round trip each
+template <int NB, int NR>
+__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ base, int pitch, int c,
+                                          uint32_t (&out)[NR][(NB + 3) / 4])
+{
+    constexpr int NO = (NB + 3) / 4;
+    constexpr int ND = (NB + 6) / 4;
+    const int a = c & ~3;
+    const int s = c - a;
+    uint32_t w[NR][ND + 1];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const gu32 *p = (const gu32 *)(const void *)(base + (ptrdiff_t)r * pitch + a);
+#pragma unroll
+        for (int k = 0; k < ND; k++) w[r][k] = p[k];
+        w[r][ND] = 0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < NO; k++) out[r][k] = __builtin_amdgcn_alignbyte(w[r][k + 1], w[r][k], s);
 }
 
 // The same bytes with every index clamped to the image (for windows that
@@ -328,21 +372,19 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
         const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
         int cx = 0, cy = 0;
         if (L.dc[dir]) {
-            const uint32_t v = L.dc[dir][(size_t)min(y >> 1, L.Hc - 1) * L.fpitch_c + min(x >> 1, L.Wc - 1)];
+            const uint32_t v = gld(L.dc[dir])[(size_t)min(y >> 1, L.Hc - 1) * L.fpitch_c + min(x >> 1, L.Wc - 1)];
             cx = 2 * unpack_x(v);
             cy = 2 * unpack_y(v);
         }
         // reference rows y-P .. y+P, columns x-P .. x+1+P
         uint32_t rr[2 * P + 1][(RB + 3) / 4];
-#pragma unroll
-        for (int r = 0; r < 2 * P + 1; r++) load_row<RB>(ref + (ptrdiff_t)(y - P + r) * yp, x - P, rr[r]);
+        load_rows<RB, 2 * P + 1>(ref + (ptrdiff_t)(y - P) * yp, yp, x - P, rr);
         // target rows, columns x+cx-R-P .. x+cx+R+P+1
         const int c0 = x + cx - R - P, r0 = y + cy - R - P;
         const bool inpad = c0 >= -kPad && c0 + NB - 1 <= W - 1 + kPad && r0 >= -kPad && r0 + NR - 1 <= H - 1 + kPad;
         uint32_t tt[NR][NBO];
         if (inpad) {
-#pragma unroll
-            for (int k = 0; k < NR; k++) load_row<NB>(tgt + (ptrdiff_t)(r0 + k) * yp, c0, tt[k]);
+            load_rows<NB, NR>(tgt + (ptrdiff_t)r0 * yp, yp, c0, tt);
         } else {
 #pragma unroll
             for (int k = 0; k < NR; k++) load_row_clamped<NB>(tgt, H, W, yp, r0 + k, c0, tt[k]);
@@ -395,8 +437,8 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                     best1 = min(best1, (s1 << 11) + K);
                 }
         }
-        uint32_t *out = L.ds[dir] + (size_t)y * L.fpitch + x;
-        uint16_t *cst = L.cs[dir] + (size_t)y * L.fpitch + x;
+        auto out = gst(L.ds[dir] + (size_t)y * L.fpitch + x);
+        auto cst = gst(L.cs[dir] + (size_t)y * L.fpitch + x);
         {
             const int idx = (int)(best0 & 127u), j = idx / NC, i = idx - j * NC;
             out[0] = pack16(cx + i - R, cy + j - R);
@@ -429,213 +471,326 @@ __device__ __forceinline__ uint32_t patch_cost(const uint32_t (&rr)[2 * P + 1][(
     constexpr int NB = 2 * P + 1;
     const int c0 = px + dx - P, r0 = py + dy - P;
     const bool inpad = c0 >= -kPad && c0 + NB - 1 <= W - 1 + kPad && r0 >= -kPad && r0 + NB - 1 <= H - 1 + kPad;
+    uint32_t t[NB][(NB + 3) / 4];
+    if (inpad) {
+        load_rows<NB, NB>(tgt + (ptrdiff_t)r0 * yp, yp, c0, t);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NB; r++) load_row_clamped<NB>(tgt, H, W, yp, r0 + r, c0, t[r]);
+    }
     uint32_t s = 0;
 #pragma unroll
     for (int r = 0; r < NB; r++) {
-        uint32_t t[(NB + 3) / 4];
-        if (inpad) load_row<NB>(tgt + (ptrdiff_t)(r0 + r) * yp, c0, t);
-        else load_row_clamped<NB>(tgt, H, W, yp, r0 + r, c0, t);
         if constexpr (P == 2) {
-            s = __builtin_amdgcn_sad_u8(rr[r][0], t[0], s);
-            s = __builtin_amdgcn_sad_u8(rr[r][1], t[1] & 0xffu, s);
+            s = __builtin_amdgcn_sad_u8(rr[r][0], t[r][0], s);
+            s = __builtin_amdgcn_sad_u8(rr[r][1], t[r][1] & 0xffu, s);
         } else {
-            s = __builtin_amdgcn_sad_u8(rr[r][0], t[0] & 0x00ffffffu, s);
+            s = __builtin_amdgcn_sad_u8(rr[r][0], t[r][0] & 0x00ffffffu, s);
         }
     }
     return s;
 }
 
-// buffers of propagation step `step` (1-based) of T: input, output
-__device__ __forceinline__ void prop_bufs(const StripLv &L, int dir, int step, int T, int M, const uint32_t *&din,
-                                          const uint16_t *&cin, uint32_t *&dout, uint16_t *&cout)
+// T Jacobi propagation steps and the median of one level in one launch,
+// with temporal blocking. A workgroup owns an output tile of
+// (64 - 2h) x TH pixels, h = T + M, and loads the search result of the
+// 64 x (TH + 2h) region around it into LDS (lane = region column, so every
+// region row is one wave instruction); step t runs on the region inset by
+// t (every step reads only the previous iterate, so the result is that of
+// T separate full-image steps), the median on the output tile, and only
+// the final flow is written. Neighbours outside the image are skipped; the
+// median clamps to the image.
+//
+// Work per step: every pixel lists the neighbour vectors it must cost (a
+// neighbour equal to an earlier candidate has the same cost and loses the
+// tie, so it is not costed; on average well under one job per pixel). Each
+// wave reserves room for its lanes' jobs with one LDS atomic and places
+// them by a ballot prefix count; all threads then share the job array, and
+// each pixel picks its winner from its own cost slots in the fixed
+// candidate order, so the result does not depend on the packing.
+__device__ __forceinline__ int wave_prefix(uint32_t c, int &total)
 {
-    din = step == 1 ? L.ds[dir] : L.dt[dir][(step - 2) & 1];
-    cin = step == 1 ? L.cs[dir] : L.ct[dir][(step - 2) & 1];
-    dout = (step == T && M == 0) ? L.df[dir] : L.dt[dir][(step - 1) & 1];
-    cout = L.ct[dir][(step - 1) & 1];
+    // exclusive prefix sum over the wave of c (0..7) and the wave total
+    int pre = 0;
+    total = 0;
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        const uint64_t m = __ballot((c >> b) & 1u);
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+        pre += below << b;
+        total += __popcll(m) << b;
+    }
+    return pre;
 }
 
-// Work per workgroup: every pixel lists the neighbour vectors it must
-// cost (on average well under one per pixel), the lists are packed into
-// one LDS job array, the threads share the jobs evenly, and each pixel
-// then picks its winner from its own cost slots in the fixed candidate
-// order, so the result does not depend on the packing order.
 template <int P, int TH>
-__global__ __launch_bounds__(64 * TH) void k_prop_step(const StripLv *__restrict__ lv,
-                                                       const int32_t *__restrict__ prefix, int n, int total, int step,
-                                                       int T, int M)
+__global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict__ lv,
+                                                       const int32_t *__restrict__ prefix, int n, int total, int T,
+                                                       int M)
 {
-    constexpr int NT = 64 * TH;
-    __shared__ uint32_t jvec[4 * NT];    // candidate vector of a job
-    __shared__ uint16_t jslot[4 * NT];   // owner thread * 4 + candidate - 1
-    __shared__ uint32_t jcost[4 * NT];   // cost, indexed by slot
-    __shared__ int njobs;
-    const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
+    constexpr int NT = kPropThreads, NW = NT / 64, RW = kPropRW;
+    extern __shared__ uint32_t smem[];
+    const int h = T + M;
+    const int OW = RW - 2 * h, RH = TH + 2 * h, NR = RW * RH;
+    uint32_t *vp = smem, *vn = smem + NR;                                       // iterates
+    uint16_t *cp = reinterpret_cast<uint16_t *>(smem + 2 * NR), *cn = cp + NR;  // their costs
+    uint16_t *slot = cn + NR;                                                   // 4 candidate costs per pixel
+    uint16_t *jobs = slot + 4 * NR;  // (row << 6 | column) << 2 | candidate - 1
+    int *njobs = reinterpret_cast<int *>(jobs + 4 * NR);
+    const int rx = threadIdx.x & 63, wave = threadIdx.x >> 6;
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         int local = t - prefix[s];
         const StripLv &L = lv[s];
         const int H = L.H, W = L.W, yp = L.ypitch, fp = L.fpitch;
-        const int ntx = ceil_div(W, kPropTW), per_dir = ntx * ceil_div(H, TH);
+        const int ntx = ceil_div(W, OW), per_dir = ntx * ceil_div(H, TH);
         const int dir = local / per_dir;
         local -= dir * per_dir;
         const int tyi = local / ntx;
-        const int x0 = (local - tyi * ntx) * kPropTW, y0 = tyi * TH;
-        const int x = x0 + lane, y = y0 + wrow;
-        const bool valid = x < W && y < H;
-        const uint32_t *din;
-        const uint16_t *cin;
-        uint32_t *dout;
-        uint16_t *cout;
-        prop_bufs(L, dir, step, T, M, din, cin, dout, cout);
-        if (threadIdx.x == 0) njobs = 0;
-        __syncthreads();
-        const size_t p = (size_t)y * fp + x;
-        uint32_t cand[5];
-        bool need[5];
-        need[0] = false;
-        if (valid) {
-            bool ok[5];
-            cand[0] = din[p];
-            ok[0] = true;
-            cand[1] = x > 0 ? din[p - 1] : 0u;
-            ok[1] = x > 0;
-            cand[2] = x < W - 1 ? din[p + 1] : 0u;
-            ok[2] = x < W - 1;
-            cand[3] = y > 0 ? din[p - fp] : 0u;
-            ok[3] = y > 0;
-            cand[4] = y < H - 1 ? din[p + fp] : 0u;
-            ok[4] = y < H - 1;
-#pragma unroll
-            for (int k = 1; k < 5; k++) {
-                bool dup = !ok[k];
-#pragma unroll
-                for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
-                need[k] = !dup;
-                if (need[k]) {
-                    const int j = atomicAdd(&njobs, 1);
-                    jvec[j] = cand[k];
-                    jslot[j] = (uint16_t)(threadIdx.x * 4 + k - 1);
+        const int gx0 = (local - tyi * ntx) * OW - h, gy0 = tyi * TH - h;  // image position of region (0, 0)
+        const int x = gx0 + rx;
+        const bool xin = x >= 0 && x < W;
+        {
+            const auto din = gld(L.ds[dir]);
+            const auto cin = gld(L.cs[dir]);
+            for (int ry = wave; ry < RH; ry += NW) {
+                const int y = gy0 + ry;
+                if (xin && y >= 0 && y < H) {
+                    vp[ry * RW + rx] = din[(size_t)y * fp + x];
+                    cp[ry * RW + rx] = cin[(size_t)y * fp + x];
                 }
             }
-        } else {
-#pragma unroll
-            for (int k = 1; k < 5; k++) need[k] = false;
         }
+        if (threadIdx.x == 0) *njobs = 0;
         __syncthreads();
-        const int nj = njobs;
         const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
-        for (int j = threadIdx.x; j < nj; j += NT) {
-            const int slot = jslot[j];
-            const int owner = slot >> 2;
-            const int px = x0 + (owner & 63), py = y0 + (owner >> 6);
-            uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
+        for (int step = 1; step <= T; step++) {
+            const bool xact = xin && rx >= step && rx < RW - step;
+            for (int ry0 = step; ry0 < RH - step; ry0 += NW) {
+                const int ry = ry0 + wave, y = gy0 + ry;
+                const bool act = xact && ry < RH - step && y >= 0 && y < H;
+                const int i = ry * RW + rx;
+                uint32_t need = 0;
+                uint32_t cand[5];
+                if (act) {
+                    bool ok[5];
+                    cand[0] = vp[i];
+                    ok[0] = true;
+                    ok[1] = x > 0;
+                    cand[1] = ok[1] ? vp[i - 1] : 0u;
+                    ok[2] = x < W - 1;
+                    cand[2] = ok[2] ? vp[i + 1] : 0u;
+                    ok[3] = y > 0;
+                    cand[3] = ok[3] ? vp[i - RW] : 0u;
+                    ok[4] = y < H - 1;
+                    cand[4] = ok[4] ? vp[i + RW] : 0u;
 #pragma unroll
-            for (int r = 0; r < 2 * P + 1; r++) {
-                load_row<2 * P + 1>(ref + (ptrdiff_t)(py - P + r) * yp, px - P, rr[r]);
-                if constexpr (P == 2) rr[r][1] &= 0xffu;
-                else rr[r][0] &= 0x00ffffffu;
-            }
-            const uint32_t v = jvec[j];
-            jcost[slot] = patch_cost<P>(rr, tgt, H, W, yp, px, py, unpack_x(v), unpack_y(v));
-        }
-        __syncthreads();
-        if (valid) {
-            uint32_t bestv = cand[0], bestc = cin[p];
+                    for (int k = 1; k < 5; k++) {
+                        bool dup = !ok[k];
 #pragma unroll
-            for (int k = 1; k < 5; k++) {
-                if (!need[k]) continue;
-                const uint32_t c = jcost[threadIdx.x * 4 + k - 1];
-                if (c < bestc) {
-                    bestc = c;
-                    bestv = cand[k];
+                        for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
+                        if (dup) slot[4 * i + k - 1] = 0xffffu;  // above every patch cost: never wins
+                        else need |= 1u << k;
+                    }
                 }
-            }
-            dout[p] = bestv;
-            cout[p] = (uint16_t)bestc;
-        }
-        __syncthreads();
-    }
-}
-
-template <int TH>
-__global__ __launch_bounds__(64 * TH) void k_median(const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix,
-                                                    int n, int total, int T, int M)
-{
-    const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
-    TILE_LOOP(total)
-    {
-        const int s = find_strip(prefix, n, t);
-        int local = t - prefix[s];
-        const StripLv &L = lv[s];
-        const int H = L.H, W = L.W, fp = L.fpitch;
-        const int ntx = ceil_div(W, kPropTW), per_dir = ntx * ceil_div(H, TH);
-        const int dir = local / per_dir;
-        local -= dir * per_dir;
-        const int tyi = local / ntx;
-        const int x = (local - tyi * ntx) * kPropTW + lane, y = tyi * TH + wrow;
-        if (x >= W || y >= H) continue;
-        const uint32_t *fin = T == 0 ? L.ds[dir] : L.dt[dir][(T - 1) & 1];
-        uint32_t outv;
-        if (M == 0) {
-            outv = fin[(size_t)y * fp + x];
-        } else {
-            int vx[9], vy[9];
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                const uint32_t *row = fin + (size_t)clampi(y + j - 1, 0, H - 1) * fp;
-#pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    const uint32_t v = row[clampi(x + i - 1, 0, W - 1)];
-                    vx[3 * j + i] = unpack_x(v);
-                    vy[3 * j + i] = unpack_y(v);
+                int wtotal;
+                const int pre = wave_prefix(__popc(need), wtotal);
+                int base = 0;
+                if (wtotal > 0) {  // wave-uniform
+                    if (rx == 0) base = atomicAdd(njobs, wtotal);
+                    base = __shfl(base, 0, 64);
                 }
+                int j = base + pre;
+#pragma unroll
+                for (int k = 1; k < 5; k++)
+                    if (need & (1u << k)) jobs[j++] = (uint16_t)((((ry << 6) | rx) << 2) | (k - 1));
             }
-            // median of 9 = med3(max of row minima, med3 of row medians, min of row maxima)
-            int mx, my;
-            {
-                int lo0 = min(min(vx[0], vx[1]), vx[2]), lo1 = min(min(vx[3], vx[4]), vx[5]),
-                    lo2 = min(min(vx[6], vx[7]), vx[8]);
-                int hi0 = max(max(vx[0], vx[1]), vx[2]), hi1 = max(max(vx[3], vx[4]), vx[5]),
-                    hi2 = max(max(vx[6], vx[7]), vx[8]);
-                int md0 = med3i(vx[0], vx[1], vx[2]), md1 = med3i(vx[3], vx[4], vx[5]),
-                    md2 = med3i(vx[6], vx[7], vx[8]);
-                mx = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
+            __syncthreads();
+            const int nj = *njobs;
+            for (int j = threadIdx.x; j < nj; j += NT) {
+                const int e = jobs[j];
+                const int k = (e & 3) + 1, jx = (e >> 2) & 63, jy = e >> 8;
+                const int i = jy * RW + jx;
+                const uint32_t v = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
+                const int px = gx0 + jx, py = gy0 + jy;
+                uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
+                load_rows<2 * P + 1, 2 * P + 1>(ref + (ptrdiff_t)(py - P) * yp, yp, px - P, rr);
+#pragma unroll
+                for (int r = 0; r < 2 * P + 1; r++) {
+                    if constexpr (P == 2) rr[r][1] &= 0xffu;
+                    else rr[r][0] &= 0x00ffffffu;
+                }
+                slot[4 * i + k - 1] = (uint16_t)patch_cost<P>(rr, tgt, H, W, yp, px, py, unpack_x(v), unpack_y(v));
             }
-            {
-                int lo0 = min(min(vy[0], vy[1]), vy[2]), lo1 = min(min(vy[3], vy[4]), vy[5]),
-                    lo2 = min(min(vy[6], vy[7]), vy[8]);
-                int hi0 = max(max(vy[0], vy[1]), vy[2]), hi1 = max(max(vy[3], vy[4]), vy[5]),
-                    hi2 = max(max(vy[6], vy[7]), vy[8]);
-                int md0 = med3i(vy[0], vy[1], vy[2]), md1 = med3i(vy[3], vy[4], vy[5]),
-                    md2 = med3i(vy[6], vy[7], vy[8]);
-                my = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
+            __syncthreads();
+            for (int ry = step + wave; ry < RH - step; ry += NW) {
+                const int y = gy0 + ry;
+                if (!xact || y < 0 || y >= H) continue;
+                const int i = ry * RW + rx;
+                uint32_t bestv = vp[i], bestc = cp[i];
+#pragma unroll
+                for (int k = 1; k < 5; k++) {
+                    const uint32_t c = slot[4 * i + k - 1];
+                    if (c < bestc) {
+                        bestc = c;
+                        bestv = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
+                    }
+                }
+                vn[i] = bestv;
+                cn[i] = (uint16_t)bestc;
             }
-            outv = pack16(mx, my);
+            if (threadIdx.x == 0) *njobs = 0;
+            __syncthreads();
+            uint32_t *tv = vp;
+            vp = vn;
+            vn = tv;
+            uint16_t *tc = cp;
+            cp = cn;
+            cn = tc;
         }
-        L.df[dir][(size_t)y * fp + x] = outv;
+        // median (or copy) of the output tile
+        const auto dst = gst(L.df[dir]);
+        if (xin && rx >= h && rx < h + OW) {
+            for (int ry = h + wave; ry < h + TH; ry += NW) {
+                const int y = gy0 + ry;
+                if (y >= H) break;
+                uint32_t outv;
+                if (M == 0) {
+                    outv = vp[ry * RW + rx];
+                } else {
+                    int vx[9], vy[9];
+#pragma unroll
+                    for (int j = 0; j < 3; j++) {
+                        const int rj = ry + clampi(y + j - 1, 0, H - 1) - y;
+#pragma unroll
+                        for (int i = 0; i < 3; i++) {
+                            const int ri = rx + clampi(x + i - 1, 0, W - 1) - x;
+                            const uint32_t v = vp[rj * RW + ri];
+                            vx[3 * j + i] = unpack_x(v);
+                            vy[3 * j + i] = unpack_y(v);
+                        }
+                    }
+                    // median of 9 = med3(max of row minima, med3 of row medians, min of row maxima)
+                    int mx, my;
+                    {
+                        int lo0 = min(min(vx[0], vx[1]), vx[2]), lo1 = min(min(vx[3], vx[4]), vx[5]),
+                            lo2 = min(min(vx[6], vx[7]), vx[8]);
+                        int hi0 = max(max(vx[0], vx[1]), vx[2]), hi1 = max(max(vx[3], vx[4]), vx[5]),
+                            hi2 = max(max(vx[6], vx[7]), vx[8]);
+                        int md0 = med3i(vx[0], vx[1], vx[2]), md1 = med3i(vx[3], vx[4], vx[5]),
+                            md2 = med3i(vx[6], vx[7], vx[8]);
+                        mx = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
+                    }
+                    {
+                        int lo0 = min(min(vy[0], vy[1]), vy[2]), lo1 = min(min(vy[3], vy[4]), vy[5]),
+                            lo2 = min(min(vy[6], vy[7]), vy[8]);
+                        int hi0 = max(max(vy[0], vy[1]), vy[2]), hi1 = max(max(vy[3], vy[4]), vy[5]),
+                            hi2 = max(max(vy[6], vy[7]), vy[8]);
+                        int md0 = med3i(vy[0], vy[1], vy[2]), md1 = med3i(vy[3], vy[4], vy[5]),
+                            md2 = med3i(vy[6], vy[7], vy[8]);
+                        my = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
+                    }
+                    outv = pack16(mx, my);
+                }
+                dst[(size_t)y * fp + x] = outv;
+            }
+        }
+        __syncthreads();  // the next tile reuses the LDS
     }
 }
 
 // --------------------------------------------------------------- refine
-// Level-0 Lucas-Kanade: central-difference gradient of Ref, normal matrix
-// summed over the window (exact in integers: 4H), plus eps I; `iters`
-// Gauss-Newton steps from the integer flow with bilinear Tgt samples; each
-// component clamped to within 1 px of the integer flow. The displacement
-// is split into floor + fraction so no FP32 coordinate is ever formed.
+// Level-0 Lucas-Kanade (step 4 of the flow): central-difference gradient
+// of Ref, normal matrix summed over the window plus eps I, `iters`
+// Gauss-Newton steps from the integer flow with bilinear Tgt samples, each
+// component clamped to within 1 px of the integer flow.
+//
+// Everything that depends only on bytes is an exact integer sum: with the
+// doubled gradients g = 2 grad A (integers), the window sums 4H = sum g g^T,
+// sum g A and, for an integer displacement d, the correlations
+// S(d) = sum g Tgt(q + d) are dot products of 16-bit pairs (v_dot2_i32_i16).
+// The bilinear sample is linear in its four corners, so the right-hand side
+// sum g (Tgt(q + u) - A) of a fractional u is the bilinear combination of
+// S(d) - sum g A over the corners d of the cell of u, formed in double with
+// the 2x2 solve. Window rows are padded to an even width with a zero
+// gradient, so the padding sample never contributes.
+//
 // A pixel whose window lies inside the image reads its Ref rows and its
-// (WN+1)^2 Tgt block straight from the padded planes; a pixel near the
-// border (its window positions are clamped, so they repeat) evaluates
-// every window position on its own.
+// (WN+1)^2 Tgt block from the padded planes; a pixel near the border (its
+// window positions are clamped and repeat), or whose Tgt block leaves the
+// padded border, evaluates every window position on its own.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int dot2(uint32_t a, uint32_t b, int c)
+{
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b), c, false);
+}
+__device__ __forceinline__ uint32_t sub2(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, a) - __builtin_bit_cast(s16x2, b));
+}
+__device__ __forceinline__ int lo16(uint32_t v) { return (int)(int16_t)(v & 0xffffu); }
+__device__ __forceinline__ int hi16(uint32_t v) { return (int)(int16_t)(v >> 16); }
+
+// bytes B, B+1 of a normalised row as a pair of 16-bit values; with Z the
+// second value is zero
+template <int B, bool Z, int NO>
+__device__ __forceinline__ uint32_t pair_at(const uint32_t (&t)[NO])
+{
+    constexpr int q = B >> 2, o = B & 3;
+    constexpr uint32_t sel = (uint32_t)o | 0x0c00u | (Z ? 0x0c0000u : (uint32_t)(o + 1) << 16) | 0x0c000000u;
+    static_assert(q < NO && (Z || o < 3 || q + 1 < NO), "pair outside the row");
+    if constexpr (Z || o < 3) return __builtin_amdgcn_perm(0u, t[q], sel);
+    else return __builtin_amdgcn_perm(t[q + 1], t[q], sel);
+}
+
+template <int NP, int K, int NO>
+__device__ __forceinline__ void odd_pairs(const uint32_t (&t)[NO], uint32_t (&o)[NP])
+{
+    // pairs of bytes (2k+1, 2k+2), the last one half zero
+    if constexpr (K < NP - 1) {
+        o[K] = pair_at<2 * K + 1, false>(t);
+        odd_pairs<NP, K + 1>(t, o);
+    } else {
+        o[K] = pair_at<2 * K + 1, true>(t);
+    }
+}
+template <int NP, int K, int NO>
+__device__ __forceinline__ void gx_pairs(const uint32_t (&t)[NO], uint32_t (&g)[NP])
+{
+    // byte 2k+2 minus byte 2k (and the next pair), the last one half zero
+    if constexpr (K < NP - 1) {
+        g[K] = sub2(pair_at<2 * K + 2, false>(t), pair_at<2 * K, false>(t));
+        gx_pairs<NP, K + 1>(t, g);
+    } else {
+        g[K] = sub2(pair_at<2 * K + 2, true>(t), pair_at<2 * K, true>(t));
+    }
+}
+template <int NP, int K, int NO>
+__device__ __forceinline__ void even_pairs(const uint32_t (&t)[NO], uint32_t (&e)[NP])
+{
+    e[K] = pair_at<2 * K, false>(t);
+    if constexpr (K + 1 < NP) even_pairs<NP, K + 1>(t, e);
+}
+template <int NP, int K, int NO>
+__device__ __forceinline__ void tgt_pairs(const uint32_t (&t)[NO], uint32_t (&e)[NP], uint32_t (&o)[NP])
+{
+    // pairs (2k, 2k+1) and (2k+1, 2k+2) of a Tgt row
+    e[K] = pair_at<2 * K, false>(t);
+    o[K] = pair_at<2 * K + 1, false>(t);
+    if constexpr (K + 1 < NP) tgt_pairs<NP, K + 1>(t, e, o);
+}
+
 template <int LP, int TH>
 __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
                                                     const int32_t *__restrict__ prefix, int n, int total, int iters,
                                                     float eps)
 {
     constexpr int TW = kRefineTW;
-    constexpr int WN = 2 * LP + 1;
-    constexpr int AB = WN + 2;  // Ref bytes per row (window + gradient taps)
+    constexpr int WN = 2 * LP + 1;  // window width
+    constexpr int NP = LP + 1;      // 16-bit pairs per window row (the last one half padding)
+    constexpr int AB = WN + 2;      // Ref bytes per row (window + gradient taps)
     const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
     TILE_LOOP(total)
     {
@@ -677,115 +832,154 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
             interior = false;
         }
         const uint8_t *A = L.y[dir], *B = L.y[1 - dir];
-        const uint32_t d0 = L.df[dir][(size_t)y * L.fpitch + x];
+        const uint32_t d0 = gld(L.df[dir])[(size_t)y * L.fpitch + x];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
 
-        // window: Ref value and doubled gradient at each (clamped) position
-        int av[WN][WN], gx[WN][WN], gy[WN][WN];
+        // doubled gradients and Ref values of the window as 16-bit pairs
+        uint32_t gxp[WN][NP], gyp[WN][NP], ap[WN][NP];
         if (interior) {
-            uint32_t ar[WN + 2][(AB + 3) / 4];
+            uint32_t op[WN + 2][NP], ar[WN + 2][(AB + 3) / 4];
+            load_rows<AB, WN + 2>(A + (ptrdiff_t)(y - LP - 1) * yp, yp, x - LP - 1, ar);
 #pragma unroll
-            for (int r = 0; r < WN + 2; r++) load_row<AB>(A + (ptrdiff_t)(y - LP - 1 + r) * yp, x - LP - 1, ar[r]);
+            for (int r = 0; r < WN + 2; r++) {
+                odd_pairs<NP, 0>(ar[r], op[r]);
+                if (r >= 1 && r <= WN) gx_pairs<NP, 0>(ar[r], gxp[r - 1]);
+            }
 #pragma unroll
             for (int j = 0; j < WN; j++)
 #pragma unroll
-                for (int i = 0; i < WN; i++) {
-                    av[j][i] = (int)byte_at(ar[j + 1], i + 1);
-                    gx[j][i] = (int)byte_at(ar[j + 1], i + 2) - (int)byte_at(ar[j + 1], i);
-                    gy[j][i] = (int)byte_at(ar[j + 2], i + 1) - (int)byte_at(ar[j], i + 1);
+                for (int k = 0; k < NP; k++) {
+                    ap[j][k] = op[j + 1][k];
+                    gyp[j][k] = sub2(op[j + 2][k], op[j][k]);
                 }
         } else {
 #pragma unroll
             for (int j = 0; j < WN; j++)
 #pragma unroll
-                for (int i = 0; i < WN; i++) {
-                    const int qx = clampi(x + i - LP, 0, W - 1), qy = clampi(y + j - LP, 0, H - 1);
-                    const uint8_t *rw = A + (ptrdiff_t)qy * yp;  // q +- 1 stays inside the border
-                    av[j][i] = rw[qx];
-                    gx[j][i] = (int)rw[qx + 1] - (int)rw[qx - 1];
-                    gy[j][i] = (int)rw[qx + yp] - (int)rw[qx - yp];
+                for (int k = 0; k < NP; k++) {
+                    uint32_t g0 = 0, g1 = 0, a0 = 0;
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        const int i = 2 * k + h;
+                        if (i >= WN) break;
+                        const int qx = clampi(x + i - LP, 0, W - 1), qy = clampi(y + j - LP, 0, H - 1);
+                        const uint8_t *rw = A + (ptrdiff_t)qy * yp;  // q +- 1 stays inside the border
+                        const uint32_t sh = 16u * h;
+                        a0 |= (uint32_t)rw[qx] << sh;
+                        g0 |= (uint32_t)(uint16_t)((int)rw[qx + 1] - (int)rw[qx - 1]) << sh;
+                        g1 |= (uint32_t)(uint16_t)((int)rw[qx + yp] - (int)rw[qx - yp]) << sh;
+                    }
+                    ap[j][k] = a0;
+                    gxp[j][k] = g0;
+                    gyp[j][k] = g1;
                 }
         }
-        int hxx = 0, hxy = 0, hyy = 0;
+        int hxx = 0, hxy = 0, hyy = 0, sax = 0, say = 0;
 #pragma unroll
         for (int j = 0; j < WN; j++)
 #pragma unroll
-            for (int i = 0; i < WN; i++) {
-                hxx += gx[j][i] * gx[j][i];
-                hxy += gx[j][i] * gy[j][i];
-                hyy += gy[j][i] * gy[j][i];
+            for (int k = 0; k < NP; k++) {
+                hxx = dot2(gxp[j][k], gxp[j][k], hxx);
+                hxy = dot2(gxp[j][k], gyp[j][k], hxy);
+                hyy = dot2(gyp[j][k], gyp[j][k], hyy);
+                sax = dot2(gxp[j][k], ap[j][k], sax);
+                say = dot2(gyp[j][k], ap[j][k], say);
             }
         const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
         const double det = Hxx * Hyy - Hxy * Hxy;
-        float ux = (float)d0x, uy = (float)d0y;
+        double ux = d0x, uy = d0y;
         for (int it = 0; it < iters; it++) {
-            const float fux = floorf(ux), fuy = floorf(uy);
-            const float fx = ux - fux, fy = uy - fuy;
+            const double fux = floor(ux), fuy = floor(uy);
+            const double fx = ux - fux, fy = uy - fuy;
             const int iux = (int)fux, iuy = (int)fuy;
-            float bxs = 0.f, bys = 0.f;
             const int c0 = x - LP + iux, r0 = y - LP + iuy;
-            if (it == 0 && interior && c0 >= -kPad && c0 + WN <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
-                // the first step starts from the integer flow: the samples are
-                // pixels (zero fractions), no interpolation
+            double bx, by;  // sum over the window of g (Tgt - A), g doubled
+            if (interior && c0 >= -kPad && c0 + WN + 1 <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
+                if (it == 0) {
+                    // the integer start: one corner
+                    int sx = 0, sy = 0;
+                    uint32_t tb[WN][(WN + 1 + 3) / 4];
+                    load_rows<WN + 1, WN>(B + (ptrdiff_t)r0 * yp, yp, c0, tb);
+#pragma unroll
+                    for (int j = 0; j < WN; j++) {
+                        uint32_t te[NP];
+                        even_pairs<NP, 0>(tb[j], te);
+#pragma unroll
+                        for (int k = 0; k < NP; k++) {
+                            sx = dot2(gxp[j][k], te[k], sx);
+                            sy = dot2(gyp[j][k], te[k], sy);
+                        }
+                    }
+                    bx = (double)(sx - sax);
+                    by = (double)(sy - say);
+                } else {
+                    int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
+                    uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
+                    load_rows<WN + 2, WN + 1>(B + (ptrdiff_t)r0 * yp, yp, c0, tb);
+#pragma unroll
+                    for (int r = 0; r <= WN; r++) {
+                        uint32_t te[NP], to[NP];
+                        tgt_pairs<NP, 0>(tb[r], te, to);
+#pragma unroll
+                        for (int k = 0; k < NP; k++) {
+                            if (r < WN) {
+                                s00x = dot2(gxp[r][k], te[k], s00x);
+                                s01x = dot2(gxp[r][k], to[k], s01x);
+                                s00y = dot2(gyp[r][k], te[k], s00y);
+                                s01y = dot2(gyp[r][k], to[k], s01y);
+                            }
+                            if (r > 0) {
+                                s10x = dot2(gxp[r - 1][k], te[k], s10x);
+                                s11x = dot2(gxp[r - 1][k], to[k], s11x);
+                                s10y = dot2(gyp[r - 1][k], te[k], s10y);
+                                s11y = dot2(gyp[r - 1][k], to[k], s11y);
+                            }
+                        }
+                    }
+                    const double tx = (double)(s00x - sax) + fx * (double)(s01x - s00x);
+                    const double bx1 = (double)(s10x - sax) + fx * (double)(s11x - s10x);
+                    const double ty = (double)(s00y - say) + fx * (double)(s01y - s00y);
+                    const double by1 = (double)(s10y - say) + fx * (double)(s11y - s10y);
+                    bx = tx + fy * (bx1 - tx);
+                    by = ty + fy * (by1 - ty);
+                }
+            } else {
+                bx = 0.0;
+                by = 0.0;
 #pragma unroll
                 for (int j = 0; j < WN; j++) {
-                    uint32_t br[(WN + 3) / 4];
-                    load_row<WN>(B + (ptrdiff_t)(r0 + j) * yp, c0, br);
+                    const int sy = clampi(y + j - LP, 0, H - 1) + iuy;
+                    const int oa = clampi(sy, 0, H - 1) * yp, ob = clampi(sy + 1, 0, H - 1) * yp;
 #pragma unroll
                     for (int i = 0; i < WN; i++) {
-                        const float e = (float)byte_at(br, i) - (float)av[j][i];
-                        bxs = fmaf(0.5f * (float)gx[j][i], e, bxs);
-                        bys = fmaf(0.5f * (float)gy[j][i], e, bys);
-                    }
-                }
-            } else if (interior && c0 >= -kPad && c0 + WN <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
-                // (WN+1)^2 block of Tgt with shared bilinear weights
-                float hrow[WN + 1][WN];
-#pragma unroll
-                for (int r = 0; r <= WN; r++) {
-                    uint32_t br[(WN + 1 + 3) / 4];
-                    load_row<WN + 1>(B + (ptrdiff_t)(r0 + r) * yp, c0, br);
-                    float prev = (float)byte_at(br, 0);
-#pragma unroll
-                    for (int c = 0; c < WN; c++) {
-                        const float nx = (float)byte_at(br, c + 1);
-                        hrow[r][c] = prev + fx * (nx - prev);
-                        prev = nx;
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < WN; j++)
-#pragma unroll
-                    for (int i = 0; i < WN; i++) {
-                        const float bs = hrow[j][i] + fy * (hrow[j + 1][i] - hrow[j][i]);
-                        const float e = bs - (float)av[j][i];
-                        bxs = fmaf(0.5f * (float)gx[j][i], e, bxs);
-                        bys = fmaf(0.5f * (float)gy[j][i], e, bys);
-                    }
-            } else {
-#pragma unroll
-                for (int j = 0; j < WN; j++)
-#pragma unroll
-                    for (int i = 0; i < WN; i++) {
-                        const int qx = clampi(x + i - LP, 0, W - 1), qy = clampi(y + j - LP, 0, H - 1);
-                        const int sx = qx + iux, sy = qy + iuy;
-                        const uint8_t *ra = B + (ptrdiff_t)clampi(sy, 0, H - 1) * yp;
-                        const uint8_t *rb = B + (ptrdiff_t)clampi(sy + 1, 0, H - 1) * yp;
+                        uint32_t gpx = gxp[j][i >> 1], gpy = gyp[j][i >> 1], apv = ap[j][i >> 1];
+                        // opaque copies: the conversions below are not hoisted
+                        // out of the iteration loop (75 live doubles otherwise)
+                        __asm__ volatile("" : "+v"(gpx), "+v"(gpy), "+v"(apv));
+                        const int gx = (i & 1) ? hi16(gpx) : lo16(gpx);
+                        const int gy = (i & 1) ? hi16(gpy) : lo16(gpy);
+                        const int av = (i & 1) ? hi16(apv) : lo16(apv);
+                        const int sx = clampi(x + i - LP, 0, W - 1) + iux;
                         const int xa = clampi(sx, 0, W - 1), xb = clampi(sx + 1, 0, W - 1);
-                        const float v00 = ra[xa], v01 = ra[xb], v10 = rb[xa], v11 = rb[xb];
-                        const float top = v00 + fx * (v01 - v00), bot = v10 + fx * (v11 - v10);
-                        const float e = top + fy * (bot - top) - (float)av[j][i];
-                        bxs = fmaf(0.5f * (float)gx[j][i], e, bxs);
-                        bys = fmaf(0.5f * (float)gy[j][i], e, bys);
+                        const float v00 = B[oa + xa], v01 = B[oa + xb], v10 = B[ob + xa], v11 = B[ob + xb];
+                        const float top = v00 + (float)fx * (v01 - v00), bot = v10 + (float)fx * (v11 - v10);
+                        const double e = (double)(top + (float)fy * (bot - top)) - (double)av;
+                        bx = fma((double)gx, e, bx);
+                        by = fma((double)gy, e, by);
                     }
+                    // keep the scheduler from hoisting the loads of every
+                    // window row (a rare path: registers matter more here)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
-            const double dx = -(Hyy * (double)bxs - Hxy * (double)bys) / det;
-            const double dy = -(Hxx * (double)bys - Hxy * (double)bxs) / det;
-            ux = fminf(fmaxf((float)((double)ux + dx), (float)(d0x - 1)), (float)(d0x + 1));
-            uy = fminf(fmaxf((float)((double)uy + dy), (float)(d0y - 1)), (float)(d0y + 1));
+            // the right-hand side of the normal equations is half of (bx, by)
+            const double dx = -0.5 * (Hyy * bx - Hxy * by) / det;
+            const double dy = -0.5 * (Hxx * by - Hxy * bx) / det;
+            ux = fmin(fmax(ux + dx, (double)(d0x - 1)), (double)(d0x + 1));
+            uy = fmin(fmax(uy + dy, (double)(d0y - 1)), (double)(d0y + 1));
         }
-        float2 *out = reinterpret_cast<float2 *>(io[s].flow[dir]);
-        out[(size_t)y * W + x] = make_float2(ux, uy);
+        const uint64_t packed = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
+        gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(size_t)y * W + x] = packed;
     }
 }
 
@@ -806,10 +1000,11 @@ __device__ __forceinline__ PixBlend blend_setup(int x, int y, int H, int W, int 
                                                 const float *flr, const float *frl, BlendParams bp)
 {
     const size_t p = (size_t)y * W + x;
-    const double t = blend ? (double)blend[p] : (axis == 0 ? (x + 1.0) / (W + 1.0) : (y + 1.0) / (H + 1.0));
-    const float2 vrl = reinterpret_cast<const float2 *>(frl)[p];
-    const float2 vlr = reinterpret_cast<const float2 *>(flr)[p];
-    const double rlx = finite0(vrl.x), rly = finite0(vrl.y), lrx = finite0(vlr.x), lry = finite0(vlr.y);
+    const double t = blend ? (double)gld(blend)[p] : (axis == 0 ? (x + 1.0) / (W + 1.0) : (y + 1.0) / (H + 1.0));
+    const uint64_t vrl = gld(reinterpret_cast<const uint64_t *>(frl))[p];
+    const uint64_t vlr = gld(reinterpret_cast<const uint64_t *>(flr))[p];
+    const double rlx = finite0(__uint_as_float((uint32_t)vrl)), rly = finite0(__uint_as_float((uint32_t)(vrl >> 32)));
+    const double lrx = finite0(__uint_as_float((uint32_t)vlr)), lry = finite0(__uint_as_float((uint32_t)(vlr >> 32)));
     const double ax = rlx * t, ay = rly * t, bx = lrx * (1.0 - t), by = lry * (1.0 - t);
     const double fax = floor(ax), fay = floor(ay), fbx = floor(bx), fby = floor(by);
     PixBlend r;
@@ -833,23 +1028,63 @@ __device__ __forceinline__ PixBlend blend_setup(int x, int y, int H, int W, int 
     return r;
 }
 
+// Bilinear RGB sample of a uint8 HWC image at (x0 + fx, y0 + fy) with
+// clamp-to-edge indices. When the two corner pixels of a row are distinct
+// and the dwords around them lie inside the image data, each row's 6
+// bytes come from one aligned dwordx3 load; otherwise byte by byte.
 __device__ __forceinline__ void sample_u8(const uint8_t *img, int pitch, int H, int W, int x0, int y0, float fx,
                                           float fy, float out[3])
 {
-    const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
     const uint8_t *ra = img + (size_t)clampi(y0, 0, H - 1) * pitch;
     const uint8_t *rb = img + (size_t)clampi(y0 + 1, 0, H - 1) * pitch;
+    float v[2][6];
+    const uintptr_t lo = (uintptr_t)img, hi = (uintptr_t)(img + (size_t)(H - 1) * pitch + 3 * (size_t)W);
+    const uintptr_t pa = (uintptr_t)(ra + 3 * x0), pb = (uintptr_t)(rb + 3 * x0);
+    const uintptr_t aa = pa & ~(uintptr_t)3, ab = pb & ~(uintptr_t)3;
+    if (x0 >= 0 && x0 + 1 <= W - 1 && aa >= lo && aa + 12 <= hi && ab >= lo && ab + 12 <= hi) {
+        const int s = (int)(pa - aa), t = (int)(pb - ab);
+        const auto qa = reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(aa);
+        const auto qb = reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(ab);
+        const uint32_t a0 = qa[0], a1 = qa[1], a2 = qa[2], b0 = qb[0], b1 = qb[1], b2 = qb[2];
+        const uint32_t ua = __builtin_amdgcn_alignbyte(a1, a0, s), wa = __builtin_amdgcn_alignbyte(a2, a1, s);
+        const uint32_t ub = __builtin_amdgcn_alignbyte(b1, b0, t), wb = __builtin_amdgcn_alignbyte(b2, b1, t);
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            v[0][c] = (float)((ua >> (8 * c)) & 0xffu);
+            v[1][c] = (float)((ub >> (8 * c)) & 0xffu);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            v[0][4 + c] = (float)((wa >> (8 * c)) & 0xffu);
+            v[1][4 + c] = (float)((wb >> (8 * c)) & 0xffu);
+        }
+    } else {
+        const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            v[0][c] = ra[3 * xa + c];
+            v[0][3 + c] = ra[3 * xb + c];
+            v[1][c] = rb[3 * xa + c];
+            v[1][3 + c] = rb[3 * xb + c];
+        }
+    }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        const float v00 = ra[3 * xa + c], v01 = ra[3 * xb + c], v10 = rb[3 * xa + c], v11 = rb[3 * xb + c];
-        const float top = v00 + fx * (v01 - v00), bot = v10 + fx * (v11 - v10);
+        const float top = v[0][c] + fx * (v[0][3 + c] - v[0][c]);
+        const float bot = v[1][c] + fx * (v[1][3 + c] - v[1][c]);
         out[c] = top + fy * (bot - top);
     }
 }
 
-__global__ __launch_bounds__(256) void k_blend(const StripIO *__restrict__ io, const int32_t *__restrict__ prefix,
-                                               int n, int total, BlendParams bp)
+// One workgroup per segment of kRowTW pixels of a row. The uint8 output of
+// the segment is staged in LDS at the byte alignment of its destination, so
+// that the segment is written with aligned dword stores (bytes only at its
+// two ends).
+__global__ __launch_bounds__(kRowTW) void k_blend(const StripIO *__restrict__ io, const int32_t *__restrict__ prefix,
+                                                  int n, int total, BlendParams bp)
 {
+    __shared__ uint32_t stage[(3 * kRowTW + 8) / 4];
+    uint8_t *sb = reinterpret_cast<uint8_t *>(stage);
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -858,21 +1093,39 @@ __global__ __launch_bounds__(256) void k_blend(const StripIO *__restrict__ io, c
         const int W = o.W, H = o.H;
         const int segs = ceil_div(W, kRowTW);
         const int y = local / segs;
-        const int x = (local - y * segs) * kRowTW + threadIdx.x;
-        if (x >= W) continue;
-        const PixBlend pb = blend_setup(x, y, H, W, o.axis, o.blend, o.flow[0], o.flow[1], bp);
-        float cl[3], cr[3];
-        sample_u8(o.L, o.pitchL, H, W, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
-        sample_u8(o.R, o.pitchR, H, W, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
-        const float sR = 1.0f - pb.sL;
-        uint8_t *fo = o.F + (size_t)y * o.pitchF + 3 * x;
+        const int xs = (local - y * segs) * kRowTW;
+        const int npx = min(kRowTW, W - xs);
+        const int x = xs + (int)threadIdx.x;
+        uint8_t *const seg = o.F + (size_t)y * o.pitchF + 3 * (size_t)xs;  // first output byte of the segment
+        const int off = (int)((uintptr_t)seg & 3);
+        if (x < W) {
+            const PixBlend pb = blend_setup(x, y, H, W, o.axis, o.blend, o.flow[0], o.flow[1], bp);
+            float cl[3], cr[3];
+            sample_u8(o.L, o.pitchL, H, W, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
+            sample_u8(o.R, o.pitchR, H, W, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
+            const float sR = 1.0f - pb.sL;
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-            const float f = pb.sL * cl[c] + sR * cr[c];
-            const float r = floorf(f + 0.5f);
-            fo[c] = (uint8_t)fminf(fmaxf(r, 0.f), 255.f);
-            if (o.Ff32) o.Ff32[3 * ((size_t)y * W + x) + c] = f;
+            for (int c = 0; c < 3; c++) {
+                const float f = pb.sL * cl[c] + sR * cr[c];
+                const float r = floorf(f + 0.5f);
+                sb[off + 3 * threadIdx.x + c] = (uint8_t)fminf(fmaxf(r, 0.f), 255.f);
+                if (o.Ff32) gst(o.Ff32)[3 * ((size_t)y * W + x) + c] = f;
+            }
         }
+        __syncthreads();
+        // bytes [off, off + nb) of the staging area go to seg - off + [off, off + nb)
+        const int nb = 3 * npx, end = off + nb;
+        const auto dst = reinterpret_cast<__attribute__((address_space(1))) uint32_t *>((uintptr_t)seg - off);
+        const int first = (off + 3) >> 2, last = end >> 2;  // whole dwords [first, last)
+        for (int k = first + (int)threadIdx.x; k < last; k += kRowTW) dst[k] = stage[k];
+        if (threadIdx.x < 8) {
+            // leading bytes [off, 4 first) and trailing bytes [4 last, end)
+            const int i = threadIdx.x < 4 ? off + (int)threadIdx.x : 4 * last + (int)threadIdx.x - 4;
+            const bool lead = threadIdx.x < 4 && i < min(4 * first, end);
+            const bool trail = threadIdx.x >= 4 && i >= max(4 * last, 4 * first) && i < end;
+            if (lead || trail) gst(seg - off)[i] = sb[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -940,37 +1193,23 @@ hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int t
 }
 
 template <int P>
-static hipError_t prop_th(const StripLv *lv, Work w, int step, int steps, int median, int th, int grid,
-                          hipStream_t s)
+static hipError_t prop_th(const StripLv *lv, Work w, int steps, int median, int th, int grid, hipStream_t s)
 {
     const int g = grid_for(w.total, grid);
-    if (step == 0) {
-        switch (th) {
-        case 1: hipLaunchKernelGGL((k_median<1>), dim3(g), dim3(64), 0, s, lv, w.prefix, w.n, w.total, steps, median); break;
-        case 2: hipLaunchKernelGGL((k_median<2>), dim3(g), dim3(128), 0, s, lv, w.prefix, w.n, w.total, steps, median); break;
-        default: hipLaunchKernelGGL((k_median<4>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total, steps, median); break;
-        }
-        return hipGetLastError();
-    }
-    switch (th) {
-    case 1:
-        hipLaunchKernelGGL((k_prop_step<P, 1>), dim3(g), dim3(64), 0, s, lv, w.prefix, w.n, w.total, step, steps, median);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_prop_step<P, 2>), dim3(g), dim3(128), 0, s, lv, w.prefix, w.n, w.total, step, steps, median);
-        break;
-    default:
-        hipLaunchKernelGGL((k_prop_step<P, 4>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total, step, steps, median);
-        break;
-    }
+    const size_t lds = prop_lds_bytes(steps + median, th);
+    if (th == 8)
+        hipLaunchKernelGGL((k_prop<P, 8>), dim3(g), dim3(kPropThreads), lds, s, lv, w.prefix, w.n, w.total, steps,
+                           median);
+    else
+        hipLaunchKernelGGL((k_prop<P, 16>), dim3(g), dim3(kPropThreads), lds, s, lv, w.prefix, w.n, w.total, steps,
+                           median);
     return hipGetLastError();
 }
 
-hipError_t launch_prop(const StripLv *lv, Work w, int patch, int step, int steps, int median, int th, int grid,
-                       hipStream_t s)
+hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid, hipStream_t s)
 {
-    if (patch == 1) return prop_th<1>(lv, w, step, steps, median, th, grid, s);
-    if (patch == 2) return prop_th<2>(lv, w, step, steps, median, th, grid, s);
+    if (patch == 1) return prop_th<1>(lv, w, steps, median, th, grid, s);
+    if (patch == 2) return prop_th<2>(lv, w, steps, median, th, grid, s);
     return hipErrorInvalidValue;
 }
 

@@ -112,7 +112,7 @@ void default_launch(abf_plan *pl)
     for (int s = 0; s < kStages; s++)
         for (int c = 0; c < kSizeClasses; c++) pl->launch[s][c] = {4, 0};
     for (int c = 0; c < kSizeClasses; c++) {
-        pl->launch[ST_PROP][c].tile_h = 4;
+        pl->launch[ST_PROP][c].tile_h = 16;
         pl->launch[ST_REFINE][c].tile_h = 4;
     }
 }
@@ -121,7 +121,7 @@ bool valid_th(int stage, int th)
 {
     switch (stage) {
     case ST_SEARCH: return th == 1 || th == 2 || th == 4 || th == 8;
-    case ST_PROP: return th == 1 || th == 2 || th == 4;
+    case ST_PROP: return th == 8 || th == 16;
     case ST_REFINE: return th == 2 || th == 4;
     default: return th == 4;
     }
@@ -172,9 +172,9 @@ size_t data_bound(const abf_plan *pl)
     for (int k = 0; k < N; k++) {
         const double f = std::ldexp(1.0, -k);
         b += 2 * (mp * f * f + S * ((Wm * f) * pd + (64 + pd) * (Hm * f + pd) + 384));
-        // per direction: 4 int16-pair buffers and 3 cost buffers
-        b += 2 * 4 * (4 * mp * f * f + S * (4 * Wm * f + 64 * Hm * f + 68 + 256));
-        b += 2 * 3 * (2 * mp * f * f + S * (2 * Wm * f + 32 * Hm * f + 34 + 256));
+        // per direction: 2 int16-pair buffers (search, final) and 1 cost buffer
+        b += 2 * 2 * (4 * mp * f * f + S * (4 * Wm * f + 64 * Hm * f + 68 + 256));
+        b += 2 * 1 * (2 * mp * f * f + S * (2 * Wm * f + 32 * Hm * f + 34 + 256));
     }
     b += S * kAlign;  // exposure sums
     return align_up((size_t)b + 4096, kAlign);
@@ -200,7 +200,7 @@ int stage_tiles(const abf_plan *pl, int stage, int cls, int H, int W)
     case ST_LUMA: return tiles_luma(H, W);
     case ST_PYR: return 2 * tiles_pyr(H, W);
     case ST_SEARCH: return tiles_search(H, W, th);
-    case ST_PROP: return tiles_prop(H, W, th);
+    case ST_PROP: return tiles_prop(H, W, th, pl->p.prop_steps + pl->p.median);
     case ST_REFINE: return tiles_refine(H, W, th, pl->p.lk_patch);
     default: return tiles_blend(H, W);
     }
@@ -301,12 +301,6 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
                 off += fb;
                 v.cs[d] = reinterpret_cast<uint16_t *>(pl->ws + off);
                 off += cb;
-                for (int q = 0; q < 2; q++) {
-                    v.dt[d][q] = reinterpret_cast<uint32_t *>(pl->ws + off);
-                    off += fb;
-                    v.ct[d][q] = reinterpret_cast<uint16_t *>(pl->ws + off);
-                    off += cb;
-                }
             }
             v.radius = k == N - 1 ? pl->p.radius_coarse : pl->p.radius;
         }
@@ -436,14 +430,9 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
             TIMED(ST_SEARCH, k,
                   launch_search(lv + (size_t)k * n, work(ST_SEARCH, k), p.patch, r, pl->launch[ST_SEARCH][c].tile_h,
                                 grid_of(pl, ST_SEARCH, c), s));
-            for (int step = 1; step <= p.prop_steps; step++)
-                TIMED(ST_PROP, k,
-                      launch_prop(lv + (size_t)k * n, work(ST_PROP, k), p.patch, step, p.prop_steps, p.median,
-                                  pl->launch[ST_PROP][c].tile_h, grid_of(pl, ST_PROP, c), s));
-            if (p.median > 0 || p.prop_steps == 0)
-                TIMED(ST_PROP, k,
-                      launch_prop(lv + (size_t)k * n, work(ST_PROP, k), p.patch, 0, p.prop_steps, p.median,
-                                  pl->launch[ST_PROP][c].tile_h, grid_of(pl, ST_PROP, c), s));
+            TIMED(ST_PROP, k,
+                  launch_prop(lv + (size_t)k * n, work(ST_PROP, k), p.patch, p.prop_steps, p.median,
+                              pl->launch[ST_PROP][c].tile_h, grid_of(pl, ST_PROP, c), s));
         }
         LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
         TIMED(ST_REFINE, 0,
@@ -777,7 +766,7 @@ abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hi
     for (int stage = 0; stage < kStages && rc == ABF_OK; stage++)
         for (int c = 0; c < kSizeClasses && rc == ABF_OK; c++) {
             std::vector<int> ths;
-            for (int th : {1, 2, 4, 8})
+            for (int th : {1, 2, 4, 8, 16})
                 if (valid_th(stage, th)) ths.push_back(th);
             Launch best = plan->launch[stage][c];
             float best_ms = 1e30f;

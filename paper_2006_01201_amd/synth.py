@@ -358,12 +358,13 @@ def random_levels(seed: int, shape, levels: int) -> np.ndarray:
 
 # ---------------------------------------------------------------------------
 # Device-side evaluation for large streams (the 32-panorama workload): the
-# same recipe and the same parameter draws as ``make_config_strip``, with
-# the per-pixel work (texture, smoothing of the flow noise, warp, sensor
-# noise) evaluated by torch on the GPU. Sensor noise comes from a torch
-# generator seeded from the strip's generator, so the images are not bit
-# for bit those of the CPU path; they are used for throughput runs, not for
-# parity.
+# recipe of ``make_config_strip`` with the per-pixel work (texture,
+# smoothing of the flow noise, warp, sensor noise) evaluated by torch on
+# the GPU. Two departures keep it fast and free of host synchronisation:
+# the flow noise is drawn on a fixed FFT grid and cropped, and the sensor
+# noise comes from a torch generator seeded from the strip's generator. The
+# images are therefore not bit for bit those of the CPU path; they are used
+# for throughput runs, not for parity.
 
 def _texture_torch(tex: Texture, x, y):
     import torch
@@ -376,23 +377,31 @@ def _texture_torch(tex: Texture, x, y):
         arg = (two_pi * tex.freq[k]) * (x * np.cos(tex.theta[k]) + y * np.sin(tex.theta[k]))
         arg = (arg - two_pi * torch.round(arg / two_pi)).float()
         s, c = torch.sin(arg), torch.cos(arg)
-        for ch in range(3):
-            out[..., ch] += float(tex.amp[k]) * (s * cph[k, ch] + c * sph[k, ch])
+        out += float(tex.amp[k]) * (s[..., None] * cph[k] + c[..., None] * sph[k])
+    # rectangles composited arithmetically (no boolean indexing, which
+    # would synchronise with the host once per rectangle)
     for r in range(len(tex.rects)):
         x0, y0, x1, y1 = tex.rects[r]
-        m = (x >= x0) & (x < x1) & (y >= y0) & (y < y1)
-        out[m] += torch.tensor(tex.offset[r], dtype=torch.float32, device=x.device)
+        m = ((x >= x0) & (x < x1) & (y >= y0) & (y < y1)).float()
+        out += m[..., None] * torch.tensor(tex.offset[r], dtype=torch.float32, device=x.device)
     return out
+
+
+# FFT sizes of the flow-noise fields: every strip's field is cut from a
+# field smoothed on one of these periodic grids, so only two transform
+# shapes are ever planned on the device
+_FIELD_GRIDS = ((4096, 1024), (9216, 1024))
 
 
 def _smooth_field_torch(rng, H, W, sigma, max_abs, device):
     import torch
 
-    noise = torch.from_numpy(rng.standard_normal((H, W))).to(device)
-    fy = torch.fft.fftfreq(H, device=device, dtype=torch.float64)[:, None]
-    fx = torch.fft.rfftfreq(W, device=device, dtype=torch.float64)[None, :]
+    gh, gw = next(((a, b) for a, b in _FIELD_GRIDS if H <= a and W <= b), (H, W))
+    noise = torch.from_numpy(rng.standard_normal((gh, gw)).astype(np.float32)).to(device)
+    fy = torch.fft.fftfreq(gh, device=device)[:, None]
+    fx = torch.fft.rfftfreq(gw, device=device)[None, :]
     g = torch.exp(-2.0 * np.pi ** 2 * sigma ** 2 * (fx ** 2 + fy ** 2))
-    f = torch.fft.irfft2(torch.fft.rfft2(noise) * g, s=(H, W))
+    f = torch.fft.irfft2(torch.fft.rfft2(noise) * g, s=(gh, gw))[:H, :W].double()
     m = f.abs().max()
     return f * (max_abs / m) if float(m) > 0 else f
 
@@ -422,10 +431,10 @@ def make_config_strip_device(cfg: int, pano: int, strip: int, device="cuda"):
                             torch.arange(w, device=device, dtype=torch.float64), indexing="ij")
     Lf = _texture_torch(tex, xx, yy)
     Rf = gain * _texture_torch(tex, xx + ux, yy + uy)
-    in_l = (xx >= xb) & (xx < xb + wb)
-    Lf[in_l] = _texture_torch(tex_o, xx[in_l], yy[in_l])
-    in_r = (xx + dob >= xb) & (xx + dob < xb + wb)
-    Rf[in_r] = gain * _texture_torch(tex_o, xx[in_r] + dob, yy[in_r])
+    in_l = ((xx >= xb) & (xx < xb + wb))[..., None]
+    Lf = torch.where(in_l, _texture_torch(tex_o, xx, yy), Lf)
+    in_r = ((xx + dob >= xb) & (xx + dob < xb + wb))[..., None]
+    Rf = torch.where(in_r, gain * _texture_torch(tex_o, xx + dob, yy), Rf)
     Lf += 2.0 * torch.randn(Lf.shape, generator=gen, device=device)
     Rf += 2.0 * torch.randn(Rf.shape, generator=gen, device=device)
     L = Lf.round_().clamp_(0, 255).to(torch.uint8)

@@ -219,3 +219,28 @@ def test_plan_limits_are_enforced(api):
         plan.flow_bidirectional(L, L)
     with pytest.raises(ValueError):
         plan.flow_bidirectional(L[:, :, :2], L[:, :, :2])
+
+
+@pytest.mark.parametrize("pad,start", [(1, 0), (2, 1), (3, 3), (5, 2)])
+def test_blend_into_pitched_output(api, pad, start):
+    # F written into a view of a larger buffer: every row starts at another
+    # byte alignment; the view's bytes equal a contiguous output and the
+    # bytes around it stay untouched
+    L, R, axis, levels = CASES["ragged_37x53"]()
+    H, W = L.shape[:2]
+    p = api.Params(levels=levels)
+    op = o_params(p)
+    o_lr, o_rl = oracle.flow_bidirectional(L, R, op)
+    args = (to_dev(L), to_dev(R), to_dev(o_lr.astype(np.float32)), to_dev(o_rl.astype(np.float32)))
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W)
+    print(f"[gpu] blend pitched output pad {pad} start {start}", flush=True)
+    ref = plan.blend_asymmetric(*args, axis=axis)
+    big = torch.full((H, W + pad, 3), 77, dtype=torch.uint8, device="cuda")
+    view = big[:, start:start + W]
+    plan.blend_asymmetric(*args, axis=axis, out=view)
+    torch.cuda.synchronize()
+    b = big.cpu().numpy()
+    assert np.array_equal(b[:, start:start + W], ref.cpu().numpy())
+    outside = np.ones((H, W + pad), bool)
+    outside[:, start:start + W] = False
+    assert (b[outside] == 77).all()
