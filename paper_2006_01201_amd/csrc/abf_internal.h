@@ -12,10 +12,16 @@ constexpr int kMaxLevels = 12;
 // window that leaves the image by up to kPad pixels reads exactly the
 // clamp-to-edge values without per-access clamping.
 constexpr int kPad = 64;
+// bytes of slack before (and after) every padded plane: the aligned row
+// loads may read up to 3 bytes outside the padded rows
+constexpr int kPlaneLead = 64;
 constexpr int kStages = 6;       // luma, pyramid, search, propagation, refine, blend
 constexpr int kSizeClasses = 4;  // by pixel count of one level over the batch
 
 enum Stage { ST_LUMA = 0, ST_PYR = 1, ST_SEARCH = 2, ST_PROP = 3, ST_REFINE = 4, ST_BLEND = 5 };
+// work lists: one per stage plus the refinement's border pixels
+constexpr int kLists = kStages + 1;
+constexpr int LIST_REFINE_BORDER = kStages;
 
 // One strip at one pyramid level, as the kernels see it. Direction d uses
 // y[d] as Ref and y[1 - d] as Tgt (d = 0: LtoR, d = 1: RtoL). Integer
@@ -91,7 +97,8 @@ hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s);
 hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int th, int grid, hipStream_t s);
 // the T propagation steps and the median of one level (one launch)
 hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid, hipStream_t s);
-hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid,
+// refine: interior tiles (work list wi) and border pixels (work list wb)
+hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work wi, Work wb, LkParams lk, int th, int grid,
                          hipStream_t s);
 hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s);
 
@@ -141,11 +148,12 @@ __host__ __device__ inline int tiles_prop(int H, int W, int th, int h)
     return 2 * ceil_div(H, th) * ceil_div(W, kPropRW - 2 * h);
 }
 __host__ __device__ inline size_t prop_lds_bytes(int h, int th) { return (size_t)kPropRW * (th + 2 * h) * 28 + 16; }
-// refine: interior tiles (window inside the image) then border tiles of
-// 64 th pixels enumerated along the border band, per direction
+// refine: tiles of 64 x th pixels over the interior rectangle (window
+// inside the image) per direction; the border band around it (per
+// direction) in tiles of kRowTW pixels enumerated along the band
 struct RefineSplit {
     int ylo, yhi, xlo, xhi;  // interior rows [ylo, yhi), columns [xlo, xhi)
-    int nint, nbord, nbp;    // interior tiles, border tiles, border pixels
+    int nint, nbp;           // interior tiles, border pixels
 };
 __host__ __device__ inline RefineSplit refine_split(int H, int W, int th, int lp)
 {
@@ -156,13 +164,12 @@ __host__ __device__ inline RefineSplit refine_split(int H, int W, int th, int lp
     r.xhi = W - lp > r.xlo ? W - lp : r.xlo;
     r.nint = ceil_div(r.yhi - r.ylo, th) * ceil_div(r.xhi - r.xlo, kRefineTW);
     r.nbp = H * W - (r.yhi - r.ylo) * (r.xhi - r.xlo);
-    r.nbord = ceil_div(r.nbp, kRefineTW * th);
     return r;
 }
-__host__ __device__ inline int tiles_refine(int H, int W, int th, int lp)
+__host__ __device__ inline int tiles_refine(int H, int W, int th, int lp) { return 2 * refine_split(H, W, th, lp).nint; }
+__host__ __device__ inline int tiles_refine_border(int H, int W, int lp)
 {
-    const RefineSplit r = refine_split(H, W, th, lp);
-    return 2 * (r.nint + r.nbord);
+    return 2 * ceil_div(refine_split(H, W, 1, lp).nbp, kRowTW);
 }
 __host__ __device__ inline int tiles_blend(int H, int W) { return H * ceil_div(W, kRowTW); }
 

@@ -72,50 +72,63 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p)
     return (__attribute__((address_space(1))) T *)(void *)p;
 }
 
-// Bytes c .. c+NB-1 of a padded luma row, normalised so that out[k] holds
-// bytes c+4k .. c+4k+3. The row must hold those bytes (|c| <= kPad away).
-template <int NB>
-__device__ __forceinline__ void load_row(const uint8_t *__restrict__ row, int c, uint32_t (&out)[(NB + 3) / 4])
+// Offset of pixel (r, c), r, c >= -kPad, of a padded plane from the
+// plane's origin (its first allocated byte). Window loads address a plane
+// as a uniform origin plus a 32-bit offset, which the global loads take
+// as a scalar base and a 32-bit vector offset (no 64-bit address
+// arithmetic per row).
+__device__ __forceinline__ const uint8_t *plane_org(const uint8_t *y, int pitch)
 {
-    constexpr int NO = (NB + 3) / 4;
-    constexpr int ND = (NB + 6) / 4;  // dwords covering NB bytes at any alignment
-    const int a = c & ~3;             // floor to a multiple of 4 (two's complement)
-    const int s = c - a;
-    // global address space: the loads count on vmcnt only and return in
-    // order, so a use waits for its own row and not for every load in flight
-    const gu32 *p = (const gu32 *)(const void *)(row + a);
-    uint32_t w[ND + 1];
-#pragma unroll
-    for (int k = 0; k < ND; k++) w[k] = p[k];
-    w[ND] = 0;
-#pragma unroll
-    for (int k = 0; k < NO; k++) out[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], s);
+    return y - (kPlaneLead + (ptrdiff_t)pitch * kPad + kPad);
+}
+__device__ __forceinline__ uint32_t pix_off(int pitch, int r, int c)
+{
+    return (uint32_t)(kPlaneLead + (r + kPad) * pitch + c + kPad);
 }
 
-// NR consecutive rows of the same columns (row r at base + r * pitch): all
-// loads are issued before the first row is normalised, so the rows are in
-// flight together rather than one round trip each
+// Bytes c .. c+NB-1 of NR consecutive rows r0 .. r0+NR-1 of a padded
+// plane (origin org), normalised so that out[r][k] holds bytes c+4k ..
+// c+4k+3 of row r0+r; the rows must hold those bytes (|c| <= kPad away
+// from the image). Split into issuing the aligned dword loads and
+// normalising them, so that several blocks can be in flight together;
+// load_rows does both, with all loads issued before the first row is
+// normalised.
+template <int NB>
+struct RawRows {
+    static constexpr int ND = (NB + 6) / 4;  // dwords covering NB bytes at any alignment
+};
 template <int NB, int NR>
-__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ base, int pitch, int c,
-                                          uint32_t (&out)[NR][(NB + 3) / 4])
+__device__ __forceinline__ int issue_rows(const uint8_t *__restrict__ org, int pitch, int r0, int c,
+                                          uint32_t (&w)[NR][RawRows<NB>::ND + 1])
 {
-    constexpr int NO = (NB + 3) / 4;
-    constexpr int ND = (NB + 6) / 4;
-    const int a = c & ~3;
-    const int s = c - a;
-    uint32_t w[NR][ND + 1];
+    constexpr int ND = RawRows<NB>::ND;
+    const uint32_t off = pix_off(pitch, r0, c), a = off & ~3u;
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        const gu32 *p = (const gu32 *)(const void *)(base + (ptrdiff_t)r * pitch + a);
+        const gu32 *p = (const gu32 *)(const void *)(org + (a + (uint32_t)(r * pitch)));
 #pragma unroll
         for (int k = 0; k < ND; k++) w[r][k] = p[k];
         w[r][ND] = 0;
     }
-    __builtin_amdgcn_sched_barrier(0);
+    return (int)(off - a);
+}
+template <int NB, int NR>
+__device__ __forceinline__ void align_rows(const uint32_t (&w)[NR][RawRows<NB>::ND + 1], int s,
+                                           uint32_t (&out)[NR][(NB + 3) / 4])
+{
 #pragma unroll
     for (int r = 0; r < NR; r++)
 #pragma unroll
-        for (int k = 0; k < NO; k++) out[r][k] = __builtin_amdgcn_alignbyte(w[r][k + 1], w[r][k], s);
+        for (int k = 0; k < (NB + 3) / 4; k++) out[r][k] = __builtin_amdgcn_alignbyte(w[r][k + 1], w[r][k], s);
+}
+template <int NB, int NR>
+__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ org, int pitch, int r0, int c,
+                                          uint32_t (&out)[NR][(NB + 3) / 4])
+{
+    uint32_t w[NR][RawRows<NB>::ND + 1];
+    const int s = issue_rows<NB, NR>(org, pitch, r0, c, w);
+    __builtin_amdgcn_sched_barrier(0);
+    align_rows<NB, NR>(w, s, out);
 }
 
 // The same bytes with every index clamped to the image (for windows that
@@ -378,13 +391,13 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
         }
         // reference rows y-P .. y+P, columns x-P .. x+1+P
         uint32_t rr[2 * P + 1][(RB + 3) / 4];
-        load_rows<RB, 2 * P + 1>(ref + (ptrdiff_t)(y - P) * yp, yp, x - P, rr);
+        load_rows<RB, 2 * P + 1>(plane_org(ref, yp), yp, y - P, x - P, rr);
         // target rows, columns x+cx-R-P .. x+cx+R+P+1
         const int c0 = x + cx - R - P, r0 = y + cy - R - P;
         const bool inpad = c0 >= -kPad && c0 + NB - 1 <= W - 1 + kPad && r0 >= -kPad && r0 + NR - 1 <= H - 1 + kPad;
         uint32_t tt[NR][NBO];
         if (inpad) {
-            load_rows<NB, NR>(tgt + (ptrdiff_t)r0 * yp, yp, c0, tt);
+            load_rows<NB, NR>(plane_org(tgt, yp), yp, r0, c0, tt);
         } else {
 #pragma unroll
             for (int k = 0; k < NR; k++) load_row_clamped<NB>(tgt, H, W, yp, r0 + k, c0, tt[k]);
@@ -473,7 +486,7 @@ __device__ __forceinline__ uint32_t patch_cost(const uint32_t (&rr)[2 * P + 1][(
     const bool inpad = c0 >= -kPad && c0 + NB - 1 <= W - 1 + kPad && r0 >= -kPad && r0 + NB - 1 <= H - 1 + kPad;
     uint32_t t[NB][(NB + 3) / 4];
     if (inpad) {
-        load_rows<NB, NB>(tgt + (ptrdiff_t)r0 * yp, yp, c0, t);
+        load_rows<NB, NB>(plane_org(tgt, yp), yp, r0, c0, t);
     } else {
 #pragma unroll
         for (int r = 0; r < NB; r++) load_row_clamped<NB>(tgt, H, W, yp, r0 + r, c0, t[r]);
@@ -552,19 +565,31 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict
         const int x = gx0 + rx;
         const bool xin = x >= 0 && x < W;
         {
+            // all loads of a thread's region rows first, then the LDS writes
+            constexpr int NQ = (TH + 2 * 5 + NW - 1) / NW;  // rows per wave at the largest halo
             const auto din = gld(L.ds[dir]);
             const auto cin = gld(L.cs[dir]);
-            for (int ry = wave; ry < RH; ry += NW) {
-                const int y = gy0 + ry;
-                if (xin && y >= 0 && y < H) {
-                    vp[ry * RW + rx] = din[(size_t)y * fp + x];
-                    cp[ry * RW + rx] = cin[(size_t)y * fp + x];
+            uint32_t tv[NQ], tc[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                const int ry = wave + q * NW, y = gy0 + ry;
+                const bool in = xin && ry < RH && y >= 0 && y < H;
+                tv[q] = in ? din[(size_t)y * fp + x] : 0u;
+                tc[q] = in ? cin[(size_t)y * fp + x] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                const int ry = wave + q * NW;
+                if (ry < RH) {
+                    vp[ry * RW + rx] = tv[q];
+                    cp[ry * RW + rx] = (uint16_t)tc[q];
                 }
             }
         }
         if (threadIdx.x == 0) *njobs = 0;
         __syncthreads();
         const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
+        const uint8_t *refo = plane_org(ref, yp), *tgto = plane_org(tgt, yp);
         for (int step = 1; step <= T; step++) {
             const bool xact = xin && rx >= step && rx < RW - step;
             for (int ry0 = step; ry0 < RH - step; ry0 += NW) {
@@ -608,20 +633,67 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict
             }
             __syncthreads();
             const int nj = *njobs;
-            for (int j = threadIdx.x; j < nj; j += NT) {
-                const int e = jobs[j];
-                const int k = (e & 3) + 1, jx = (e >> 2) & 63, jy = e >> 8;
-                const int i = jy * RW + jx;
-                const uint32_t v = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
-                const int px = gx0 + jx, py = gy0 + jy;
-                uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
-                load_rows<2 * P + 1, 2 * P + 1>(ref + (ptrdiff_t)(py - P) * yp, yp, px - P, rr);
+            // two jobs per iteration, the Ref and Tgt rows of both in flight together
+            for (int j = threadIdx.x; j < nj; j += 2 * NT) {
+                int sl[2], px[2], py[2], dx[2], dy[2];
+                bool inpad = true;
 #pragma unroll
-                for (int r = 0; r < 2 * P + 1; r++) {
-                    if constexpr (P == 2) rr[r][1] &= 0xffu;
-                    else rr[r][0] &= 0x00ffffffu;
+                for (int q = 0; q < 2; q++) {
+                    const int e = jobs[min(j + q * NT, nj - 1)];
+                    const int k = (e & 3) + 1, jx = (e >> 2) & 63, jy = e >> 8;
+                    const int i = jy * RW + jx;
+                    const uint32_t v = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
+                    sl[q] = 4 * i + k - 1;
+                    px[q] = gx0 + jx;
+                    py[q] = gy0 + jy;
+                    dx[q] = unpack_x(v);
+                    dy[q] = unpack_y(v);
+                    const int c0 = px[q] + dx[q] - P, r0 = py[q] + dy[q] - P;
+                    inpad &= c0 >= -kPad && c0 + 2 * P <= W - 1 + kPad && r0 >= -kPad && r0 + 2 * P <= H - 1 + kPad;
                 }
-                slot[4 * i + k - 1] = (uint16_t)patch_cost<P>(rr, tgt, H, W, yp, px, py, unpack_x(v), unpack_y(v));
+                uint32_t cost[2];
+                if (inpad) {
+                    constexpr int NB = 2 * P + 1, ND = RawRows<NB>::ND;
+                    uint32_t wr[2][NB][ND + 1], wt[2][NB][ND + 1];
+                    int sr[2], st[2];
+#pragma unroll
+                    for (int q = 0; q < 2; q++) {
+                        sr[q] = issue_rows<NB, NB>(refo, yp, py[q] - P, px[q] - P, wr[q]);
+                        st[q] = issue_rows<NB, NB>(tgto, yp, py[q] + dy[q] - P, px[q] + dx[q] - P, wt[q]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int q = 0; q < 2; q++) {
+                        uint32_t rr[NB][(NB + 3) / 4], tt[NB][(NB + 3) / 4];
+                        align_rows<NB, NB>(wr[q], sr[q], rr);
+                        align_rows<NB, NB>(wt[q], st[q], tt);
+                        uint32_t c = 0;
+#pragma unroll
+                        for (int r = 0; r < NB; r++) {
+                            if constexpr (P == 2) {
+                                c = __builtin_amdgcn_sad_u8(rr[r][0], tt[r][0], c);
+                                c = __builtin_amdgcn_sad_u8(rr[r][1] & 0xffu, tt[r][1] & 0xffu, c);
+                            } else {
+                                c = __builtin_amdgcn_sad_u8(rr[r][0] & 0x00ffffffu, tt[r][0] & 0x00ffffffu, c);
+                            }
+                        }
+                        cost[q] = c;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 2; q++) {
+                        uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
+                        load_rows<2 * P + 1, 2 * P + 1>(refo, yp, py[q] - P, px[q] - P, rr);
+#pragma unroll
+                        for (int r = 0; r < 2 * P + 1; r++) {
+                            if constexpr (P == 2) rr[r][1] &= 0xffu;
+                            else rr[r][0] &= 0x00ffffffu;
+                        }
+                        cost[q] = patch_cost<P>(rr, tgt, H, W, yp, px[q], py[q], dx[q], dy[q]);
+                    }
+                }
+                slot[sl[0]] = (uint16_t)cost[0];
+                if (j + NT < nj) slot[sl[1]] = (uint16_t)cost[1];
             }
             __syncthreads();
             for (int ry = step + wave; ry < RH - step; ry += NW) {
@@ -799,47 +871,24 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
         const StripLv &L = lv[s];
         const int H = L.H, W = L.W, yp = L.ypitch;
         const RefineSplit sp = refine_split(H, W, TH, LP);
-        const int per_dir = sp.nint + sp.nbord;
-        const int dir = local / per_dir;
-        local -= dir * per_dir;
-        int x, y;
-        bool interior;
-        if (local < sp.nint) {  // a tile of the interior rectangle
-            const int ntx = ceil_div(sp.xhi - sp.xlo, TW);
-            const int tyi = local / ntx;
-            x = sp.xlo + (local - tyi * ntx) * TW + lane;
-            y = sp.ylo + tyi * TH + wrow;
-            if (x >= sp.xhi || y >= sp.yhi) continue;  // no barrier in this kernel
-            interior = true;
-        } else {  // border band: rows above and below, then columns left and right
-            int b = (local - sp.nint) * TW * TH + (int)threadIdx.x;
-            if (b >= sp.nbp) continue;
-            const int top = sp.ylo * W, bot = (H - sp.yhi) * W;
-            if (b < top) {
-                y = b / W;
-                x = b - y * W;
-            } else if (b < top + bot) {
-                b -= top;
-                y = sp.yhi + b / W;
-                x = b - (b / W) * W;
-            } else {
-                b -= top + bot;
-                const int k = sp.xlo + W - sp.xhi;
-                y = sp.ylo + b / k;
-                const int c = b - (b / k) * k;
-                x = c < sp.xlo ? c : sp.xhi + (c - sp.xlo);
-            }
-            interior = false;
-        }
-        const uint8_t *A = L.y[dir], *B = L.y[1 - dir];
-        const uint32_t d0 = gld(L.df[dir])[(size_t)y * L.fpitch + x];
+        const int dir = local / sp.nint;
+        local -= dir * sp.nint;
+        const int ntx = ceil_div(sp.xhi - sp.xlo, TW);
+        const int tyi = local / ntx;
+        const int x = sp.xlo + (local - tyi * ntx) * TW + lane;
+        const int y = sp.ylo + tyi * TH + wrow;
+        if (x >= sp.xhi || y >= sp.yhi) continue;  // no barrier in this kernel
+        const uint8_t *Ao = plane_org(L.y[dir], yp), *Bo = plane_org(L.y[1 - dir], yp);
+        const uint32_t d0 = gld(L.df[dir])[(uint32_t)(y * L.fpitch + x)];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
 
         // doubled gradients and Ref values of the window as 16-bit pairs
-        uint32_t gxp[WN][NP], gyp[WN][NP], ap[WN][NP];
-        if (interior) {
+        // (the window and its gradient taps lie inside the padded plane)
+        uint32_t gxp[WN][NP], gyp[WN][NP];
+        int hxx = 0, hxy = 0, hyy = 0, sax = 0, say = 0;
+        {
             uint32_t op[WN + 2][NP], ar[WN + 2][(AB + 3) / 4];
-            load_rows<AB, WN + 2>(A + (ptrdiff_t)(y - LP - 1) * yp, yp, x - LP - 1, ar);
+            load_rows<AB, WN + 2>(Ao, yp, y - LP - 1, x - LP - 1, ar);
 #pragma unroll
             for (int r = 0; r < WN + 2; r++) {
                 odd_pairs<NP, 0>(ar[r], op[r]);
@@ -849,137 +898,170 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
             for (int j = 0; j < WN; j++)
 #pragma unroll
                 for (int k = 0; k < NP; k++) {
-                    ap[j][k] = op[j + 1][k];
                     gyp[j][k] = sub2(op[j + 2][k], op[j][k]);
-                }
-        } else {
-#pragma unroll
-            for (int j = 0; j < WN; j++)
-#pragma unroll
-                for (int k = 0; k < NP; k++) {
-                    uint32_t g0 = 0, g1 = 0, a0 = 0;
-#pragma unroll
-                    for (int h = 0; h < 2; h++) {
-                        const int i = 2 * k + h;
-                        if (i >= WN) break;
-                        const int qx = clampi(x + i - LP, 0, W - 1), qy = clampi(y + j - LP, 0, H - 1);
-                        const uint8_t *rw = A + (ptrdiff_t)qy * yp;  // q +- 1 stays inside the border
-                        const uint32_t sh = 16u * h;
-                        a0 |= (uint32_t)rw[qx] << sh;
-                        g0 |= (uint32_t)(uint16_t)((int)rw[qx + 1] - (int)rw[qx - 1]) << sh;
-                        g1 |= (uint32_t)(uint16_t)((int)rw[qx + yp] - (int)rw[qx - yp]) << sh;
-                    }
-                    ap[j][k] = a0;
-                    gxp[j][k] = g0;
-                    gyp[j][k] = g1;
+                    hxx = dot2(gxp[j][k], gxp[j][k], hxx);
+                    hxy = dot2(gxp[j][k], gyp[j][k], hxy);
+                    hyy = dot2(gyp[j][k], gyp[j][k], hyy);
+                    sax = dot2(gxp[j][k], op[j + 1][k], sax);
+                    say = dot2(gyp[j][k], op[j + 1][k], say);
                 }
         }
-        int hxx = 0, hxy = 0, hyy = 0, sax = 0, say = 0;
-#pragma unroll
-        for (int j = 0; j < WN; j++)
-#pragma unroll
-            for (int k = 0; k < NP; k++) {
-                hxx = dot2(gxp[j][k], gxp[j][k], hxx);
-                hxy = dot2(gxp[j][k], gyp[j][k], hxy);
-                hyy = dot2(gyp[j][k], gyp[j][k], hyy);
-                sax = dot2(gxp[j][k], ap[j][k], sax);
-                say = dot2(gyp[j][k], ap[j][k], say);
-            }
+        // the step is -H^-1 (b / 2): keep the entries of H^-1 / 2
         const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
-        const double det = Hxx * Hyy - Hxy * Hxy;
+        const double hdet = 0.5 / (Hxx * Hyy - Hxy * Hxy);
+        const double ixx = Hyy * hdet, ixy = Hxy * hdet, iyy = Hxx * hdet;
         double ux = d0x, uy = d0y;
         for (int it = 0; it < iters; it++) {
             const double fux = floor(ux), fuy = floor(uy);
             const double fx = ux - fux, fy = uy - fuy;
-            const int iux = (int)fux, iuy = (int)fuy;
-            const int c0 = x - LP + iux, r0 = y - LP + iuy;
+            // the (WN+1)^2 target block at the cell of u; a block beyond the
+            // padded border lies wholly on one side of the image, where every
+            // sample is the edge value, so its origin is clamped to the
+            // padded range without changing any sample
+            const int c0 = clampi(x - LP + (int)fux, -kPad, W - 1 + kPad - (WN + 1));
+            const int r0 = clampi(y - LP + (int)fuy, -kPad, H - 1 + kPad - WN);
             double bx, by;  // sum over the window of g (Tgt - A), g doubled
-            if (interior && c0 >= -kPad && c0 + WN + 1 <= W - 1 + kPad && r0 >= -kPad && r0 + WN <= H - 1 + kPad) {
-                if (it == 0) {
-                    // the integer start: one corner
-                    int sx = 0, sy = 0;
-                    uint32_t tb[WN][(WN + 1 + 3) / 4];
-                    load_rows<WN + 1, WN>(B + (ptrdiff_t)r0 * yp, yp, c0, tb);
-#pragma unroll
-                    for (int j = 0; j < WN; j++) {
-                        uint32_t te[NP];
-                        even_pairs<NP, 0>(tb[j], te);
-#pragma unroll
-                        for (int k = 0; k < NP; k++) {
-                            sx = dot2(gxp[j][k], te[k], sx);
-                            sy = dot2(gyp[j][k], te[k], sy);
-                        }
-                    }
-                    bx = (double)(sx - sax);
-                    by = (double)(sy - say);
-                } else {
-                    int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
-                    uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
-                    load_rows<WN + 2, WN + 1>(B + (ptrdiff_t)r0 * yp, yp, c0, tb);
-#pragma unroll
-                    for (int r = 0; r <= WN; r++) {
-                        uint32_t te[NP], to[NP];
-                        tgt_pairs<NP, 0>(tb[r], te, to);
-#pragma unroll
-                        for (int k = 0; k < NP; k++) {
-                            if (r < WN) {
-                                s00x = dot2(gxp[r][k], te[k], s00x);
-                                s01x = dot2(gxp[r][k], to[k], s01x);
-                                s00y = dot2(gyp[r][k], te[k], s00y);
-                                s01y = dot2(gyp[r][k], to[k], s01y);
-                            }
-                            if (r > 0) {
-                                s10x = dot2(gxp[r - 1][k], te[k], s10x);
-                                s11x = dot2(gxp[r - 1][k], to[k], s11x);
-                                s10y = dot2(gyp[r - 1][k], te[k], s10y);
-                                s11y = dot2(gyp[r - 1][k], to[k], s11y);
-                            }
-                        }
-                    }
-                    const double tx = (double)(s00x - sax) + fx * (double)(s01x - s00x);
-                    const double bx1 = (double)(s10x - sax) + fx * (double)(s11x - s10x);
-                    const double ty = (double)(s00y - say) + fx * (double)(s01y - s00y);
-                    const double by1 = (double)(s10y - say) + fx * (double)(s11y - s10y);
-                    bx = tx + fy * (bx1 - tx);
-                    by = ty + fy * (by1 - ty);
-                }
-            } else {
-                bx = 0.0;
-                by = 0.0;
+            if (it == 0) {
+                // the integer start: one corner
+                int sx = 0, sy = 0;
+                uint32_t tb[WN][(WN + 1 + 3) / 4];
+                load_rows<WN + 1, WN>(Bo, yp, r0, c0, tb);
 #pragma unroll
                 for (int j = 0; j < WN; j++) {
-                    const int sy = clampi(y + j - LP, 0, H - 1) + iuy;
-                    const int oa = clampi(sy, 0, H - 1) * yp, ob = clampi(sy + 1, 0, H - 1) * yp;
+                    uint32_t te[NP];
+                    even_pairs<NP, 0>(tb[j], te);
 #pragma unroll
-                    for (int i = 0; i < WN; i++) {
-                        uint32_t gpx = gxp[j][i >> 1], gpy = gyp[j][i >> 1], apv = ap[j][i >> 1];
-                        // opaque copies: the conversions below are not hoisted
-                        // out of the iteration loop (75 live doubles otherwise)
-                        __asm__ volatile("" : "+v"(gpx), "+v"(gpy), "+v"(apv));
-                        const int gx = (i & 1) ? hi16(gpx) : lo16(gpx);
-                        const int gy = (i & 1) ? hi16(gpy) : lo16(gpy);
-                        const int av = (i & 1) ? hi16(apv) : lo16(apv);
-                        const int sx = clampi(x + i - LP, 0, W - 1) + iux;
-                        const int xa = clampi(sx, 0, W - 1), xb = clampi(sx + 1, 0, W - 1);
-                        const float v00 = B[oa + xa], v01 = B[oa + xb], v10 = B[ob + xa], v11 = B[ob + xb];
-                        const float top = v00 + (float)fx * (v01 - v00), bot = v10 + (float)fx * (v11 - v10);
-                        const double e = (double)(top + (float)fy * (bot - top)) - (double)av;
-                        bx = fma((double)gx, e, bx);
-                        by = fma((double)gy, e, by);
+                    for (int k = 0; k < NP; k++) {
+                        sx = dot2(gxp[j][k], te[k], sx);
+                        sy = dot2(gyp[j][k], te[k], sy);
                     }
-                    // keep the scheduler from hoisting the loads of every
-                    // window row (a rare path: registers matter more here)
-                    __builtin_amdgcn_sched_barrier(0);
                 }
+                bx = (double)(sx - sax);
+                by = (double)(sy - say);
+            } else {
+                int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
+                uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
+                load_rows<WN + 2, WN + 1>(Bo, yp, r0, c0, tb);
+#pragma unroll
+                for (int r = 0; r <= WN; r++) {
+                    uint32_t te[NP], to[NP];
+                    tgt_pairs<NP, 0>(tb[r], te, to);
+#pragma unroll
+                    for (int k = 0; k < NP; k++) {
+                        if (r < WN) {
+                            s00x = dot2(gxp[r][k], te[k], s00x);
+                            s01x = dot2(gxp[r][k], to[k], s01x);
+                            s00y = dot2(gyp[r][k], te[k], s00y);
+                            s01y = dot2(gyp[r][k], to[k], s01y);
+                        }
+                        if (r > 0) {
+                            s10x = dot2(gxp[r - 1][k], te[k], s10x);
+                            s11x = dot2(gxp[r - 1][k], to[k], s11x);
+                            s10y = dot2(gyp[r - 1][k], te[k], s10y);
+                            s11y = dot2(gyp[r - 1][k], to[k], s11y);
+                        }
+                    }
+                }
+                const double tx = (double)(s00x - sax) + fx * (double)(s01x - s00x);
+                const double bx1 = (double)(s10x - sax) + fx * (double)(s11x - s10x);
+                const double ty = (double)(s00y - say) + fx * (double)(s01y - s00y);
+                const double by1 = (double)(s10y - say) + fx * (double)(s11y - s10y);
+                bx = tx + fy * (bx1 - tx);
+                by = ty + fy * (by1 - ty);
             }
-            // the right-hand side of the normal equations is half of (bx, by)
-            const double dx = -0.5 * (Hyy * bx - Hxy * by) / det;
-            const double dy = -0.5 * (Hxx * by - Hxy * bx) / det;
+            const double dx = ixy * by - ixx * bx;
+            const double dy = ixy * bx - iyy * by;
             ux = fmin(fmax(ux + dx, (double)(d0x - 1)), (double)(d0x + 1));
             uy = fmin(fmax(uy + dy, (double)(d0y - 1)), (double)(d0y + 1));
         }
         const uint64_t packed = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
-        gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(size_t)y * W + x] = packed;
+        gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(uint32_t)(y * W + x)] = packed;
+    }
+}
+
+// The pixels whose window leaves the image (within LP of the border): every
+// window position is clamped to the image on its own, so positions repeat;
+// each is evaluated with its own loads (a small fraction of the pixels).
+template <int LP>
+__global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restrict__ lv,
+                                                          const StripIO *__restrict__ io,
+                                                          const int32_t *__restrict__ prefix, int n, int total,
+                                                          int iters, float eps)
+{
+    constexpr int WN = 2 * LP + 1;
+    TILE_LOOP(total)
+    {
+        const int s = find_strip(prefix, n, t);
+        int local = t - prefix[s];
+        const StripLv &L = lv[s];
+        const int H = L.H, W = L.W, yp = L.ypitch;
+        const RefineSplit sp = refine_split(H, W, 1, LP);
+        const int nbt = ceil_div(sp.nbp, kRowTW);
+        const int dir = local / nbt;
+        local -= dir * nbt;
+        int b = local * kRowTW + (int)threadIdx.x;
+        if (b >= sp.nbp) continue;
+        // border band: rows above and below, then columns left and right
+        int x, y;
+        const int top = sp.ylo * W, bot = (H - sp.yhi) * W;
+        if (b < top) {
+            y = b / W;
+            x = b - y * W;
+        } else if (b < top + bot) {
+            b -= top;
+            y = sp.yhi + b / W;
+            x = b - (b / W) * W;
+        } else {
+            b -= top + bot;
+            const int k = sp.xlo + W - sp.xhi;
+            y = sp.ylo + b / k;
+            const int c = b - (b / k) * k;
+            x = c < sp.xlo ? c : sp.xhi + (c - sp.xlo);
+        }
+        const uint8_t *A = L.y[dir], *B = L.y[1 - dir];  // pixel (0, 0); the rows carry a replicated border
+        const uint32_t d0 = L.df[dir][(size_t)y * L.fpitch + x];
+        const int d0x = unpack_x(d0), d0y = unpack_y(d0);
+        int hxx = 0, hxy = 0, hyy = 0;
+        for (int j = 0; j < WN; j++)
+            for (int i = 0; i < WN; i++) {
+                const uint8_t *q = A + (ptrdiff_t)clampi(y + j - LP, 0, H - 1) * yp + clampi(x + i - LP, 0, W - 1);
+                const int gx = (int)q[1] - (int)q[-1], gy = (int)q[yp] - (int)q[-yp];
+                hxx += gx * gx;
+                hxy += gx * gy;
+                hyy += gy * gy;
+            }
+        const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
+        const double hdet = 0.5 / (Hxx * Hyy - Hxy * Hxy);
+        const double ixx = Hyy * hdet, ixy = Hxy * hdet, iyy = Hxx * hdet;
+        double ux = d0x, uy = d0y;
+        for (int it = 0; it < iters; it++) {
+            const double fux = floor(ux), fuy = floor(uy);
+            const float fx = (float)(ux - fux), fy = (float)(uy - fuy);
+            const int iux = (int)fux, iuy = (int)fuy;
+            double bx = 0.0, by = 0.0;
+            for (int j = 0; j < WN; j++) {
+                const int qy = clampi(y + j - LP, 0, H - 1);
+                const uint8_t *ra = B + (ptrdiff_t)clampi(qy + iuy, 0, H - 1) * yp;
+                const uint8_t *rb = B + (ptrdiff_t)clampi(qy + iuy + 1, 0, H - 1) * yp;
+                for (int i = 0; i < WN; i++) {
+                    const int qx = clampi(x + i - LP, 0, W - 1);
+                    const uint8_t *q = A + (ptrdiff_t)qy * yp + qx;
+                    const int gx = (int)q[1] - (int)q[-1], gy = (int)q[yp] - (int)q[-yp];
+                    const int xa = clampi(qx + iux, 0, W - 1), xb = clampi(qx + iux + 1, 0, W - 1);
+                    const float v00 = ra[xa], v01 = ra[xb], v10 = rb[xa], v11 = rb[xb];
+                    const float tp = v00 + fx * (v01 - v00), bt = v10 + fx * (v11 - v10);
+                    const double e = (double)(tp + fy * (bt - tp)) - (double)q[0];
+                    bx = fma((double)gx, e, bx);
+                    by = fma((double)gy, e, by);
+                }
+            }
+            const double dx = ixy * by - ixx * bx;
+            const double dy = ixy * bx - iyy * by;
+            ux = fmin(fmax(ux + dx, (double)(d0x - 1)), (double)(d0x + 1));
+            uy = fmin(fmax(uy + dy, (double)(d0y - 1)), (double)(d0y + 1));
+        }
+        float2 *out = reinterpret_cast<float2 *>(io[s].flow[dir]);
+        out[(size_t)y * W + x] = make_float2((float)ux, (float)uy);
     }
 }
 
@@ -1214,26 +1296,33 @@ hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int medi
 }
 
 template <int LP>
-static hipError_t refine_th(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid,
+static hipError_t refine_lp(const StripLv *lv0, const StripIO *io, Work wi, Work wb, LkParams lk, int th, int grid,
                             hipStream_t s)
 {
-    const int g = grid_for(w.total, grid);
-    if (th == 2)
-        hipLaunchKernelGGL((k_refine<LP, 2>), dim3(g), dim3(128), 0, s, lv0, io, w.prefix, w.n, w.total, lk.iters,
-                           lk.eps);
-    else
-        hipLaunchKernelGGL((k_refine<LP, 4>), dim3(g), dim3(256), 0, s, lv0, io, w.prefix, w.n, w.total, lk.iters,
-                           lk.eps);
+    if (wi.total > 0) {
+        const int g = grid_for(wi.total, grid);
+        if (th == 2)
+            hipLaunchKernelGGL((k_refine<LP, 2>), dim3(g), dim3(128), 0, s, lv0, io, wi.prefix, wi.n, wi.total,
+                               lk.iters, lk.eps);
+        else
+            hipLaunchKernelGGL((k_refine<LP, 4>), dim3(g), dim3(256), 0, s, lv0, io, wi.prefix, wi.n, wi.total,
+                               lk.iters, lk.eps);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (wb.total > 0)
+        hipLaunchKernelGGL((k_refine_border<LP>), dim3(wb.total), dim3(kRowTW), 0, s, lv0, io, wb.prefix, wb.n,
+                           wb.total, lk.iters, lk.eps);
     return hipGetLastError();
 }
 
-hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid,
+hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work wi, Work wb, LkParams lk, int th, int grid,
                          hipStream_t s)
 {
     switch (lk.patch) {
-    case 1: return refine_th<1>(lv0, io, w, lk, th, grid, s);
-    case 2: return refine_th<2>(lv0, io, w, lk, th, grid, s);
-    case 3: return refine_th<3>(lv0, io, w, lk, th, grid, s);
+    case 1: return refine_lp<1>(lv0, io, wi, wb, lk, th, grid, s);
+    case 2: return refine_lp<2>(lv0, io, wi, wb, lk, th, grid, s);
+    case 3: return refine_lp<3>(lv0, io, wi, wb, lk, th, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -148,14 +148,17 @@ abf_status check_params(const abf_params *p)
 // aligned rows, plus 64 bytes of slack before and after (the aligned
 // row loads may read a few bytes past the last padded row).
 inline int ypitch_of(int w) { return (int)align_up((size_t)w + 2 * kPad, 64); }
-inline size_t plane_bytes(int H, int W) { return align_up(64 + (size_t)ypitch_of(W) * (H + 2 * kPad) + 64, kAlign); }
+inline size_t plane_bytes(int H, int W)
+{
+    return align_up(kPlaneLead + (size_t)ypitch_of(W) * (H + 2 * kPad) + kPlaneLead, kAlign);
+}
 inline int fpitch_of(int w) { return (int)align_up((size_t)w, 16); }
 
 size_t header_bytes(int n, int N)
 {
     size_t b = align_up(sizeof(StripIO) * n, kAlign);
     b += align_up(sizeof(StripLv) * n * N, kAlign);
-    b += align_up(sizeof(int32_t) * (n + 1) * (size_t)(kStages * N), kAlign);
+    b += align_up(sizeof(int32_t) * (n + 1) * (size_t)(kLists * N), kAlign);
     return b;
 }
 
@@ -192,16 +195,18 @@ void level_sizes(int H, int W, int N, std::vector<int> &hs, std::vector<int> &ws
     }
 }
 
-// Tiles of one strip at one level for a stage.
+// Tiles of one strip at one level for a work list (a stage, or the
+// refinement's border pixels).
 int stage_tiles(const abf_plan *pl, int stage, int cls, int H, int W)
 {
-    const int th = pl->launch[stage][cls].tile_h;
+    const int th = stage < kStages ? pl->launch[stage][cls].tile_h : 1;
     switch (stage) {
     case ST_LUMA: return tiles_luma(H, W);
     case ST_PYR: return 2 * tiles_pyr(H, W);
     case ST_SEARCH: return tiles_search(H, W, th);
     case ST_PROP: return tiles_prop(H, W, th, pl->p.prop_steps + pl->p.median);
     case ST_REFINE: return tiles_refine(H, W, th, pl->p.lk_patch);
+    case LIST_REFINE_BORDER: return tiles_refine_border(H, W, pl->p.lk_patch);
     default: return tiles_blend(H, W);
     }
 }
@@ -210,7 +215,7 @@ struct Batch {
     Layout lay;
     std::vector<StripIO> io;
     std::vector<StripLv> lv;              // [k * n + s]
-    std::vector<int32_t> prefix;          // [(stage * N + k) * (n + 1) + s]
+    std::vector<int32_t> prefix;          // [(list * N + k) * (n + 1) + s]
     std::vector<int> cls;                 // [k] size class of level k over the batch
     std::vector<int64_t> level_px;        // [k]
 };
@@ -251,7 +256,7 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
     L.hdr_io = 0;
     L.hdr_lv = align_up(sizeof(StripIO) * n, kAlign);
     L.hdr_prefix = L.hdr_lv + align_up(sizeof(StripLv) * n * N, kAlign);
-    L.hdr_bytes = L.hdr_prefix + align_up(sizeof(int32_t) * (n + 1) * (size_t)(kStages * N), kAlign);
+    L.hdr_bytes = L.hdr_prefix + align_up(sizeof(int32_t) * (n + 1) * (size_t)(kLists * N), kAlign);
     if (L.hdr_bytes > pl->hdr_cap) return fail(pl, ABF_E_WORKSPACE, "descriptor tables exceed the reserved head");
 
     b.io.resize(n);
@@ -289,7 +294,7 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
             v.ypitch = ypitch_of(v.W);
             v.fpitch = fpitch_of(v.W);
             for (int d = 0; d < 2; d++) {
-                v.y[d] = pl->ws + off + 64 + (size_t)v.ypitch * kPad + kPad;
+                v.y[d] = pl->ws + off + kPlaneLead + (size_t)v.ypitch * kPad + kPad;
                 off += plane_bytes(v.H, v.W);
             }
             const size_t fb = align_up((size_t)v.fpitch * 4 * v.H, kAlign);
@@ -329,8 +334,8 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
         return fail(pl, ABF_E_WORKSPACE, "batch needs %zu workspace bytes, %zu bound", off, pl->ws_bytes);
 
     // tile prefix sums per stage and level
-    b.prefix.assign((size_t)(n + 1) * kStages * N, 0);
-    for (int stg = 0; stg < kStages; stg++)
+    b.prefix.assign((size_t)(n + 1) * kLists * N, 0);
+    for (int stg = 0; stg < kLists; stg++)
         for (int k = 0; k < N; k++) {
             int32_t *pre = &b.prefix[((size_t)stg * N + k) * (n + 1)];
             int64_t acc = 0;
@@ -436,8 +441,8 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
         }
         LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
         TIMED(ST_REFINE, 0,
-              launch_refine(lv, io, work(ST_REFINE, 0), lk, pl->launch[ST_REFINE][b.cls[0]].tile_h,
-                            grid_of(pl, ST_REFINE, b.cls[0]), s));
+              launch_refine(lv, io, work(ST_REFINE, 0), work(LIST_REFINE_BORDER, 0), lk,
+                            pl->launch[ST_REFINE][b.cls[0]].tile_h, grid_of(pl, ST_REFINE, b.cls[0]), s));
     }
     if (blend) {
         BlendParams bp{p.k_sharp, p.k_flowmag, p.blend_mode};
