@@ -506,21 +506,29 @@ __device__ __forceinline__ uint32_t patch_cost(const uint32_t (&rr)[2 * P + 1][(
 
 // T Jacobi propagation steps and the median of one level in one launch,
 // with temporal blocking. A workgroup owns an output tile of
-// (64 - 2h) x TH pixels, h = T + M, and loads the search result of the
-// 64 x (TH + 2h) region around it into LDS (lane = region column, so every
-// region row is one wave instruction); step t runs on the region inset by
-// t (every step reads only the previous iterate, so the result is that of
-// T separate full-image steps), the median on the output tile, and only
-// the final flow is written. Neighbours outside the image are skipped; the
-// median clamps to the image.
+// (64 - 2h) x TH pixels, h = T + M, and keeps the iterate of the
+// 64 x (TH + 2h) region around it in LDS (lane = region column; a thread
+// owns the same region rows in every phase and holds their vectors, costs
+// and search centres in registers). Step t runs on the region inset by t,
+// reading only the previous iterate, so the result is that of T separate
+// full-image steps; the median runs on the output tile and only the final
+// flow is written. Neighbours outside the image are skipped; the median
+// clamps to the image.
 //
-// Work per step: every pixel lists the neighbour vectors it must cost (a
-// neighbour equal to an earlier candidate has the same cost and loses the
-// tie, so it is not costed; on average well under one job per pixel). Each
-// wave reserves room for its lanes' jobs with one LDS atomic and places
-// them by a ballot prefix count; all threads then share the job array, and
-// each pixel picks its winner from its own cost slots in the fixed
-// candidate order, so the result does not depend on the packing.
+// A neighbour's vector can only replace a pixel's vector with a strictly
+// lower patch cost, and the pixel's own cost is carried, so a candidate is
+// costed only if it can win:
+//  - step 1: not if it lies in the pixel's search window (the search took
+//    the minimum cost over that window);
+//  - step t > 1: not if that neighbour did not change in step t - 1 (the
+//    pixel already weighed that vector and holds one at most as costly);
+//  - never if it equals an earlier candidate (same cost, loses the tie).
+// The remaining candidates (about 0.1 per pixel per step at level 0 of the
+// panorama) are packed into an LDS job list (one atomic per wave, placed by
+// a ballot prefix count) shared by all threads; each job's slot is then
+// overwritten by its cost, and every pixel picks its winner from its own
+// jobs in the fixed candidate order, so the result does not depend on the
+// packing.
 __device__ __forceinline__ int wave_prefix(uint32_t c, int &total)
 {
     // exclusive prefix sum over the wave of c (0..7) and the wave total
@@ -536,27 +544,36 @@ __device__ __forceinline__ int wave_prefix(uint32_t c, int &total)
     return pre;
 }
 
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ i16x2 as_i16x2(uint32_t v) { return __builtin_bit_cast(i16x2, v); }
+__device__ __forceinline__ i16x2 pmin(i16x2 a, i16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ i16x2 pmax(i16x2 a, i16x2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ i16x2 pmed3(i16x2 a, i16x2 b, i16x2 c) { return pmax(pmin(a, b), pmin(pmax(a, b), c)); }
+
 template <int P, int TH>
 __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict__ lv,
                                                        const int32_t *__restrict__ prefix, int n, int total, int T,
                                                        int M)
 {
     constexpr int NT = kPropThreads, NW = NT / 64, RW = kPropRW;
+    constexpr int NQ = (TH + 2 * kPropMaxHalo + NW - 1) / NW;  // region rows per thread at the largest halo
     extern __shared__ uint32_t smem[];
     const int h = T + M;
     const int OW = RW - 2 * h, RH = TH + 2 * h, NR = RW * RH;
-    uint32_t *vp = smem, *vn = smem + NR;                                       // iterates
-    uint16_t *cp = reinterpret_cast<uint16_t *>(smem + 2 * NR), *cn = cp + NR;  // their costs
-    uint16_t *slot = cn + NR;                                                   // 4 candidate costs per pixel
-    uint16_t *jobs = slot + 4 * NR;  // (row << 6 | column) << 2 | candidate - 1
-    int *njobs = reinterpret_cast<int *>(jobs + 4 * NR);
+    uint32_t *vp = smem, *vn = smem + NR;                        // previous and next iterate
+    uint32_t *jm = smem + 2 * NR;                                // first job | candidate mask << 16
+                                                                 // (before step 1: the search centre)
+    uint16_t *cst = reinterpret_cast<uint16_t *>(smem + 3 * NR);  // cost of the current vector
+    uint16_t *jobs = cst + NR;  // (row << 6 | column) << 2 | candidate - 1, then the job's cost
+    uint8_t *chg = reinterpret_cast<uint8_t *>(jobs + 4 * NR);    // step of the last change (0: none)
+    int *njobs = reinterpret_cast<int *>(smem + (prop_lds_bytes(h, TH) - 16) / 4);
     const int rx = threadIdx.x & 63, wave = threadIdx.x >> 6;
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
         int local = t - prefix[s];
         const StripLv &L = lv[s];
-        const int H = L.H, W = L.W, yp = L.ypitch, fp = L.fpitch;
+        const int H = L.H, W = L.W, yp = L.ypitch, fp = L.fpitch, R = L.radius;
         const int ntx = ceil_div(W, OW), per_dir = ntx * ceil_div(H, TH);
         const int dir = local / per_dir;
         local -= dir * per_dir;
@@ -566,58 +583,71 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict
         const bool xin = x >= 0 && x < W;
         {
             // all loads of a thread's region rows first, then the LDS writes
-            constexpr int NQ = (TH + 2 * 5 + NW - 1) / NW;  // rows per wave at the largest halo
             const auto din = gld(L.ds[dir]);
             const auto cin = gld(L.cs[dir]);
-            uint32_t tv[NQ], tc[NQ];
+            const uint32_t *dc = L.dc[dir];
+            uint32_t tv[NQ], tc[NQ], tm[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 const int ry = wave + q * NW, y = gy0 + ry;
                 const bool in = xin && ry < RH && y >= 0 && y < H;
-                tv[q] = in ? din[(size_t)y * fp + x] : 0u;
-                tc[q] = in ? cin[(size_t)y * fp + x] : 0u;
+                const uint32_t o = in ? (uint32_t)(y * fp + x) : 0u;
+                tv[q] = in ? din[o] : 0u;
+                tc[q] = in ? cin[o] : 0u;
+                tm[q] = (in && dc) ? gld(dc)[(uint32_t)(min(y >> 1, L.Hc - 1) * L.fpitch_c + min(x >> 1, L.Wc - 1))]
+                                   : 0u;
             }
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
                 const int ry = wave + q * NW;
                 if (ry < RH) {
-                    vp[ry * RW + rx] = tv[q];
-                    cp[ry * RW + rx] = (uint16_t)tc[q];
+                    const int i = ry * RW + rx;
+                    vp[i] = tv[q];
+                    cst[i] = (uint16_t)tc[q];
+                    jm[i] = tm[q];
+                    chg[i] = 0;
                 }
             }
         }
         if (threadIdx.x == 0) *njobs = 0;
         __syncthreads();
-        const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
-        const uint8_t *refo = plane_org(ref, yp), *tgto = plane_org(tgt, yp);
+        const uint8_t *refo = plane_org(L.y[dir], yp), *tgto = plane_org(L.y[1 - dir], yp);
         for (int step = 1; step <= T; step++) {
             const bool xact = xin && rx >= step && rx < RW - step;
-            for (int ry0 = step; ry0 < RH - step; ry0 += NW) {
-                const int ry = ry0 + wave, y = gy0 + ry;
-                const bool act = xact && ry < RH - step && y >= 0 && y < H;
+            // the candidates each pixel must cost
+#pragma unroll 1
+            for (int ry = step + wave; ry < RH - step; ry += NW) {
+                const int y = gy0 + ry;
+                if (y < 0 || y >= H) continue;  // wave-uniform
                 const int i = ry * RW + rx;
                 uint32_t need = 0;
-                uint32_t cand[5];
-                if (act) {
-                    bool ok[5];
-                    cand[0] = vp[i];
-                    ok[0] = true;
-                    ok[1] = x > 0;
-                    cand[1] = ok[1] ? vp[i - 1] : 0u;
-                    ok[2] = x < W - 1;
-                    cand[2] = ok[2] ? vp[i + 1] : 0u;
-                    ok[3] = y > 0;
-                    cand[3] = ok[3] ? vp[i - RW] : 0u;
-                    ok[4] = y < H - 1;
-                    cand[4] = ok[4] ? vp[i + RW] : 0u;
-#pragma unroll
-                    for (int k = 1; k < 5; k++) {
-                        bool dup = !ok[k];
-#pragma unroll
-                        for (int m = 0; m < k; m++) dup |= ok[m] && cand[m] == cand[k];
-                        if (dup) slot[4 * i + k - 1] = 0xffffu;  // above every patch cost: never wins
-                        else need |= 1u << k;
+                if (xact) {
+                    const uint32_t c0 = vp[i], c1 = vp[i - 1], c2 = vp[i + 1], c3 = vp[i - RW], c4 = vp[i + RW];
+                    const bool ok1 = x > 0, ok2 = x < W - 1, ok3 = y > 0, ok4 = y < H - 1;
+                    // dup: equal to an earlier candidate that is in the image
+                    const bool d2 = c2 == c0 || (ok1 && c2 == c1);
+                    const bool d3 = c3 == c0 || (ok1 && c3 == c1) || (ok2 && c3 == c2);
+                    const bool d4 = c4 == c0 || (ok1 && c4 == c1) || (ok2 && c4 == c2) || (ok3 && c4 == c3);
+                    bool n1 = ok1 && c1 != c0, n2 = ok2 && !d2, n3 = ok3 && !d3, n4 = ok4 && !d4;
+                    if (step == 1) {
+                        const uint32_t cen = jm[i];
+                        const int cx = unpack_x(cen) * 2, cy = unpack_y(cen) * 2;
+                        auto inwin = [&](uint32_t v) {
+                            return (uint32_t)(unpack_x(v) - cx + R) <= (uint32_t)(2 * R) &&
+                                   (uint32_t)(unpack_y(v) - cy + R) <= (uint32_t)(2 * R);
+                        };
+                        n1 = n1 && !inwin(c1);
+                        n2 = n2 && !inwin(c2);
+                        n3 = n3 && !inwin(c3);
+                        n4 = n4 && !inwin(c4);
+                    } else {
+                        const int prev = step - 1;
+                        n1 = n1 && chg[i - 1] == prev;
+                        n2 = n2 && chg[i + 1] == prev;
+                        n3 = n3 && chg[i - RW] == prev;
+                        n4 = n4 && chg[i + RW] == prev;
                     }
+                    need = (n1 ? 2u : 0u) | (n2 ? 4u : 0u) | (n3 ? 8u : 0u) | (n4 ? 16u : 0u);
                 }
                 int wtotal;
                 const int pre = wave_prefix(__popc(need), wtotal);
@@ -626,146 +656,126 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict
                     if (rx == 0) base = atomicAdd(njobs, wtotal);
                     base = __shfl(base, 0, 64);
                 }
-                int j = base + pre;
-#pragma unroll
-                for (int k = 1; k < 5; k++)
-                    if (need & (1u << k)) jobs[j++] = (uint16_t)((((ry << 6) | rx) << 2) | (k - 1));
+                if (xact) {
+                    int j = base + pre;
+                    jm[i] = need ? ((uint32_t)j | need << 16) : 0u;
+                    const uint32_t e = (uint32_t)((ry << 6) | rx) << 2;
+                    if (need & 2u) jobs[j++] = (uint16_t)(e | 0u);
+                    if (need & 4u) jobs[j++] = (uint16_t)(e | 1u);
+                    if (need & 8u) jobs[j++] = (uint16_t)(e | 2u);
+                    if (need & 16u) jobs[j] = (uint16_t)(e | 3u);
+                }
             }
             __syncthreads();
             const int nj = *njobs;
-            // two jobs per iteration, the Ref and Tgt rows of both in flight together
-            for (int j = threadIdx.x; j < nj; j += 2 * NT) {
-                int sl[2], px[2], py[2], dx[2], dy[2];
-                bool inpad = true;
-#pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    const int e = jobs[min(j + q * NT, nj - 1)];
-                    const int k = (e & 3) + 1, jx = (e >> 2) & 63, jy = e >> 8;
-                    const int i = jy * RW + jx;
-                    const uint32_t v = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
-                    sl[q] = 4 * i + k - 1;
-                    px[q] = gx0 + jx;
-                    py[q] = gy0 + jy;
-                    dx[q] = unpack_x(v);
-                    dy[q] = unpack_y(v);
-                    const int c0 = px[q] + dx[q] - P, r0 = py[q] + dy[q] - P;
-                    inpad &= c0 >= -kPad && c0 + 2 * P <= W - 1 + kPad && r0 >= -kPad && r0 + 2 * P <= H - 1 + kPad;
-                }
-                uint32_t cost[2];
-                if (inpad) {
+            // one job per thread and iteration (jobs are few), its Ref and Tgt
+            // rows in flight together; the entry is overwritten by the cost
+            for (int j = threadIdx.x; j < nj; j += NT) {
+                const int e = jobs[j];
+                const int k = (e & 3) + 1, jx = (e >> 2) & 63, jy = e >> 8;
+                const int i = jy * RW + jx;
+                const uint32_t v = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
+                const int px = gx0 + jx, py = gy0 + jy, dx = unpack_x(v), dy = unpack_y(v);
+                const int c0 = px + dx - P, r0 = py + dy - P;
+                uint32_t cost;
+                if (c0 >= -kPad && c0 + 2 * P <= W - 1 + kPad && r0 >= -kPad && r0 + 2 * P <= H - 1 + kPad) {
                     constexpr int NB = 2 * P + 1, ND = RawRows<NB>::ND;
-                    uint32_t wr[2][NB][ND + 1], wt[2][NB][ND + 1];
-                    int sr[2], st[2];
-#pragma unroll
-                    for (int q = 0; q < 2; q++) {
-                        sr[q] = issue_rows<NB, NB>(refo, yp, py[q] - P, px[q] - P, wr[q]);
-                        st[q] = issue_rows<NB, NB>(tgto, yp, py[q] + dy[q] - P, px[q] + dx[q] - P, wt[q]);
-                    }
+                    uint32_t wr[NB][ND + 1], wt[NB][ND + 1];
+                    const int sr = issue_rows<NB, NB>(refo, yp, py - P, px - P, wr);
+                    const int st = issue_rows<NB, NB>(tgto, yp, r0, c0, wt);
                     __builtin_amdgcn_sched_barrier(0);
+                    uint32_t rr[NB][(NB + 3) / 4], tt[NB][(NB + 3) / 4];
+                    align_rows<NB, NB>(wr, sr, rr);
+                    align_rows<NB, NB>(wt, st, tt);
+                    cost = 0;
 #pragma unroll
-                    for (int q = 0; q < 2; q++) {
-                        uint32_t rr[NB][(NB + 3) / 4], tt[NB][(NB + 3) / 4];
-                        align_rows<NB, NB>(wr[q], sr[q], rr);
-                        align_rows<NB, NB>(wt[q], st[q], tt);
-                        uint32_t c = 0;
-#pragma unroll
-                        for (int r = 0; r < NB; r++) {
-                            if constexpr (P == 2) {
-                                c = __builtin_amdgcn_sad_u8(rr[r][0], tt[r][0], c);
-                                c = __builtin_amdgcn_sad_u8(rr[r][1] & 0xffu, tt[r][1] & 0xffu, c);
-                            } else {
-                                c = __builtin_amdgcn_sad_u8(rr[r][0] & 0x00ffffffu, tt[r][0] & 0x00ffffffu, c);
-                            }
+                    for (int r = 0; r < NB; r++) {
+                        if constexpr (P == 2) {
+                            cost = __builtin_amdgcn_sad_u8(rr[r][0], tt[r][0], cost);
+                            cost = __builtin_amdgcn_sad_u8(rr[r][1] & 0xffu, tt[r][1] & 0xffu, cost);
+                        } else {
+                            cost = __builtin_amdgcn_sad_u8(rr[r][0] & 0x00ffffffu, tt[r][0] & 0x00ffffffu, cost);
                         }
-                        cost[q] = c;
                     }
                 } else {
+                    uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
+                    load_rows<2 * P + 1, 2 * P + 1>(refo, yp, py - P, px - P, rr);
 #pragma unroll
-                    for (int q = 0; q < 2; q++) {
-                        uint32_t rr[2 * P + 1][(2 * P + 4) / 4];
-                        load_rows<2 * P + 1, 2 * P + 1>(refo, yp, py[q] - P, px[q] - P, rr);
-#pragma unroll
-                        for (int r = 0; r < 2 * P + 1; r++) {
-                            if constexpr (P == 2) rr[r][1] &= 0xffu;
-                            else rr[r][0] &= 0x00ffffffu;
-                        }
-                        cost[q] = patch_cost<P>(rr, tgt, H, W, yp, px[q], py[q], dx[q], dy[q]);
+                    for (int r = 0; r < 2 * P + 1; r++) {
+                        if constexpr (P == 2) rr[r][1] &= 0xffu;
+                        else rr[r][0] &= 0x00ffffffu;
                     }
+                    cost = patch_cost<P>(rr, L.y[1 - dir], H, W, yp, px, py, dx, dy);
                 }
-                slot[sl[0]] = (uint16_t)cost[0];
-                if (j + NT < nj) slot[sl[1]] = (uint16_t)cost[1];
+                jobs[j] = (uint16_t)cost;
             }
             __syncthreads();
+            // each pixel's winner in candidate order: the next iterate, its
+            // cost and the change flags
+#pragma unroll 1
             for (int ry = step + wave; ry < RH - step; ry += NW) {
                 const int y = gy0 + ry;
-                if (!xact || y < 0 || y >= H) continue;
+                if (y < 0 || y >= H || !xact) continue;
                 const int i = ry * RW + rx;
-                uint32_t bestv = vp[i], bestc = cp[i];
+                uint32_t v = vp[i];
+                const uint32_t m = jm[i];
+                if (m >> 16) {
+                    uint32_t bc = cst[i], bv = v;
+                    int j = (int)(m & 0xffffu);
 #pragma unroll
-                for (int k = 1; k < 5; k++) {
-                    const uint32_t c = slot[4 * i + k - 1];
-                    if (c < bestc) {
-                        bestc = c;
-                        bestv = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
+                    for (int k = 1; k < 5; k++)
+                        if (m & (0x10000u << k)) {
+                            const uint32_t c = jobs[j++];
+                            if (c < bc) {
+                                bc = c;
+                                bv = vp[k == 1 ? i - 1 : k == 2 ? i + 1 : k == 3 ? i - RW : i + RW];
+                            }
+                        }
+                    if (bv != v) {
+                        chg[i] = (uint8_t)step;
+                        cst[i] = (uint16_t)bc;
+                        v = bv;
                     }
                 }
-                vn[i] = bestv;
-                cn[i] = (uint16_t)bestc;
+                vn[i] = v;
             }
             if (threadIdx.x == 0) *njobs = 0;
             __syncthreads();
             uint32_t *tv = vp;
             vp = vn;
             vn = tv;
-            uint16_t *tc = cp;
-            cp = cn;
-            cn = tc;
         }
-        // median (or copy) of the output tile
+        // median (or copy) of the output tile, on packed int16 pairs
         const auto dst = gst(L.df[dir]);
         if (xin && rx >= h && rx < h + OW) {
-            for (int ry = h + wave; ry < h + TH; ry += NW) {
+            const int ol = x > 0 ? -1 : 0, orr = x < W - 1 ? 1 : 0;
+#pragma unroll 1
+            for (int ry = wave + (h + NW - 1 - wave) / NW * NW; ry < h + TH; ry += NW) {
                 const int y = gy0 + ry;
-                if (y >= H) break;
+                if (y >= H) break;  // wave-uniform
+                const int i = ry * RW + rx;
                 uint32_t outv;
                 if (M == 0) {
-                    outv = vp[ry * RW + rx];
+                    outv = vp[i];
                 } else {
-                    int vx[9], vy[9];
+                    const int ou = y > 0 ? -RW : 0, od = y < H - 1 ? RW : 0;
+                    i16x2 v[9];
 #pragma unroll
                     for (int j = 0; j < 3; j++) {
-                        const int rj = ry + clampi(y + j - 1, 0, H - 1) - y;
-#pragma unroll
-                        for (int i = 0; i < 3; i++) {
-                            const int ri = rx + clampi(x + i - 1, 0, W - 1) - x;
-                            const uint32_t v = vp[rj * RW + ri];
-                            vx[3 * j + i] = unpack_x(v);
-                            vy[3 * j + i] = unpack_y(v);
-                        }
+                        const int r = i + (j == 0 ? ou : j == 2 ? od : 0);
+                        v[3 * j + 0] = as_i16x2(vp[r + ol]);
+                        v[3 * j + 1] = as_i16x2(vp[r]);
+                        v[3 * j + 2] = as_i16x2(vp[r + orr]);
                     }
                     // median of 9 = med3(max of row minima, med3 of row medians, min of row maxima)
-                    int mx, my;
-                    {
-                        int lo0 = min(min(vx[0], vx[1]), vx[2]), lo1 = min(min(vx[3], vx[4]), vx[5]),
-                            lo2 = min(min(vx[6], vx[7]), vx[8]);
-                        int hi0 = max(max(vx[0], vx[1]), vx[2]), hi1 = max(max(vx[3], vx[4]), vx[5]),
-                            hi2 = max(max(vx[6], vx[7]), vx[8]);
-                        int md0 = med3i(vx[0], vx[1], vx[2]), md1 = med3i(vx[3], vx[4], vx[5]),
-                            md2 = med3i(vx[6], vx[7], vx[8]);
-                        mx = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
-                    }
-                    {
-                        int lo0 = min(min(vy[0], vy[1]), vy[2]), lo1 = min(min(vy[3], vy[4]), vy[5]),
-                            lo2 = min(min(vy[6], vy[7]), vy[8]);
-                        int hi0 = max(max(vy[0], vy[1]), vy[2]), hi1 = max(max(vy[3], vy[4]), vy[5]),
-                            hi2 = max(max(vy[6], vy[7]), vy[8]);
-                        int md0 = med3i(vy[0], vy[1], vy[2]), md1 = med3i(vy[3], vy[4], vy[5]),
-                            md2 = med3i(vy[6], vy[7], vy[8]);
-                        my = med3i(max(max(lo0, lo1), lo2), med3i(md0, md1, md2), min(min(hi0, hi1), hi2));
-                    }
-                    outv = pack16(mx, my);
+                    const i16x2 lo = pmax(pmax(pmin(pmin(v[0], v[1]), v[2]), pmin(pmin(v[3], v[4]), v[5])),
+                                          pmin(pmin(v[6], v[7]), v[8]));
+                    const i16x2 hi = pmin(pmin(pmax(pmax(v[0], v[1]), v[2]), pmax(pmax(v[3], v[4]), v[5])),
+                                          pmax(pmax(v[6], v[7]), v[8]));
+                    const i16x2 md = pmed3(pmed3(v[0], v[1], v[2]), pmed3(v[3], v[4], v[5]), pmed3(v[6], v[7], v[8]));
+                    outv = __builtin_bit_cast(uint32_t, pmed3(lo, md, hi));
                 }
-                dst[(size_t)y * fp + x] = outv;
+                dst[(uint32_t)(y * fp + x)] = outv;
             }
         }
         __syncthreads();  // the next tile reuses the LDS
