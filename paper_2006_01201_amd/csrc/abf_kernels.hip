@@ -619,36 +619,37 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict
             for (int ry = step + wave; ry < RH - step; ry += NW) {
                 const int y = gy0 + ry;
                 if (y < 0 || y >= H) continue;  // wave-uniform
+                // straight-line for every lane: the neighbour indices of a row
+                // strictly inside the region are valid LDS indices for every
+                // column, and inactive lanes end with an empty mask
                 const int i = ry * RW + rx;
-                uint32_t need = 0;
-                if (xact) {
-                    const uint32_t c0 = vp[i], c1 = vp[i - 1], c2 = vp[i + 1], c3 = vp[i - RW], c4 = vp[i + RW];
-                    const bool ok1 = x > 0, ok2 = x < W - 1, ok3 = y > 0, ok4 = y < H - 1;
-                    // dup: equal to an earlier candidate that is in the image
-                    const bool d2 = c2 == c0 || (ok1 && c2 == c1);
-                    const bool d3 = c3 == c0 || (ok1 && c3 == c1) || (ok2 && c3 == c2);
-                    const bool d4 = c4 == c0 || (ok1 && c4 == c1) || (ok2 && c4 == c2) || (ok3 && c4 == c3);
-                    bool n1 = ok1 && c1 != c0, n2 = ok2 && !d2, n3 = ok3 && !d3, n4 = ok4 && !d4;
-                    if (step == 1) {
-                        const uint32_t cen = jm[i];
-                        const int cx = unpack_x(cen) * 2, cy = unpack_y(cen) * 2;
-                        auto inwin = [&](uint32_t v) {
-                            return (uint32_t)(unpack_x(v) - cx + R) <= (uint32_t)(2 * R) &&
-                                   (uint32_t)(unpack_y(v) - cy + R) <= (uint32_t)(2 * R);
-                        };
-                        n1 = n1 && !inwin(c1);
-                        n2 = n2 && !inwin(c2);
-                        n3 = n3 && !inwin(c3);
-                        n4 = n4 && !inwin(c4);
-                    } else {
-                        const int prev = step - 1;
-                        n1 = n1 && chg[i - 1] == prev;
-                        n2 = n2 && chg[i + 1] == prev;
-                        n3 = n3 && chg[i - RW] == prev;
-                        n4 = n4 && chg[i + RW] == prev;
-                    }
-                    need = (n1 ? 2u : 0u) | (n2 ? 4u : 0u) | (n3 ? 8u : 0u) | (n4 ? 16u : 0u);
+                const uint32_t c0 = vp[i], c1 = vp[i - 1], c2 = vp[i + 1], c3 = vp[i - RW], c4 = vp[i + RW];
+                const bool ok1 = xact & (x > 0), ok2 = xact & (x < W - 1), ok3 = xact & (y > 0),
+                           ok4 = xact & (y < H - 1);
+                // a candidate equal to an earlier one in the image is not costed
+                bool n1 = ok1 & (c1 != c0);
+                bool n2 = ok2 & (c2 != c0) & !(ok1 & (c2 == c1));
+                bool n3 = ok3 & (c3 != c0) & !(ok1 & (c3 == c1)) & !(ok2 & (c3 == c2));
+                bool n4 = ok4 & (c4 != c0) & !(ok1 & (c4 == c1)) & !(ok2 & (c4 == c2)) & !(ok3 & (c4 == c3));
+                if (step == 1) {  // uniform
+                    const uint32_t cen = jm[i];
+                    const int cx = unpack_x(cen) * 2, cy = unpack_y(cen) * 2;
+                    const uint32_t w = (uint32_t)(2 * R);
+                    auto out = [&](uint32_t v) {
+                        return ((uint32_t)(unpack_x(v) - cx + R) > w) | ((uint32_t)(unpack_y(v) - cy + R) > w);
+                    };
+                    n1 &= out(c1);
+                    n2 &= out(c2);
+                    n3 &= out(c3);
+                    n4 &= out(c4);
+                } else {
+                    const uint32_t prev = (uint32_t)(step - 1);
+                    n1 &= chg[i - 1] == prev;
+                    n2 &= chg[i + 1] == prev;
+                    n3 &= chg[i - RW] == prev;
+                    n4 &= chg[i + RW] == prev;
                 }
+                const uint32_t need = (n1 ? 2u : 0u) | (n2 ? 4u : 0u) | (n3 ? 8u : 0u) | (n4 ? 16u : 0u);
                 int wtotal;
                 const int pre = wave_prefix(__popc(need), wtotal);
                 int base = 0;
@@ -656,14 +657,14 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict
                     if (rx == 0) base = atomicAdd(njobs, wtotal);
                     base = __shfl(base, 0, 64);
                 }
-                if (xact) {
-                    int j = base + pre;
-                    jm[i] = need ? ((uint32_t)j | need << 16) : 0u;
+                const int j = base + pre;
+                if (xact) jm[i] = need ? ((uint32_t)j | need << 16) : 0u;
+                if (need) {
                     const uint32_t e = (uint32_t)((ry << 6) | rx) << 2;
-                    if (need & 2u) jobs[j++] = (uint16_t)(e | 0u);
-                    if (need & 4u) jobs[j++] = (uint16_t)(e | 1u);
-                    if (need & 8u) jobs[j++] = (uint16_t)(e | 2u);
-                    if (need & 16u) jobs[j] = (uint16_t)(e | 3u);
+                    int q = j;
+#pragma unroll
+                    for (int k = 1; k < 5; k++)
+                        if (need & (1u << k)) jobs[q++] = (uint16_t)(e | (uint32_t)(k - 1));
                 }
             }
             __syncthreads();
