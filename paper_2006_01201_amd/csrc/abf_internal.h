@@ -41,15 +41,21 @@ struct StripLv {
 };
 
 // The caller's buffers of one strip.
+// slots per exposure sum (spread of the luma kernel's atomics)
+constexpr int kSumSlots = 64;
+
 struct StripIO {
     const uint8_t *L, *R;
-    unsigned long long *sums;  // device: intensity sums of L and R (exposure step)
+    unsigned long long *sums;  // device: intensity sums of L, R (exposure step), kSumSlots slots each
     const float *blend;
     float *flow[2];  // [0] = FlowLtoR, [1] = FlowRtoL
     uint8_t *F;
     float *Ff32;
     int32_t pitchL, pitchR, pitchF;
     int32_t H, W, axis;
+    int32_t pad_;
+    double inv_ext1;  // 1 / (extent + 1) across the seam (eq. (1) ramp)
+    double inv_ext;   // 1 / extent across the seam (flow magnitude scale)
 };
 
 // Launch of one stage over a batch: the strip table, per-strip tile
@@ -78,12 +84,12 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 
 // search tiles: 128 x TH pixels (64 threads per row, two pixels each);
 // refine: 64 x TH; propagation: (64 - 2h) x TH outputs, TH = 8 or 16; luma, exposure step and blend:
-// 256 pixels of one row; pyramid: 64 x 4 output pixels. Luma, exposure
+// 256 pixels of one row; pyramid: 256 x 4 output pixels (4 per thread). Luma, exposure
 // and pyramid tiles cover the padded planes.
 constexpr int kSearchTW = 128;
 constexpr int kRefineTW = 64;
 constexpr int kRowTW = 256;
-constexpr int kPyrTW = 64;
+constexpr int kPyrTW = 256;
 constexpr int kPyrTH = 4;
 
 // ---------------------------------------------------------------------

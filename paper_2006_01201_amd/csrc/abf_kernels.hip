@@ -200,15 +200,41 @@ __device__ __forceinline__ void wg_minmax4(int &a0, int &a1, int &a2, int &a3, i
 // written over the padded planes (a border pixel takes the value of the
 // nearest image pixel). The intensity sums over the image (for the
 // exposure step) are accumulated with 64-bit integer atomics, so they do
-// not depend on the order of the additions.
+// not depend on the order of the additions; each sum is spread over
+// kSumSlots slots (by workgroup) so that the atomics of the many
+// workgroups do not all queue on one address.
 __global__ __launch_bounds__(256) void k_zero_sums(const StripIO *__restrict__ io, int n)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < 2 * n) io[i >> 1].sums[i & 1] = 0ull;
+    if (i < 2 * kSumSlots * n) gst(io[i / (2 * kSumSlots)].sums)[i % (2 * kSumSlots)] = 0ull;
 }
 
 __device__ __forceinline__ int luma_of(uint32_t r, uint32_t g, uint32_t b) { return (77 * r + 150 * g + 29 * b + 128) >> 8; }
 
+// Four consecutive RGB pixels (12 bytes) of a row starting at p, from
+// aligned dwords when those lie inside [lo, hi) (the image data), else
+// byte by byte; luma of each.
+__device__ __forceinline__ void luma4(const uint8_t *p, uintptr_t lo, uintptr_t hi, int (&yv)[4])
+{
+    const uintptr_t a = (uintptr_t)p & ~(uintptr_t)3;
+    if (a >= lo && a + 16 <= hi) {
+        const auto q = reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(a);
+        const uint32_t w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
+        const int sh = (int)((uintptr_t)p - a);
+        const uint32_t a0 = __builtin_amdgcn_alignbyte(w1, w0, sh), a1 = __builtin_amdgcn_alignbyte(w2, w1, sh),
+                       a2 = __builtin_amdgcn_alignbyte(w3, w2, sh);
+        yv[0] = luma_of(a0 & 0xff, (a0 >> 8) & 0xff, (a0 >> 16) & 0xff);
+        yv[1] = luma_of(a0 >> 24, a1 & 0xff, (a1 >> 8) & 0xff);
+        yv[2] = luma_of((a1 >> 16) & 0xff, a1 >> 24, a2 & 0xff);
+        yv[3] = luma_of((a2 >> 8) & 0xff, (a2 >> 16) & 0xff, a2 >> 24);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) yv[k] = luma_of(p[3 * k], p[3 * k + 1], p[3 * k + 2]);
+    }
+}
+
+// A thread makes four outputs of a padded row; a group wholly in the left
+// or right border repeats the edge pixel's luma.
 __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
                                               const int32_t *__restrict__ prefix, int n, int total)
 {
@@ -225,22 +251,22 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
         const int cy = clampi(y, 0, H - 1);
         unsigned long long sl = 0, sr = 0;
         if (px < W + 2 * kPad) {
-            const uint8_t *rl = io[s].L + (size_t)cy * io[s].pitchL;
-            const uint8_t *rr = io[s].R + (size_t)cy * io[s].pitchR;
+            const StripIO &o = io[s];
+            const uint8_t *rl = o.L + (size_t)cy * o.pitchL;
+            const uint8_t *rr = o.R + (size_t)cy * o.pitchR;
             int yl[4], yr[4];
-            // four image pixels from 12-byte aligned runs when possible
-            if (x >= 0 && x + 3 <= W - 1 && ((reinterpret_cast<uintptr_t>(rl + 3 * x) | reinterpret_cast<uintptr_t>(rr + 3 * x)) & 3) == 0) {
-                const uint32_t *ql = reinterpret_cast<const uint32_t *>(rl + 3 * x);
-                const uint32_t *qr = reinterpret_cast<const uint32_t *>(rr + 3 * x);
-                const uint32_t a0 = ql[0], a1 = ql[1], a2 = ql[2], b0 = qr[0], b1 = qr[1], b2 = qr[2];
-                yl[0] = luma_of(a0 & 0xff, (a0 >> 8) & 0xff, (a0 >> 16) & 0xff);
-                yl[1] = luma_of(a0 >> 24, a1 & 0xff, (a1 >> 8) & 0xff);
-                yl[2] = luma_of((a1 >> 16) & 0xff, a1 >> 24, a2 & 0xff);
-                yl[3] = luma_of((a2 >> 8) & 0xff, (a2 >> 16) & 0xff, a2 >> 24);
-                yr[0] = luma_of(b0 & 0xff, (b0 >> 8) & 0xff, (b0 >> 16) & 0xff);
-                yr[1] = luma_of(b0 >> 24, b1 & 0xff, (b1 >> 8) & 0xff);
-                yr[2] = luma_of((b1 >> 16) & 0xff, b1 >> 24, b2 & 0xff);
-                yr[3] = luma_of((b2 >> 8) & 0xff, (b2 >> 16) & 0xff, b2 >> 24);
+            if (x >= 0 && x + 3 <= W - 1) {
+                luma4(rl + 3 * x, (uintptr_t)o.L, (uintptr_t)(o.L + (size_t)(H - 1) * o.pitchL + 3 * (size_t)W), yl);
+                luma4(rr + 3 * x, (uintptr_t)o.R, (uintptr_t)(o.R + (size_t)(H - 1) * o.pitchR + 3 * (size_t)W), yr);
+            } else if (x + 3 < 0 || x > W - 1) {
+                const int cx = x < 0 ? 0 : W - 1;
+                const int vl = luma_of(rl[3 * cx], rl[3 * cx + 1], rl[3 * cx + 2]);
+                const int vr = luma_of(rr[3 * cx], rr[3 * cx + 1], rr[3 * cx + 2]);
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    yl[k] = vl;
+                    yr[k] = vr;
+                }
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
@@ -249,10 +275,10 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
                     yr[k] = luma_of(rr[3 * cx], rr[3 * cx + 1], rr[3 * cx + 2]);
                 }
             }
-            const ptrdiff_t o = (ptrdiff_t)y * lv[s].ypitch + x;  // 4-byte aligned (padded rows are)
-            *reinterpret_cast<uint32_t *>(lv[s].y[0] + o) =
+            const ptrdiff_t off = (ptrdiff_t)y * lv[s].ypitch + x;  // 4-byte aligned (padded rows are)
+            gst(reinterpret_cast<uint32_t *>(lv[s].y[0] + off))[0] =
                 (uint32_t)yl[0] | ((uint32_t)yl[1] << 8) | ((uint32_t)yl[2] << 16) | ((uint32_t)yl[3] << 24);
-            *reinterpret_cast<uint32_t *>(lv[s].y[1] + o) =
+            gst(reinterpret_cast<uint32_t *>(lv[s].y[1] + off))[0] =
                 (uint32_t)yr[0] | ((uint32_t)yr[1] << 8) | ((uint32_t)yr[2] << 16) | ((uint32_t)yr[3] << 24);
             if (y == cy) {
 #pragma unroll
@@ -278,8 +304,9 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
         if (threadIdx.x == 0) {
             const unsigned long long a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
             const unsigned long long b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-            if (a) atomicAdd(&io[s].sums[0], a);
-            if (b) atomicAdd(&io[s].sums[1], b);
+            const int slot = (int)(blockIdx.x % kSumSlots);
+            if (a) atomicAdd(&io[s].sums[slot], a);
+            if (b) atomicAdd(&io[s].sums[kSumSlots + slot], b);
         }
         __syncthreads();
     }
@@ -290,6 +317,7 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
 __global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
                                               const int32_t *__restrict__ prefix, int n, int total)
 {
+    static_assert(kSumSlots == 64, "one slot per lane");
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -298,7 +326,14 @@ __global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, co
         const int segs = ceil_div(W + 2 * kPad, kLumaTW);
         const int py = local / segs;
         const int px = (local - py * segs) * kLumaTW + 4 * (int)threadIdx.x;
-        const unsigned long long sl = io[s].sums[0], sr = io[s].sums[1];
+        // the two sums of the strip: every wave adds up the slots
+        const auto sums = gld(io[s].sums);
+        unsigned long long sl = sums[threadIdx.x & 63], sr = sums[kSumSlots + (threadIdx.x & 63)];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            sl += __shfl_xor(sl, m, 64);
+            sr += __shfl_xor(sr, m, 64);
+        }
         if (sr == 0 || px >= W + 2 * kPad) continue;
         const unsigned long long a = (sl << 16) / sr;
         uint32_t *p = reinterpret_cast<uint32_t *>(lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch + (px - kPad));
@@ -318,9 +353,29 @@ __global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, co
 // even positions, clamped borders, rounding (s + 128) >> 8. Outputs cover
 // the padded plane (a border pixel takes the value at the nearest image
 // pixel); the taps of an image pixel stay inside the finer plane's border.
+// A thread makes four horizontally adjacent outputs: inside the image it
+// reads the 11 input bytes of each of the 5 rows as aligned dwords and
+// forms the horizontal taps with byte dot products; a group wholly in the
+// left or right border repeats the edge output.
+__device__ __forceinline__ uint32_t pyr_one(const uint8_t *src, int pf, int x, int y)
+{
+    constexpr int w5[5] = {1, 4, 6, 4, 1};
+    int acc = 0;
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        const uint8_t *row = src + (ptrdiff_t)(2 * y + j - 2) * pf + (2 * x - 2);
+        int hs = 0;
+#pragma unroll
+        for (int i = 0; i < 5; i++) hs += w5[i] * row[i];
+        acc += w5[j] * hs;
+    }
+    return (uint32_t)((acc + 128) >> 8);
+}
+
 __global__ __launch_bounds__(256) void k_pyr(const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix,
                                              int n, int total)
 {
+    constexpr uint32_t W4 = 0x04060401u;  // taps 1 4 6 4 on bytes 0..3
     constexpr int w5[5] = {1, 4, 6, 4, 1};
     TILE_LOOP(total)
     {
@@ -332,23 +387,42 @@ __global__ __launch_bounds__(256) void k_pyr(const StripLv *__restrict__ lv, con
         local -= img * per_img;
         const int tx = ceil_div(L.W + 2 * kPad, kPyrTW);
         const int ty = local / tx;
-        const int px = (local - ty * tx) * kPyrTW + (int)(threadIdx.x & (kPyrTW - 1));
-        const int py = ty * kPyrTH + (int)(threadIdx.x / kPyrTW);
-        if (px < L.W + 2 * kPad && py < L.H + 2 * kPad) {
-            const int x = clampi(px - kPad, 0, L.W - 1), y = clampi(py - kPad, 0, L.H - 1);
-            const uint8_t *src = L.yfine[img];
-            const int pf = L.ypitch_f;
-            int acc = 0;
+        const int px = (local - ty * tx) * kPyrTW + 4 * (int)(threadIdx.x & 63);
+        const int py = ty * kPyrTH + (int)(threadIdx.x >> 6);
+        if (px >= L.W + 2 * kPad || py >= L.H + 2 * kPad) continue;  // no barrier in this kernel
+        const int x0 = px - kPad, y = clampi(py - kPad, 0, L.H - 1);
+        const uint8_t *src = L.yfine[img];
+        const int pf = L.ypitch_f;
+        uint32_t out;
+        if (x0 >= 0 && x0 + 3 <= L.W - 1) {
+            uint32_t r[5][3];
+            load_rows<11, 5>(plane_org(src, pf), pf, 2 * y - 2, 2 * x0 - 2, r);
+            uint32_t acc[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int j = 0; j < 5; j++) {
-                const uint8_t *row = src + (ptrdiff_t)(2 * y + j - 2) * pf + (2 * x - 2);
-                int h = 0;
-#pragma unroll
-                for (int i = 0; i < 5; i++) h += w5[i] * row[i];
-                acc += w5[j] * h;
+                // output k takes bytes 2k .. 2k+4 of the row
+                const uint32_t d1 = __builtin_amdgcn_alignbyte(r[j][1], r[j][0], 2);
+                const uint32_t d3 = __builtin_amdgcn_alignbyte(r[j][2], r[j][1], 2);
+                const uint32_t hs0 = __builtin_amdgcn_udot4(r[j][0], W4, (r[j][1] >> 0) & 0xffu, false);
+                const uint32_t hs1 = __builtin_amdgcn_udot4(d1, W4, (r[j][1] >> 16) & 0xffu, false);
+                const uint32_t hs2 = __builtin_amdgcn_udot4(r[j][1], W4, (r[j][2] >> 0) & 0xffu, false);
+                const uint32_t hs3 = __builtin_amdgcn_udot4(d3, W4, (r[j][2] >> 16) & 0xffu, false);
+                acc[0] += w5[j] * hs0;
+                acc[1] += w5[j] * hs1;
+                acc[2] += w5[j] * hs2;
+                acc[3] += w5[j] * hs3;
             }
-            L.y[img][(ptrdiff_t)(py - kPad) * L.ypitch + (px - kPad)] = (uint8_t)((acc + 128) >> 8);
+            out = ((acc[0] + 128) >> 8) | (((acc[1] + 128) >> 8) << 8) | (((acc[2] + 128) >> 8) << 16) |
+                  (((acc[3] + 128) >> 8) << 24);
+        } else if (x0 + 3 < 0 || x0 > L.W - 1) {
+            out = pyr_one(src, pf, x0 < 0 ? 0 : L.W - 1, y) * 0x01010101u;
+        } else {
+            out = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) out |= pyr_one(src, pf, clampi(x0 + k, 0, L.W - 1), y) << (8 * k);
         }
+        // padded rows are 64-byte aligned and px is a multiple of 4
+        gst(reinterpret_cast<uint32_t *>(L.y[img] + (ptrdiff_t)(py - kPad) * L.ypitch + x0))[0] = out;
     }
 }
 
@@ -1089,16 +1163,17 @@ struct PixBlend {
 
 __device__ __forceinline__ float finite0(float v) { return isfinite(v) ? v : 0.f; }
 
-__device__ __forceinline__ PixBlend blend_setup(int x, int y, int H, int W, int axis, const float *blend,
-                                                const float *flr, const float *frl, BlendParams bp)
+__device__ __forceinline__ PixBlend blend_setup(int x, int y, int axis, double inv_ext1, double inv_ext, int W,
+                                                const float *blend, const float *flr, const float *frl, BlendParams bp)
 {
-    const size_t p = (size_t)y * W + x;
-    const double t = blend ? (double)gld(blend)[p] : (axis == 0 ? (x + 1.0) / (W + 1.0) : (y + 1.0) / (H + 1.0));
+    const uint32_t p = (uint32_t)(y * W + x);
+    const double t = blend ? (double)gld(blend)[p] : (double)((axis == 0 ? x : y) + 1) * inv_ext1;
     const uint64_t vrl = gld(reinterpret_cast<const uint64_t *>(frl))[p];
     const uint64_t vlr = gld(reinterpret_cast<const uint64_t *>(flr))[p];
-    const double rlx = finite0(__uint_as_float((uint32_t)vrl)), rly = finite0(__uint_as_float((uint32_t)(vrl >> 32)));
-    const double lrx = finite0(__uint_as_float((uint32_t)vlr)), lry = finite0(__uint_as_float((uint32_t)(vlr >> 32)));
-    const double ax = rlx * t, ay = rly * t, bx = lrx * (1.0 - t), by = lry * (1.0 - t);
+    const float frx = finite0(__uint_as_float((uint32_t)vrl)), fry = finite0(__uint_as_float((uint32_t)(vrl >> 32)));
+    const float flx = finite0(__uint_as_float((uint32_t)vlr)), fly = finite0(__uint_as_float((uint32_t)(vlr >> 32)));
+    // displacements in double (split into cell and fraction exactly)
+    const double ax = (double)frx * t, ay = (double)fry * t, bx = (double)flx * (1.0 - t), by = (double)fly * (1.0 - t);
     const double fax = floor(ax), fay = floor(ay), fbx = floor(bx), fby = floor(by);
     PixBlend r;
     r.lx = x + (int)fax;
@@ -1112,8 +1187,10 @@ __device__ __forceinline__ PixBlend blend_setup(int x, int y, int H, int W, int 
     if (bp.mode == 1) {
         r.sL = (float)(1.0 - t);
     } else {
-        const double S = axis == 0 ? (double)W : (double)H;
-        const double mrl = sqrt(rlx * rlx + rly * rly) / S, mlr = sqrt(lrx * lrx + lry * lry) / S;
+        // the exponents in double: with large flows both can be in the
+        // hundreds and nearly equal, where FP32 rounding would move F
+        const double mrl = sqrt((double)frx * frx + (double)fry * fry) * inv_ext;
+        const double mlr = sqrt((double)flx * flx + (double)fly * fly) * inv_ext;
         const double zL = (double)bp.k_sharp * (1.0 - t) * (1.0 + (double)bp.k_flowmag * mrl);
         const double zR = (double)bp.k_sharp * t * (1.0 + (double)bp.k_flowmag * mlr);
         r.sL = 1.0f / (1.0f + expf((float)(zR - zL)));
@@ -1192,7 +1269,7 @@ __global__ __launch_bounds__(kRowTW) void k_blend(const StripIO *__restrict__ io
         uint8_t *const seg = o.F + (size_t)y * o.pitchF + 3 * (size_t)xs;  // first output byte of the segment
         const int off = (int)((uintptr_t)seg & 3);
         if (x < W) {
-            const PixBlend pb = blend_setup(x, y, H, W, o.axis, o.blend, o.flow[0], o.flow[1], bp);
+            const PixBlend pb = blend_setup(x, y, o.axis, o.inv_ext1, o.inv_ext, W, o.blend, o.flow[0], o.flow[1], bp);
             float cl[3], cr[3];
             sample_u8(o.L, o.pitchL, H, W, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
             sample_u8(o.R, o.pitchR, H, W, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
@@ -1237,7 +1314,7 @@ hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, 
 
 hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_sums, dim3(ceil_div(2 * n, 256)), dim3(256), 0, s, io, n);
+    hipLaunchKernelGGL(k_zero_sums, dim3(ceil_div(2 * kSumSlots * n, 256)), dim3(256), 0, s, io, n);
     return hipGetLastError();
 }
 

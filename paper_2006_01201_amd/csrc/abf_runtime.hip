@@ -179,7 +179,7 @@ size_t data_bound(const abf_plan *pl)
         b += 2 * 2 * (4 * mp * f * f + S * (4 * Wm * f + 64 * Hm * f + 68 + 256));
         b += 2 * 1 * (2 * mp * f * f + S * (2 * Wm * f + 32 * Hm * f + 34 + 256));
     }
-    b += S * kAlign;  // exposure sums
+    b += S * align_up(2 * kSumSlots * sizeof(unsigned long long), kAlign);  // exposure sums
     return align_up((size_t)b + 4096, kAlign);
 }
 
@@ -284,9 +284,14 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
         io.H = x.H;
         io.W = x.W;
         io.axis = x.axis;
+        {
+            const int ext = x.axis == 0 ? x.W : x.H;
+            io.inv_ext1 = 1.0 / (ext + 1.0);
+            io.inv_ext = 1.0 / ext;
+        }
         if (!flows) continue;
         io.sums = reinterpret_cast<unsigned long long *>(pl->ws + off);
-        off += kAlign;
+        off += align_up(2 * kSumSlots * sizeof(unsigned long long), kAlign);
         for (int k = 0; k < N; k++) {
             StripLv &v = b.lv[(size_t)k * n + s];
             v.H = L.hk[s][k];
