@@ -119,6 +119,30 @@ def run_stream(n_pano, p, timed, log):
             "mpix_s_with_refine": round(total_px / (ms_f + ms_r) / 1e3, 1)}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_01201_amd", "csrc", "abf_kernels.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a copy of known size), or None when there is no entry or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("kernel="):
+            continue
+        f = dict(kv.strip().split("=", 1) for kv in line.strip().split(";"))
+        if f["kernel"] == kernel and f["source_sha256"] == digest:
+            return int(float(f["fetch_kib"]) * 1024 * float(f["fetch_scale"]) +
+                       float(f["write_kib"]) * 1024 * float(f["write_scale"]))
+    return None
+
+
 def rate(amount, ms, unit):
     s = ms / 1e3
     return amount / s / (1e9 if unit == "GB/s" else 1e12)
@@ -236,7 +260,7 @@ def main():
     bound, amount, unit, peak = algorithmic(dom_st, dom_k, shapes, p)
     achieved = rate(amount, dom_ms, unit)
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(kernel_name(dom_st, dom_k, p)),
                 "kernel": kernel_name(dom_st, dom_k, p), "launch_ms": round(dom_ms, 4),
                 "work_per_launch": amount}
     per_launch = []

@@ -1106,14 +1106,26 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
         const uint8_t *A = L.y[dir], *B = L.y[1 - dir];  // pixel (0, 0); the rows carry a replicated border
         const uint32_t d0 = L.df[dir][(size_t)y * L.fpitch + x];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
-        int hxx = 0, hxy = 0, hyy = 0;
+        // every window position's Ref value and doubled gradient (all loads
+        // of the window in flight together)
+        int av[WN][WN], gx[WN][WN], gy[WN][WN];
+#pragma unroll
         for (int j = 0; j < WN; j++)
+#pragma unroll
             for (int i = 0; i < WN; i++) {
                 const uint8_t *q = A + (ptrdiff_t)clampi(y + j - LP, 0, H - 1) * yp + clampi(x + i - LP, 0, W - 1);
-                const int gx = (int)q[1] - (int)q[-1], gy = (int)q[yp] - (int)q[-yp];
-                hxx += gx * gx;
-                hxy += gx * gy;
-                hyy += gy * gy;
+                av[j][i] = q[0];
+                gx[j][i] = (int)q[1] - (int)q[-1];
+                gy[j][i] = (int)q[yp] - (int)q[-yp];
+            }
+        int hxx = 0, hxy = 0, hyy = 0;
+#pragma unroll
+        for (int j = 0; j < WN; j++)
+#pragma unroll
+            for (int i = 0; i < WN; i++) {
+                hxx += gx[j][i] * gx[j][i];
+                hxy += gx[j][i] * gy[j][i];
+                hyy += gy[j][i] * gy[j][i];
             }
         const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
         const double hdet = 0.5 / (Hxx * Hyy - Hxy * Hxy);
@@ -1124,20 +1136,20 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
             const float fx = (float)(ux - fux), fy = (float)(uy - fuy);
             const int iux = (int)fux, iuy = (int)fuy;
             double bx = 0.0, by = 0.0;
+#pragma unroll
             for (int j = 0; j < WN; j++) {
                 const int qy = clampi(y + j - LP, 0, H - 1);
                 const uint8_t *ra = B + (ptrdiff_t)clampi(qy + iuy, 0, H - 1) * yp;
                 const uint8_t *rb = B + (ptrdiff_t)clampi(qy + iuy + 1, 0, H - 1) * yp;
+#pragma unroll
                 for (int i = 0; i < WN; i++) {
                     const int qx = clampi(x + i - LP, 0, W - 1);
-                    const uint8_t *q = A + (ptrdiff_t)qy * yp + qx;
-                    const int gx = (int)q[1] - (int)q[-1], gy = (int)q[yp] - (int)q[-yp];
                     const int xa = clampi(qx + iux, 0, W - 1), xb = clampi(qx + iux + 1, 0, W - 1);
                     const float v00 = ra[xa], v01 = ra[xb], v10 = rb[xa], v11 = rb[xb];
                     const float tp = v00 + fx * (v01 - v00), bt = v10 + fx * (v11 - v10);
-                    const double e = (double)(tp + fy * (bt - tp)) - (double)q[0];
-                    bx = fma((double)gx, e, bx);
-                    by = fma((double)gy, e, by);
+                    const double e = (double)(tp + fy * (bt - tp)) - (double)av[j][i];
+                    bx = fma((double)gx[j][i], e, bx);
+                    by = fma((double)gy[j][i], e, by);
                 }
             }
             const double dx = ixy * by - ixx * bx;
