@@ -103,9 +103,9 @@ hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s);
 hipError_t launch_search(const StripLv *lv, Work w, int patch, int radius, int th, int grid, hipStream_t s);
 // the T propagation steps and the median of one level (one launch)
 hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int median, int th, int grid, hipStream_t s);
-// refine: interior tiles (work list wi) and border pixels (work list wb)
-hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work wi, Work wb, LkParams lk, int th, int grid,
-                         hipStream_t s);
+// refine: interior tiles and, separately, the border pixels
+hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid, hipStream_t s);
+hipError_t launch_refine_border(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, hipStream_t s);
 hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s);
 
 // One strip of a batched refinement: u[0] is the caller's flow, u[1] the

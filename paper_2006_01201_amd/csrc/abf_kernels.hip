@@ -1396,33 +1396,45 @@ hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int medi
 }
 
 template <int LP>
-static hipError_t refine_lp(const StripLv *lv0, const StripIO *io, Work wi, Work wb, LkParams lk, int th, int grid,
+static hipError_t refine_lp(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid,
                             hipStream_t s)
 {
-    if (wi.total > 0) {
-        const int g = grid_for(wi.total, grid);
-        if (th == 2)
-            hipLaunchKernelGGL((k_refine<LP, 2>), dim3(g), dim3(128), 0, s, lv0, io, wi.prefix, wi.n, wi.total,
-                               lk.iters, lk.eps);
-        else
-            hipLaunchKernelGGL((k_refine<LP, 4>), dim3(g), dim3(256), 0, s, lv0, io, wi.prefix, wi.n, wi.total,
-                               lk.iters, lk.eps);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (wb.total > 0)
-        hipLaunchKernelGGL((k_refine_border<LP>), dim3(wb.total), dim3(kRowTW), 0, s, lv0, io, wb.prefix, wb.n,
-                           wb.total, lk.iters, lk.eps);
+    if (w.total == 0) return hipSuccess;
+    const int g = grid_for(w.total, grid);
+    if (th == 2)
+        hipLaunchKernelGGL((k_refine<LP, 2>), dim3(g), dim3(128), 0, s, lv0, io, w.prefix, w.n, w.total, lk.iters,
+                           lk.eps);
+    else
+        hipLaunchKernelGGL((k_refine<LP, 4>), dim3(g), dim3(256), 0, s, lv0, io, w.prefix, w.n, w.total, lk.iters,
+                           lk.eps);
     return hipGetLastError();
 }
 
-hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work wi, Work wb, LkParams lk, int th, int grid,
-                         hipStream_t s)
+hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid, hipStream_t s)
 {
     switch (lk.patch) {
-    case 1: return refine_lp<1>(lv0, io, wi, wb, lk, th, grid, s);
-    case 2: return refine_lp<2>(lv0, io, wi, wb, lk, th, grid, s);
-    case 3: return refine_lp<3>(lv0, io, wi, wb, lk, th, grid, s);
+    case 1: return refine_lp<1>(lv0, io, w, lk, th, grid, s);
+    case 2: return refine_lp<2>(lv0, io, w, lk, th, grid, s);
+    case 3: return refine_lp<3>(lv0, io, w, lk, th, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LP>
+static hipError_t refine_border_lp(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, hipStream_t s)
+{
+    if (w.total > 0)
+        hipLaunchKernelGGL((k_refine_border<LP>), dim3(w.total), dim3(kRowTW), 0, s, lv0, io, w.prefix, w.n, w.total,
+                           lk.iters, lk.eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_border(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, hipStream_t s)
+{
+    switch (lk.patch) {
+    case 1: return refine_border_lp<1>(lv0, io, w, lk, s);
+    case 2: return refine_border_lp<2>(lv0, io, w, lk, s);
+    case 3: return refine_border_lp<3>(lv0, io, w, lk, s);
     default: return hipErrorInvalidValue;
     }
 }

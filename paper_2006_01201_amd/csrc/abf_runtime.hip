@@ -445,9 +445,13 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
                               pl->launch[ST_PROP][c].tile_h, grid_of(pl, ST_PROP, c), s));
         }
         LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
-        TIMED(ST_REFINE, 0,
-              launch_refine(lv, io, work(ST_REFINE, 0), work(LIST_REFINE_BORDER, 0), lk,
-                            pl->launch[ST_REFINE][b.cls[0]].tile_h, grid_of(pl, ST_REFINE, b.cls[0]), s));
+        // interior tiles, then the border pixels (a forked stream that ran the
+        // border concurrently made the graph replay slower)
+        HIP_TRY(pl, mark(ST_REFINE, 0));
+        HIP_TRY(pl, launch_refine(lv, io, work(ST_REFINE, 0), lk, pl->launch[ST_REFINE][b.cls[0]].tile_h,
+                                  grid_of(pl, ST_REFINE, b.cls[0]), s));
+        HIP_TRY(pl, launch_refine_border(lv, io, work(LIST_REFINE_BORDER, 0), lk, s));
+        HIP_TRY(pl, mark(ST_REFINE, 0));
     }
     if (blend) {
         BlendParams bp{p.k_sharp, p.k_flowmag, p.blend_mode};
@@ -595,6 +599,7 @@ abf_status abf_create_plan(const abf_params *params, int32_t max_strips, int64_t
             return ABF_E_DEVICE;
         }
     }
+
     const char *cache = getenv("ABF_TUNE_CACHE");
     if (cache) {
         FILE *f = fopen(cache, "r");
@@ -691,6 +696,7 @@ abf_status abf_destroy(abf_plan *plan)
     if (!plan) return ABF_E_INVALID;
     clear_graphs(plan);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+
     for (int k = 0; k < kSlots; k++) {
         if (plan->ev[k]) {
             if (plan->ev_used[k]) (void)hipEventSynchronize(plan->ev[k]);
