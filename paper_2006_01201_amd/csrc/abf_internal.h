@@ -83,7 +83,7 @@ struct BlendParams {
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // search tiles: 128 x TH pixels (64 threads per row, two pixels each);
-// refine: 64 x TH; propagation: (64 - 2h) x TH outputs, TH = 8 or 16; luma, exposure step and blend:
+// refine: 64 x TH; propagation: (64 - 2h) x TH outputs, TH = 8, 16 or 32; luma, exposure step and blend:
 // 256 pixels of one row; pyramid: 256 x 4 output pixels (4 per thread). Luma, exposure
 // and pyramid tiles cover the padded planes.
 constexpr int kSearchTW = 128;

@@ -1382,8 +1382,11 @@ static hipError_t prop_th(const StripLv *lv, Work w, int steps, int median, int 
     if (th == 8)
         hipLaunchKernelGGL((k_prop<P, 8>), dim3(g), dim3(kPropThreads), lds, s, lv, w.prefix, w.n, w.total, steps,
                            median);
-    else
+    else if (th == 16)
         hipLaunchKernelGGL((k_prop<P, 16>), dim3(g), dim3(kPropThreads), lds, s, lv, w.prefix, w.n, w.total, steps,
+                           median);
+    else
+        hipLaunchKernelGGL((k_prop<P, 32>), dim3(g), dim3(kPropThreads), lds, s, lv, w.prefix, w.n, w.total, steps,
                            median);
     return hipGetLastError();
 }

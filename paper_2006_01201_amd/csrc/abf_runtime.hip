@@ -121,7 +121,7 @@ bool valid_th(int stage, int th)
 {
     switch (stage) {
     case ST_SEARCH: return th == 1 || th == 2 || th == 4 || th == 8;
-    case ST_PROP: return th == 8 || th == 16;
+    case ST_PROP: return th == 8 || th == 16 || th == 32;
     case ST_REFINE: return th == 2 || th == 4;
     default: return th == 4;
     }
@@ -782,7 +782,7 @@ abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hi
     for (int stage = 0; stage < kStages && rc == ABF_OK; stage++)
         for (int c = 0; c < kSizeClasses && rc == ABF_OK; c++) {
             std::vector<int> ths;
-            for (int th : {1, 2, 4, 8, 16})
+            for (int th : {1, 2, 4, 8, 16, 32})
                 if (valid_th(stage, th)) ths.push_back(th);
             Launch best = plan->launch[stage][c];
             float best_ms = 1e30f;
