@@ -1065,15 +1065,25 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
 }
 
 // The pixels whose window leaves the image (within LP of the border): every
-// window position is clamped to the image on its own, so positions repeat;
-// each is evaluated with its own loads (a small fraction of the pixels).
+// window position is clamped to the image on its own, so positions repeat.
+// The clamped positions never decrease and step by 0 or 1, so the bytes a
+// pixel needs from a row still form one short run: each window row loads
+// its own (clamped) Ref and Tgt rows of the padded planes, and the 16-bit
+// pairs of the dot products are gathered from the normalised run with
+// per-pixel v_perm_b32 selectors. The arithmetic is that of k_refine.
+__device__ __forceinline__ uint32_t psel(int b0, int b1)
+{
+    // selector of bytes b0, b1 (0..7 of hi:lo) as a 16-bit pair; b1 < 0: zero
+    return (uint32_t)b0 | 0x0c00u | (b1 < 0 ? 0x0c0000u : (uint32_t)b1 << 16) | 0x0c000000u;
+}
+
 template <int LP>
 __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restrict__ lv,
                                                           const StripIO *__restrict__ io,
                                                           const int32_t *__restrict__ prefix, int n, int total,
                                                           int iters, float eps)
 {
-    constexpr int WN = 2 * LP + 1;
+    constexpr int WN = 2 * LP + 1, NP = LP + 1, AB = WN + 2;
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -1103,62 +1113,118 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
             const int c = b - (b / k) * k;
             x = c < sp.xlo ? c : sp.xhi + (c - sp.xlo);
         }
-        const uint8_t *A = L.y[dir], *B = L.y[1 - dir];  // pixel (0, 0); the rows carry a replicated border
-        const uint32_t d0 = L.df[dir][(size_t)y * L.fpitch + x];
+        const uint8_t *Ao = plane_org(L.y[dir], yp), *Bo = plane_org(L.y[1 - dir], yp);
+        const uint32_t d0 = gld(L.df[dir])[(uint32_t)(y * L.fpitch + x)];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
-        // every window position's Ref value and doubled gradient (all loads
-        // of the window in flight together)
-        int av[WN][WN], gx[WN][WN], gy[WN][WN];
+        int qx[WN], qy[WN];
+#pragma unroll
+        for (int i = 0; i < WN; i++) {
+            qx[i] = clampi(x + i - LP, 0, W - 1);
+            qy[i] = clampi(y + i - LP, 0, H - 1);
+        }
+        // selectors: the Ref run starts at column qx[0] - 1, the Tgt run at
+        // the cell column of qx[0]
+        uint32_t sA[NP], sL[NP], sR[NP], sE[NP], sO[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const int i0 = 2 * k, i1 = 2 * k + 1;
+            const int c0 = qx[i0] - qx[0] + 1, c1 = i1 < WN ? qx[i1] - qx[0] + 1 : -1;
+            sA[k] = psel(c0, c1);
+            sL[k] = psel(c0 - 1, c1 < 0 ? -1 : c1 - 1);
+            sR[k] = psel(c0 + 1, c1 < 0 ? -1 : c1 + 1);
+            sE[k] = psel(c0 - 1, c1 < 0 ? -1 : c1 - 1);
+            sO[k] = psel(c0, c1);
+        }
+        // doubled gradients at the clamped positions as 16-bit pairs
+        uint32_t gxp[WN][NP], gyp[WN][NP];
+        int hxx = 0, hxy = 0, hyy = 0, sax = 0, say = 0;
+        // the 3 WN Ref rows (clamped rows - 1, 0, + 1 of each window row), all
+        // loads issued before the first is used
+        uint32_t rw[WN][3][1][RawRows<AB>::ND + 1];
+        int rs = 0;
 #pragma unroll
         for (int j = 0; j < WN; j++)
 #pragma unroll
-            for (int i = 0; i < WN; i++) {
-                const uint8_t *q = A + (ptrdiff_t)clampi(y + j - LP, 0, H - 1) * yp + clampi(x + i - LP, 0, W - 1);
-                av[j][i] = q[0];
-                gx[j][i] = (int)q[1] - (int)q[-1];
-                gy[j][i] = (int)q[yp] - (int)q[-yp];
-            }
-        int hxx = 0, hxy = 0, hyy = 0;
+            for (int d = 0; d < 3; d++) rs = issue_rows<AB, 1>(Ao, yp, qy[j] + d - 1, qx[0] - 1, rw[j][d]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int j = 0; j < WN; j++)
+        for (int j = 0; j < WN; j++) {
+            uint32_t r[3][(AB + 3) / 4];
 #pragma unroll
-            for (int i = 0; i < WN; i++) {
-                hxx += gx[j][i] * gx[j][i];
-                hxy += gx[j][i] * gy[j][i];
-                hyy += gy[j][i] * gy[j][i];
+            for (int d = 0; d < 3; d++) {
+                uint32_t rr[1][(AB + 3) / 4];
+                align_rows<AB, 1>(rw[j][d], rs, rr);
+#pragma unroll
+                for (int k = 0; k < (AB + 3) / 4; k++) r[d][k] = rr[0][k];
             }
+#pragma unroll
+            for (int k = 0; k < NP; k++) {
+                const uint32_t av = __builtin_amdgcn_perm(r[1][1], r[1][0], sA[k]);
+                gxp[j][k] = sub2(__builtin_amdgcn_perm(r[1][1], r[1][0], sR[k]),
+                                 __builtin_amdgcn_perm(r[1][1], r[1][0], sL[k]));
+                gyp[j][k] = sub2(__builtin_amdgcn_perm(r[2][1], r[2][0], sA[k]),
+                                 __builtin_amdgcn_perm(r[0][1], r[0][0], sA[k]));
+                hxx = dot2(gxp[j][k], gxp[j][k], hxx);
+                hxy = dot2(gxp[j][k], gyp[j][k], hxy);
+                hyy = dot2(gyp[j][k], gyp[j][k], hyy);
+                sax = dot2(gxp[j][k], av, sax);
+                say = dot2(gyp[j][k], av, say);
+            }
+        }
         const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
         const double hdet = 0.5 / (Hxx * Hyy - Hxy * Hxy);
         const double ixx = Hyy * hdet, ixy = Hxy * hdet, iyy = Hxx * hdet;
         double ux = d0x, uy = d0y;
         for (int it = 0; it < iters; it++) {
             const double fux = floor(ux), fuy = floor(uy);
-            const float fx = (float)(ux - fux), fy = (float)(uy - fuy);
-            const int iux = (int)fux, iuy = (int)fuy;
-            double bx = 0.0, by = 0.0;
+            const double fx = ux - fux, fy = uy - fuy;
+            // the Tgt run of a row: samples at qx[i] + ux, cell columns
+            // qx[i] + floor(ux) (+ 1); a run beyond the padded border lies
+            // wholly on one side of the image and is clamped to it unchanged
+            const int c0 = clampi(qx[0] + (int)fux, -kPad, W - 1 + kPad - (WN + 1));
+            int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
+            // the 2 WN Tgt rows of the cells, all loads issued first
+            uint32_t tw[WN][2][1][RawRows<WN + 2>::ND + 1];
+            int ts = 0;
+#pragma unroll
+            for (int j = 0; j < WN; j++)
+#pragma unroll
+                for (int d = 0; d < 2; d++)
+                    ts = issue_rows<WN + 2, 1>(Bo, yp, clampi(qy[j] + (int)fuy + d, -kPad, H - 1 + kPad), c0, tw[j][d]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < WN; j++) {
-                const int qy = clampi(y + j - LP, 0, H - 1);
-                const uint8_t *ra = B + (ptrdiff_t)clampi(qy + iuy, 0, H - 1) * yp;
-                const uint8_t *rb = B + (ptrdiff_t)clampi(qy + iuy + 1, 0, H - 1) * yp;
+                uint32_t ta[1][(WN + 2 + 3) / 4], tb[1][(WN + 2 + 3) / 4];
+                align_rows<WN + 2, 1>(tw[j][0], ts, ta);
+                align_rows<WN + 2, 1>(tw[j][1], ts, tb);
 #pragma unroll
-                for (int i = 0; i < WN; i++) {
-                    const int qx = clampi(x + i - LP, 0, W - 1);
-                    const int xa = clampi(qx + iux, 0, W - 1), xb = clampi(qx + iux + 1, 0, W - 1);
-                    const float v00 = ra[xa], v01 = ra[xb], v10 = rb[xa], v11 = rb[xb];
-                    const float tp = v00 + fx * (v01 - v00), bt = v10 + fx * (v11 - v10);
-                    const double e = (double)(tp + fy * (bt - tp)) - (double)av[j][i];
-                    bx = fma((double)gx[j][i], e, bx);
-                    by = fma((double)gy[j][i], e, by);
+                for (int k = 0; k < NP; k++) {
+                    const uint32_t ea = __builtin_amdgcn_perm(ta[0][1], ta[0][0], sE[k]);
+                    const uint32_t oa = __builtin_amdgcn_perm(ta[0][1], ta[0][0], sO[k]);
+                    const uint32_t eb = __builtin_amdgcn_perm(tb[0][1], tb[0][0], sE[k]);
+                    const uint32_t ob = __builtin_amdgcn_perm(tb[0][1], tb[0][0], sO[k]);
+                    s00x = dot2(gxp[j][k], ea, s00x);
+                    s01x = dot2(gxp[j][k], oa, s01x);
+                    s10x = dot2(gxp[j][k], eb, s10x);
+                    s11x = dot2(gxp[j][k], ob, s11x);
+                    s00y = dot2(gyp[j][k], ea, s00y);
+                    s01y = dot2(gyp[j][k], oa, s01y);
+                    s10y = dot2(gyp[j][k], eb, s10y);
+                    s11y = dot2(gyp[j][k], ob, s11y);
                 }
             }
+            const double tx = (double)(s00x - sax) + fx * (double)(s01x - s00x);
+            const double bx1 = (double)(s10x - sax) + fx * (double)(s11x - s10x);
+            const double ty = (double)(s00y - say) + fx * (double)(s01y - s00y);
+            const double by1 = (double)(s10y - say) + fx * (double)(s11y - s10y);
+            const double bx = tx + fy * (bx1 - tx), by = ty + fy * (by1 - ty);
             const double dx = ixy * by - ixx * bx;
             const double dy = ixy * bx - iyy * by;
             ux = fmin(fmax(ux + dx, (double)(d0x - 1)), (double)(d0x + 1));
             uy = fmin(fmax(uy + dy, (double)(d0y - 1)), (double)(d0y + 1));
         }
-        float2 *out = reinterpret_cast<float2 *>(io[s].flow[dir]);
-        out[(size_t)y * W + x] = make_float2((float)ux, (float)uy);
+        const uint64_t packed = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
+        gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(uint32_t)(y * W + x)] = packed;
     }
 }
 
