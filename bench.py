@@ -45,6 +45,8 @@ def level_sizes(H, W, N):
 def kernel_name(stage, level, p):
     if stage == 0:
         return "k_luma level 0" if level == 0 else "k_gain level 0"
+    if stage == 4:
+        return "k_refine level 0" if level == 0 else "k_refine_border level 0"
     if stage == 3:
         return f"k_prop ({p.prop_steps} steps + median) level {level}"
     return f"{KERNELS[stage]} level {level}"
@@ -69,6 +71,11 @@ def algorithmic(stage, level, shapes, p):
         return "alu", 2.0 * px * p.prop_steps * 4 * win, "TOP/s", AD_PEAK_TOPS
     if stage == 4:  # per window sample and iteration: 3 lerps (6), residual (1), 2 FMAs (4)
         wn = (2 * p.lk_patch + 1) ** 2
+        lp = p.lk_patch
+        # level-0 pixels whose window lies inside the strip (interior launch)
+        # or not (border launch, reported in the level-1 slot)
+        inner = sum(max(H - 2 * lp, 0) * max(W - 2 * lp, 0) for (H, W, _) in shapes)
+        px = inner if level == 0 else sum(H * W for (H, W, _) in shapes) - inner
         return "alu", 2.0 * px * p.lk_iters * wn * 11, "TFLOP/s", FP32_PEAK_TFLOPS
     # blend: L, R (6 B) and two float2 flows (16 B) in, F (3 B) out
     return "hbm", px * 25.0, "GB/s", HBM_PEAK_GBS

@@ -446,12 +446,12 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
         }
         LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
         // interior tiles, then the border pixels (a forked stream that ran the
-        // border concurrently made the graph replay slower)
-        HIP_TRY(pl, mark(ST_REFINE, 0));
-        HIP_TRY(pl, launch_refine(lv, io, work(ST_REFINE, 0), lk, pl->launch[ST_REFINE][b.cls[0]].tile_h,
-                                  grid_of(pl, ST_REFINE, b.cls[0]), s));
-        HIP_TRY(pl, launch_refine_border(lv, io, work(LIST_REFINE_BORDER, 0), lk, s));
-        HIP_TRY(pl, mark(ST_REFINE, 0));
+        // border concurrently made the graph replay slower); the border launch
+        // is timed in the level-1 slot of the stage (refinement runs at level 0)
+        TIMED(ST_REFINE, 0,
+              launch_refine(lv, io, work(ST_REFINE, 0), lk, pl->launch[ST_REFINE][b.cls[0]].tile_h,
+                            grid_of(pl, ST_REFINE, b.cls[0]), s));
+        TIMED(ST_REFINE, 1, launch_refine_border(lv, io, work(LIST_REFINE_BORDER, 0), lk, s));
     }
     if (blend) {
         BlendParams bp{p.k_sharp, p.k_flowmag, p.blend_mode};
