@@ -24,6 +24,7 @@ _lib = None
 
 u8p = ctypes.POINTER(ctypes.c_uint8)
 i32p = ctypes.POINTER(ctypes.c_int32)
+i64p = ctypes.POINTER(ctypes.c_int64)
 f64p = ctypes.POINTER(ctypes.c_double)
 c_int, c_long, c_double = ctypes.c_int, ctypes.c_long, ctypes.c_double
 
@@ -85,6 +86,11 @@ def _load():
                                  c_double, f64p]),
         "orc_blend_grad": (None, [f64p, f64p, f64p, f64p, f64p, c_int, c_int, c_int, c_double, c_double,
                                   c_int, f64p, f64p, f64p, f64p, f64p]),
+        "orc_canvas_dist2": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
+        "orc_canvas_blend": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, f64p]),
+        "orc_overlap_box": (None, [u8p, u8p, c_long, c_int, c_int, i32p]),
+        "orc_composite": (None, [f64p, f64p, u8p, u8p, c_long, c_int, c_int, f64p, f64p, i32p, c_int, f64p,
+                                 c_double, c_double, c_int, f64p, u8p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -291,3 +297,68 @@ def blend_grad(L, R, flow_lr, flow_rl, g_F, blend=None, axis: int = 0, params: P
                            params.k_sharp, params.k_flowmag, params.blend_mode, _p(gF, f64p),
                            *[_p(o, f64p) for o in out])
     return tuple(out)
+
+
+# ---------------------------------------------------------------------------
+# Canvas (eq. (1) and Code 1 with coverage masks of any shape)
+
+
+def _points(H, W, points):
+    if points is None:
+        ys, xs = np.mgrid[0:H, 0:W]
+        return _i32(xs.ravel()), _i32(ys.ravel())
+    pts = np.asarray(points)
+    return _i32(pts[:, 0]), _i32(pts[:, 1])
+
+
+def canvas_dist2(mask_L, mask_R, points=None):
+    """Squared distances (int64) from canvas points to the nearest Area1
+    and Area2 pixel (-1 if that area is empty), by brute force. ``points``
+    is an (n, 2) array of (x, y); None = every pixel (returned H x W)."""
+    mL, mR = _u8(mask_L), _u8(mask_R)
+    H, W = mL.shape
+    xs, ys = _points(H, W, points)
+    n = xs.size
+    d1, d2 = np.empty(n, np.int64), np.empty(n, np.int64)
+    _load().orc_canvas_dist2(_p(mL, u8p), _p(mR, u8p), W, H, W, n, _p(xs, i32p), _p(ys, i32p), _p(d1, i64p),
+                             _p(d2, i64p))
+    if points is None:
+        return d1.reshape(H, W), d2.reshape(H, W)
+    return d1, d2
+
+
+def canvas_blend(mask_L, mask_R, points=None):
+    """eq. (1) on a canvas (float64), at ``points`` or at every pixel."""
+    mL, mR = _u8(mask_L), _u8(mask_R)
+    H, W = mL.shape
+    xs, ys = _points(H, W, points)
+    out = np.empty(xs.size, np.float64)
+    _load().orc_canvas_blend(_p(mL, u8p), _p(mR, u8p), W, H, W, xs.size, _p(xs, i32p), _p(ys, i32p),
+                             _p(out, f64p))
+    return out.reshape(H, W) if points is None else out
+
+
+def overlap_box(mask_L, mask_R):
+    """Bounding box of Area3 as (x, y, w, h); zeros if there is none."""
+    mL, mR = _u8(mask_L), _u8(mask_R)
+    H, W = mL.shape
+    box = np.zeros(4, np.int32)
+    _load().orc_overlap_box(_p(mL, u8p), _p(mR, u8p), W, H, W, _p(box, i32p))
+    return tuple(int(v) for v in box)
+
+
+def composite(L, R, mask_L, mask_R, flow_lr, flow_rl, box, axis: int = 0, blend=None, params: Params = Params()):
+    """Code 1 over a canvas; flows cover the overlap box. Returns
+    (F float64 H x W x 3, F uint8)."""
+    Ld, Rd = _f64(L), _f64(R)
+    mL, mR = _u8(mask_L), _u8(mask_R)
+    H, W, _ = Ld.shape
+    flr, frl = _f64(flow_lr), _f64(flow_rl)
+    b = None if blend is None else _f64(blend)
+    bx = _i32(box)
+    F = np.empty((H, W, 3), np.float64)
+    F8 = np.empty((H, W, 3), np.uint8)
+    _load().orc_composite(_p(Ld, f64p), _p(Rd, f64p), _p(mL, u8p), _p(mR, u8p), W, H, W, _p(flr, f64p),
+                          _p(frl, f64p), _p(bx, i32p), axis, _p(b, f64p), params.k_sharp, params.k_flowmag,
+                          params.blend_mode, _p(F, f64p), _p(F8, u8p))
+    return F, F8

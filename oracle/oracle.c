@@ -26,6 +26,10 @@
  *   - eq. (1): the global blending coefficient; for a rectangular strip the
  *     minimum distances to Area1 / Area2 are x+1 and W-x (pixel centres).
  *   - Code 1: per-pixel asymmetric warp and softmax composite.
+ *   - Canvas (eq. (1) and Code 1 with coverage masks of any shape): Area1
+ *     / Area2 / Area3 come from the two masks, Lmin / Rmin are brute-force
+ *     distances between pixel centres, and OverlappedL / OverlappedR are the
+ *     crops of the bounding box of Area3.
  *   - The energy and its gradients (photometric Charbonnier + TV) are not
  *     in the paper; they define the flow-refinement extension.
  */
@@ -658,4 +662,160 @@ void orc_blend_grad(const double *L, const double *R, const double *flow_lr, con
                 g_flow_lr[2 * p + 1] = okly ? glr_y : 0;
             }
         }
+}
+
+/* ------------------------------------------------------------------ */
+/* Canvas: eq. (1) and Code 1 with coverage masks of any shape
+ * (Section III.C: Area1 holds only L, Area2 only R, Area3 both). */
+
+/* Area of canvas pixel (x, y) from the coverage masks (nonzero = the image
+ * covers the pixel): 1 = only L, 2 = only R, 3 = both, 0 = neither. */
+static int canvas_area(const uint8_t *mL, const uint8_t *mR, long pitch, int x, int y)
+{
+    int l = mL[(long)y * pitch + x] != 0, r = mR[(long)y * pitch + x] != 0;
+    return l && r ? 3 : (l ? 1 : (r ? 2 : 0));
+}
+
+/* Squared Euclidean distance between the centre of (x, y) and the centre
+ * of the nearest canvas pixel of area `a`, over every pixel of the canvas;
+ * -1 when no pixel has that area. */
+static long long nearest_d2(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int x, int y, int a)
+{
+    long long best = -1;
+    for (int v = 0; v < H; v++)
+        for (int u = 0; u < W; u++) {
+            if (canvas_area(mL, mR, pitch, u, v) != a) continue;
+            long long d = (long long)(u - x) * (u - x) + (long long)(v - y) * (v - y);
+            if (best < 0 || d < best) best = d;
+        }
+    return best;
+}
+
+/* Squared distances from n canvas points to Area1 (d2_1) and Area2 (d2_2). */
+void orc_canvas_dist2(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, long n, const int32_t *xs,
+                      const int32_t *ys, long long *d2_1, long long *d2_2)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < n; i++) {
+        d2_1[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 1);
+        d2_2[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 2);
+    }
+}
+
+/* eq. (1) at n canvas points: 0 in Area1, 1 in Area2, 0.5 outside both
+ * images, Lmin / (Lmin + Rmin) in Area3 with Lmin / Rmin the distances to
+ * Area1 / Area2. An empty Area1 is infinitely far (Blend 1), an empty
+ * Area2 likewise (Blend 0); with both empty Area3 takes 0.5. */
+void orc_canvas_blend(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, long n, const int32_t *xs,
+                      const int32_t *ys, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < n; i++) {
+        int x = xs[i], y = ys[i], a = canvas_area(mL, mR, pitch, x, y);
+        if (a == 1) {
+            out[i] = 0.0;
+        } else if (a == 2) {
+            out[i] = 1.0;
+        } else if (a == 0) {
+            out[i] = 0.5;
+        } else {
+            long long d1 = nearest_d2(mL, mR, pitch, H, W, x, y, 1);
+            long long d2 = nearest_d2(mL, mR, pitch, H, W, x, y, 2);
+            if (d1 < 0 && d2 < 0)
+                out[i] = 0.5;
+            else if (d1 < 0)
+                out[i] = 1.0;
+            else if (d2 < 0)
+                out[i] = 0.0;
+            else {
+                double lmin = sqrt((double)d1), rmin = sqrt((double)d2);
+                out[i] = lmin / (lmin + rmin);
+            }
+        }
+    }
+}
+
+/* Bounding box of Area3 as {x, y, width, height}; {0, 0, 0, 0} if empty. */
+void orc_overlap_box(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int32_t box[4])
+{
+    int x0 = W, y0 = H, x1 = -1, y1 = -1;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++)
+            if (canvas_area(mL, mR, pitch, x, y) == 3) {
+                if (x < x0) x0 = x;
+                if (x > x1) x1 = x;
+                if (y < y0) y0 = y;
+                if (y > y1) y1 = y;
+            }
+    if (x1 < 0) {
+        box[0] = box[1] = box[2] = box[3] = 0;
+    } else {
+        box[0] = x0;
+        box[1] = y0;
+        box[2] = x1 - x0 + 1;
+        box[3] = y1 - y0 + 1;
+    }
+}
+
+/* Code 1 over a canvas. L, R: double H x W x 3 canvas images. The flows
+ * are box[3] x box[2] x 2 over the overlap box {x, y, w, h}: OverlappedL /
+ * OverlappedR are the box's crops of L and R, and Area3 pixels are warped
+ * and blended exactly as in orc_blend on that crop (samples clamped to the
+ * crop, flow magnitude divided by the box extent across the seam), with
+ * Blend taken from `blend` (H x W canvas array) or from eq. (1) if NULL.
+ * Area1 copies L, Area2 copies R, every other pixel (and an Area3 pixel
+ * outside the box, which has no flow) is 0. */
+void orc_composite(const double *L, const double *R, const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W,
+                   const double *flow_lr, const double *flow_rl, const int32_t box[4], int axis,
+                   const double *blend, double kS, double kF, int mode, double *F, uint8_t *F8)
+{
+    int bx = box[0], by = box[1], bw = box[2], bh = box[3];
+    long nb = (long)bw * bh;
+    double *Lc = NULL, *Rc = NULL, *Bc = NULL, *Fc = NULL;
+    if (nb > 0) {
+        Lc = (double *)malloc(sizeof(double) * 3 * nb);
+        Rc = (double *)malloc(sizeof(double) * 3 * nb);
+        Bc = (double *)malloc(sizeof(double) * nb);
+        Fc = (double *)malloc(sizeof(double) * 3 * nb);
+        int32_t *xs = (int32_t *)malloc(sizeof(int32_t) * nb), *ys = (int32_t *)malloc(sizeof(int32_t) * nb);
+        for (int y = 0; y < bh; y++)
+            for (int x = 0; x < bw; x++) {
+                long q = (long)y * bw + x, p = (long)(y + by) * W + (x + bx);
+                for (int c = 0; c < 3; c++) {
+                    Lc[3 * q + c] = L[3 * p + c];
+                    Rc[3 * q + c] = R[3 * p + c];
+                }
+                xs[q] = x + bx;
+                ys[q] = y + by;
+                if (blend) Bc[q] = blend[p];
+            }
+        if (!blend) orc_canvas_blend(mL, mR, pitch, H, W, nb, xs, ys, Bc);
+        orc_blend(Lc, Rc, flow_lr, flow_rl, Bc, axis, bh, bw, kS, kF, mode, Fc, NULL);
+        free(xs);
+        free(ys);
+    }
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            long p = (long)y * W + x;
+            int a = canvas_area(mL, mR, pitch, x, y);
+            int inbox = x >= bx && x < bx + bw && y >= by && y < by + bh;
+            for (int c = 0; c < 3; c++) {
+                double f = 0.0;
+                if (a == 1)
+                    f = L[3 * p + c];
+                else if (a == 2)
+                    f = R[3 * p + c];
+                else if (a == 3 && inbox)
+                    f = Fc[3 * ((long)(y - by) * bw + (x - bx)) + c];
+                F[3 * p + c] = f;
+                if (F8) {
+                    double r = floor(f + 0.5);
+                    F8[3 * p + c] = (uint8_t)(r < 0 ? 0 : (r > 255 ? 255 : r));
+                }
+            }
+        }
+    free(Lc);
+    free(Rc);
+    free(Bc);
+    free(Fc);
 }

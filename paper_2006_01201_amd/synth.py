@@ -357,6 +357,107 @@ def random_levels(seed: int, shape, levels: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Canvases: two photos placed on a common canvas with coverage masks of any
+# shape (the inputs of canvas compositing).
+
+
+@dataclass
+class Canvas:
+    """A pair canvas: L and R (H x W x 3, zero where the photo does not
+    reach) with their coverage masks (uint8, 1 = covered)."""
+
+    L: np.ndarray
+    R: np.ndarray
+    mask_L: np.ndarray
+    mask_R: np.ndarray
+    axis: int
+    flow_rl_gt: np.ndarray  # R(p) ~ L(p + u) over the whole canvas
+    meta: dict = field(default_factory=dict)
+
+
+def _edge(rng, n, centre, slope, bow):
+    """A slanted, slightly bowed photo edge: position along the other axis
+    for each of n rows (or columns)."""
+    t = np.arange(n, dtype=np.float64)
+    return centre + slope * (t - n / 2.0) + bow * np.sin(np.pi * t / max(n - 1, 1))
+
+
+def canvas_masks(rng, H: int, W: int, overlap: float, holes: int = 0):
+    """Coverage of two photos side by side (seam running top to bottom):
+    L reaches from the left to a slanted, bowed edge, R from another such
+    edge to the right, with overlap ~ ``overlap`` W between them; both have
+    slanted top and bottom edges (canvas corners stay uncovered), and
+    ``holes`` elliptical gaps are cut out of R's coverage inside the
+    overlap (Area1 islands inside Area3)."""
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    ow = overlap * W
+    cx = rng.uniform(0.45, 0.55) * W
+    right_L = _edge(rng, H, cx + ow / 2, rng.uniform(-0.08, 0.08) * W / max(H, 1), rng.uniform(-0.03, 0.03) * W)
+    left_R = _edge(rng, H, cx - ow / 2, rng.uniform(-0.08, 0.08) * W / max(H, 1), rng.uniform(-0.03, 0.03) * W)
+    mL = xx <= right_L[:, None]
+    mR = xx >= left_R[:, None]
+    for m in (mL, mR):
+        top = _edge(rng, W, rng.uniform(0.0, 0.04) * H, rng.uniform(-0.04, 0.04) * H / max(W, 1), 0.0)
+        bot = _edge(rng, W, rng.uniform(0.96, 1.0) * H, rng.uniform(-0.04, 0.04) * H / max(W, 1), 0.0)
+        m &= (yy >= top[None, :]) & (yy <= bot[None, :])
+    for _ in range(holes):
+        ex, ey = rng.uniform(cx - ow / 3, cx + ow / 3), rng.uniform(0.15, 0.85) * H
+        ax, ay = rng.uniform(0.05, 0.2) * ow + 1, rng.uniform(0.02, 0.08) * H + 1
+        mR &= ((xx - ex) / ax) ** 2 + ((yy - ey) / ay) ** 2 > 1.0
+    return mL.astype(np.uint8), mR.astype(np.uint8)
+
+
+def make_canvas(seed: int, H: int, W: int, axis: int = 0, overlap: float = 0.3, holes: int = 0,
+                max_ux: float = 6.0, max_uy: float = 2.0, noise: float = 2.0) -> Canvas:
+    """A pair canvas (seed slot cfg = 110). Draw order: masks, texture,
+    flow field, noise on L, noise on R. For axis 1 (seam running left to
+    right, Area1 above) the canvas is generated transposed."""
+    rng = rng_for(110, seed, axis)
+    h, w = (H, W) if axis == 0 else (W, H)
+    mL, mR = canvas_masks(rng, h, w, overlap, holes)
+    tex = Texture(rng, h, w)
+    sigma = max(8.0, 0.05 * min(h, w))
+    ux = smooth_field(rng, h, w, sigma, max_ux)
+    uy = smooth_field(rng, h, w, sigma, max_uy)
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    Lf = tex(xx, yy)
+    Rf = tex(xx + ux, yy + uy)
+    if noise:
+        Lf = Lf + rng.normal(0.0, noise, Lf.shape)
+        Rf = Rf + rng.normal(0.0, noise, Rf.shape)
+    L = _quantise(Lf) * mL[..., None]
+    R = _quantise(Rf) * mR[..., None]
+    u = np.stack([ux, uy], axis=-1)
+    if axis == 1:
+        L, R = L.transpose(1, 0, 2), R.transpose(1, 0, 2)
+        mL, mR = mL.T, mR.T
+        u = u.transpose(1, 0, 2)[..., ::-1]
+    return Canvas(np.ascontiguousarray(L), np.ascontiguousarray(R), np.ascontiguousarray(mL),
+                  np.ascontiguousarray(mR), axis, np.ascontiguousarray(u), {"holes": holes})
+
+
+def random_masks(seed: int, H: int, W: int, blobs: int = 6, p_empty: float = 0.0):
+    """Two coverage masks made of random discs and rectangles (general,
+    non-convex, possibly disconnected shapes for distance tests)."""
+    rng = rng_for(111, seed, 0)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    out = []
+    for _ in range(2):
+        m = np.zeros((H, W), bool)
+        if rng.uniform() >= p_empty:
+            for _ in range(blobs):
+                cx, cy = rng.uniform(-0.1, 1.1) * W, rng.uniform(-0.1, 1.1) * H
+                if rng.uniform() < 0.5:
+                    r = rng.uniform(0.03, 0.35) * max(H, W)
+                    m |= (xx - cx) ** 2 + (yy - cy) ** 2 <= r * r
+                else:
+                    hw, hh = rng.uniform(0.02, 0.4) * W, rng.uniform(0.02, 0.4) * H
+                    m |= (np.abs(xx - cx) <= hw) & (np.abs(yy - cy) <= hh)
+        out.append(m.astype(np.uint8))
+    return out[0], out[1]
+
+
+# ---------------------------------------------------------------------------
 # Device-side evaluation for large streams (the 32-panorama workload): the
 # recipe of ``make_config_strip`` with the per-pixel work (texture,
 # smoothing of the flow noise, warp, sensor noise) evaluated by torch on
