@@ -226,6 +226,58 @@ abf_status abf_blend_asymmetric_f32(abf_plan *plan, const float *L, const float 
                                     int32_t axis, int32_t H, int32_t W, float *F, void *hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Canvas compositing: eq. (1) (Section III.C.2) and Code 1 (Section
+ * III.C.3) on a canvas H x W (1..32767 on each side) where the areas have
+ * any shape. The areas come from two coverage masks (uint8 H x W, rows
+ * pitch_mask bytes apart, nonzero = the image covers the pixel): Area1 =
+ * covered by L only, Area2 = by R only, Area3 = by both. OverlappedL /
+ * OverlappedR are the crops of L and R to the bounding box of Area3 (the
+ * "overlap box" {x, y, w, h}); the flows of the pair are computed on those
+ * crops (abf_flow_bidirectional with the crop's first pixel and the
+ * canvas pitches). Scratch comes from the plan's workspace:
+ * abf_canvas_workspace_bytes gives the size a plan needs bound to handle an
+ * H x W canvas (ABF_E_WORKSPACE otherwise). */
+
+/* Workspace bytes for canvases up to H x W (at least abf_workspace_bytes). */
+size_t abf_canvas_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W);
+
+/* Bounding box of Area3, written as int32 {x, y, w, h} to `box` (device,
+ * 4 entries); {0, 0, 0, 0} when no pixel is covered by both images. */
+abf_status abf_overlap_box(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
+                           int32_t pitch_mask, int32_t *box, void *hip_stream);
+
+/* eq. (1) over the canvas: Blend (float32, rows pitch_blend floats apart)
+ * is 0 on Area1, 1 on Area2, 0.5 outside both images, and on Area3
+ * Lmin / (Lmin + Rmin), with Lmin / Rmin the Euclidean distances between
+ * pixel centres to the nearest Area1 / Area2 pixel (exact: integer squared
+ * distances, then the ratio in double, rounded to float). An empty Area1
+ * gives 1 on Area3, an empty Area2 gives 0, both empty give 0.5.
+ * If dist2_1 / dist2_2 are non-null (both or neither; int32, rows
+ * pitch_dist apart), they receive the squared distances of every canvas
+ * pixel to Area1 / Area2 (0 inside the area, -1 if the area is empty).
+ * blend may be null when the distances are requested. */
+abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
+                            int32_t pitch_mask, float *blend, int32_t pitch_blend, int32_t *dist2_1,
+                            int32_t *dist2_2, int32_t pitch_dist, void *hip_stream);
+
+/* Code 1 over the canvas: F (uint8 RGB, rows pitch_F bytes apart) = L on
+ * Area1, R on Area2, 0 outside both images; an Area3 pixel inside the box
+ * is warped and blended exactly as pixel (x - box x, y - box y) of the
+ * strip OverlappedL / OverlappedR by abf_blend_asymmetric (flows box h x
+ * box w x 2, samples clamped to the box, flow magnitude divided by the box
+ * width for axis 0, height for axis 1) with Blend read from `blend`
+ * (float32 canvas array, rows pitch_blend floats apart) or, if null,
+ * computed by eq. (1) as in abf_canvas_blend. An Area3 pixel outside the
+ * box has no flow and is written as 0. `box` is a host array {x, y, w, h}
+ * inside the canvas (w or h 0: no Area3 pixel is blended). F_f32
+ * (nullable, H x W x 3 contiguous) receives the unrounded composite. */
+abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t *R, const uint8_t *mask_L,
+                                const uint8_t *mask_R, int32_t H, int32_t W, int32_t pitch_L, int32_t pitch_R,
+                                int32_t pitch_mask, const float *flow_LtoR, const float *flow_RtoL,
+                                const int32_t *box, int32_t axis, const float *blend, int32_t pitch_blend,
+                                uint8_t *F, int32_t pitch_F, float *F_f32, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* Autotuning of launch shapes (never of results): times the candidate
  * tile heights and persistent grid sizes of each stage on the batch
  * `strips` and keeps the fastest per (stage, level-size class). Writes

@@ -64,6 +64,11 @@ _SIGS = {
     "abf_refine_strips": (c_i32, [c_vp, ctypes.POINTER(AbfRefineStrip), c_i32, c_i32, c_f32, c_f32, c_f32, c_f32,
                                   c_vp]),
     "abf_profile": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_i32, ctypes.POINTER(c_f32), c_vp]),
+    "abf_canvas_workspace_bytes": (c_sz, [c_vp, c_i32, c_i32]),
+    "abf_overlap_box": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
+    "abf_canvas_blend": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_vp]),
+    "abf_composite_canvas": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp,
+                                     ctypes.POINTER(c_i32), c_i32, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp]),
 }
 
 MAX_LEVELS = 12
@@ -202,3 +207,24 @@ def profile(plan, strips, n, reps, stream):
 
 def refine_strips(plan, strips, n, steps, eta, lam, eps, clip_px, stream) -> int:
     return load().abf_refine_strips(plan, strips, n, steps, eta, lam, eps, clip_px, stream)
+
+
+def canvas_workspace_bytes(plan, H, W) -> int:
+    return load().abf_canvas_workspace_bytes(plan, H, W)
+
+
+def overlap_box(plan, mask_L, mask_R, H, W, pitch_mask, box, stream) -> int:
+    return load().abf_overlap_box(plan, mask_L, mask_R, H, W, pitch_mask, box, stream)
+
+
+def canvas_blend(plan, mask_L, mask_R, H, W, pitch_mask, blend, pitch_blend, dist2_1, dist2_2, pitch_dist,
+                 stream) -> int:
+    return load().abf_canvas_blend(plan, mask_L, mask_R, H, W, pitch_mask, blend, pitch_blend, dist2_1, dist2_2,
+                                   pitch_dist, stream)
+
+
+def composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_mask, flow_LtoR, flow_RtoL, box,
+                     axis, blend, pitch_blend, F, pitch_F, F_f32, stream) -> int:
+    b = (c_i32 * 4)(*box)
+    return load().abf_composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_mask, flow_LtoR,
+                                       flow_RtoL, b, axis, blend, pitch_blend, F, pitch_F, F_f32, stream)

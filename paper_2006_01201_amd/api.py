@@ -60,6 +60,13 @@ def _img_u8(t: torch.Tensor, name: str):
     return t.shape[0], t.shape[1], t.stride(0)
 
 
+def _mask(t: torch.Tensor, name: str):
+    if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_cuda or t.stride(1) != 1:
+        raise ValueError(f"{name}: expected a CUDA uint8 (H, W) tensor with unit column stride, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
 def _f32(t: torch.Tensor, shape, name: str):
     if t.dtype != torch.float32 or tuple(t.shape) != tuple(shape) or not t.is_cuda or not t.is_contiguous():
         raise ValueError(f"{name}: expected a contiguous CUDA float32 tensor {tuple(shape)}, "
@@ -81,7 +88,9 @@ class Plan:
     """An abf_plan with its workspace."""
 
     def __init__(self, params: Params = Params(), max_strips: int = 1, max_pixels: int | None = None,
-                 max_H: int = 4096, max_W: int = 4096):
+                 max_H: int = 4096, max_W: int = 4096, canvas: tuple[int, int] | None = None):
+        """``canvas`` = (H, W): also size the workspace for canvases up to
+        that size (canvas compositing)."""
         if max_pixels is None:
             max_pixels = max_strips * max_H * max_W
         self.params = params
@@ -89,6 +98,8 @@ class Plan:
         _abi.check(st, None, "abf_create_plan")
         self.h = h
         nbytes = _abi.workspace_bytes(h)
+        if canvas is not None:
+            nbytes = max(nbytes, _abi.canvas_workspace_bytes(h, *canvas))
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
         self._ws_off = (-base) % 256
@@ -261,6 +272,73 @@ class Plan:
         return tuple(out)
 
     # -- inspection ------------------------------------------------------
+    # -- canvas compositing (eq. (1) and Code 1 with general areas) ----
+    def overlap_box(self, mask_L, mask_R):
+        """Bounding box (x, y, w, h) of Area3 (host tuple; synchronises)."""
+        H, W, pm = _mask(mask_L, "mask_L")
+        if _mask(mask_R, "mask_R") != (H, W, pm):
+            raise ValueError("mask_L and mask_R differ in shape or pitch")
+        box = torch.empty(4, dtype=torch.int32, device=mask_L.device)
+        st = _abi.overlap_box(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, box.data_ptr(), _stream())
+        _abi.check(st, self.h, "abf_overlap_box")
+        return tuple(int(v) for v in box.cpu())
+
+    def canvas_blend(self, mask_L, mask_R, distances: bool = False):
+        """eq. (1) over the canvas (float32 H x W); with ``distances`` also
+        the squared distances to Area1 and Area2 (int32, -1 = empty)."""
+        H, W, pm = _mask(mask_L, "mask_L")
+        if _mask(mask_R, "mask_R") != (H, W, pm):
+            raise ValueError("mask_L and mask_R differ in shape or pitch")
+        dev = mask_L.device
+        B = torch.empty((H, W), dtype=torch.float32, device=dev)
+        d1 = torch.empty((H, W), dtype=torch.int32, device=dev) if distances else None
+        d2 = torch.empty((H, W), dtype=torch.int32, device=dev) if distances else None
+        st = _abi.canvas_blend(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, B.data_ptr(), W,
+                               d1.data_ptr() if distances else None, d2.data_ptr() if distances else None, W,
+                               _stream())
+        _abi.check(st, self.h, "abf_canvas_blend")
+        return (B, d1, d2) if distances else B
+
+    def composite_canvas(self, L, R, mask_L, mask_R, flow_lr, flow_rl, box, axis: int = 0, blend=None,
+                         f32: bool = False, out=None):
+        """Code 1 over the canvas; flows cover the overlap ``box``. Returns
+        F (uint8 H x W x 3) and, if ``f32``, the unrounded composite."""
+        H, W, pl = _img_u8(L, "L")
+        H2, W2, pr = _img_u8(R, "R")
+        Hm, Wm, pm = _mask(mask_L, "mask_L")
+        if (H, W) != (H2, W2) or (H, W) != (Hm, Wm) or _mask(mask_R, "mask_R") != (Hm, Wm, pm):
+            raise ValueError("canvas inputs differ in size")
+        bx, by, bw, bh = (int(v) for v in box)
+        F = torch.empty((H, W, 3), dtype=torch.uint8, device=L.device) if out is None else out
+        _, _, pf = _img_u8(F, "F")
+        Ff = torch.empty((H, W, 3), dtype=torch.float32, device=L.device) if f32 else None
+        fl = fr = None
+        if bw > 0 and bh > 0:
+            fl = _f32(flow_lr, (bh, bw, 2), "flow_LtoR")
+            fr = _f32(flow_rl, (bh, bw, 2), "flow_RtoL")
+        bp, pb = None, 0
+        if blend is not None:
+            if blend.dtype != torch.float32 or blend.dim() != 2 or tuple(blend.shape) != (H, W) or blend.stride(1) != 1:
+                raise ValueError("blend: expected a CUDA float32 (H, W) tensor with unit column stride")
+            bp, pb = blend.data_ptr(), blend.stride(0)
+        st = _abi.composite_canvas(self.h, L.data_ptr(), R.data_ptr(), mask_L.data_ptr(), mask_R.data_ptr(), H, W,
+                                   pl, pr, pm, fl, fr, (bx, by, bw, bh), axis, bp, pb, F.data_ptr(), pf,
+                                   Ff.data_ptr() if Ff is not None else None, _stream())
+        _abi.check(st, self.h, "abf_composite_canvas")
+        return (F, Ff) if f32 else F
+
+    def stitch_canvas(self, L, R, mask_L, mask_R, axis: int = 0, f32: bool = False):
+        """The whole pair: overlap box, both flows on its crops, eq. (1)
+        and Code 1 over the canvas. Returns (F[, F_f32], box, flow_lr,
+        flow_rl)."""
+        box = self.overlap_box(mask_L, mask_R)
+        bx, by, bw, bh = box
+        flr = frl = None
+        if bw > 0 and bh > 0:
+            flr, frl = self.flow_bidirectional(L[by:by + bh, bx:bx + bw], R[by:by + bh, bx:bx + bw])
+        res = self.composite_canvas(L, R, mask_L, mask_R, flr, frl, box, axis=axis, f32=f32)
+        return (*res, box, flr, frl) if f32 else (res, box, flr, frl)
+
     def view(self, kind: int, strip: int, level: int, direction: int) -> torch.Tensor:
         """A copy of one intermediate of the last flow call: kind 0 luma
         (uint8 H x W), 1 raw search / 2 final integer flow (int16 H x W x 2)."""

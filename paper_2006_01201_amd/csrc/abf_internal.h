@@ -134,6 +134,46 @@ hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *fl
                                  float *g_flr, float *g_frl, float *g_L, float *g_R, unsigned long long *fixL,
                                  unsigned long long *fixR, hipStream_t s);
 
+// ---------------------------------------------------------------------
+// Canvas compositing (defined in abf_canvas.hip). Canvases are at most
+// kCanvasMaxDim on a side, so squared distances fit in 31 bits and row
+// distances in uint16 (0xffff = no pixel of the area in the row).
+constexpr int kCanvasMaxDim = 32767;
+constexpr int kCanvasChunk = 16;    // columns per thread in the row pass
+constexpr int kCanvasThreads = 256;
+constexpr int kCanvasMaxChunks = (kCanvasMaxDim + kCanvasChunk - 1) / kCanvasChunk;
+constexpr int kCanvasBH = 32;       // rows per block minimum of the column search
+static_assert(kCanvasMaxChunks <= 8 * kCanvasThreads, "row scan holds 8 chunks per thread");
+
+// Coverage masks and the scratch planes of the distance passes: G holds
+// the row distance to Area1 (low half) and Area2 (high half) of every
+// pixel, M its minimum over each kCanvasBH-row block of a column; both
+// have gpitch (a multiple of 64) entries per row.
+struct CanvasGeom {
+    const uint8_t *mL, *mR;
+    uint32_t *G, *M;
+    int32_t pitchM, H, W, gpitch;
+};
+__host__ __device__ inline int canvas_gpitch(int W) { return (W + 63) / 64 * 64; }
+
+struct CompositeArgs {
+    const uint8_t *L, *R, *mL, *mR;
+    const float *blend;       // canvas Blend map (pitchB floats per row)
+    const float *flr, *frl;   // bh x bw x 2 over the overlap box
+    uint8_t *F;
+    float *Ff32;              // H x W x 3 contiguous, or null
+    int32_t pitchL, pitchR, pitchM, pitchB, pitchF;
+    int32_t H, W, bx, by, bw, bh, axis;
+    int32_t pad_;
+    double inv_ext;           // 1 / the box's extent across the seam
+};
+
+hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *box,
+                              hipStream_t s);
+hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int32_t *d1, int32_t *d2, int pitchD,
+                              hipStream_t s);
+hipError_t launch_composite(const CompositeArgs &o, BlendParams bp, hipStream_t s);
+
 // tiles of one strip for a stage (both directions where the stage has two)
 // luma and exposure: 4 pixels per thread over the padded rows
 constexpr int kLumaTW = 4 * kRowTW;

@@ -19,12 +19,11 @@
 // The integer stages are bit-exact by construction (integer arithmetic,
 // fixed candidate order, Jacobi updates into separate buffers). Patch
 // costs use v_sad_u8 on byte-packed dwords.
-#include "abf_internal.h"
+#include "abf_device.h"
 
 namespace abf {
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 __device__ __forceinline__ int find_strip(const int32_t *__restrict__ prefix, int n, int t)
 {
@@ -55,22 +54,6 @@ __device__ __forceinline__ uint32_t pack16(int x, int y)
 }
 __device__ __forceinline__ int unpack_x(uint32_t v) { return (int)(int16_t)(v & 0xffffu); }
 __device__ __forceinline__ int unpack_y(uint32_t v) { return (int)(int16_t)(v >> 16); }
-
-typedef const __attribute__((address_space(1))) uint32_t gu32;
-
-// The buffers are plain device memory: accessing them through global
-// (rather than generic) pointers makes the loads count on vmcnt only, so
-// waits for them do not also wait for LDS traffic and vice versa.
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T *gld(const T *p)
-{
-    return (const __attribute__((address_space(1))) T *)(const void *)p;
-}
-template <typename T>
-__device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p)
-{
-    return (__attribute__((address_space(1))) T *)(void *)p;
-}
 
 // Offset of pixel (r, c), r, c >= -kPad, of a padded plane from the
 // plane's origin (its first allocated byte). Window loads address a plane
@@ -1229,101 +1212,6 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
 }
 
 // ----------------------------------------------------------------- blend
-// Code 1 per pixel. The scalar chain (Blend, displacements, flow
-// magnitudes, softmax exponent difference) is evaluated in double so that
-// no FP32 coordinate or large exponent is formed; bilinear sampling and
-// the composite are FP32.
-struct PixBlend {
-    int lx, ly, rx, ry;      // integer cell corners of the L and R samples
-    float lfx, lfy, rfx, rfy;
-    float sL;                // SoftmaxL (SoftmaxR = 1 - sL)
-};
-
-__device__ __forceinline__ float finite0(float v) { return isfinite(v) ? v : 0.f; }
-
-__device__ __forceinline__ PixBlend blend_setup(int x, int y, int axis, double inv_ext1, double inv_ext, int W,
-                                                const float *blend, const float *flr, const float *frl, BlendParams bp)
-{
-    const uint32_t p = (uint32_t)(y * W + x);
-    const double t = blend ? (double)gld(blend)[p] : (double)((axis == 0 ? x : y) + 1) * inv_ext1;
-    const uint64_t vrl = gld(reinterpret_cast<const uint64_t *>(frl))[p];
-    const uint64_t vlr = gld(reinterpret_cast<const uint64_t *>(flr))[p];
-    const float frx = finite0(__uint_as_float((uint32_t)vrl)), fry = finite0(__uint_as_float((uint32_t)(vrl >> 32)));
-    const float flx = finite0(__uint_as_float((uint32_t)vlr)), fly = finite0(__uint_as_float((uint32_t)(vlr >> 32)));
-    // displacements in double (split into cell and fraction exactly)
-    const double ax = (double)frx * t, ay = (double)fry * t, bx = (double)flx * (1.0 - t), by = (double)fly * (1.0 - t);
-    const double fax = floor(ax), fay = floor(ay), fbx = floor(bx), fby = floor(by);
-    PixBlend r;
-    r.lx = x + (int)fax;
-    r.ly = y + (int)fay;
-    r.rx = x + (int)fbx;
-    r.ry = y + (int)fby;
-    r.lfx = (float)(ax - fax);
-    r.lfy = (float)(ay - fay);
-    r.rfx = (float)(bx - fbx);
-    r.rfy = (float)(by - fby);
-    if (bp.mode == 1) {
-        r.sL = (float)(1.0 - t);
-    } else {
-        // the exponents in double: with large flows both can be in the
-        // hundreds and nearly equal, where FP32 rounding would move F
-        const double mrl = sqrt((double)frx * frx + (double)fry * fry) * inv_ext;
-        const double mlr = sqrt((double)flx * flx + (double)fly * fly) * inv_ext;
-        const double zL = (double)bp.k_sharp * (1.0 - t) * (1.0 + (double)bp.k_flowmag * mrl);
-        const double zR = (double)bp.k_sharp * t * (1.0 + (double)bp.k_flowmag * mlr);
-        r.sL = 1.0f / (1.0f + expf((float)(zR - zL)));
-    }
-    return r;
-}
-
-// Bilinear RGB sample of a uint8 HWC image at (x0 + fx, y0 + fy) with
-// clamp-to-edge indices. When the two corner pixels of a row are distinct
-// and the dwords around them lie inside the image data, each row's 6
-// bytes come from one aligned dwordx3 load; otherwise byte by byte.
-__device__ __forceinline__ void sample_u8(const uint8_t *img, int pitch, int H, int W, int x0, int y0, float fx,
-                                          float fy, float out[3])
-{
-    const uint8_t *ra = img + (size_t)clampi(y0, 0, H - 1) * pitch;
-    const uint8_t *rb = img + (size_t)clampi(y0 + 1, 0, H - 1) * pitch;
-    float v[2][6];
-    const uintptr_t lo = (uintptr_t)img, hi = (uintptr_t)(img + (size_t)(H - 1) * pitch + 3 * (size_t)W);
-    const uintptr_t pa = (uintptr_t)(ra + 3 * x0), pb = (uintptr_t)(rb + 3 * x0);
-    const uintptr_t aa = pa & ~(uintptr_t)3, ab = pb & ~(uintptr_t)3;
-    if (x0 >= 0 && x0 + 1 <= W - 1 && aa >= lo && aa + 12 <= hi && ab >= lo && ab + 12 <= hi) {
-        const int s = (int)(pa - aa), t = (int)(pb - ab);
-        const auto qa = reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(aa);
-        const auto qb = reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(ab);
-        const uint32_t a0 = qa[0], a1 = qa[1], a2 = qa[2], b0 = qb[0], b1 = qb[1], b2 = qb[2];
-        const uint32_t ua = __builtin_amdgcn_alignbyte(a1, a0, s), wa = __builtin_amdgcn_alignbyte(a2, a1, s);
-        const uint32_t ub = __builtin_amdgcn_alignbyte(b1, b0, t), wb = __builtin_amdgcn_alignbyte(b2, b1, t);
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-            v[0][c] = (float)((ua >> (8 * c)) & 0xffu);
-            v[1][c] = (float)((ub >> (8 * c)) & 0xffu);
-        }
-#pragma unroll
-        for (int c = 0; c < 2; c++) {
-            v[0][4 + c] = (float)((wa >> (8 * c)) & 0xffu);
-            v[1][4 + c] = (float)((wb >> (8 * c)) & 0xffu);
-        }
-    } else {
-        const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            v[0][c] = ra[3 * xa + c];
-            v[0][3 + c] = ra[3 * xb + c];
-            v[1][c] = rb[3 * xa + c];
-            v[1][3 + c] = rb[3 * xb + c];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        const float top = v[0][c] + fx * (v[0][3 + c] - v[0][c]);
-        const float bot = v[1][c] + fx * (v[1][3 + c] - v[1][c]);
-        out[c] = top + fy * (bot - top);
-    }
-}
-
 // One workgroup per segment of kRowTW pixels of a row. The uint8 output of
 // the segment is staged in LDS at the byte alignment of its destination, so
 // that the segment is written with aligned dword stores (bytes only at its
@@ -1347,7 +1235,9 @@ __global__ __launch_bounds__(kRowTW) void k_blend(const StripIO *__restrict__ io
         uint8_t *const seg = o.F + (size_t)y * o.pitchF + 3 * (size_t)xs;  // first output byte of the segment
         const int off = (int)((uintptr_t)seg & 3);
         if (x < W) {
-            const PixBlend pb = blend_setup(x, y, o.axis, o.inv_ext1, o.inv_ext, W, o.blend, o.flow[0], o.flow[1], bp);
+            const uint32_t p = (uint32_t)(y * W + x);
+            const double bl = o.blend ? (double)gld(o.blend)[p] : (double)((o.axis == 0 ? x : y) + 1) * o.inv_ext1;
+            const PixBlend pb = blend_setup(x, y, bl, p, o.inv_ext, o.flow[0], o.flow[1], bp);
             float cl[3], cr[3];
             sample_u8(o.L, o.pitchL, H, W, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
             sample_u8(o.R, o.pitchR, H, W, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);

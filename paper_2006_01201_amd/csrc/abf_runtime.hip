@@ -835,6 +835,135 @@ static abf_status grad_scratch(abf_plan *plan, size_t need, uint8_t **out)
     return ABF_OK;
 }
 
+// ------------------------------------------------------------ canvas
+// Scratch of the canvas passes: the row-distance plane G, its block minima
+// M and (when the caller gives no Blend array) a Blend map, in the
+// workspace's data region.
+static size_t canvas_scratch(int H, int W)
+{
+    const size_t gp = (size_t)canvas_gpitch(W);
+    return 2 * align_up(sizeof(uint32_t) * gp * H, kAlign) +
+           align_up(sizeof(uint32_t) * gp * (size_t)ceil_div(H, kCanvasBH), kAlign);
+}
+
+static abf_status canvas_setup(abf_plan *plan, const uint8_t *mL, const uint8_t *mR, int32_t H, int32_t W,
+                               int32_t pitchM, CanvasGeom &g, float **bmap)
+{
+    if (!mL || !mR) return fail(plan, ABF_E_INVALID, "null mask");
+    if (H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim)
+        return fail(plan, ABF_E_SHAPE, "canvas %d x %d (1..%d per side)", H, W, kCanvasMaxDim);
+    if (pitchM < W) return fail(plan, ABF_E_SHAPE, "mask pitch %d < W %d", pitchM, W);
+    uint8_t *scr = nullptr;
+    abf_status rc = grad_scratch(plan, canvas_scratch(H, W), &scr);
+    if (rc != ABF_OK) return rc;
+    const size_t gp = (size_t)canvas_gpitch(W);
+    const size_t plane = align_up(sizeof(uint32_t) * gp * H, kAlign);
+    g.mL = mL;
+    g.mR = mR;
+    g.G = reinterpret_cast<uint32_t *>(scr);
+    g.M = reinterpret_cast<uint32_t *>(scr + plane);
+    *bmap = reinterpret_cast<float *>(scr + plane + align_up(sizeof(uint32_t) * gp * (size_t)ceil_div(H, kCanvasBH), kAlign));
+    g.pitchM = pitchM;
+    g.H = H;
+    g.W = W;
+    g.gpitch = (int32_t)gp;
+    return ABF_OK;
+}
+
+size_t abf_canvas_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W)
+{
+    if (!plan || H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim) return 0;
+    const size_t need = plan->hdr_cap + canvas_scratch(H, W);
+    const size_t base = abf_workspace_bytes(plan);
+    return need > base ? need : base;
+}
+
+abf_status abf_overlap_box(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
+                           int32_t pitch_mask, int32_t *box, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!mask_L || !mask_R || !box) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim)
+        return fail(plan, ABF_E_SHAPE, "canvas %d x %d (1..%d per side)", H, W, kCanvasMaxDim);
+    if (pitch_mask < W) return fail(plan, ABF_E_SHAPE, "mask pitch %d < W %d", pitch_mask, W);
+    HIP_TRY(plan, launch_overlap_box(mask_L, mask_R, pitch_mask, H, W, box, static_cast<hipStream_t>(hip_stream)));
+    return ABF_OK;
+}
+
+abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
+                            int32_t pitch_mask, float *blend, int32_t pitch_blend, int32_t *dist2_1,
+                            int32_t *dist2_2, int32_t pitch_dist, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if ((dist2_1 == nullptr) != (dist2_2 == nullptr))
+        return fail(plan, ABF_E_INVALID, "dist2_1 and dist2_2 go together");
+    if (!blend && !dist2_1) return fail(plan, ABF_E_INVALID, "no output");
+    if (blend && pitch_blend < W) return fail(plan, ABF_E_SHAPE, "blend pitch %d < W %d", pitch_blend, W);
+    if (dist2_1 && pitch_dist < W) return fail(plan, ABF_E_SHAPE, "distance pitch %d < W %d", pitch_dist, W);
+    CanvasGeom g{};
+    float *bmap = nullptr;
+    abf_status rc = canvas_setup(plan, mask_L, mask_R, H, W, pitch_mask, g, &bmap);
+    if (rc != ABF_OK) return rc;
+    HIP_TRY(plan, launch_canvas_dist(g, blend, pitch_blend, dist2_1, dist2_2, pitch_dist,
+                                     static_cast<hipStream_t>(hip_stream)));
+    return ABF_OK;
+}
+
+abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t *R, const uint8_t *mask_L,
+                                const uint8_t *mask_R, int32_t H, int32_t W, int32_t pitch_L, int32_t pitch_R,
+                                int32_t pitch_mask, const float *flow_LtoR, const float *flow_RtoL,
+                                const int32_t *box, int32_t axis, const float *blend, int32_t pitch_blend,
+                                uint8_t *F, int32_t pitch_F, float *F_f32, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!L || !R || !F || !box) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (axis != 0 && axis != 1) return fail(plan, ABF_E_INVALID, "axis %d", axis);
+    if (pitch_L < 3 * W || pitch_R < 3 * W || pitch_F < 3 * W)
+        return fail(plan, ABF_E_SHAPE, "image pitch smaller than 3 W");
+    const int bx = box[0], by = box[1], bw = box[2], bh = box[3];
+    if (bx < 0 || by < 0 || bw < 0 || bh < 0 || bx + bw > W || by + bh > H)
+        return fail(plan, ABF_E_SHAPE, "box {%d, %d, %d, %d} outside the %d x %d canvas", bx, by, bw, bh, H, W);
+    const bool any = bw > 0 && bh > 0;
+    if (any && (!flow_LtoR || !flow_RtoL)) return fail(plan, ABF_E_INVALID, "null flow");
+    if (blend && pitch_blend < W) return fail(plan, ABF_E_SHAPE, "blend pitch %d < W %d", pitch_blend, W);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    CanvasGeom g{};
+    float *bmap = nullptr;
+    abf_status rc = canvas_setup(plan, mask_L, mask_R, H, W, pitch_mask, g, &bmap);
+    if (rc != ABF_OK) return rc;
+    CompositeArgs o{};
+    o.blend = blend;
+    o.pitchB = pitch_blend;
+    if (!blend && any) {
+        HIP_TRY(plan, launch_canvas_dist(g, bmap, g.gpitch, nullptr, nullptr, 0, s));
+        o.blend = bmap;
+        o.pitchB = g.gpitch;
+    }
+    o.L = L;
+    o.R = R;
+    o.mL = mask_L;
+    o.mR = mask_R;
+    o.flr = flow_LtoR;
+    o.frl = flow_RtoL;
+    o.F = F;
+    o.Ff32 = F_f32;
+    o.pitchL = pitch_L;
+    o.pitchR = pitch_R;
+    o.pitchM = pitch_mask;
+    o.pitchF = pitch_F;
+    o.H = H;
+    o.W = W;
+    o.bx = any ? bx : 0;
+    o.by = any ? by : 0;
+    o.bw = any ? bw : 0;
+    o.bh = any ? bh : 0;
+    o.axis = axis;
+    o.inv_ext = any ? 1.0 / (double)(axis == 0 ? bw : bh) : 0.0;
+    BlendParams bp{plan->p.k_sharp, plan->p.k_flowmag, plan->p.blend_mode};
+    HIP_TRY(plan, launch_composite(o, bp, s));
+    return ABF_OK;
+}
+
 abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H, int32_t W,
                       float lambda, float eps, float *E_dev, float *g_u, float *g_Ref, float *g_Tgt,
                       int32_t deterministic, void *hip_stream)

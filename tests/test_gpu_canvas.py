@@ -1,0 +1,224 @@
+"""GPU parity of canvas compositing (eq. (1) with coverage masks of any
+shape, Code 1 with its Area1 / Area2 / else branches) against the CPU
+oracle: the overlap box and the squared distances bit for bit, the Blend
+map within two float32 ulps of the oracle's double, the composite within
+0.5/255 (uint8 equal away from rounding boundaries)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_01201_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 0.5 / 255.0
+B_TOL = 1.2e-7
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_01201_amd import api as _api
+
+    return _api
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def pitched(a, extra):
+    """A device view of `a` whose rows are `extra` elements longer."""
+    H, W = a.shape[:2]
+    big = np.zeros((H, W + extra) + a.shape[2:], a.dtype)
+    big[:, :W] = a
+    return dev(big)[:, :W]
+
+
+def plan_for(api, H, W, **kw):
+    return api.Plan(api.Params(**kw), max_strips=1, max_H=max(H, 8), max_W=max(W, 8), canvas=(H, W))
+
+
+MASKS = {
+    "blobs_23x41": lambda: synth.random_masks(1, 23, 41),
+    "blobs_64x33": lambda: synth.random_masks(2, 64, 33),
+    "row_1x57": lambda: synth.random_masks(4, 1, 57),
+    "column_49x1": lambda: synth.random_masks(5, 49, 1),
+    "blobs_130x97": lambda: synth.random_masks(6, 130, 97, blobs=9),
+    "blobs_75x300": lambda: synth.random_masks(8, 75, 300, blobs=4),
+    "sparse_200x70": lambda: synth.random_masks(9, 200, 70, blobs=2),
+    "one_empty_60x50": lambda: synth.random_masks(10, 60, 50, p_empty=0.5),
+    "pair_96x160": lambda: (lambda c: (c.mask_L, c.mask_R))(synth.make_canvas(3, 96, 160, holes=2)),
+    "pair_axis1_150x90": lambda: (lambda c: (c.mask_L, c.mask_R))(synth.make_canvas(4, 150, 90, axis=1)),
+}
+
+
+def _single_pixels():
+    mL = np.zeros((40, 37), np.uint8)
+    mR = np.zeros((40, 37), np.uint8)
+    mL[3, 5] = 1
+    mR[35, 30] = 1
+    mL[20:, 10:] = 1
+    mR[20:, 10:] = 1
+    return mL, mR
+
+
+MASKS["single_pixels_40x37"] = _single_pixels
+MASKS["identical_30x30"] = lambda: (np.ones((30, 30), np.uint8), np.ones((30, 30), np.uint8))
+
+
+@pytest.mark.parametrize("name", list(MASKS))
+def test_overlap_box_distances_and_blend(api, name):
+    mL, mR = MASKS[name]()
+    H, W = mL.shape
+    plan = plan_for(api, H, W)
+    print(f"[gpu] canvas distances {name}", flush=True)
+    pad = 5 if H % 2 else 0  # odd heights use pitched masks
+    dL, dR = (pitched(mL, pad), pitched(mR, pad)) if pad else (dev(mL), dev(mR))
+    assert plan.overlap_box(dL, dR) == oracle.overlap_box(mL, mR)
+    B, d1, d2 = plan.canvas_blend(dL, dR, distances=True)
+    torch.cuda.synchronize()
+    o1, o2 = oracle.canvas_dist2(mL, mR)
+    assert np.array_equal(d1.cpu().numpy().astype(np.int64), o1)
+    assert np.array_equal(d2.cpu().numpy().astype(np.int64), o2)
+    oB = oracle.canvas_blend(mL, mR)
+    assert np.abs(B.cpu().numpy().astype(np.float64) - oB).max() <= B_TOL
+    # the Blend-only launch (no distances) searches only Area3 pixels
+    B2 = plan.canvas_blend(dL, dR)
+    torch.cuda.synchronize()
+    assert torch.equal(B, B2)
+
+
+def test_large_canvas_sampled(api):
+    # 4000 x 2400 pair canvas (two side photos, 2 Area1 islands inside the
+    # overlap): distances checked one by one at sampled pixels
+    rng = synth.rng_for(113, 0, 0)
+    mL, mR = synth.canvas_masks(rng, 4000, 2400, 0.3, holes=2)
+    H, W = mL.shape
+    plan = plan_for(api, H, W)
+    print("[gpu] canvas distances 4000x2400 sampled", flush=True)
+    dL, dR = dev(mL), dev(mR)
+    assert plan.overlap_box(dL, dR) == oracle.overlap_box(mL, mR)
+    B, d1, d2 = plan.canvas_blend(dL, dR, distances=True)
+    torch.cuda.synchronize()
+    a = (mL > 0) + 2 * (mR > 0)
+    ys, xs = np.nonzero(a == 3)
+    pick = rng.choice(len(xs), 300, replace=False)
+    pts = np.concatenate([np.stack([xs[pick], ys[pick]], 1),
+                          np.stack([rng.integers(0, W, 100), rng.integers(0, H, 100)], 1),
+                          np.array([[0, 0], [W - 1, H - 1], [0, H - 1], [W - 1, 0]])])
+    o1, o2 = oracle.canvas_dist2(mL, mR, pts)
+    g1 = d1.cpu().numpy()[pts[:, 1], pts[:, 0]]
+    g2 = d2.cpu().numpy()[pts[:, 1], pts[:, 0]]
+    assert np.array_equal(g1.astype(np.int64), o1)
+    assert np.array_equal(g2.astype(np.int64), o2)
+    oB = oracle.canvas_blend(mL, mR, pts)
+    assert np.abs(B.cpu().numpy()[pts[:, 1], pts[:, 0]].astype(np.float64) - oB).max() <= B_TOL
+    # properties at every pixel: 0 inside the area, positive outside it
+    h1, h2 = d1.cpu().numpy(), d2.cpu().numpy()
+    assert (h1[a == 1] == 0).all() and (h1[a != 1] > 0).all()
+    assert (h2[a == 2] == 0).all() and (h2[a != 2] > 0).all()
+
+
+def _check_F(F8, Ff, oF):
+    assert np.abs(Ff - oF).max() <= F_TOL
+    r = oF - np.floor(oF)
+    safe = np.abs(r - 0.5) > F_TOL
+    o8 = np.clip(np.floor(oF + 0.5), 0, 255).astype(np.uint8)
+    assert np.array_equal(F8[safe], o8[safe])
+    assert np.abs(F8.astype(int) - o8.astype(int)).max() <= 1
+
+
+def _flows(seed, bh, bw, scale):
+    r = synth.rng_for(114, seed, 0)
+    return (r.uniform(-scale, scale, (bh, bw, 2)).astype(np.float32),
+            r.uniform(-scale, scale, (bh, bw, 2)).astype(np.float32))
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("mode", ["eq1", "user", "linear"])
+def test_composite_parity(api, axis, mode):
+    c = synth.make_canvas(5 + axis, 90, 140, axis=axis, holes=1)
+    H, W = c.mask_L.shape
+    box = oracle.overlap_box(c.mask_L, c.mask_R)
+    flr, frl = _flows(axis, box[3], box[2], 6.0)
+    blend = synth.rng_for(115, axis, 0).uniform(0, 1, (H, W)).astype(np.float32) if mode == "user" else None
+    kw = dict(blend_mode=1) if mode == "linear" else {}
+    plan = plan_for(api, H, W, **kw)
+    print(f"[gpu] composite axis {axis} {mode}", flush=True)
+    F8, Ff = plan.composite_canvas(pitched(c.L, 7), dev(c.R), dev(c.mask_L), dev(c.mask_R), dev(flr), dev(frl), box,
+                                   axis=axis, blend=None if blend is None else dev(blend), f32=True)
+    torch.cuda.synchronize()
+    op = oracle.Params(**kw)
+    oF, _ = oracle.composite(c.L, c.R, c.mask_L, c.mask_R, flr, frl, box, axis=axis, blend=blend, params=op)
+    _check_F(F8.cpu().numpy(), Ff.cpu().numpy(), oF)
+
+
+def test_composite_box_smaller_than_area3_and_pitched_output(api):
+    c = synth.make_canvas(7, 64, 100, holes=1)
+    H, W = c.mask_L.shape
+    bx, by, bw, bh = oracle.overlap_box(c.mask_L, c.mask_R)
+    box = (bx + 2, by + 1, bw - 5, bh - 3)
+    flr, frl = _flows(3, box[3], box[2], 3.0)
+    plan = plan_for(api, H, W)
+    print("[gpu] composite small box", flush=True)
+    out = torch.zeros((H, W + 3, 3), dtype=torch.uint8, device="cuda")[:, 1:W + 1]
+    F8, Ff = plan.composite_canvas(dev(c.L), dev(c.R), dev(c.mask_L), dev(c.mask_R), dev(flr), dev(frl), box,
+                                   f32=True, out=out)
+    torch.cuda.synchronize()
+    oF, _ = oracle.composite(c.L, c.R, c.mask_L, c.mask_R, flr, frl, box)
+    _check_F(F8.cpu().numpy(), Ff.cpu().numpy(), oF)
+    full = out.cpu().numpy()
+    assert F8.data_ptr() == out.data_ptr() and np.array_equal(full, F8.cpu().numpy())
+
+
+def test_composite_without_overlap(api):
+    # side by side without overlap: no flow, Area1 / Area2 copies and zeros
+    H, W = 20, 30
+    mL = np.zeros((H, W), np.uint8)
+    mR = np.zeros((H, W), np.uint8)
+    mL[:, :12] = 1
+    mR[2:, 15:] = 1
+    s = synth.make_random(9, H, W)
+    plan = plan_for(api, H, W)
+    print("[gpu] composite without overlap", flush=True)
+    assert plan.overlap_box(dev(mL), dev(mR)) == (0, 0, 0, 0)
+    F8 = plan.composite_canvas(dev(s.L), dev(s.R), dev(mL), dev(mR), None, None, (0, 0, 0, 0))
+    torch.cuda.synchronize()
+    oF, o8 = oracle.composite(s.L, s.R, mL, mR, np.zeros((0, 0, 2)), np.zeros((0, 0, 2)), (0, 0, 0, 0))
+    assert np.array_equal(F8.cpu().numpy(), o8)
+
+
+def test_stitch_canvas_end_to_end(api):
+    # box -> both flows on the box crops -> eq. (1) -> Code 1; the composite
+    # is checked against the oracle's given the GPU's flows (the flows
+    # themselves are checked against the oracle's by the flow tests)
+    c = synth.make_canvas(8, 320, 400, holes=1)
+    H, W = c.mask_L.shape
+    plan = plan_for(api, H, W, levels=4)
+    print("[gpu] stitch_canvas 320x400", flush=True)
+    F8, Ff, box, flr, frl = plan.stitch_canvas(dev(c.L), dev(c.R), dev(c.mask_L), dev(c.mask_R), f32=True)
+    torch.cuda.synchronize()
+    assert box == oracle.overlap_box(c.mask_L, c.mask_R)
+    bx, by, bw, bh = box
+    of_lr, of_rl = oracle.flow_bidirectional(c.L[by:by + bh, bx:bx + bw], c.R[by:by + bh, bx:bx + bw],
+                                             oracle.Params(levels=4))
+    assert np.abs(flr.cpu().numpy() - of_lr).max() <= 1e-2
+    assert np.abs(frl.cpu().numpy() - of_rl).max() <= 1e-2
+    oF, _ = oracle.composite(c.L, c.R, c.mask_L, c.mask_R, flr.cpu().numpy(), frl.cpu().numpy(), box)
+    _check_F(F8.cpu().numpy(), Ff.cpu().numpy(), oF)
+
+
+def test_canvas_limits_are_enforced(api):
+    plan = api.Plan(api.Params(), max_strips=1, max_H=64, max_W=64)
+    m = torch.ones((4000, 3000), dtype=torch.uint8, device="cuda")
+    with pytest.raises(Exception, match="workspace"):
+        plan.canvas_blend(m, m)
+    small = plan_for(api, 16, 16)
+    m = torch.ones((16, 16), dtype=torch.uint8, device="cuda")
+    img = torch.zeros((16, 16, 3), dtype=torch.uint8, device="cuda")
+    f = torch.zeros((16, 16, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        small.composite_canvas(img, img, m, m, f, f, (1, 0, 16, 16))
