@@ -126,6 +126,62 @@ def run_stream(n_pano, p, timed, log):
             "mpix_s_with_refine": round(total_px / (ms_f + ms_r) / 1e3, 1)}
 
 
+def run_canvas(p, timed, log, steps):
+    """Canvas compositing of one photo pair: a 4000 x 2400 canvas with two
+    side photos (overlap ~0.3 W with slanted, bowed edges, two Area1
+    islands inside it). One step = overlap box, both flows on the box
+    crops, eq. (1) over the canvas, Code 1 over the canvas."""
+    import numpy as np
+    import torch
+
+    from paper_2006_01201_amd import api, synth
+
+    t0 = time.time()
+    c = synth.make_canvas(0, 4000, 2400, holes=2)
+    H, W = c.mask_L.shape
+    L, R = torch.from_numpy(c.L).cuda(), torch.from_numpy(c.R).cuda()
+    mL, mR = torch.from_numpy(c.mask_L).cuda(), torch.from_numpy(c.mask_R).cuda()
+    a = (c.mask_L > 0).astype(np.int64) + 2 * (c.mask_R > 0)
+    counts = [int((a == k).sum()) for k in range(4)]
+    log(f"canvas: {H} x {W} generated in {time.time() - t0:.1f} s, areas (none, 1, 2, 3) = {counts}")
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, canvas=(H, W))
+    box = plan.overlap_box(mL, mR)
+    bx, by, bw, bh = box
+    n3 = int((a[by:by + bh, bx:bx + bw] == 3).sum())
+    Lc, Rc = L[by:by + bh, bx:bx + bw], R[by:by + bh, bx:bx + bw]
+    flr = torch.empty((bh, bw, 2), device="cuda")
+    frl = torch.empty((bh, bw, 2), device="cuda")
+    B = torch.empty((H, W), device="cuda")
+    F = torch.empty((H, W, 3), dtype=torch.uint8, device="cuda")
+    dbox = torch.empty(4, dtype=torch.int32, device="cuda")
+    parts = {
+        "overlap_box": lambda: plan.overlap_box(mL, mR, out=dbox),
+        "flow_both_ways": lambda: plan.flow_bidirectional(Lc, Rc, out=(flr, frl)),
+        "eq1_blend_map": lambda: plan.canvas_blend(mL, mR, out=B),
+        "code1_composite": lambda: plan.composite_canvas(L, R, mL, mR, flr, frl, box, blend=B, out=F),
+    }
+    for fn in parts.values():
+        fn()
+    ms = {k: timed(fn, steps)[0] for k, fn in parts.items()}
+    total = sum(ms.values())
+    npx = H * W
+    # algorithmic bytes: masks in, row distances out (row pass), row
+    # distances in (block minima), masks + row distances in and Blend out
+    # (search); masks in, one image in on Area1 / Area2, both images +
+    # Blend + two float2 flows on Area3, F out (composite)
+    b_map = npx * (2 + 4) + npx * 4 + npx * (2 + 4 + 4)
+    b_comp = npx * (2 + 3) + 3 * (counts[1] + counts[2]) + (6 + 4 + 16) * n3
+    roof = {k: {"bound": "hbm", "ms": round(ms[k], 4), "bytes": b,
+                "achieved": round(b / ms[k] / 1e6, 1), "unit": "GB/s", "frac": round(b / ms[k] / 1e6 / HBM_PEAK_GBS, 4)}
+            for k, b in (("eq1_blend_map", b_map), ("code1_composite", b_comp))}
+    log(f"canvas: {total:.3f} ms per canvas ({', '.join(f'{k} {v:.3f}' for k, v in ms.items())})")
+    return {"workload": f"{H} x {W} pair canvas (two side photos, overlap box {bw} x {bh}, Area3 {counts[3]} px "
+                        f"with 2 Area1 islands), box + flows on the box + eq. (1) + Code 1",
+            "canvas_mpix": round(npx / 1e6, 3), "ms_per_canvas": round(total, 4),
+            "mpix_s": round(npx / total / 1e3, 1), "ms": {k: round(v, 4) for k, v in ms.items()},
+            "areas_none_1_2_3": counts, "roofline": roof}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_01201_amd", "csrc", "abf_kernels.hip")
 
@@ -170,6 +226,7 @@ def main():
                          "traffic, for scaling hardware byte counters)")
     ap.add_argument("--refine", action="store_true",
                     help="also time 50 gradient-descent refinement steps on the 2048 x 512 float strip")
+    ap.add_argument("--no-canvas", action="store_true", help="skip the canvas-compositing leg")
     ap.add_argument("--stream", type=int, default=0, metavar="PANORAMAS",
                     help="also time a stream of this many panoramas of the cfg4 workload (7 strips of drawn "
                          "sizes each; flow + blend batched per 4 panoramas, then 20 batched refinement steps)")
@@ -293,6 +350,8 @@ def main():
                   "mpix_steps_s": round(H3 * W3 * 50 / ms_r / 1e3, 1)}
         log(f"refine 50 steps: {ms_r:.3f} ms")
 
+    canvas = None if args.no_canvas else run_canvas(p, timed, log, args.steps)
+
     stream = None
     if args.stream:
         stream = run_stream(args.stream, p, timed, log)
@@ -346,6 +405,7 @@ def main():
         "top_launches": per_launch,
         "roofline": roofline,
         "refine_flow": refine,
+        "canvas": canvas,
         "stream": stream,
         "cpu_baseline": cpu,
     }

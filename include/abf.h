@@ -242,7 +242,8 @@ abf_status abf_blend_asymmetric_f32(abf_plan *plan, const float *L, const float 
 size_t abf_canvas_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W);
 
 /* Bounding box of Area3, written as int32 {x, y, w, h} to `box` (device,
- * 4 entries); {0, 0, 0, 0} when no pixel is covered by both images. */
+ * 4 entries); {0, 0, 0, 0} when no pixel is covered by both images.
+ * Scratch: 8 bytes per canvas row. */
 abf_status abf_overlap_box(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
                            int32_t pitch_mask, int32_t *box, void *hip_stream);
 

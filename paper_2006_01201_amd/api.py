@@ -273,24 +273,30 @@ class Plan:
 
     # -- inspection ------------------------------------------------------
     # -- canvas compositing (eq. (1) and Code 1 with general areas) ----
-    def overlap_box(self, mask_L, mask_R):
-        """Bounding box (x, y, w, h) of Area3 (host tuple; synchronises)."""
+    def overlap_box(self, mask_L, mask_R, out=None):
+        """Bounding box (x, y, w, h) of Area3: a host tuple (synchronises),
+        or, with ``out`` (int32 CUDA tensor of 4), written there without
+        synchronising."""
         H, W, pm = _mask(mask_L, "mask_L")
         if _mask(mask_R, "mask_R") != (H, W, pm):
             raise ValueError("mask_L and mask_R differ in shape or pitch")
-        box = torch.empty(4, dtype=torch.int32, device=mask_L.device)
+        box = torch.empty(4, dtype=torch.int32, device=mask_L.device) if out is None else out
+        if box.dtype != torch.int32 or box.numel() != 4 or not box.is_cuda or not box.is_contiguous():
+            raise ValueError("out: expected a contiguous CUDA int32 tensor of 4")
         st = _abi.overlap_box(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, box.data_ptr(), _stream())
         _abi.check(st, self.h, "abf_overlap_box")
-        return tuple(int(v) for v in box.cpu())
+        return box if out is not None else tuple(int(v) for v in box.cpu())
 
-    def canvas_blend(self, mask_L, mask_R, distances: bool = False):
-        """eq. (1) over the canvas (float32 H x W); with ``distances`` also
-        the squared distances to Area1 and Area2 (int32, -1 = empty)."""
+    def canvas_blend(self, mask_L, mask_R, distances: bool = False, out=None):
+        """eq. (1) over the canvas (float32 H x W, into ``out`` if given);
+        with ``distances`` also the squared distances to Area1 and Area2
+        (int32, -1 = empty)."""
         H, W, pm = _mask(mask_L, "mask_L")
         if _mask(mask_R, "mask_R") != (H, W, pm):
             raise ValueError("mask_L and mask_R differ in shape or pitch")
         dev = mask_L.device
-        B = torch.empty((H, W), dtype=torch.float32, device=dev)
+        B = torch.empty((H, W), dtype=torch.float32, device=dev) if out is None else out
+        _f32(B, (H, W), "out")
         d1 = torch.empty((H, W), dtype=torch.int32, device=dev) if distances else None
         d2 = torch.empty((H, W), dtype=torch.int32, device=dev) if distances else None
         st = _abi.canvas_blend(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, B.data_ptr(), W,

@@ -11,15 +11,13 @@
 //      area (one workgroup per row; 16-pixel chunks, a workgroup scan of
 //      the chunks' first/last members carries the nearest one across
 //      chunks). Both areas are kept as a uint16 pair per pixel, and a
-//      second kernel stores the minimum of g over every 32-row block of a
+//      second kernel stores the minimum of g over every 16-row block of a
 //      column.
 //   2. columns: D(x, y) = min over rows y' of (y - y')^2 + g(x, y')^2,
-//      searched outward from y. A block of rows whose nearest row is k
-//      rows away and whose minimum g is m cannot beat k^2 + m^2, so it is
-//      skipped when that bound reaches the best value found, and the
-//      search ends in a direction once k^2 does. The work per pixel
-//      grows with the distance only through the number of 32-row blocks
-//      passed over, not their rows.
+//      searched outward from y, a 16-row block at a time. A block whose
+//      nearest row is k rows away and whose minimum g is m cannot beat
+//      k^2 + m^2, so it is skipped when that bound reaches the best value
+//      found, and the search ends in a direction once k^2 does.
 #include "abf_device.h"
 
 namespace abf {
@@ -177,116 +175,160 @@ __global__ __launch_bounds__(kCanvasThreads) void k_canvas_colmin(CanvasGeom a)
 }
 
 // ------------------------------------------------------- column search
-// The two squared distances of the pixel of this lane. Every lane of a
-// wave is on row y (wave-uniform loop bounds); `best1` / `best2` start at
-// the row distance of the pixel itself squared, or 0 for an area whose
-// distance is not needed (then nothing is searched for it).
-__device__ __forceinline__ void col_search(const CanvasGeom &a, int x, int y, bool in, uint32_t &best1,
-                                           uint32_t &best2)
+// One workgroup per 64 columns of one kCanvasBH-row block (the tile; wave
+// w holds tile rows w, w + 4, w + 8, w + 12). The tile's own rows, then
+// the blocks above and below at increasing distance, are staged in LDS
+// (one coalesced 4 KiB load each) and every pixel of the tile takes its
+// candidates from there, so the rows that neighbouring pixels share are
+// read from memory once per tile. Block minima are examined kWin blocks
+// per direction at a time: a block j blocks away is at least 16 j - 15
+// rows from every row of the tile, so it is staged only if, for some
+// column and area, that distance squared plus the block minimum squared
+// is below the largest best value of the column's tile pixels; a
+// direction ends once that distance squared reaches the largest best value
+// of the tile. Squared distances saturate at 0xffffffff (no pixel of the
+// area seen yet); pixels whose distances are not needed start at 0.
+constexpr int kTileQ = kCanvasBH / 4;  // pixels (rows) per lane
+constexpr int kWin = 8;                // blocks examined per direction at a time
+
+__device__ __forceinline__ uint32_t sqg(uint32_t g) { return g == kInf16 ? kInf32 : g * g; }
+__device__ __forceinline__ uint32_t adds(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
+
+// candidates of the lane's tile pixels (rows yq[q]) from the staged rows
+// r0 .. r0 + kCanvasBH - 1 of its column. With `m` (the block's minima of
+// the column) a pixel skips the block when its nearest row (dk rows away)
+// and those minima cannot beat its best values.
+__device__ __forceinline__ void eval_rows(const uint32_t (*rows)[64], int lane, int r0, const int (&yq)[kTileQ],
+                                          uint32_t (&b1)[kTileQ], uint32_t (&b2)[kTileQ], bool bounded = false,
+                                          uint32_t m = 0)
 {
-    const int H = a.H, b0 = y / kCanvasBH;
-    const uint32_t *G = a.G;
-    auto row = [&](int r, bool act) {
-        const uint32_t k = (uint32_t)abs(r - y), k2 = k * k;
-        if (act && k2 < max(best1, best2)) {
-            const uint32_t g = gld(G)[(size_t)r * a.gpitch + x];
-            best1 = min(best1, cand(k2, g & 0xffffu));
-            best2 = min(best2, cand(k2, g >> 16));
+    const uint32_t ms1 = sqg(m & 0xffffu), ms2 = sqg(m >> 16);
+#pragma unroll
+    for (int q = 0; q < kTileQ; q++) {
+        if (bounded) {
+            const int dk = yq[q] < r0 ? r0 - yq[q] : yq[q] - (r0 + kCanvasBH - 1);
+            const uint32_t dk2 = (uint32_t)(dk * dk);
+            if (!(adds(dk2, ms1) < b1[q] || adds(dk2, ms2) < b2[q])) continue;
         }
-    };
-    auto live = [&](uint32_t k2, bool act) { return __ballot(act && in && k2 < max(best1, best2)) != 0; };
-    // rows of the pixel's own block, nearest first
-    const int lo = b0 * kCanvasBH, hi = min(lo + kCanvasBH, H) - 1;
-    for (int k = 1; y - k >= lo || y + k <= hi; k++) {
-        if (!live((uint32_t)(k * k), true)) break;
-        if (y - k >= lo) row(y - k, in);
-        if (y + k <= hi) row(y + k, in);
-    }
-    // blocks above, nearest first
-    for (int b = b0 - 1; b >= 0; b--) {
-        const uint32_t dk = (uint32_t)(y - (b * kCanvasBH + kCanvasBH - 1)), dk2 = dk * dk;
-        if (!live(dk2, true)) break;
-        bool scan = false;
-        if (in) {
-            const uint32_t m = gld(a.M)[(size_t)b * a.gpitch + x];
-            scan = cand(dk2, m & 0xffffu) < best1 || cand(dk2, m >> 16) < best2;
-        }
-        for (int r = b * kCanvasBH + kCanvasBH - 1; r >= b * kCanvasBH; r--) {
-            const uint32_t k = (uint32_t)(y - r);
-            if (!live(k * k, scan)) break;
-            row(r, scan);
-        }
-    }
-    // blocks below, nearest first
-    const int nb = ceil_div(H, kCanvasBH);
-    for (int b = b0 + 1; b < nb; b++) {
-        const uint32_t dk = (uint32_t)(b * kCanvasBH - y), dk2 = dk * dk;
-        if (!live(dk2, true)) break;
-        bool scan = false;
-        if (in) {
-            const uint32_t m = gld(a.M)[(size_t)b * a.gpitch + x];
-            scan = cand(dk2, m & 0xffffu) < best1 || cand(dk2, m >> 16) < best2;
-        }
-        const int rend = min(b * kCanvasBH + kCanvasBH, H);
-        for (int r = b * kCanvasBH; r < rend; r++) {
-            const uint32_t k = (uint32_t)(r - y);
-            if (!live(k * k, scan)) break;
-            row(r, scan);
+#pragma unroll
+        for (int rr = 0; rr < kCanvasBH; rr++) {
+            const uint32_t g = rows[rr][lane];
+            const int k = yq[q] - (r0 + rr);
+            const uint32_t k2 = (uint32_t)(k * k);
+            b1[q] = min(b1[q], adds(k2, sqg(g & 0xffffu)));
+            b2[q] = min(b2[q], adds(k2, sqg(g >> 16)));
         }
     }
 }
 
-// One wave per 64 columns of a row (workgroup = 4 rows). Writes Blend
-// (eq. (1)) and, if requested, both squared distances of every pixel
-// (-1 where the area is empty).
 __global__ __launch_bounds__(256) void k_canvas_dist(CanvasGeom a, float *blend, int pitchB, int32_t *d1, int32_t *d2,
                                                      int pitchD)
 {
-    const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
-    if (y >= a.H) return;  // whole waves
-    const bool in = x < a.W;
-    int area = 0;
-    uint32_t g0 = kInf32;
-    if (in) {
-        area = (gld(a.mL)[(size_t)y * a.pitchM + x] != 0) + 2 * (gld(a.mR)[(size_t)y * a.pitchM + x] != 0);
-        g0 = gld(a.G)[(size_t)y * a.gpitch + x];
-    }
+    __shared__ uint32_t own[kCanvasBH][64];
+    __shared__ uint32_t nbr[2][kCanvasBH][64];  // staged block above / below
+    __shared__ uint32_t nbm[2][64];             // and its block minima
+    __shared__ uint32_t flags[2][4];            // by window parity: a window may end without a barrier
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int x = blockIdx.x * 64 + lane, b0 = blockIdx.y, y0 = b0 * kCanvasBH;
+    const int H = a.H, nb = ceil_div(H, kCanvasBH);
+    const bool inx = x < a.W;
     const bool all = d1 != nullptr;
-    const bool need = in && (all || area == 3);
-    uint32_t best1 = need ? cand(0, g0 & 0xffffu) : 0u;
-    uint32_t best2 = need ? cand(0, g0 >> 16) : 0u;
-    col_search(a, x, y, in, best1, best2);
-    if (!in) return;
-    if (blend) {
-        float t;
-        if (area == 1) t = 0.f;
-        else if (area == 2) t = 1.f;
-        else if (area == 0) t = 0.5f;
-        else if (best1 == kInf32 && best2 == kInf32) t = 0.5f;
-        else if (best1 == kInf32) t = 1.f;
-        else if (best2 == kInf32) t = 0.f;
-        else {
-            const double l = sqrt((double)best1), r = sqrt((double)best2);
-            t = (float)(l / (l + r));
+    auto stage = [&](uint32_t (*dst)[64], int b) {
+#pragma unroll
+        for (int q = 0; q < kTileQ; q++) {
+            const int i = w + 4 * q, r = b * kCanvasBH + i;
+            dst[i][lane] = inx && r < H ? gld(a.G)[(size_t)r * a.gpitch + x] : kInf32;
         }
-        gst(blend)[(size_t)y * pitchB + x] = t;
+    };
+    stage(own, b0);
+    int area[kTileQ], yq[kTileQ];
+    uint32_t best1[kTileQ], best2[kTileQ];
+#pragma unroll
+    for (int q = 0; q < kTileQ; q++) {
+        const int y = y0 + w + 4 * q;
+        const bool in = inx && y < H;
+        yq[q] = y;
+        area[q] = in ? (gld(a.mL)[(size_t)y * a.pitchM + x] != 0) + 2 * (gld(a.mR)[(size_t)y * a.pitchM + x] != 0) : 0;
+        best1[q] = best2[q] = in && (all || area[q] == 3) ? kInf32 : 0u;
     }
-    if (all) {
-        gst(d1)[(size_t)y * pitchD + x] = best1 == kInf32 ? -1 : (int32_t)best1;
-        gst(d2)[(size_t)y * pitchD + x] = best2 == kInf32 ? -1 : (int32_t)best2;
+    __syncthreads();
+    eval_rows(own, lane, y0, yq, best1, best2);
+    bool up = b0 > 0, down = b0 + 1 < nb;
+    for (int j0 = 1; up || down; j0 += kWin) {
+        uint32_t m1 = 0, m2 = 0;
+#pragma unroll
+        for (int q = 0; q < kTileQ; q++) {
+            m1 = max(m1, best1[q]);
+            m2 = max(m2, best2[q]);
+        }
+        const uint32_t mm = max(m1, m2);
+        uint32_t f = 0;
+#pragma unroll
+        for (int t = 0; t < kWin; t++) {
+            const int bu = b0 - j0 - t, bd = b0 + j0 + t;
+            const uint32_t dk = (uint32_t)(16 * (j0 + t) - 15), dk2 = dk * dk;
+            const uint32_t mu = up && inx && bu >= 0 ? gld(a.M)[(size_t)bu * a.gpitch + x] : kInf32;
+            const uint32_t md = down && inx && bd < nb ? gld(a.M)[(size_t)bd * a.gpitch + x] : kInf32;
+            f |= (adds(dk2, sqg(mu & 0xffffu)) < m1 || adds(dk2, sqg(mu >> 16)) < m2) ? 1u << t : 0u;
+            f |= (adds(dk2, sqg(md & 0xffffu)) < m1 || adds(dk2, sqg(md >> 16)) < m2) ? 1u << (kWin + t) : 0u;
+        }
+        const uint32_t dn = (uint32_t)(16 * (j0 + kWin) - 15);
+        f |= dn * dn < mm ? 3u << (2 * kWin) : 0u;
+        // OR over the wave, then over the workgroup
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) f |= (uint32_t)__shfl_xor((int)f, o);
+        const int par = (j0 / kWin) & 1;
+        if (lane == 0) flags[par][w] = f;
+        __syncthreads();
+        const uint32_t F = flags[par][0] | flags[par][1] | flags[par][2] | flags[par][3];
+        for (int t = 0; t < kWin; t++) {
+            const bool su = up && ((F >> t) & 1u), sd = down && ((F >> (kWin + t)) & 1u);
+            if (!su && !sd) continue;  // workgroup-uniform
+            const int bu = b0 - j0 - t, bd = b0 + j0 + t;
+            if (su) stage(nbr[0], bu);
+            if (sd) stage(nbr[1], bd);
+            if (w == 0 && su) nbm[0][lane] = inx ? gld(a.M)[(size_t)bu * a.gpitch + x] : kInf32;
+            if (w == 1 && sd) nbm[1][lane] = inx ? gld(a.M)[(size_t)bd * a.gpitch + x] : kInf32;
+            __syncthreads();
+            if (su) eval_rows(nbr[0], lane, bu * kCanvasBH, yq, best1, best2, true, nbm[0][lane]);
+            if (sd) eval_rows(nbr[1], lane, bd * kCanvasBH, yq, best1, best2, true, nbm[1][lane]);
+            __syncthreads();
+        }
+        up = up && b0 - j0 - kWin >= 0 && ((F >> (2 * kWin)) & 1u);
+        down = down && b0 + j0 + kWin < nb && ((F >> (2 * kWin)) & 1u);
+    }
+#pragma unroll
+    for (int q = 0; q < kTileQ; q++) {
+        const int y = yq[q];
+        if (!inx || y >= H) continue;
+        const uint32_t e1 = best1[q], e2 = best2[q];
+        if (blend) {
+            float t;
+            if (area[q] == 1) t = 0.f;
+            else if (area[q] == 2) t = 1.f;
+            else if (area[q] == 0) t = 0.5f;
+            else if (e1 == kInf32 && e2 == kInf32) t = 0.5f;
+            else if (e1 == kInf32) t = 1.f;
+            else if (e2 == kInf32) t = 0.f;
+            else {
+                const double l = sqrt((double)e1), r = sqrt((double)e2);
+                t = (float)(l / (l + r));
+            }
+            gst(blend)[(size_t)y * pitchB + x] = t;
+        }
+        if (all) {
+            gst(d1)[(size_t)y * pitchD + x] = e1 == kInf32 ? -1 : (int32_t)e1;
+            gst(d2)[(size_t)y * pitchD + x] = e2 == kInf32 ? -1 : (int32_t)e2;
+        }
     }
 }
 
 // ------------------------------------------------------------ overlap box
-__global__ void k_box_init(int32_t *box)
-{
-    if (threadIdx.x < 4) gst(box)[threadIdx.x] = threadIdx.x < 2 ? 0x7fffffff : -1;
-}
-
-// One workgroup per row: extent of the row's Area3 pixels, merged into
-// {x0, y0, x1, y1} with atomics.
+// One workgroup per row: the extent {x0, x1} of the row's Area3 pixels
+// ({INT_MAX, -1} if none) into part[2 y], part[2 y + 1]. Each thread reads 16 consecutive
+// columns of both masks with all loads in flight at once.
 __global__ __launch_bounds__(kCanvasThreads) void k_box_rows(const uint8_t *mL, const uint8_t *mR, int pitchM, int W,
-                                                             int32_t *box)
+                                                             int32_t *part)
 {
     __shared__ int32_t s[2];
     const int y = blockIdx.x;
@@ -295,35 +337,68 @@ __global__ __launch_bounds__(kCanvasThreads) void k_box_rows(const uint8_t *mL, 
         s[1] = -1;
     }
     __syncthreads();
+    const uint8_t *rl = mL + (size_t)y * pitchM, *rr = mR + (size_t)y * pitchM;
     int lo = 0x7fffffff, hi = -1;
-    for (int x = threadIdx.x; x < W; x += kCanvasThreads)
-        if (gld(mL)[(size_t)y * pitchM + x] != 0 && gld(mR)[(size_t)y * pitchM + x] != 0) {
-            lo = min(lo, x);
-            hi = max(hi, x);
+    for (int x0 = kCanvasChunk * (int)threadIdx.x; x0 < W; x0 += kCanvasChunk * kCanvasThreads) {
+        uint8_t l[kCanvasChunk], r[kCanvasChunk];
+#pragma unroll
+        for (int k = 0; k < kCanvasChunk; k++) {
+            l[k] = x0 + k < W ? gld(rl)[x0 + k] : 0;
+            r[k] = x0 + k < W ? gld(rr)[x0 + k] : 0;
         }
+#pragma unroll
+        for (int k = 0; k < kCanvasChunk; k++)
+            if (l[k] != 0 && r[k] != 0) {
+                lo = min(lo, x0 + k);
+                hi = max(hi, x0 + k);
+            }
+    }
     if (hi >= 0) {
         atomicMin(&s[0], lo);
         atomicMax(&s[1], hi);
     }
     __syncthreads();
-    if (threadIdx.x == 0 && s[1] >= 0) {
-        atomicMin(&box[0], s[0]);
-        atomicMin(&box[1], y);
-        atomicMax(&box[2], s[1]);
-        atomicMax(&box[3], y);
+    if (threadIdx.x == 0) {
+        gst(part)[2 * y] = s[0];
+        gst(part)[2 * y + 1] = s[1];
     }
 }
 
-// {x0, y0, x1, y1} -> {x, y, w, h}, zeros when there is no Area3 pixel
-__global__ void k_box_fin(int32_t *box)
+// Merge of the row extents into {x, y, w, h} (zeros when no row has an
+// Area3 pixel); one workgroup.
+__global__ __launch_bounds__(1024) void k_box_fin(const int32_t *part, int H, int32_t *box)
 {
+    __shared__ int32_t s[4];
     if (threadIdx.x == 0) {
-        const int x0 = box[0], y0 = box[1], x1 = box[2], y1 = box[3];
-        const bool e = x1 < 0;
-        gst(box)[0] = e ? 0 : x0;
-        gst(box)[1] = e ? 0 : y0;
-        gst(box)[2] = e ? 0 : x1 - x0 + 1;
-        gst(box)[3] = e ? 0 : y1 - y0 + 1;
+        s[0] = 0x7fffffff;
+        s[1] = 0x7fffffff;
+        s[2] = -1;
+        s[3] = -1;
+    }
+    __syncthreads();
+    int x0 = 0x7fffffff, y0 = 0x7fffffff, x1 = -1, y1 = -1;
+    for (int y = threadIdx.x; y < H; y += blockDim.x) {
+        const int32_t ex = gld(part)[2 * y], ey = gld(part)[2 * y + 1];
+        if (ey >= 0) {
+            x0 = min(x0, ex);
+            x1 = max(x1, ey);
+            y0 = min(y0, y);
+            y1 = max(y1, y);
+        }
+    }
+    if (x1 >= 0) {
+        atomicMin(&s[0], x0);
+        atomicMin(&s[1], y0);
+        atomicMax(&s[2], x1);
+        atomicMax(&s[3], y1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const bool e = s[2] < 0;
+        gst(box)[0] = e ? 0 : s[0];
+        gst(box)[1] = e ? 0 : s[1];
+        gst(box)[2] = e ? 0 : s[2] - s[0] + 1;
+        gst(box)[3] = e ? 0 : s[3] - s[1] + 1;
     }
 }
 
@@ -385,12 +460,11 @@ __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendPara
 }
 
 // ------------------------------------------------------------- launchers
-hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *box,
-                              hipStream_t s)
+hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *part,
+                              int32_t *box, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_box_init, dim3(1), dim3(64), 0, s, box);
-    hipLaunchKernelGGL(k_box_rows, dim3(H), dim3(kCanvasThreads), 0, s, mL, mR, pitchM, W, box);
-    hipLaunchKernelGGL(k_box_fin, dim3(1), dim3(64), 0, s, box);
+    hipLaunchKernelGGL(k_box_rows, dim3(H), dim3(kCanvasThreads), 0, s, mL, mR, pitchM, W, part);
+    hipLaunchKernelGGL(k_box_fin, dim3(1), dim3(1024), 0, s, part, H, box);
     return hipGetLastError();
 }
 
@@ -400,8 +474,8 @@ hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int
     hipLaunchKernelGGL(k_canvas_rows, dim3(a.H), dim3(kCanvasThreads), 0, s, a);
     hipLaunchKernelGGL(k_canvas_colmin, dim3(ceil_div(a.W, kCanvasThreads), ceil_div(a.H, kCanvasBH)),
                        dim3(kCanvasThreads), 0, s, a);
-    hipLaunchKernelGGL(k_canvas_dist, dim3(ceil_div(a.W, 64), ceil_div(a.H, 4)), dim3(64, 4), 0, s, a, blend, pitchB,
-                       d1, d2, pitchD);
+    hipLaunchKernelGGL(k_canvas_dist, dim3(ceil_div(a.W, 64), ceil_div(a.H, kCanvasBH)), dim3(256), 0, s, a, blend,
+                       pitchB, d1, d2, pitchD);
     return hipGetLastError();
 }
 

@@ -142,7 +142,7 @@ constexpr int kCanvasMaxDim = 32767;
 constexpr int kCanvasChunk = 16;    // columns per thread in the row pass
 constexpr int kCanvasThreads = 256;
 constexpr int kCanvasMaxChunks = (kCanvasMaxDim + kCanvasChunk - 1) / kCanvasChunk;
-constexpr int kCanvasBH = 32;       // rows per block minimum of the column search
+constexpr int kCanvasBH = 16;       // rows per block minimum of the column search
 static_assert(kCanvasMaxChunks <= 8 * kCanvasThreads, "row scan holds 8 chunks per thread");
 
 // Coverage masks and the scratch planes of the distance passes: G holds
@@ -168,8 +168,9 @@ struct CompositeArgs {
     double inv_ext;           // 1 / the box's extent across the seam
 };
 
-hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *box,
-                              hipStream_t s);
+// part: 2 H int32 of scratch (row extents)
+hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *part,
+                              int32_t *box, hipStream_t s);
 hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int32_t *d1, int32_t *d2, int pitchD,
                               hipStream_t s);
 hipError_t launch_composite(const CompositeArgs &o, BlendParams bp, hipStream_t s);

@@ -886,7 +886,11 @@ abf_status abf_overlap_box(abf_plan *plan, const uint8_t *mask_L, const uint8_t 
     if (H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim)
         return fail(plan, ABF_E_SHAPE, "canvas %d x %d (1..%d per side)", H, W, kCanvasMaxDim);
     if (pitch_mask < W) return fail(plan, ABF_E_SHAPE, "mask pitch %d < W %d", pitch_mask, W);
-    HIP_TRY(plan, launch_overlap_box(mask_L, mask_R, pitch_mask, H, W, box, static_cast<hipStream_t>(hip_stream)));
+    uint8_t *scr = nullptr;
+    abf_status rc = grad_scratch(plan, 2 * sizeof(int32_t) * (size_t)H, &scr);
+    if (rc != ABF_OK) return rc;
+    HIP_TRY(plan, launch_overlap_box(mask_L, mask_R, pitch_mask, H, W, reinterpret_cast<int32_t *>(scr), box,
+                                     static_cast<hipStream_t>(hip_stream)));
     return ABF_OK;
 }
 
