@@ -279,6 +279,40 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
                                 uint8_t *F, int32_t pitch_F, float *F_f32, void *hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Repeated pairwise merging (Sections I and III.A: the two-photo blend is
+ * applied photo after photo until the set is merged). Every photo is given
+ * on the common canvas H x W: image (RGB uint8, `pitch` bytes per row) and
+ * coverage mask (uint8, nonzero = covered, pitch_mask bytes per row, the
+ * same pitch for every mask and for `coverage`). Photo 0 starts the merged
+ * canvas; photo i (i >= 1) is blended into the canvas merged so far with
+ * the canvas path: overlap box, abf_flow_bidirectional on the box crops,
+ * eq. (1), Code 1. side 0: the merged canvas plays L (Area1, left for
+ * axis 0 / above for axis 1) and the photo R; side 1: the photo plays L.
+ * A ring of photos merged left to right takes axis 0, side 0; a top photo
+ * merged last takes axis 1, side 1 (Area1 = the top photo, above).
+ * Outputs: `canvas` (merged RGB), `coverage` (1 where any photo reached);
+ * `spare` (a second canvas-sized buffer) holds intermediate results. If
+ * `boxes` (host, 4 n int32) is non-null it receives each step's overlap box
+ * (zeros for photo 0). Each box must fit the plan's strip limits
+ * (ABF_E_SHAPE otherwise). Synchronises the stream once per photo (the box
+ * sizes the flow computation); not for graph capture. */
+typedef struct abf_photo {
+    const uint8_t *image;
+    const uint8_t *mask;
+    int32_t pitch;
+    int32_t axis;
+    int32_t side;
+} abf_photo;
+
+/* Workspace bytes for merges on an H x W canvas (flows of the largest box
+ * the plan admits kept beside the canvas passes' scratch). */
+size_t abf_merge_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W);
+
+abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, int32_t H, int32_t W,
+                            int32_t pitch_mask, uint8_t *canvas, int32_t pitch_canvas, uint8_t *spare,
+                            int32_t pitch_spare, uint8_t *coverage, int32_t *boxes, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* Autotuning of launch shapes (never of results): times the candidate
  * tile heights and persistent grid sizes of each stage on the batch
  * `strips` and keeps the fastest per (stage, level-size class). Writes

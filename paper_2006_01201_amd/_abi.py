@@ -34,6 +34,10 @@ class AbfStrip(ctypes.Structure):
     ]
 
 
+class AbfPhoto(ctypes.Structure):
+    _fields_ = [("image", c_vp), ("mask", c_vp), ("pitch", c_i32), ("axis", c_i32), ("side", c_i32)]
+
+
 class AbfRefineStrip(ctypes.Structure):
     _fields_ = [("Ref", c_vp), ("Tgt", c_vp), ("u", c_vp), ("H", c_i32), ("W", c_i32)]
 
@@ -65,6 +69,9 @@ _SIGS = {
                                   c_vp]),
     "abf_profile": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_i32, ctypes.POINTER(c_f32), c_vp]),
     "abf_canvas_workspace_bytes": (c_sz, [c_vp, c_i32, c_i32]),
+    "abf_merge_workspace_bytes": (c_sz, [c_vp, c_i32, c_i32]),
+    "abf_merge_photos": (c_i32, [c_vp, ctypes.POINTER(AbfPhoto), c_i32, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp, c_i32,
+                                 c_vp, ctypes.POINTER(c_i32), c_vp]),
     "abf_overlap_box": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
     "abf_canvas_blend": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_vp]),
     "abf_composite_canvas": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp,
@@ -228,3 +235,14 @@ def composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_m
     b = (c_i32 * 4)(*box)
     return load().abf_composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_mask, flow_LtoR,
                                        flow_RtoL, b, axis, blend, pitch_blend, F, pitch_F, F_f32, stream)
+
+
+def merge_workspace_bytes(plan, H, W) -> int:
+    return load().abf_merge_workspace_bytes(plan, H, W)
+
+
+def merge_photos(plan, photos, n, H, W, pitch_mask, canvas, pitch_canvas, spare, pitch_spare, coverage, stream):
+    boxes = (c_i32 * (4 * n))()
+    st = load().abf_merge_photos(plan, photos, n, H, W, pitch_mask, canvas, pitch_canvas, spare, pitch_spare,
+                                 coverage, boxes, stream)
+    return st, [tuple(boxes[4 * i:4 * i + 4]) for i in range(n)]

@@ -99,7 +99,7 @@ class Plan:
         self.h = h
         nbytes = _abi.workspace_bytes(h)
         if canvas is not None:
-            nbytes = max(nbytes, _abi.canvas_workspace_bytes(h, *canvas))
+            nbytes = max(nbytes, _abi.canvas_workspace_bytes(h, *canvas), _abi.merge_workspace_bytes(h, *canvas))
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
         self._ws_off = (-base) % 256
@@ -344,6 +344,32 @@ class Plan:
             flr, frl = self.flow_bidirectional(L[by:by + bh, bx:bx + bw], R[by:by + bh, bx:bx + bw])
         res = self.composite_canvas(L, R, mask_L, mask_R, flr, frl, box, axis=axis, f32=f32)
         return (*res, box, flr, frl) if f32 else (res, box, flr, frl)
+
+    def merge_photos(self, photos, out=None):
+        """Repeated pairwise merging of photos placed on one canvas.
+        ``photos``: list of (image uint8 H x W x 3, mask uint8 H x W, axis,
+        side), merged in list order (photo 0 starts the canvas). Returns
+        (canvas uint8 H x W x 3, coverage uint8 H x W, boxes)."""
+        if not photos:
+            raise ValueError("no photos")
+        H, W, pm = _mask(photos[0][1], "mask")
+        arr = (_abi.AbfPhoto * len(photos))()
+        keep = []
+        for i, (img, mask, axis, side) in enumerate(photos):
+            h, w, pi = _img_u8(img, f"photo {i}")
+            if (h, w) != (H, W) or _mask(mask, f"mask {i}") != (H, W, pm):
+                raise ValueError(f"photo {i}: canvas size or mask pitch differs")
+            arr[i] = _abi.AbfPhoto(img.data_ptr(), mask.data_ptr(), pi, axis, side)
+            keep.append((img, mask))
+        dev = photos[0][0].device
+        canvas = torch.empty((H, W, 3), dtype=torch.uint8, device=dev) if out is None else out
+        spare = torch.empty_like(canvas)
+        cov = torch.empty((H, pm), dtype=torch.uint8, device=dev)[:, :W]
+        _, _, pc = _img_u8(canvas, "out")
+        st, boxes = _abi.merge_photos(self.h, arr, len(photos), H, W, pm, canvas.data_ptr(), pc, spare.data_ptr(),
+                                      spare.stride(0), cov.data_ptr(), _stream())
+        _abi.check(st, self.h, "abf_merge_photos")
+        return canvas, cov, boxes
 
     def view(self, kind: int, strip: int, level: int, direction: int) -> torch.Tensor:
         """A copy of one intermediate of the last flow call: kind 0 luma

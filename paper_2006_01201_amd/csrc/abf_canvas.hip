@@ -459,6 +459,28 @@ __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendPara
     }
 }
 
+// ------------------------------------------------------- photo merging
+// The first photo of a merge: dst = image on its coverage, 0 elsewhere;
+// cov = 1 on the coverage, 0 elsewhere. One thread per pixel.
+__global__ __launch_bounds__(256) void k_photo_init(const uint8_t *img, int pitchI, const uint8_t *mask, int pitchM,
+                                                    int H, int W, uint8_t *dst, int pitchD, uint8_t *cov, int pitchC)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= W) return;
+    const bool m = gld(mask)[(size_t)y * pitchM + x] != 0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) gst(dst)[(size_t)y * pitchD + 3 * x + c] = m ? gld(img)[(size_t)y * pitchI + 3 * x + c] : 0;
+    gst(cov)[(size_t)y * pitchC + x] = m ? 1 : 0;
+}
+
+// cov |= (mask != 0) after a photo has been merged
+__global__ __launch_bounds__(256) void k_mask_or(uint8_t *cov, int pitchC, const uint8_t *mask, int pitchM, int W)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= W) return;
+    if (gld(mask)[(size_t)y * pitchM + x] != 0) gst(cov)[(size_t)y * pitchC + x] = 1;
+}
+
 // ------------------------------------------------------------- launchers
 hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *part,
                               int32_t *box, hipStream_t s)
@@ -476,6 +498,20 @@ hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int
                        dim3(kCanvasThreads), 0, s, a);
     hipLaunchKernelGGL(k_canvas_dist, dim3(ceil_div(a.W, 64), ceil_div(a.H, kCanvasBH)), dim3(256), 0, s, a, blend,
                        pitchB, d1, d2, pitchD);
+    return hipGetLastError();
+}
+
+hipError_t launch_photo_init(const uint8_t *img, int pitchI, const uint8_t *mask, int pitchM, int H, int W,
+                             uint8_t *dst, int pitchD, uint8_t *cov, int pitchC, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_photo_init, dim3(ceil_div(W, 256), H), dim3(256), 0, s, img, pitchI, mask, pitchM, H, W, dst,
+                       pitchD, cov, pitchC);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_or(uint8_t *cov, int pitchC, const uint8_t *mask, int pitchM, int H, int W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mask_or, dim3(ceil_div(W, 256), H), dim3(256), 0, s, cov, pitchC, mask, pitchM, W);
     return hipGetLastError();
 }
 

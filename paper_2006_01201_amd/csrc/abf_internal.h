@@ -174,6 +174,9 @@ hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, 
 hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int32_t *d1, int32_t *d2, int pitchD,
                               hipStream_t s);
 hipError_t launch_composite(const CompositeArgs &o, BlendParams bp, hipStream_t s);
+hipError_t launch_photo_init(const uint8_t *img, int pitchI, const uint8_t *mask, int pitchM, int H, int W,
+                             uint8_t *dst, int pitchD, uint8_t *cov, int pitchC, hipStream_t s);
+hipError_t launch_mask_or(uint8_t *cov, int pitchC, const uint8_t *mask, int pitchM, int H, int W, hipStream_t s);
 
 // tiles of one strip for a stage (both directions where the stage has two)
 // luma and exposure: 4 pixels per thread over the padded rows

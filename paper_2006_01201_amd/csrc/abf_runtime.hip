@@ -968,6 +968,124 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
     return ABF_OK;
 }
 
+// ------------------------------------------------------ photo merging
+// Workspace of a merge: [head][flow path's data region, or the canvas
+// passes' scratch, whichever is larger][FlowLtoR][FlowRtoL][box]. The
+// flows of a step must survive the canvas passes that follow them.
+static size_t merge_tail(const abf_plan *plan, int H, int W)
+{
+    const size_t a = data_bound(plan), b = canvas_scratch(H, W);
+    return plan->hdr_cap + align_up(a > b ? a : b, kAlign);
+}
+static size_t merge_flow_bytes(const abf_plan *plan)
+{
+    return align_up(2 * sizeof(float) * (size_t)plan->max_pixels, kAlign);
+}
+
+size_t abf_merge_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W)
+{
+    if (!plan || H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim) return 0;
+    return merge_tail(plan, H, W) + 2 * merge_flow_bytes(plan) + kAlign;
+}
+
+abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, int32_t H, int32_t W,
+                            int32_t pitch_mask, uint8_t *canvas, int32_t pitch_canvas, uint8_t *spare,
+                            int32_t pitch_spare, uint8_t *coverage, int32_t *boxes, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!photos || n < 1 || !canvas || !spare || !coverage) return fail(plan, ABF_E_INVALID, "null pointer or no photo");
+    if (H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim)
+        return fail(plan, ABF_E_SHAPE, "canvas %d x %d (1..%d per side)", H, W, kCanvasMaxDim);
+    if (pitch_mask < W || pitch_canvas < 3 * W || pitch_spare < 3 * W)
+        return fail(plan, ABF_E_SHAPE, "pitch below the canvas width");
+    for (int i = 0; i < n; i++) {
+        const abf_photo &p = photos[i];
+        if (!p.image || !p.mask) return fail(plan, ABF_E_INVALID, "photo %d: null pointer", i);
+        if (p.pitch < 3 * W) return fail(plan, ABF_E_SHAPE, "photo %d: pitch smaller than 3 W", i);
+        if ((p.axis != 0 && p.axis != 1) || (p.side != 0 && p.side != 1))
+            return fail(plan, ABF_E_INVALID, "photo %d: axis %d, side %d", i, p.axis, p.side);
+    }
+    if (!plan->ws) return fail(plan, ABF_E_WORKSPACE, "no workspace bound");
+    const size_t need = abf_merge_workspace_bytes(plan, H, W);
+    if (plan->ws_bytes < need)
+        return fail(plan, ABF_E_WORKSPACE, "a %d x %d merge needs %zu workspace bytes, %zu bound", H, W, need,
+                    plan->ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    uint8_t *tail = plan->ws + merge_tail(plan, H, W);
+    float *flr = reinterpret_cast<float *>(tail);
+    float *frl = reinterpret_cast<float *>(tail + merge_flow_bytes(plan));
+    int32_t *dbox = reinterpret_cast<int32_t *>(tail + 2 * merge_flow_bytes(plan));
+    uint8_t *buf[2] = {canvas, spare};
+    const int32_t pitch[2] = {pitch_canvas, pitch_spare};
+    // the buffer that holds the canvas merged so far; chosen so that the
+    // last step writes `canvas`
+    int cur = (n - 1) % 2 == 0 ? 0 : 1;
+    HIP_TRY(plan, launch_photo_init(photos[0].image, photos[0].pitch, photos[0].mask, pitch_mask, H, W, buf[cur],
+                                    pitch[cur], coverage, pitch_mask, s));
+    if (boxes) boxes[0] = boxes[1] = boxes[2] = boxes[3] = 0;
+    BlendParams bp{plan->p.k_sharp, plan->p.k_flowmag, plan->p.blend_mode};
+    for (int i = 1; i < n; i++) {
+        const abf_photo &p = photos[i];
+        // L / R of this pairwise blend: the merged canvas and the photo
+        const uint8_t *L = p.side == 0 ? buf[cur] : p.image, *R = p.side == 0 ? p.image : buf[cur];
+        const int32_t pL = p.side == 0 ? pitch[cur] : p.pitch, pR = p.side == 0 ? p.pitch : pitch[cur];
+        const uint8_t *mL = p.side == 0 ? coverage : p.mask, *mR = p.side == 0 ? p.mask : coverage;
+        // the overlap box decides the size of the flow computation: read back
+        HIP_TRY(plan, launch_overlap_box(mL, mR, pitch_mask, H, W, reinterpret_cast<int32_t *>(plan->ws + plan->hdr_cap),
+                                         dbox, s));
+        int32_t hb[4];
+        HIP_TRY(plan, hipMemcpyAsync(hb, dbox, sizeof(hb), hipMemcpyDeviceToHost, s));
+        HIP_TRY(plan, hipStreamSynchronize(s));
+        if (boxes) memcpy(boxes + 4 * i, hb, sizeof(hb));
+        const bool any = hb[2] > 0 && hb[3] > 0;
+        if (any) {
+            abf_strip st{};
+            st.L = L + (size_t)hb[1] * pL + 3 * (size_t)hb[0];
+            st.R = R + (size_t)hb[1] * pR + 3 * (size_t)hb[0];
+            st.H = hb[3];
+            st.W = hb[2];
+            st.pitch_L = pL;
+            st.pitch_R = pR;
+            st.axis = p.axis;
+            st.flow_LtoR = flr;
+            st.flow_RtoL = frl;
+            abf_status rc = run(plan, &st, 1, true, false, false, s);
+            if (rc != ABF_OK) return rc;
+        }
+        CanvasGeom g{};
+        float *bmap = nullptr;
+        abf_status rc = canvas_setup(plan, mL, mR, H, W, pitch_mask, g, &bmap);
+        if (rc != ABF_OK) return rc;
+        if (any) HIP_TRY(plan, launch_canvas_dist(g, bmap, g.gpitch, nullptr, nullptr, 0, s));
+        CompositeArgs o{};
+        o.L = L;
+        o.R = R;
+        o.mL = mL;
+        o.mR = mR;
+        o.blend = bmap;
+        o.pitchB = g.gpitch;
+        o.flr = flr;
+        o.frl = frl;
+        o.F = buf[cur ^ 1];
+        o.pitchL = pL;
+        o.pitchR = pR;
+        o.pitchM = pitch_mask;
+        o.pitchF = pitch[cur ^ 1];
+        o.H = H;
+        o.W = W;
+        o.bx = any ? hb[0] : 0;
+        o.by = any ? hb[1] : 0;
+        o.bw = any ? hb[2] : 0;
+        o.bh = any ? hb[3] : 0;
+        o.axis = p.axis;
+        o.inv_ext = any ? 1.0 / (double)(p.axis == 0 ? hb[2] : hb[3]) : 0.0;
+        HIP_TRY(plan, launch_composite(o, bp, s));
+        HIP_TRY(plan, launch_mask_or(coverage, pitch_mask, p.mask, pitch_mask, H, W, s));
+        cur ^= 1;
+    }
+    return ABF_OK;
+}
+
 abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H, int32_t W,
                       float lambda, float eps, float *E_dev, float *g_u, float *g_Ref, float *g_Tgt,
                       int32_t deterministic, void *hip_stream)

@@ -457,6 +457,75 @@ def random_masks(seed: int, H: int, W: int, blobs: int = 6, p_empty: float = 0.0
     return out[0], out[1]
 
 
+def panorama_masks(rng, H: int, W: int, n_ring: int, top: bool = True):
+    """Coverage of a photo set on a panorama canvas: n_ring photos side by
+    side (seams running top to bottom, overlaps U[480, 960] x W / 9000
+    wide, slanted and bowed edges) reaching from ~0.15 H (bowed) to the
+    bottom, and, if ``top``, one photo over the full width from the top to
+    ~0.3 H (bowed): its seam with the ring is a band of ~0.15 H."""
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    seams = [(k + 1) * W / n_ring for k in range(n_ring - 1)]
+    ov = rng.uniform(480.0, 960.0, len(seams)) * W / 9000.0
+    lefts, rights = [np.zeros(H) - 1.0], []
+    for x, o in zip(seams, ov):
+        slope = rng.uniform(-0.02, 0.02) * W / max(H, 1) / n_ring
+        rights.append(_edge(rng, H, x + o / 2, slope, rng.uniform(-0.1, 0.1) * o))
+        lefts.append(_edge(rng, H, x - o / 2, slope, rng.uniform(-0.1, 0.1) * o))
+    rights.append(np.zeros(H) + W)
+    ring_top = _edge(rng, W, 0.15 * H, 0.0, rng.uniform(-0.02, 0.02) * H)
+    masks = [((xx > lo[:, None]) & (xx < hi[:, None]) & (yy >= ring_top[None, :])).astype(np.uint8)
+             for lo, hi in zip(lefts, rights)]
+    if top:
+        bottom = _edge(rng, W, 0.30 * H, 0.0, rng.uniform(-0.02, 0.02) * H)
+        masks.append((yy <= bottom[None, :]).astype(np.uint8))
+    return masks
+
+
+def make_panorama_photos(seed: int, H: int, W: int, n_ring: int = 6, top: bool = True, max_ux: float = 6.0,
+                         max_uy: float = 2.0, noise: float = 2.0, device=None):
+    """A photo set placed on one H x W canvas (seed slot cfg = 120): one
+    scene texture seen by every photo through its own smooth residual
+    misalignment (|u| <= max_ux, max_uy px), exposure gain U[0.95, 1.05]
+    and sensor noise, zero outside the photo's coverage. Returns a list of
+    (image H x W x 3 uint8, mask H x W uint8, axis, side) in merge order:
+    the ring left to right (axis 0, side 0), then the top photo (axis 1,
+    side 1). Arrays are numpy, or torch tensors on ``device`` (evaluated
+    there)."""
+    rng = rng_for(120, seed, 0)
+    masks = panorama_masks(rng, H, W, n_ring, top)
+    tex = Texture(rng, H, W)
+    sigma = max(8.0, 0.05 * min(H, W))
+    out = []
+    for i, m in enumerate(masks):
+        gain = float(rng.uniform(0.95, 1.05))
+        if device is None:
+            ux = smooth_field(rng, H, W, sigma, max_ux)
+            uy = smooth_field(rng, H, W, sigma, max_uy)
+            yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+            f = gain * tex(xx + ux, yy + uy)
+            if noise:
+                f = f + rng.normal(0.0, noise, f.shape)
+            img = _quantise(f) * m[..., None]
+        else:
+            import torch
+
+            ux = _smooth_field_torch(rng, H, W, sigma, max_ux, device)
+            uy = _smooth_field_torch(rng, H, W, sigma, max_uy, device)
+            gen = torch.Generator(device=device)
+            gen.manual_seed(int(rng.integers(0, 2 ** 62)))
+            yy, xx = torch.meshgrid(torch.arange(H, device=device, dtype=torch.float64),
+                                    torch.arange(W, device=device, dtype=torch.float64), indexing="ij")
+            f = gain * _texture_torch(tex, xx + ux, yy + uy)
+            if noise:
+                f += noise * torch.randn(f.shape, generator=gen, device=device)
+            mt = torch.from_numpy(m).to(device)
+            img = f.round_().clamp_(0, 255).to(torch.uint8) * mt[..., None]
+            m = mt
+        last_top = top and i == len(masks) - 1
+        out.append((img, m, 1 if last_top else 0, 1 if last_top else 0))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Device-side evaluation for large streams (the 32-panorama workload): the
 # recipe of ``make_config_strip`` with the per-pixel work (texture,

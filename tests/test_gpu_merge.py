@@ -1,0 +1,108 @@
+"""Repeated pairwise merging of a photo set (ring left to right, then the
+top photo) on the GPU: the native scheduler equals the same steps issued
+one call at a time, bit for bit, and every step matches the oracle's
+canvas composite given that step's inputs and flows (0.5/255), with the
+overlap boxes and the coverage exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_01201_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 0.5 / 255.0
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_01201_amd import api as _api
+
+    return _api
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _photos(seed, H, W, n_ring):
+    return [(dev(i), dev(m), ax, sd) for i, m, ax, sd in synth.make_panorama_photos(seed, H, W, n_ring=n_ring)]
+
+
+def _stepwise(plan, photos):
+    """The merge issued call by call: returns the states after every step
+    and the flows of every step."""
+    img0, m0 = photos[0][0], photos[0][1]
+    acc = img0 * (m0 > 0)[..., None]
+    cov = (m0 > 0).to(torch.uint8)
+    states, flows, boxes = [(acc.clone(), cov.clone())], [None], [(0, 0, 0, 0)]
+    for img, m, axis, side in photos[1:]:
+        L, R, mL, mR = (acc, img, cov, m) if side == 0 else (img, acc, m, cov)
+        box = plan.overlap_box(mL, mR)
+        bx, by, bw, bh = box
+        flr = frl = None
+        if bw > 0 and bh > 0:
+            flr, frl = plan.flow_bidirectional(L[by:by + bh, bx:bx + bw], R[by:by + bh, bx:bx + bw])
+        acc = plan.composite_canvas(L, R, mL, mR, flr, frl, box, axis=axis)
+        cov = torch.maximum(cov, (m > 0).to(torch.uint8))
+        states.append((acc.clone(), cov.clone()))
+        flows.append((flr, frl))
+        boxes.append(box)
+    torch.cuda.synchronize()
+    return states, flows, boxes
+
+
+@pytest.mark.parametrize("n_ring", [2, 3])
+def test_merge_equals_stepwise_calls(api, n_ring):
+    H, W = 160, 120 * n_ring
+    photos = _photos(n_ring, H, W, n_ring)
+    plan = api.Plan(api.Params(levels=3), max_strips=1, max_H=H, max_W=W, canvas=(H, W))
+    print(f"[gpu] merge {n_ring} ring photos + top, {H}x{W}", flush=True)
+    canvas, cov, boxes = plan.merge_photos(photos)
+    torch.cuda.synchronize()
+    states, _, sboxes = _stepwise(plan, photos)
+    assert boxes == sboxes
+    assert torch.equal(canvas, states[-1][0])
+    assert torch.equal(cov, states[-1][1])
+    assert int(cov.min()) == 1  # the set covers the canvas
+
+
+def test_merge_steps_match_oracle(api):
+    H, W, n_ring = 150, 330, 3
+    photos_np = synth.make_panorama_photos(7, H, W, n_ring=n_ring)
+    photos = [(dev(i), dev(m), ax, sd) for i, m, ax, sd in photos_np]
+    p = api.Params(levels=3)
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, canvas=(H, W))
+    print("[gpu] merge steps vs oracle", flush=True)
+    states, flows, boxes = _stepwise(plan, photos)
+    op = oracle.Params(levels=3)
+    cov = photos_np[0][1].copy()
+    for i in range(1, len(photos)):
+        acc = states[i - 1][0].cpu().numpy()
+        img, m, axis, side = photos_np[i]
+        L, R, mL, mR = (acc, img, cov, m) if side == 0 else (img, acc, m, cov)
+        box = oracle.overlap_box(mL, mR)
+        assert box == boxes[i]
+        bx, by, bw, bh = box
+        flr, frl = (f.cpu().numpy() for f in flows[i])
+        o_lr, o_rl = oracle.flow_bidirectional(L[by:by + bh, bx:bx + bw], R[by:by + bh, bx:bx + bw], op)
+        assert np.abs(flr - o_lr).max() <= 1e-2 and np.abs(frl - o_rl).max() <= 1e-2
+        oF, _ = oracle.composite(L, R, mL, mR, flr, frl, box, axis=axis, params=op)
+        F8 = states[i][0].cpu().numpy()
+        o8 = np.clip(np.floor(oF + 0.5), 0, 255).astype(np.uint8)
+        safe = np.abs(oF - np.floor(oF) - 0.5) > F_TOL
+        assert np.array_equal(F8[safe], o8[safe]), i
+        assert np.abs(F8.astype(int) - o8.astype(int)).max() <= 1
+        cov = np.maximum(cov, (m > 0).astype(np.uint8))
+        assert np.array_equal(states[i][1].cpu().numpy(), cov)
+
+
+def test_merge_box_beyond_plan_limits(api):
+    H, W = 120, 240
+    photos = _photos(3, H, W, 2)
+    plan = api.Plan(api.Params(levels=3), max_strips=1, max_H=16, max_W=16, canvas=(H, W))
+    with pytest.raises(ValueError):
+        plan.merge_photos(photos)
