@@ -182,6 +182,42 @@ def run_canvas(p, timed, log, steps):
             "areas_none_1_2_3": counts, "roofline": roof}
 
 
+def run_merge(p, log, reps):
+    """Repeated pairwise merging of one photo set on a 4000 x 9000 canvas:
+    6 ring photos left to right, then the top photo (7 photos, 6 seams of
+    the ring with overlaps U[480, 960] px and a ~600-row top band), images
+    generated on the GPU. One step = one whole merge (abf_merge_photos,
+    which reads every overlap box back to size the flows)."""
+    import torch
+
+    from paper_2006_01201_amd import api, synth
+
+    t0 = time.time()
+    H, W = 4000, 9000
+    photos = synth.make_panorama_photos(0, H, W, n_ring=6, device="cuda")
+    torch.cuda.synchronize()
+    log(f"merge: 7 photos on {H} x {W} generated in {time.time() - t0:.1f} s")
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, max_pixels=8 << 20, canvas=(H, W))
+    out = torch.empty((H, W, 3), dtype=torch.uint8, device="cuda")
+    _, _, boxes = plan.merge_photos(photos, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(reps):
+        plan.merge_photos(photos, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) * 1e3 / reps
+    ms = e0.elapsed_time(e1) / reps
+    log(f"merge: {ms:.3f} ms per panorama (wall {wall:.3f})")
+    return {"workload": f"{H} x {W} canvas, 7 photos (6 ring left to right + top), overlap boxes "
+                        f"{[list(b) for b in boxes[1:]]}, each step box + flows + eq. (1) + Code 1 over the canvas",
+            "ms_per_panorama": round(ms, 3), "wall_ms_per_panorama": round(wall, 3),
+            "canvas_mpix_s": round(H * W / ms / 1e3, 1)}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_01201_amd", "csrc", "abf_kernels.hip")
 
@@ -227,6 +263,7 @@ def main():
     ap.add_argument("--refine", action="store_true",
                     help="also time 50 gradient-descent refinement steps on the 2048 x 512 float strip")
     ap.add_argument("--no-canvas", action="store_true", help="skip the canvas-compositing leg")
+    ap.add_argument("--no-merge", action="store_true", help="skip the photo-set merging leg")
     ap.add_argument("--stream", type=int, default=0, metavar="PANORAMAS",
                     help="also time a stream of this many panoramas of the cfg4 workload (7 strips of drawn "
                          "sizes each; flow + blend batched per 4 panoramas, then 20 batched refinement steps)")
@@ -351,6 +388,7 @@ def main():
         log(f"refine 50 steps: {ms_r:.3f} ms")
 
     canvas = None if args.no_canvas else run_canvas(p, timed, log, args.steps)
+    merge = None if args.no_merge else run_merge(p, log, max(2, args.steps // 4))
 
     stream = None
     if args.stream:
@@ -406,6 +444,7 @@ def main():
         "roofline": roofline,
         "refine_flow": refine,
         "canvas": canvas,
+        "merge": merge,
         "stream": stream,
         "cpu_baseline": cpu,
     }
