@@ -86,6 +86,10 @@ def _load():
                                  c_double, f64p]),
         "orc_blend_grad": (None, [f64p, f64p, f64p, f64p, f64p, c_int, c_int, c_int, c_double, c_double,
                                   c_int, f64p, f64p, f64p, f64p, f64p]),
+        "orc_lk_level": (None, [u8p, u8p, c_int, c_int, f64p, c_int, c_int, c_double, f64p]),
+        "orc_flow_lk": (None, [u8p, u8p, c_int, c_int, c_int, c_int, c_int, c_double, f64p]),
+        "orc_flow_lk_bidirectional": (None, [u8p, u8p, c_int, c_int, c_long, c_long, c_int, c_int, c_int, c_double,
+                                             c_int, f64p, f64p]),
         "orc_canvas_dist2": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
         "orc_canvas_blend": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, f64p]),
         "orc_overlap_box": (None, [u8p, u8p, c_long, c_int, c_int, i32p]),
@@ -362,3 +366,46 @@ def composite(L, R, mask_L, mask_R, flow_lr, flow_rl, box, axis: int = 0, blend=
                           _p(frl, f64p), _p(bx, i32p), axis, _p(b, f64p), params.k_sharp, params.k_flowmag,
                           params.blend_mode, _p(F, f64p), _p(F8, u8p))
     return F, F8
+
+
+# ---------------------------------------------------------------------------
+# Classic coarse-to-fine Lucas-Kanade (float flows at every level)
+
+
+def lk_level(A, B, seed=None, P: int = 2, K: int = 4, eps: float = 25.0):
+    """One pyramid level of the classic method: K Gauss-Newton steps from
+    ``seed`` (H x W x 2, None = 0)."""
+    A, B = _u8(A), _u8(B)
+    H, W = A.shape
+    sd = None if seed is None else _f64(seed)
+    u = np.empty((H, W, 2), np.float64)
+    _load().orc_lk_level(_p(A, u8p), _p(B, u8p), H, W, _p(sd, f64p), P, K, eps, _p(u, f64p))
+    return u
+
+
+def flow_lk(yref, ytgt, N: int, P: int = 2, K: int = 4, eps: float = 25.0):
+    """One direction over the pyramid; returns every level's flow, level 0
+    first."""
+    yref, ytgt = _u8(yref), _u8(ytgt)
+    H, W = yref.shape
+    sizes = level_sizes(H, W, N)
+    tot = sum(h * w for h, w in sizes)
+    f = np.empty(tot * 2, np.float64)
+    _load().orc_flow_lk(_p(yref, u8p), _p(ytgt, u8p), H, W, N, P, K, eps, _p(f, f64p))
+    return _split_levels(f, sizes)
+
+
+def flow_lk_bidirectional(L, R, params: Params = Params(), K: int | None = None):
+    """Both flows of a strip with the classic method (K = params.lk_iters
+    Gauss-Newton steps per level). Returns (levels_lr, levels_rl), each a
+    list of H_k x W_k x 2 float64 flows, level 0 first."""
+    L, R = _u8(L), _u8(R)
+    H, W, _ = L.shape
+    N = params.levels
+    K = params.lk_iters if K is None else K
+    sizes = level_sizes(H, W, N)
+    tot = sum(h * w for h, w in sizes)
+    a, b = np.empty(tot * 2, np.float64), np.empty(tot * 2, np.float64)
+    _load().orc_flow_lk_bidirectional(_p(L, u8p), _p(R, u8p), H, W, W * 3, W * 3, N, params.lk_patch, K,
+                                      params.lk_eps, params.gain_comp, _p(a, f64p), _p(b, f64p))
+    return _split_levels(a, sizes), _split_levels(b, sizes)

@@ -366,6 +366,124 @@ void orc_refine(const uint8_t *A, const uint8_t *B, int H, int W, const int32_t 
         }
 }
 
+/* ------------------------------------------------------------------ */
+/* Classic coarse-to-fine Lucas-Kanade (the "LK pyramid" of III.C.1, as an
+ * alternative to the integer search): float flows at every level. */
+
+/* One level: A = Ref, B = Tgt intensity (H x W). The flow of every pixel
+ * starts at seed (H x W x 2; NULL = 0) and takes K Gauss-Newton steps
+ * u <- u - (sum g g^T + eps I)^-1 sum g (B~(q + u) - A(q)) over the
+ * (2P+1)^2 window, g the central-difference gradient of A, B~ bilinear
+ * with clamped indices; no clamp on u. */
+void orc_lk_level(const uint8_t *A, const uint8_t *B, int H, int W, const double *seed, int P, int K, double eps,
+                  double *u_out)
+{
+#pragma omp parallel for
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            long p = (long)y * W + x;
+            double hxx = eps, hxy = 0, hyy = eps;
+            for (int j = -P; j <= P; j++)
+                for (int i = -P; i <= P; i++) {
+                    int qy = clampi(y + j, 0, H - 1), qx = clampi(x + i, 0, W - 1);
+                    double gx = 0.5 * ((double)A[(long)qy * W + clampi(qx + 1, 0, W - 1)] -
+                                       (double)A[(long)qy * W + clampi(qx - 1, 0, W - 1)]);
+                    double gy = 0.5 * ((double)A[(long)clampi(qy + 1, 0, H - 1) * W + qx] -
+                                       (double)A[(long)clampi(qy - 1, 0, H - 1) * W + qx]);
+                    hxx += gx * gx;
+                    hxy += gx * gy;
+                    hyy += gy * gy;
+                }
+            double det = hxx * hyy - hxy * hxy;
+            double ux = seed ? seed[2 * p] : 0.0, uy = seed ? seed[2 * p + 1] : 0.0;
+            for (int it = 0; it < K; it++) {
+                double fux = floor(ux), fuy = floor(uy);
+                double fx = ux - fux, fy = uy - fuy;
+                double bx = 0, by = 0;
+                for (int j = -P; j <= P; j++)
+                    for (int i = -P; i <= P; i++) {
+                        int qy = clampi(y + j, 0, H - 1), qx = clampi(x + i, 0, W - 1);
+                        double gx = 0.5 * ((double)A[(long)qy * W + clampi(qx + 1, 0, W - 1)] -
+                                           (double)A[(long)qy * W + clampi(qx - 1, 0, W - 1)]);
+                        double gy = 0.5 * ((double)A[(long)clampi(qy + 1, 0, H - 1) * W + qx] -
+                                           (double)A[(long)clampi(qy - 1, 0, H - 1) * W + qx]);
+                        double e = bilin1(B, H, W, qx + (int)fux, qy + (int)fuy, fx, fy) -
+                                   (double)A[(long)qy * W + qx];
+                        bx += gx * e;
+                        by += gy * e;
+                    }
+                ux -= (hyy * bx - hxy * by) / det;
+                uy -= (hxx * by - hxy * bx) / det;
+            }
+            u_out[2 * p] = ux;
+            u_out[2 * p + 1] = uy;
+        }
+}
+
+/* One direction over the pyramid: level N-1 from 0, every finer level k
+ * from 2 u_{k+1}(floor(x/2), floor(y/2)) (clamped to the coarser size).
+ * Writes every level's flow (concatenated, level 0 first, 2 doubles per
+ * pixel) to flow_all. */
+void orc_flow_lk(const uint8_t *yref, const uint8_t *ytgt, int H, int W, int N, int P, int K, double eps,
+                 double *flow_all)
+{
+    int32_t hs[32], ws[32];
+    long off[33] = {0};
+    orc_level_sizes(H, W, N, hs, ws);
+    for (int k = 0; k < N; k++) off[k + 1] = off[k] + (long)hs[k] * ws[k];
+    uint8_t **pr = (uint8_t **)calloc(N, sizeof(uint8_t *));
+    uint8_t **pt = (uint8_t **)calloc(N, sizeof(uint8_t *));
+    pr[0] = (uint8_t *)malloc(off[1]);
+    pt[0] = (uint8_t *)malloc(off[1]);
+    memcpy(pr[0], yref, off[1]);
+    memcpy(pt[0], ytgt, off[1]);
+    for (int k = 1; k < N; k++) {
+        pr[k] = (uint8_t *)malloc(off[k + 1] - off[k]);
+        pt[k] = (uint8_t *)malloc(off[k + 1] - off[k]);
+        orc_pyr_down(pr[k - 1], hs[k - 1], ws[k - 1], pr[k]);
+        orc_pyr_down(pt[k - 1], hs[k - 1], ws[k - 1], pt[k]);
+    }
+    double *seed = (double *)malloc(sizeof(double) * 2 * off[1]);
+    for (int k = N - 1; k >= 0; k--) {
+        const double *sd = NULL;
+        if (k < N - 1) {
+            const double *c = flow_all + 2 * off[k + 1];
+            for (int y = 0; y < hs[k]; y++)
+                for (int x = 0; x < ws[k]; x++) {
+                    long q = (long)clampi(y / 2, 0, hs[k + 1] - 1) * ws[k + 1] + clampi(x / 2, 0, ws[k + 1] - 1);
+                    seed[2 * ((long)y * ws[k] + x)] = 2.0 * c[2 * q];
+                    seed[2 * ((long)y * ws[k] + x) + 1] = 2.0 * c[2 * q + 1];
+                }
+            sd = seed;
+        }
+        orc_lk_level(pr[k], pt[k], hs[k], ws[k], sd, P, K, eps, flow_all + 2 * off[k]);
+    }
+    for (int k = 0; k < N; k++) {
+        free(pr[k]);
+        free(pt[k]);
+    }
+    free(pr);
+    free(pt);
+    free(seed);
+}
+
+/* Both flows of one strip with the classic method (luma and exposure step
+ * as in the integer chain). flow_all_lr / flow_all_rl: every level, as in
+ * orc_flow_lk (level 0 first). */
+void orc_flow_lk_bidirectional(const uint8_t *L, const uint8_t *R, int H, int W, long pitchL, long pitchR, int N,
+                               int P, int K, double eps, int gain, double *flow_all_lr, double *flow_all_rl)
+{
+    long n = (long)H * W;
+    uint8_t *yl = (uint8_t *)malloc(n), *yr = (uint8_t *)malloc(n);
+    orc_luma(L, H, W, pitchL, yl);
+    orc_luma(R, H, W, pitchR, yr);
+    if (gain) orc_gain_comp(yl, yr, n);
+    orc_flow_lk(yl, yr, H, W, N, P, K, eps, flow_all_lr);
+    orc_flow_lk(yr, yl, H, W, N, P, K, eps, flow_all_rl);
+    free(yl);
+    free(yr);
+}
+
 /* Both flows of one strip (Section III.C.1). FlowLtoR: Ref = L, Tgt = R.
  * FlowRtoL: Ref = R, Tgt = L; with `gain`, R's intensity is compensated
  * first (step 1b) and both directions use it. Optional integer outputs: per-level search
