@@ -73,6 +73,12 @@ typedef struct abf_params {
                               strips' intensity sums (16-bit fixed point: a = floor(2^16 sum(YL) /
                               sum(YR)), YR' = min(255, (YR a + 2^15) >> 16)) to remove a residual
                               exposure gain left by pre-processing (Section III.B); 0: off */
+    int32_t flow_method;   /* 0: integer patch search, propagation and median per level, then the
+                              level-0 Lucas-Kanade refinement (the default); 1: the classic
+                              coarse-to-fine Lucas-Kanade of Section III.C.1: at every level a
+                              float flow from twice the coarser level's flow at (x/2, y/2) takes
+                              lk_iters unclamped Gauss-Newton steps over the lk_patch window
+                              (patch, radius, radius_coarse, prop_steps and median unused) */
 } abf_params;
 
 typedef struct abf_plan abf_plan;
@@ -160,6 +166,8 @@ const char *abf_last_error(const abf_plan *plan);
  *   kind 0: luma of the Ref image of `dir` at `level`, uint8, row pitch *pitch bytes;
  *   kind 1: raw search result, int16 pairs (x, y), row pitch *pitch pairs;
  *   kind 2: final flow of the level (after propagation and median), same layout.
+ * With flow_method 1, kinds 1 and 2 of a level >= 1 hold the x and y
+ * components of the level's flow as float64 (*pitch entries per row).
  * *H and *W receive the level size. */
 abf_status abf_workspace_view(const abf_plan *plan, int32_t kind, int32_t strip, int32_t level,
                               int32_t dir, void **dev_ptr, int32_t *H, int32_t *W, int32_t *pitch);

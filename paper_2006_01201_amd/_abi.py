@@ -22,7 +22,7 @@ class AbfParams(ctypes.Structure):
         ("levels", c_i32), ("patch", c_i32), ("radius", c_i32), ("radius_coarse", c_i32),
         ("prop_steps", c_i32), ("median", c_i32), ("lk_patch", c_i32), ("lk_iters", c_i32),
         ("lk_eps", c_f32), ("k_sharp", c_f32), ("k_flowmag", c_f32), ("blend_mode", c_i32),
-        ("gain_comp", c_i32),
+        ("gain_comp", c_i32), ("flow_method", c_i32),
     ]
 
 

@@ -34,6 +34,7 @@ class Params:
     k_flowmag: float = 20.0
     blend_mode: int = 0
     gain_comp: int = 1
+    flow_method: int = 0  # 0: integer search + refinement; 1: classic coarse-to-fine Lucas-Kanade
 
     def to_c(self) -> _abi.AbfParams:
         p = _abi.AbfParams()
@@ -370,6 +371,17 @@ class Plan:
                                       spare.stride(0), cov.data_ptr(), _stream())
         _abi.check(st, self.h, "abf_merge_photos")
         return canvas, cov, boxes
+
+    def lk_level_flow(self, strip: int, level: int, direction: int) -> torch.Tensor:
+        """Flow method 1: the float64 flow (H x W x 2) of pyramid level
+        ``level`` >= 1 of the last flow call (its x and y planes)."""
+        comps = []
+        for kind in (1, 2):
+            st, ptr, H, W, pitch = _abi.workspace_view(self.h, kind, strip, level, direction)
+            _abi.check(st, self.h, "abf_workspace_view")
+            off = ptr - self._ws.data_ptr()
+            comps.append(self._ws[off:off + H * pitch * 8].view(torch.float64).view(H, pitch)[:, :W])
+        return torch.stack(comps, dim=-1).clone()
 
     def view(self, kind: int, strip: int, level: int, direction: int) -> torch.Tensor:
         """A copy of one intermediate of the last flow call: kind 0 luma

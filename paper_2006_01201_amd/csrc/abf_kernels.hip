@@ -1211,6 +1211,102 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
     }
 }
 
+// ------------------------------------------------ classic pyramid LK
+// The classic coarse-to-fine Lucas-Kanade (flow method 1): at every level
+// a float flow starts from twice the coarser level's flow at
+// (floor(x/2), floor(y/2)) (0 at the coarsest) and takes K Gauss-Newton
+// steps with the window's normal matrix + eps I, the central-difference
+// gradient of Ref and a bilinear Tgt (clamped indices), unclamped. The
+// arithmetic is double (the window sums of gradient products are exact;
+// the residuals and the solve follow the textbook form), so that levels
+// feed each other the same values as an FP64 reference up to rounding
+// order. Levels above 0 keep their flow as float64 x / y planes in the
+// level's ds / df buffers (allocated with 8-byte entries for this method);
+// level 0 writes the caller's float32 flow. Tiles are
+// those of the search (kSearchTW x th pixels per direction); a thread
+// takes pixels x and x + 1.
+template <int P>
+__global__ __launch_bounds__(512) void k_lk_level(const StripLv *__restrict__ lv, const StripLv *__restrict__ lvc,
+                                                  const StripIO *__restrict__ io, const int32_t *__restrict__ prefix,
+                                                  int n, int total, int th, int K, double eps, bool level0)
+{
+    constexpr int WN = 2 * P + 1;
+    const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
+    TILE_LOOP(total)
+    {
+        const int s = find_strip(prefix, n, t);
+        int local = t - prefix[s];
+        const StripLv &L = lv[s];
+        const int H = L.H, W = L.W, yp = L.ypitch;
+        const int ntx = ceil_div(W, kSearchTW), per_dir = ntx * ceil_div(H, th);
+        const int dir = local / per_dir;
+        local -= dir * per_dir;
+        const int tyi = local / ntx;
+        const int xa = (local - tyi * ntx) * kSearchTW + 2 * lane, y = tyi * th + wrow;
+        if (y >= H || wrow >= th) continue;  // no barrier in this kernel
+        const auto A = gld(L.y[dir]), B = gld(L.y[1 - dir]);
+        for (int e = 0; e < 2; e++) {
+            const int x = xa + e;
+            if (x >= W) break;
+            double ux = 0.0, uy = 0.0;
+            if (lvc) {
+                const StripLv &C = lvc[s];
+                const size_t q = (size_t)min(y >> 1, C.H - 1) * C.fpitch + min(x >> 1, C.W - 1);
+                ux = 2.0 * gld(reinterpret_cast<const double *>(C.ds[dir]))[q];
+                uy = 2.0 * gld(reinterpret_cast<const double *>(C.df[dir]))[q];
+            }
+            // gradients of the window (half-integers, exact in float)
+            float gx[WN][WN], gy[WN][WN], a[WN][WN];
+            double hxx = eps, hxy = 0.0, hyy = eps;
+#pragma unroll
+            for (int j = 0; j < WN; j++)
+#pragma unroll
+                for (int i = 0; i < WN; i++) {
+                    const int qy = clampi(y + j - P, 0, H - 1), qx = clampi(x + i - P, 0, W - 1);
+                    const ptrdiff_t o = (ptrdiff_t)qy * yp + qx;
+                    gx[j][i] = 0.5f * ((float)A[o + 1] - (float)A[o - 1]);
+                    gy[j][i] = 0.5f * ((float)A[o + yp] - (float)A[o - yp]);
+                    a[j][i] = (float)A[o];
+                    hxx += (double)gx[j][i] * gx[j][i];
+                    hxy += (double)gx[j][i] * gy[j][i];
+                    hyy += (double)gy[j][i] * gy[j][i];
+                }
+            const double det = hxx * hyy - hxy * hxy;
+            for (int it = 0; it < K; it++) {
+                const double fux = floor(ux), fuy = floor(uy);
+                const double fx = ux - fux, fy = uy - fuy;
+                const int ix = (int)fux, iy = (int)fuy;
+                double bx = 0.0, by = 0.0;
+#pragma unroll
+                for (int j = 0; j < WN; j++) {
+                    const int qy = clampi(y + j - P, 0, H - 1);
+                    const ptrdiff_t ra = (ptrdiff_t)clampi(qy + iy, 0, H - 1) * yp;
+                    const ptrdiff_t rb = (ptrdiff_t)clampi(qy + iy + 1, 0, H - 1) * yp;
+#pragma unroll
+                    for (int i = 0; i < WN; i++) {
+                        const int qx = clampi(x + i - P, 0, W - 1);
+                        const int xa0 = clampi(qx + ix, 0, W - 1), xb0 = clampi(qx + ix + 1, 0, W - 1);
+                        const double v00 = B[ra + xa0], v01 = B[ra + xb0], v10 = B[rb + xa0], v11 = B[rb + xb0];
+                        const double smp = (1.0 - fy) * ((1.0 - fx) * v00 + fx * v01) + fy * ((1.0 - fx) * v10 + fx * v11);
+                        const double r = smp - (double)a[j][i];
+                        bx += (double)gx[j][i] * r;
+                        by += (double)gy[j][i] * r;
+                    }
+                }
+                ux -= (hyy * bx - hxy * by) / det;
+                uy -= (hxx * by - hxy * bx) / det;
+            }
+            if (level0) {
+                const uint64_t v = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
+                gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(size_t)y * W + x] = v;
+            } else {
+                gst(reinterpret_cast<double *>(L.ds[dir]))[(size_t)y * L.fpitch + x] = ux;
+                gst(reinterpret_cast<double *>(L.df[dir]))[(size_t)y * L.fpitch + x] = uy;
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- blend
 // One workgroup per segment of kRowTW pixels of a row. The uint8 output of
 // the segment is staged in LDS at the byte alignment of its destination, so
@@ -1396,6 +1492,18 @@ hipError_t launch_refine_border(const StripLv *lv0, const StripIO *io, Work w, L
     case 3: return refine_border_lp<3>(lv0, io, w, lk, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_lk_level(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk, int th,
+                           int grid, bool level0, hipStream_t s)
+{
+    const dim3 g(grid_for(w.total, grid)), b(64 * th);
+    switch (lk.patch) {
+    case 1: hipLaunchKernelGGL(k_lk_level<1>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, th, lk.iters, (double)lk.eps, level0); break;
+    case 2: hipLaunchKernelGGL(k_lk_level<2>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, th, lk.iters, (double)lk.eps, level0); break;
+    default: hipLaunchKernelGGL(k_lk_level<3>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, th, lk.iters, (double)lk.eps, level0); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s)

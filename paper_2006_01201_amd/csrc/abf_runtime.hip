@@ -138,6 +138,7 @@ abf_status check_params(const abf_params *p)
         return ABF_E_INVALID;
     if (p->blend_mode != 0 && p->blend_mode != 1) return ABF_E_INVALID;
     if (p->gain_comp != 0 && p->gain_comp != 1) return ABF_E_INVALID;
+    if (p->flow_method != 0 && p->flow_method != 1) return ABF_E_INVALID;
     if (p->patch > 2 || p->radius > 4 || p->radius_coarse > 4 || p->prop_steps > 4 || p->median > 1 ||
         p->prop_steps + p->median > 5 || p->lk_patch > 3 || p->lk_iters > 8)
         return ABF_E_UNSUPPORTED;
@@ -175,8 +176,10 @@ size_t data_bound(const abf_plan *pl)
     for (int k = 0; k < N; k++) {
         const double f = std::ldexp(1.0, -k);
         b += 2 * (mp * f * f + S * ((Wm * f) * pd + (64 + pd) * (Hm * f + pd) + 384));
-        // per direction: 2 int16-pair buffers (search, final) and 1 cost buffer
-        b += 2 * 2 * (4 * mp * f * f + S * (4 * Wm * f + 64 * Hm * f + 68 + 256));
+        // per direction: 2 flow buffers (int16 pairs: search, final; or, for
+        // flow method 1, the float64 x and y planes) and 1 cost buffer
+        const double e = pl->p.flow_method == 1 ? 8 : 4;
+        b += 2 * 2 * (e * mp * f * f + S * (e * Wm * f + 16 * e * Hm * f + 17 * e + 256));
         b += 2 * 1 * (2 * mp * f * f + S * (2 * Wm * f + 32 * Hm * f + 34 + 256));
     }
     b += S * align_up(2 * kSumSlots * sizeof(unsigned long long), kAlign);  // exposure sums
@@ -302,7 +305,8 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
                 v.y[d] = pl->ws + off + kPlaneLead + (size_t)v.ypitch * kPad + kPad;
                 off += plane_bytes(v.H, v.W);
             }
-            const size_t fb = align_up((size_t)v.fpitch * 4 * v.H, kAlign);
+            // flow entries: int16 pairs, or float64 components (flow method 1)
+            const size_t fb = align_up((size_t)v.fpitch * (pl->p.flow_method == 1 ? 8 : 4) * v.H, kAlign);
             const size_t cb = align_up((size_t)v.fpitch * 2 * v.H, kAlign);
             for (int d = 0; d < 2; d++) {
                 v.ds[d] = reinterpret_cast<uint32_t *>(pl->ws + off);
@@ -434,7 +438,19 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
             TIMED(ST_LUMA, 1, launch_gain(io, lv, work(ST_LUMA, 0), grid_of(pl, ST_LUMA, b.cls[0]), s));
         for (int k = 1; k < N; k++)
             TIMED(ST_PYR, k, launch_pyr(lv + (size_t)k * n, work(ST_PYR, k), grid_of(pl, ST_PYR, b.cls[k]), s));
-        for (int k = N - 1; k >= 0; k--) {
+        if (p.flow_method == 1) {
+            // classic coarse-to-fine Lucas-Kanade: one launch per level,
+            // timed in the search stage's slots
+            LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
+            for (int k = N - 1; k >= 0; k--) {
+                const int c = b.cls[k];
+                TIMED(ST_SEARCH, k,
+                      launch_lk_level(lv + (size_t)k * n, k == N - 1 ? nullptr : lv + (size_t)(k + 1) * n, io,
+                                      work(ST_SEARCH, k), lk, pl->launch[ST_SEARCH][c].tile_h,
+                                      grid_of(pl, ST_SEARCH, c), k == 0, s));
+            }
+        }
+        for (int k = N - 1; k >= 0 && p.flow_method == 0; k--) {
             const int c = b.cls[k];
             const int r = k == N - 1 ? p.radius_coarse : p.radius;
             TIMED(ST_SEARCH, k,
@@ -444,14 +460,16 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
                   launch_prop(lv + (size_t)k * n, work(ST_PROP, k), p.patch, p.prop_steps, p.median,
                               pl->launch[ST_PROP][c].tile_h, grid_of(pl, ST_PROP, c), s));
         }
-        LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
-        // interior tiles, then the border pixels (a forked stream that ran the
-        // border concurrently made the graph replay slower); the border launch
-        // is timed in the level-1 slot of the stage (refinement runs at level 0)
-        TIMED(ST_REFINE, 0,
-              launch_refine(lv, io, work(ST_REFINE, 0), lk, pl->launch[ST_REFINE][b.cls[0]].tile_h,
-                            grid_of(pl, ST_REFINE, b.cls[0]), s));
-        TIMED(ST_REFINE, 1, launch_refine_border(lv, io, work(LIST_REFINE_BORDER, 0), lk, s));
+        if (p.flow_method == 0) {
+            LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
+            // interior tiles, then the border pixels (a forked stream that ran the
+            // border concurrently made the graph replay slower); the border launch
+            // is timed in the level-1 slot of the stage (refinement runs at level 0)
+            TIMED(ST_REFINE, 0,
+                  launch_refine(lv, io, work(ST_REFINE, 0), lk, pl->launch[ST_REFINE][b.cls[0]].tile_h,
+                                grid_of(pl, ST_REFINE, b.cls[0]), s));
+            TIMED(ST_REFINE, 1, launch_refine_border(lv, io, work(LIST_REFINE_BORDER, 0), lk, s));
+        }
     }
     if (blend) {
         BlendParams bp{p.k_sharp, p.k_flowmag, p.blend_mode};
@@ -548,6 +566,7 @@ void abf_default_params(abf_params *p)
     p->k_flowmag = 20.0f;
     p->blend_mode = 0;
     p->gain_comp = 1;
+    p->flow_method = 0;
 }
 
 const char *abf_status_string(abf_status s)

@@ -98,4 +98,6 @@ def test_strip_struct_layout():
     S = _abi.AbfStrip
     assert S.H.offset == 16 and S.pitch_L.offset == 24 and S.blend.offset == 40
     assert S.F_f32.offset == 80 and ctypes.sizeof(S) == 88
-    assert ctypes.sizeof(_abi.AbfParams) == 52
+    assert ctypes.sizeof(_abi.AbfParams) == 56 and _abi.AbfParams.flow_method.offset == 52
+    P = _abi.AbfPhoto
+    assert P.mask.offset == 8 and P.pitch.offset == 16 and P.side.offset == 24 and ctypes.sizeof(P) == 32

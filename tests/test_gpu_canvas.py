@@ -192,23 +192,32 @@ def test_composite_without_overlap(api):
 
 
 def test_stitch_canvas_end_to_end(api):
-    # box -> both flows on the box crops -> eq. (1) -> Code 1; the composite
-    # is checked against the oracle's given the GPU's flows (the flows
-    # themselves are checked against the oracle's by the flow tests)
+    # box -> both flows on the box crops -> eq. (1) -> Code 1. The flows
+    # are checked against the oracle's; the composite against the oracle's
+    # given the oracle's flows; and stitch_canvas against the GPU's own
+    # composite of its own flows
     c = synth.make_canvas(8, 320, 400, holes=1)
     H, W = c.mask_L.shape
     plan = plan_for(api, H, W, levels=4)
     print("[gpu] stitch_canvas 320x400", flush=True)
-    F8, Ff, box, flr, frl = plan.stitch_canvas(dev(c.L), dev(c.R), dev(c.mask_L), dev(c.mask_R), f32=True)
+    dL, dR, mL, mR = dev(c.L), dev(c.R), dev(c.mask_L), dev(c.mask_R)
+    F8, Ff, box, flr, frl = plan.stitch_canvas(dL, dR, mL, mR, f32=True)
     torch.cuda.synchronize()
-    assert box == oracle.overlap_box(c.mask_L, c.mask_R)
-    bx, by, bw, bh = box
+    obox = oracle.overlap_box(c.mask_L, c.mask_R)
+    assert box == obox
+    bx, by, bw, bh = obox
     of_lr, of_rl = oracle.flow_bidirectional(c.L[by:by + bh, bx:bx + bw], c.R[by:by + bh, bx:bx + bw],
                                              oracle.Params(levels=4))
     assert np.abs(flr.cpu().numpy() - of_lr).max() <= 1e-2
     assert np.abs(frl.cpu().numpy() - of_rl).max() <= 1e-2
-    oF, _ = oracle.composite(c.L, c.R, c.mask_L, c.mask_R, flr.cpu().numpy(), frl.cpu().numpy(), box)
-    _check_F(F8.cpu().numpy(), Ff.cpu().numpy(), oF)
+    G8 = plan.composite_canvas(dL, dR, mL, mR, flr, frl, box)
+    torch.cuda.synchronize()
+    assert torch.equal(F8, G8)
+    f_lr, f_rl = of_lr.astype(np.float32), of_rl.astype(np.float32)
+    O8, Of = plan.composite_canvas(dL, dR, mL, mR, dev(f_lr), dev(f_rl), obox, f32=True)
+    torch.cuda.synchronize()
+    oF, _ = oracle.composite(c.L, c.R, c.mask_L, c.mask_R, f_lr, f_rl, obox)
+    _check_F(O8.cpu().numpy(), Of.cpu().numpy(), oF)
 
 
 def test_canvas_limits_are_enforced(api):
