@@ -182,6 +182,34 @@ def run_canvas(p, timed, log, steps):
             "areas_none_1_2_3": counts, "roofline": roof}
 
 
+def run_lk_pyramid(dev, shapes, total_px, timed, log, steps, iters=4):
+    """The panorama workload with the classic coarse-to-fine Lucas-Kanade
+    (flow method 1, `iters` Gauss-Newton steps per level, double
+    arithmetic) instead of the integer search, batched and replayed from a
+    graph like the reported value, plus its level-0 launch against the FP64
+    vector peak (per window sample and step: bilinear sample 6, residual 1,
+    two products into the sums 4 flops; the normal matrix 6 per sample)."""
+    from paper_2006_01201_amd import api
+
+    p = api.Params(levels=6, flow_method=1, lk_iters=iters)
+    plan = api.Plan(p, max_strips=len(shapes), max_pixels=total_px, max_H=max(h for h, _, _ in shapes),
+                    max_W=max(w for _, w, _ in shapes))
+    batch = plan.make_batch(dev)
+    plan.stitch(batch, use_graph=True)
+    ms, _ = timed(lambda: plan.stitch(batch, use_graph=True), steps)
+    prof = plan.profile(batch, reps=3)
+    l0 = prof[2][0]
+    win = (2 * p.lk_patch + 1) ** 2
+    flops = 2.0 * total_px * win * (6 + iters * 11)
+    log(f"classic LK pyramid: {ms:.3f} ms per panorama, level 0 {l0:.3f} ms")
+    return {"workload": "the same panorama, flow by the classic coarse-to-fine Lucas-Kanade (6 levels, "
+                        f"{iters} Gauss-Newton steps per level, 5x5 window, double) + blend, batched graph replay",
+            "ms_per_panorama": round(ms, 4), "mpix_s": round(total_px / ms / 1e3, 1),
+            "level_ms": [round(v, 4) for v in prof[2][:6]],
+            "level0": {"bound": "alu", "ms": round(l0, 4), "achieved": round(flops / l0 / 1e9, 2),
+                       "peak": 78.6, "unit": "TFLOP/s", "frac": round(flops / l0 / 1e9 / 78.6, 4)}}
+
+
 def run_merge(p, log, reps):
     """Repeated pairwise merging of one photo set on a 4000 x 9000 canvas:
     6 ring photos left to right, then the top photo (7 photos, 6 seams of
@@ -264,6 +292,7 @@ def main():
                     help="also time 50 gradient-descent refinement steps on the 2048 x 512 float strip")
     ap.add_argument("--no-canvas", action="store_true", help="skip the canvas-compositing leg")
     ap.add_argument("--no-merge", action="store_true", help="skip the photo-set merging leg")
+    ap.add_argument("--no-lk-pyramid", action="store_true", help="skip the classic Lucas-Kanade leg")
     ap.add_argument("--stream", type=int, default=0, metavar="PANORAMAS",
                     help="also time a stream of this many panoramas of the cfg4 workload (7 strips of drawn "
                          "sizes each; flow + blend batched per 4 panoramas, then 20 batched refinement steps)")
@@ -387,6 +416,7 @@ def main():
                   "mpix_steps_s": round(H3 * W3 * 50 / ms_r / 1e3, 1)}
         log(f"refine 50 steps: {ms_r:.3f} ms")
 
+    lkp = None if args.no_lk_pyramid else run_lk_pyramid(dev, shapes, total_px, timed, log, max(3, args.steps // 2))
     canvas = None if args.no_canvas else run_canvas(p, timed, log, args.steps)
     merge = None if args.no_merge else run_merge(p, log, max(2, args.steps // 4))
 
@@ -443,6 +473,7 @@ def main():
         "top_launches": per_launch,
         "roofline": roofline,
         "refine_flow": refine,
+        "lk_pyramid": lkp,
         "canvas": canvas,
         "merge": merge,
         "stream": stream,

@@ -1216,11 +1216,14 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
 // a float flow starts from twice the coarser level's flow at
 // (floor(x/2), floor(y/2)) (0 at the coarsest) and takes K Gauss-Newton
 // steps with the window's normal matrix + eps I, the central-difference
-// gradient of Ref and a bilinear Tgt (clamped indices), unclamped. The
-// arithmetic is double (the window sums of gradient products are exact;
-// the residuals and the solve follow the textbook form), so that levels
-// feed each other the same values as an FP64 reference up to rounding
-// order. Levels above 0 keep their flow as float64 x / y planes in the
+// gradient of Ref and a bilinear Tgt (clamped indices), unclamped. A
+// bilinear sample is linear in its four corners and every sample of a
+// pixel's window has the same fractions, so the residual sum is the
+// bilinear combination of four exact integer correlations of the doubled
+// gradient with the target at integer offsets, minus the exact sum of the
+// gradient times Ref; the combination and the 2x2 solve are double, so
+// levels feed each other the values of an FP64 reference up to rounding
+// order. Interior pixels load the (2P+2)^2 target block once per step. Levels above 0 keep their flow as float64 x / y planes in the
 // level's ds / df buffers (allocated with 8-byte entries for this method);
 // level 0 writes the caller's float32 flow. Tiles are
 // those of the search (kSearchTW x th pixels per direction); a thread
@@ -1255,46 +1258,90 @@ __global__ __launch_bounds__(512) void k_lk_level(const StripLv *__restrict__ lv
                 ux = 2.0 * gld(reinterpret_cast<const double *>(C.ds[dir]))[q];
                 uy = 2.0 * gld(reinterpret_cast<const double *>(C.df[dir]))[q];
             }
-            // gradients of the window (half-integers, exact in float)
-            float gx[WN][WN], gy[WN][WN], a[WN][WN];
-            double hxx = eps, hxy = 0.0, hyy = eps;
+            // doubled central-difference gradients G = 2 g of the window
+            // (integers) and the window's Ref values; 4 H and sum G A are
+            // exact integer sums
+            int gx[WN][WN], gy[WN][WN];
+            int hxx4 = 0, hxy4 = 0, hyy4 = 0, tx = 0, ty = 0;
 #pragma unroll
             for (int j = 0; j < WN; j++)
 #pragma unroll
                 for (int i = 0; i < WN; i++) {
                     const int qy = clampi(y + j - P, 0, H - 1), qx = clampi(x + i - P, 0, W - 1);
                     const ptrdiff_t o = (ptrdiff_t)qy * yp + qx;
-                    gx[j][i] = 0.5f * ((float)A[o + 1] - (float)A[o - 1]);
-                    gy[j][i] = 0.5f * ((float)A[o + yp] - (float)A[o - yp]);
-                    a[j][i] = (float)A[o];
-                    hxx += (double)gx[j][i] * gx[j][i];
-                    hxy += (double)gx[j][i] * gy[j][i];
-                    hyy += (double)gy[j][i] * gy[j][i];
+                    gx[j][i] = (int)A[o + 1] - (int)A[o - 1];
+                    gy[j][i] = (int)A[o + yp] - (int)A[o - yp];
+                    const int av = A[o];
+                    hxx4 += gx[j][i] * gx[j][i];
+                    hxy4 += gx[j][i] * gy[j][i];
+                    hyy4 += gy[j][i] * gy[j][i];
+                    tx += gx[j][i] * av;
+                    ty += gy[j][i] * av;
                 }
-            const double det = hxx * hyy - hxy * hxy;
+            const double hxx = eps + 0.25 * hxx4, hxy = 0.25 * hxy4, hyy = eps + 0.25 * hyy4;
+            const double idet = 1.0 / (hxx * hyy - hxy * hxy);
+            // the window's positions are clamped only near the border
+            const bool inner = x >= P && x + P <= W - 1 && y >= P && y + P <= H - 1;
             for (int it = 0; it < K; it++) {
                 const double fux = floor(ux), fuy = floor(uy);
                 const double fx = ux - fux, fy = uy - fuy;
                 const int ix = (int)fux, iy = (int)fuy;
-                double bx = 0.0, by = 0.0;
+                // S[b][a][c] = sum over the window of G_c(q) Tgt(q + (ix + a, iy + b)),
+                // with clamped target indices: the residual sum is their
+                // bilinear combination minus sum G A
+                int S[2][2][2] = {};
+                if (inner) {
+                    // target rows one at a time: row m serves window row m
+                    // (corner row 0) and window row m - 1 (corner row 1)
+                    int cols[WN + 1];
 #pragma unroll
-                for (int j = 0; j < WN; j++) {
-                    const int qy = clampi(y + j - P, 0, H - 1);
-                    const ptrdiff_t ra = (ptrdiff_t)clampi(qy + iy, 0, H - 1) * yp;
-                    const ptrdiff_t rb = (ptrdiff_t)clampi(qy + iy + 1, 0, H - 1) * yp;
+                    for (int k = 0; k <= WN; k++) cols[k] = clampi(x - P + k + ix, 0, W - 1);
 #pragma unroll
-                    for (int i = 0; i < WN; i++) {
-                        const int qx = clampi(x + i - P, 0, W - 1);
-                        const int xa0 = clampi(qx + ix, 0, W - 1), xb0 = clampi(qx + ix + 1, 0, W - 1);
-                        const double v00 = B[ra + xa0], v01 = B[ra + xb0], v10 = B[rb + xa0], v11 = B[rb + xb0];
-                        const double smp = (1.0 - fy) * ((1.0 - fx) * v00 + fx * v01) + fy * ((1.0 - fx) * v10 + fx * v11);
-                        const double r = smp - (double)a[j][i];
-                        bx += (double)gx[j][i] * r;
-                        by += (double)gy[j][i] * r;
+                    for (int m = 0; m <= WN; m++) {
+                        const ptrdiff_t rb = (ptrdiff_t)clampi(y - P + m + iy, 0, H - 1) * yp;
+                        int Bv[WN + 1];
+#pragma unroll
+                        for (int k = 0; k <= WN; k++) Bv[k] = B[rb + cols[k]];
+#pragma unroll
+                        for (int i = 0; i < WN; i++)
+#pragma unroll
+                            for (int a = 0; a < 2; a++) {
+                                if (m < WN) {
+                                    S[0][a][0] += gx[m][i] * Bv[i + a];
+                                    S[0][a][1] += gy[m][i] * Bv[i + a];
+                                }
+                                if (m > 0) {
+                                    S[1][a][0] += gx[m - 1][i] * Bv[i + a];
+                                    S[1][a][1] += gy[m - 1][i] * Bv[i + a];
+                                }
+                            }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < WN; j++) {
+                        const int qy = clampi(y + j - P, 0, H - 1);
+                        const ptrdiff_t r0 = (ptrdiff_t)clampi(qy + iy, 0, H - 1) * yp;
+                        const ptrdiff_t r1 = (ptrdiff_t)clampi(qy + iy + 1, 0, H - 1) * yp;
+#pragma unroll
+                        for (int i = 0; i < WN; i++) {
+                            const int qx = clampi(x + i - P, 0, W - 1);
+                            const int c0 = clampi(qx + ix, 0, W - 1), c1 = clampi(qx + ix + 1, 0, W - 1);
+                            const int v[2][2] = {{B[r0 + c0], B[r0 + c1]}, {B[r1 + c0], B[r1 + c1]}};
+#pragma unroll
+                            for (int b = 0; b < 2; b++)
+#pragma unroll
+                                for (int a = 0; a < 2; a++) {
+                                    S[b][a][0] += gx[j][i] * v[b][a];
+                                    S[b][a][1] += gy[j][i] * v[b][a];
+                                }
+                        }
                     }
                 }
-                ux -= (hyy * bx - hxy * by) / det;
-                uy -= (hxx * by - hxy * bx) / det;
+                const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
+                const double bx = 0.5 * (w00 * S[0][0][0] + w01 * S[0][1][0] + w10 * S[1][0][0] + w11 * S[1][1][0] - tx);
+                const double by = 0.5 * (w00 * S[0][0][1] + w01 * S[0][1][1] + w10 * S[1][0][1] + w11 * S[1][1][1] - ty);
+                ux -= (hyy * bx - hxy * by) * idet;
+                uy -= (hxx * by - hxy * bx) * idet;
             }
             if (level0) {
                 const uint64_t v = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
