@@ -44,7 +44,7 @@ def level_sizes(H, W, N):
 
 def kernel_name(stage, level, p):
     if stage == 0:
-        return "k_luma level 0" if level == 0 else "k_gain level 0"
+        return "k_luma level 0" if level == 0 else "k_gain_prep + k_gain level 0"
     if stage == 4:
         return "k_refine level 0" if level == 0 else "k_refine_border level 0"
     if stage == 3:

@@ -41,12 +41,15 @@ struct StripLv {
 };
 
 // The caller's buffers of one strip.
-// slots per exposure sum (spread of the luma kernel's atomics)
+// slots per exposure sum (spread of the luma kernel's atomics); after the
+// two sums' slots: the gain a of the exposure step
 constexpr int kSumSlots = 64;
+constexpr int kSumGain = 2 * kSumSlots;
+constexpr int kSumWords = 2 * kSumSlots + 1;
 
 struct StripIO {
     const uint8_t *L, *R;
-    unsigned long long *sums;  // device: intensity sums of L, R (exposure step), kSumSlots slots each
+    unsigned long long *sums;  // device: intensity sums of L, R (kSumSlots slots each), then the gain
     const float *blend;
     float *flow[2];  // [0] = FlowLtoR, [1] = FlowRtoL
     uint8_t *F;

@@ -189,7 +189,7 @@ __device__ __forceinline__ void wg_minmax4(int &a0, int &a1, int &a2, int &a3, i
 __global__ __launch_bounds__(256) void k_zero_sums(const StripIO *__restrict__ io, int n)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < 2 * kSumSlots * n) gst(io[i / (2 * kSumSlots)].sums)[i % (2 * kSumSlots)] = 0ull;
+    if (i < kSumWords * n) gst(io[i / kSumWords].sums)[i % kSumWords] = 0ull;
 }
 
 __device__ __forceinline__ int luma_of(uint32_t r, uint32_t g, uint32_t b) { return (77 * r + 150 * g + 29 * b + 128) >> 8; }
@@ -295,12 +295,32 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
     }
 }
 
+// The gain of every strip from its two exposure sums (one wave per strip):
+// a = floor(2^16 sum(YL) / sum(YR)), held at 2^24 (every nonzero byte
+// saturates from there on, so the exposure step's result is the same and
+// its products fit 32 bits); all-zero YR: 2^16, the identity.
+__global__ __launch_bounds__(64) void k_gain_prep(const StripIO *__restrict__ io)
+{
+    static_assert(kSumSlots == 64, "one slot per lane");
+    unsigned long long *const sums = io[blockIdx.x].sums;
+    unsigned long long l = gld(sums)[threadIdx.x], r = gld(sums)[kSumSlots + threadIdx.x];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        l += __shfl_xor(l, m, 64);
+        r += __shfl_xor(r, m, 64);
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long a = r ? (l << 16) / r : 65536ull;
+        gst(sums)[kSumGain] = a > (1ull << 24) ? (1ull << 24) : a;
+    }
+}
+
 // Exposure step: R's padded luma plane scaled by a = floor(2^16 sum(YL) /
-// sum(YR)): YR' = min(255, (YR a + 2^15) >> 16); all-zero YR is kept.
+// sum(YR)) (made by k_gain_prep): YR' = min(255, (YR a + 2^15) >> 16);
+// all-zero YR is kept (a = 2^16).
 __global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
                                               const int32_t *__restrict__ prefix, int n, int total)
 {
-    static_assert(kSumSlots == 64, "one slot per lane");
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -309,25 +329,17 @@ __global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, co
         const int segs = ceil_div(W + 2 * kPad, kLumaTW);
         const int py = local / segs;
         const int px = (local - py * segs) * kLumaTW + 4 * (int)threadIdx.x;
-        // the two sums of the strip: every wave adds up the slots
-        const auto sums = gld(io[s].sums);
-        unsigned long long sl = sums[threadIdx.x & 63], sr = sums[kSumSlots + (threadIdx.x & 63)];
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            sl += __shfl_xor(sl, m, 64);
-            sr += __shfl_xor(sr, m, 64);
-        }
-        if (sr == 0 || px >= W + 2 * kPad) continue;
-        const unsigned long long a = (sl << 16) / sr;
-        uint32_t *p = reinterpret_cast<uint32_t *>(lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch + (px - kPad));
-        const uint32_t v = *p;
+        if (px >= W + 2 * kPad) continue;
+        const uint32_t a = (uint32_t)gld(io[s].sums)[kSumGain];
+        const auto p = gst(reinterpret_cast<uint32_t *>(lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch + (px - kPad)));
+        const uint32_t v = p[0];
         uint32_t o = 0;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const unsigned long long g = ((unsigned long long)((v >> (8 * k)) & 0xffu) * a + (1ull << 15)) >> 16;
-            o |= (uint32_t)(g > 255ull ? 255ull : g) << (8 * k);
+            const uint32_t g = (((v >> (8 * k)) & 0xffu) * a + (1u << 15)) >> 16;
+            o |= (g > 255u ? 255u : g) << (8 * k);
         }
-        *p = o;
+        p[0] = o;
     }
 }
 
@@ -1425,12 +1437,13 @@ hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, 
 
 hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_sums, dim3(ceil_div(2 * kSumSlots * n, 256)), dim3(256), 0, s, io, n);
+    hipLaunchKernelGGL(k_zero_sums, dim3(ceil_div(kSumWords * n, 256)), dim3(256), 0, s, io, n);
     return hipGetLastError();
 }
 
 hipError_t launch_gain(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s)
 {
+    hipLaunchKernelGGL(k_gain_prep, dim3(w.n), dim3(64), 0, s, io);
     hipLaunchKernelGGL(k_gain, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n, w.total);
     return hipGetLastError();
 }

@@ -182,7 +182,7 @@ size_t data_bound(const abf_plan *pl)
         b += 2 * 2 * (e * mp * f * f + S * (e * Wm * f + 16 * e * Hm * f + 17 * e + 256));
         b += 2 * 1 * (2 * mp * f * f + S * (2 * Wm * f + 32 * Hm * f + 34 + 256));
     }
-    b += S * align_up(2 * kSumSlots * sizeof(unsigned long long), kAlign);  // exposure sums
+    b += S * align_up(kSumWords * sizeof(unsigned long long), kAlign);  // exposure sums
     return align_up((size_t)b + 4096, kAlign);
 }
 
@@ -294,7 +294,7 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
         }
         if (!flows) continue;
         io.sums = reinterpret_cast<unsigned long long *>(pl->ws + off);
-        off += align_up(2 * kSumSlots * sizeof(unsigned long long), kAlign);
+        off += align_up(kSumWords * sizeof(unsigned long long), kAlign);
         for (int k = 0; k < N; k++) {
             StripLv &v = b.lv[(size_t)k * n + s];
             v.H = L.hk[s][k];
