@@ -34,6 +34,29 @@ __device__ __forceinline__ uint32_t cand(uint32_t k2, uint32_t g)
     return g == kInf16 ? kInf32 : k2 + g * g;
 }
 
+// Nonzero bytes of row[x0 .. x0 + n) (n <= 16) as a bit mask (bit k = byte
+// x0 + k): four aligned dword loads when the 16 bytes are whole and
+// 4-byte aligned, else byte by byte.
+__device__ __forceinline__ uint32_t chunk_nz(const uint8_t *row, int x0, int n)
+{
+    const uint8_t *p = row + x0;
+    if (n == kCanvasChunk && ((uintptr_t)p & 3) == 0) {
+        const auto q = gld(reinterpret_cast<const uint32_t *>(p));
+        uint32_t m = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t v = q[j];
+            // high bit of each byte set iff the byte is nonzero
+            const uint32_t h = (((v & 0x7f7f7f7fu) + 0x7f7f7f7fu) | v) & 0x80808080u;
+            m |= (((h >> 7) & 1u) | ((h >> 14) & 2u) | ((h >> 21) & 4u) | ((h >> 28) & 8u)) << (4 * j);
+        }
+        return m;
+    }
+    uint32_t m = 0;
+    for (int k = 0; k < n; k++) m |= (uint32_t)(gld(p)[k] != 0) << k;
+    return m;
+}
+
 // ------------------------------------------------------------ row pass
 // One workgroup per canvas row. Chunk c covers columns [16 c, 16 c + 16).
 __global__ __launch_bounds__(kCanvasThreads) void k_canvas_rows(CanvasGeom a)
@@ -49,12 +72,8 @@ __global__ __launch_bounds__(kCanvasThreads) void k_canvas_rows(CanvasGeom a)
     constexpr int INF = 0x7fffffff;
     for (int c = t; c < nC; c += kCanvasThreads) {
         const int x0 = c * kCanvasChunk, n = min(kCanvasChunk, W - x0);
-        uint32_t b1 = 0, b2 = 0;
-        for (int k = 0; k < n; k++) {
-            const bool l = gld(rl)[x0 + k] != 0, r = gld(rr)[x0 + k] != 0;
-            b1 |= (uint32_t)(l && !r) << k;
-            b2 |= (uint32_t)(r && !l) << k;
-        }
+        const uint32_t ml = chunk_nz(rl, x0, n), mr = chunk_nz(rr, x0, n);
+        const uint32_t b1 = ml & ~mr, b2 = mr & ~ml;
         bits[c] = b1 | (b2 << 16);
         lastA[c] = b1 ? x0 + 31 - __clz(b1) : -1;
         lastB[c] = b2 ? x0 + 31 - __clz(b2) : -1;
@@ -340,18 +359,12 @@ __global__ __launch_bounds__(kCanvasThreads) void k_box_rows(const uint8_t *mL, 
     const uint8_t *rl = mL + (size_t)y * pitchM, *rr = mR + (size_t)y * pitchM;
     int lo = 0x7fffffff, hi = -1;
     for (int x0 = kCanvasChunk * (int)threadIdx.x; x0 < W; x0 += kCanvasChunk * kCanvasThreads) {
-        uint8_t l[kCanvasChunk], r[kCanvasChunk];
-#pragma unroll
-        for (int k = 0; k < kCanvasChunk; k++) {
-            l[k] = x0 + k < W ? gld(rl)[x0 + k] : 0;
-            r[k] = x0 + k < W ? gld(rr)[x0 + k] : 0;
+        const int n = min(kCanvasChunk, W - x0);
+        const uint32_t m = chunk_nz(rl, x0, n) & chunk_nz(rr, x0, n);
+        if (m) {
+            lo = min(lo, x0 + __ffs(m) - 1);
+            hi = max(hi, x0 + 31 - __clz(m));
         }
-#pragma unroll
-        for (int k = 0; k < kCanvasChunk; k++)
-            if (l[k] != 0 && r[k] != 0) {
-                lo = min(lo, x0 + k);
-                hi = max(hi, x0 + k);
-            }
     }
     if (hi >= 0) {
         atomicMin(&s[0], lo);
@@ -406,7 +419,8 @@ __global__ __launch_bounds__(1024) void k_box_fin(const int32_t *part, int H, in
 // Code 1 over the canvas, one workgroup per kRowTW pixels of a row: Area1
 // copies L, Area2 copies R, Area3 inside the overlap box is warped and
 // blended as a strip pixel of the box (images and flows cropped to the
-// box), everything else is 0. The uint8 output is staged in LDS at the
+// box), everything else is 0. With `cov` (a photo merge), the union of the
+// two coverages is written there (pitch of the masks). The uint8 output is staged in LDS at the
 // byte alignment of its destination and written with aligned dwords.
 __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendParams bp)
 {
@@ -420,6 +434,7 @@ __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendPara
     if (x < W) {
         const size_t pm = (size_t)y * o.pitchM + x;
         const int area = (gld(o.mL)[pm] != 0) + 2 * (gld(o.mR)[pm] != 0);
+        if (o.cov) gst(o.cov)[pm] = area != 0;  // may be one of the masks: read above, by this thread only
         const int xb = x - o.bx, yb = y - o.by;
         float f[3] = {0.f, 0.f, 0.f};
         if (area == 1 || area == 2) {
@@ -473,14 +488,6 @@ __global__ __launch_bounds__(256) void k_photo_init(const uint8_t *img, int pitc
     gst(cov)[(size_t)y * pitchC + x] = m ? 1 : 0;
 }
 
-// cov |= (mask != 0) after a photo has been merged
-__global__ __launch_bounds__(256) void k_mask_or(uint8_t *cov, int pitchC, const uint8_t *mask, int pitchM, int W)
-{
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-    if (x >= W) return;
-    if (gld(mask)[(size_t)y * pitchM + x] != 0) gst(cov)[(size_t)y * pitchC + x] = 1;
-}
-
 // ------------------------------------------------------------- launchers
 hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *part,
                               int32_t *box, hipStream_t s)
@@ -506,12 +513,6 @@ hipError_t launch_photo_init(const uint8_t *img, int pitchI, const uint8_t *mask
 {
     hipLaunchKernelGGL(k_photo_init, dim3(ceil_div(W, 256), H), dim3(256), 0, s, img, pitchI, mask, pitchM, H, W, dst,
                        pitchD, cov, pitchC);
-    return hipGetLastError();
-}
-
-hipError_t launch_mask_or(uint8_t *cov, int pitchC, const uint8_t *mask, int pitchM, int H, int W, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_mask_or, dim3(ceil_div(W, 256), H), dim3(256), 0, s, cov, pitchC, mask, pitchM, W);
     return hipGetLastError();
 }
 

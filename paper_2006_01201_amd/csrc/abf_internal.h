@@ -170,6 +170,7 @@ struct CompositeArgs {
     const float *flr, *frl;   // bh x bw x 2 over the overlap box
     uint8_t *F;
     float *Ff32;              // H x W x 3 contiguous, or null
+    uint8_t *cov;             // union of the coverages (pitchM), or null
     int32_t pitchL, pitchR, pitchM, pitchB, pitchF;
     int32_t H, W, bx, by, bw, bh, axis;
     int32_t pad_;
@@ -184,7 +185,6 @@ hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int
 hipError_t launch_composite(const CompositeArgs &o, BlendParams bp, hipStream_t s);
 hipError_t launch_photo_init(const uint8_t *img, int pitchI, const uint8_t *mask, int pitchM, int H, int W,
                              uint8_t *dst, int pitchD, uint8_t *cov, int pitchC, hipStream_t s);
-hipError_t launch_mask_or(uint8_t *cov, int pitchC, const uint8_t *mask, int pitchM, int H, int W, hipStream_t s);
 
 // tiles of one strip for a stage (both directions where the stage has two)
 // luma and exposure: 4 pixels per thread over the padded rows

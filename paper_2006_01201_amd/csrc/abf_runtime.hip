@@ -1098,8 +1098,8 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
         o.bh = any ? hb[3] : 0;
         o.axis = p.axis;
         o.inv_ext = any ? 1.0 / (double)(p.axis == 0 ? hb[2] : hb[3]) : 0.0;
+        o.cov = coverage;  // coverage |= the photo's mask, in the same pass
         HIP_TRY(plan, launch_composite(o, bp, s));
-        HIP_TRY(plan, launch_mask_or(coverage, pitch_mask, p.mask, pitch_mask, H, W, s));
         cur ^= 1;
     }
     return ABF_OK;

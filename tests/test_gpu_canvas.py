@@ -231,3 +231,9 @@ def test_canvas_limits_are_enforced(api):
     f = torch.zeros((16, 16, 2), dtype=torch.float32, device="cuda")
     with pytest.raises(ValueError):
         small.composite_canvas(img, img, m, m, f, f, (1, 0, 16, 16))
+    # sides beyond 32767 (row distances are uint16) are refused
+    wide = torch.ones((1, 32768), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        small.overlap_box(wide, wide)
+    with pytest.raises(ValueError):
+        small.canvas_blend(wide, wide)
