@@ -110,11 +110,15 @@ hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int medi
 hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid, hipStream_t s);
 hipError_t launch_refine_border(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, hipStream_t s);
 hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s);
-// classic coarse-to-fine Lucas-Kanade, one level (flow method 1), on the
-// search stage's tiles; lvc = the next coarser level's entries (null at the
-// coarsest); level0 writes the caller's flows
-hipError_t launch_lk_level(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk, int th,
-                           int grid, bool level0, hipStream_t s);
+// classic coarse-to-fine Lucas-Kanade, one level (flow method 1): the
+// border pixels on the refinement's border list of the level and the
+// interior pixels (exact pair sums) on its refinement tiles (th 2 or 4);
+// lvc = the next coarser level's entries (null at the coarsest); level0
+// writes the caller's flows
+hipError_t launch_lk_border(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk, bool level0,
+                            hipStream_t s);
+hipError_t launch_lk_interior(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk, int th,
+                              int grid, bool level0, hipStream_t s);
 
 // One strip of a batched refinement: u[0] is the caller's flow, u[1] the
 // other half of the descent ping-pong (workspace).

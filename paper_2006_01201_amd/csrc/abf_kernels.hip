@@ -1059,6 +1059,27 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
     }
 }
 
+// Border pixel b (0 .. nbp - 1) of a level split by refine_split: the rows
+// above and below the interior band, then the columns left and right of it.
+__device__ __forceinline__ void border_pixel(const RefineSplit &sp, int H, int W, int b, int &x, int &y)
+{
+    const int top = sp.ylo * W, bot = (H - sp.yhi) * W;
+    if (b < top) {
+        y = b / W;
+        x = b - y * W;
+    } else if (b < top + bot) {
+        b -= top;
+        y = sp.yhi + b / W;
+        x = b - (b / W) * W;
+    } else {
+        b -= top + bot;
+        const int k = sp.xlo + W - sp.xhi;
+        y = sp.ylo + b / k;
+        const int c = b - (b / k) * k;
+        x = c < sp.xlo ? c : sp.xhi + (c - sp.xlo);
+    }
+}
+
 // The pixels whose window leaves the image (within LP of the border): every
 // window position is clamped to the image on its own, so positions repeat.
 // The clamped positions never decrease and step by 0 or 1, so the bytes a
@@ -1091,23 +1112,8 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
         local -= dir * nbt;
         int b = local * kRowTW + (int)threadIdx.x;
         if (b >= sp.nbp) continue;
-        // border band: rows above and below, then columns left and right
         int x, y;
-        const int top = sp.ylo * W, bot = (H - sp.yhi) * W;
-        if (b < top) {
-            y = b / W;
-            x = b - y * W;
-        } else if (b < top + bot) {
-            b -= top;
-            y = sp.yhi + b / W;
-            x = b - (b / W) * W;
-        } else {
-            b -= top + bot;
-            const int k = sp.xlo + W - sp.xhi;
-            y = sp.ylo + b / k;
-            const int c = b - (b / k) * k;
-            x = c < sp.xlo ? c : sp.xhi + (c - sp.xlo);
-        }
+        border_pixel(sp, H, W, b, x, y);
         const uint8_t *Ao = plane_org(L.y[dir], yp), *Bo = plane_org(L.y[1 - dir], yp);
         const uint32_t d0 = gld(L.df[dir])[(uint32_t)(y * L.fpitch + x)];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
@@ -1235,17 +1241,136 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
 // gradient with the target at integer offsets, minus the exact sum of the
 // gradient times Ref; the combination and the 2x2 solve are double, so
 // levels feed each other the values of an FP64 reference up to rounding
-// order. Interior pixels load the (2P+2)^2 target block once per step. Levels above 0 keep their flow as float64 x / y planes in the
+// order. Levels above 0 keep their flow as float64 x / y planes in the
 // level's ds / df buffers (allocated with 8-byte entries for this method);
-// level 0 writes the caller's float32 flow. Tiles are
-// those of the search (kSearchTW x th pixels per direction); a thread
-// takes pixels x and x + 1.
+// level 0 writes the caller's float32 flow. Interior pixels take
+// k_lk_interior (16-bit pair sums, as k_refine); the pixels within P of
+// the image edge, whose window positions repeat, take lk_pixel with
+// plain integer sums, one thread each.
+
+// One pixel of the classic method (any pixel; the window positions and the
+// target indices are clamped as in the textbook form).
 template <int P>
-__global__ __launch_bounds__(512) void k_lk_level(const StripLv *__restrict__ lv, const StripLv *__restrict__ lvc,
-                                                  const StripIO *__restrict__ io, const int32_t *__restrict__ prefix,
-                                                  int n, int total, int th, int K, double eps, bool level0)
+__device__ __forceinline__ void lk_pixel(const StripLv &L, const StripLv *__restrict__ lvc, const StripIO *__restrict__ io,
+                                         int s, int dir, int x, int y, int K, double eps, bool level0)
 {
     constexpr int WN = 2 * P + 1;
+    const int H = L.H, W = L.W, yp = L.ypitch;
+    const auto A = gld(L.y[dir]), B = gld(L.y[1 - dir]);
+    double ux = 0.0, uy = 0.0;
+    if (lvc) {
+        const StripLv &C = lvc[s];
+        const size_t q = (size_t)min(y >> 1, C.H - 1) * C.fpitch + min(x >> 1, C.W - 1);
+        ux = 2.0 * gld(reinterpret_cast<const double *>(C.ds[dir]))[q];
+        uy = 2.0 * gld(reinterpret_cast<const double *>(C.df[dir]))[q];
+    }
+    // doubled central-difference gradients G = 2 g of the window
+    // (integers) and the window's Ref values; 4 H and sum G A are
+    // exact integer sums
+    int gx[WN][WN], gy[WN][WN];
+    int hxx4 = 0, hxy4 = 0, hyy4 = 0, tx = 0, ty = 0;
+#pragma unroll
+    for (int j = 0; j < WN; j++)
+#pragma unroll
+        for (int i = 0; i < WN; i++) {
+            const int qy = clampi(y + j - P, 0, H - 1), qx = clampi(x + i - P, 0, W - 1);
+            const ptrdiff_t o = (ptrdiff_t)qy * yp + qx;
+            gx[j][i] = (int)A[o + 1] - (int)A[o - 1];
+            gy[j][i] = (int)A[o + yp] - (int)A[o - yp];
+            const int av = A[o];
+            hxx4 += gx[j][i] * gx[j][i];
+            hxy4 += gx[j][i] * gy[j][i];
+            hyy4 += gy[j][i] * gy[j][i];
+            tx += gx[j][i] * av;
+            ty += gy[j][i] * av;
+        }
+    const double hxx = eps + 0.25 * hxx4, hxy = 0.25 * hxy4, hyy = eps + 0.25 * hyy4;
+    const double idet = 1.0 / (hxx * hyy - hxy * hxy);
+    for (int it = 0; it < K; it++) {
+        const double fux = floor(ux), fuy = floor(uy);
+        const double fx = ux - fux, fy = uy - fuy;
+        const int ix = (int)fux, iy = (int)fuy;
+        // S[b][a][c] = sum over the window of G_c(q) Tgt(q + (ix + a, iy + b)),
+        // with clamped target indices: the residual sum is their
+        // bilinear combination minus sum G A
+        int S[2][2][2] = {};
+        {
+#pragma unroll
+            for (int j = 0; j < WN; j++) {
+                const int qy = clampi(y + j - P, 0, H - 1);
+                const ptrdiff_t r0 = (ptrdiff_t)clampi(qy + iy, 0, H - 1) * yp;
+                const ptrdiff_t r1 = (ptrdiff_t)clampi(qy + iy + 1, 0, H - 1) * yp;
+#pragma unroll
+                for (int i = 0; i < WN; i++) {
+                    const int qx = clampi(x + i - P, 0, W - 1);
+                    const int c0 = clampi(qx + ix, 0, W - 1), c1 = clampi(qx + ix + 1, 0, W - 1);
+                    const int v[2][2] = {{B[r0 + c0], B[r0 + c1]}, {B[r1 + c0], B[r1 + c1]}};
+#pragma unroll
+                    for (int b = 0; b < 2; b++)
+#pragma unroll
+                        for (int a = 0; a < 2; a++) {
+                            S[b][a][0] += gx[j][i] * v[b][a];
+                            S[b][a][1] += gy[j][i] * v[b][a];
+                        }
+                }
+            }
+        }
+        const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
+        const double bx = 0.5 * (w00 * S[0][0][0] + w01 * S[0][1][0] + w10 * S[1][0][0] + w11 * S[1][1][0] - tx);
+        const double by = 0.5 * (w00 * S[0][0][1] + w01 * S[0][1][1] + w10 * S[1][0][1] + w11 * S[1][1][1] - ty);
+        ux -= (hyy * bx - hxy * by) * idet;
+        uy -= (hxx * by - hxy * bx) * idet;
+    }
+    if (level0) {
+        const uint64_t v = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
+        gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(size_t)y * W + x] = v;
+    } else {
+        gst(reinterpret_cast<double *>(L.ds[dir]))[(size_t)y * L.fpitch + x] = ux;
+        gst(reinterpret_cast<double *>(L.df[dir]))[(size_t)y * L.fpitch + x] = uy;
+    }
+}
+
+// The classic method's border pixels (within P of the image edge), one per
+// thread, on the refinement's border list of the level.
+template <int P>
+__global__ __launch_bounds__(kRowTW) void k_lk_border(const StripLv *__restrict__ lv, const StripLv *__restrict__ lvc,
+                                                      const StripIO *__restrict__ io, const int32_t *__restrict__ prefix,
+                                                      int n, int total, int K, double eps, bool level0)
+{
+    TILE_LOOP(total)
+    {
+        const int s = find_strip(prefix, n, t);
+        int local = t - prefix[s];
+        const StripLv &L = lv[s];
+        const RefineSplit sp = refine_split(L.H, L.W, 1, P);
+        const int nbt = ceil_div(sp.nbp, kRowTW);
+        const int dir = local / nbt;
+        local -= dir * nbt;
+        const int b = local * kRowTW + (int)threadIdx.x;
+        if (b >= sp.nbp) continue;
+        int x, y;
+        border_pixel(sp, L.H, L.W, b, x, y);
+        lk_pixel<P>(L, lvc, io, s, dir, x, y, K, eps, level0);
+    }
+}
+
+// The classic method's interior pixels (window and gradient taps inside the
+// image), with the exact 16-bit-pair sums of k_refine: doubled gradients,
+// 4 H, sum G Ref and, per step, the four corner correlations of the target
+// block at the cell of u (its origin clamped to the padded range as in
+// k_refine), combined with the bilinear weights in double. The seed is
+// fractional, so every step takes the four corners; no clamp.
+template <int LP, int TH>
+__global__ __launch_bounds__(64 * TH) void k_lk_interior(const StripLv *__restrict__ lv,
+                                                         const StripLv *__restrict__ lvc,
+                                                         const StripIO *__restrict__ io,
+                                                         const int32_t *__restrict__ prefix, int n, int total,
+                                                         int iters, double eps, bool level0)
+{
+    constexpr int TW = kRefineTW;
+    constexpr int WN = 2 * LP + 1;
+    constexpr int NP = LP + 1;
+    constexpr int AB = WN + 2;
     const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
     TILE_LOOP(total)
     {
@@ -1253,115 +1378,91 @@ __global__ __launch_bounds__(512) void k_lk_level(const StripLv *__restrict__ lv
         int local = t - prefix[s];
         const StripLv &L = lv[s];
         const int H = L.H, W = L.W, yp = L.ypitch;
-        const int ntx = ceil_div(W, kSearchTW), per_dir = ntx * ceil_div(H, th);
-        const int dir = local / per_dir;
-        local -= dir * per_dir;
+        const RefineSplit sp = refine_split(H, W, TH, LP);
+        const int dir = local / sp.nint;
+        local -= dir * sp.nint;
+        const int ntx = ceil_div(sp.xhi - sp.xlo, TW);
         const int tyi = local / ntx;
-        const int xa = (local - tyi * ntx) * kSearchTW + 2 * lane, y = tyi * th + wrow;
-        if (y >= H || wrow >= th) continue;  // no barrier in this kernel
-        const auto A = gld(L.y[dir]), B = gld(L.y[1 - dir]);
-        for (int e = 0; e < 2; e++) {
-            const int x = xa + e;
-            if (x >= W) break;
-            double ux = 0.0, uy = 0.0;
-            if (lvc) {
-                const StripLv &C = lvc[s];
-                const size_t q = (size_t)min(y >> 1, C.H - 1) * C.fpitch + min(x >> 1, C.W - 1);
-                ux = 2.0 * gld(reinterpret_cast<const double *>(C.ds[dir]))[q];
-                uy = 2.0 * gld(reinterpret_cast<const double *>(C.df[dir]))[q];
+        const int x = sp.xlo + (local - tyi * ntx) * TW + lane;
+        const int y = sp.ylo + tyi * TH + wrow;
+        if (x >= sp.xhi || y >= sp.yhi) continue;  // no barrier in this kernel
+        const uint8_t *Ao = plane_org(L.y[dir], yp), *Bo = plane_org(L.y[1 - dir], yp);
+        double ux = 0.0, uy = 0.0;
+        if (lvc) {
+            const StripLv &C = lvc[s];
+            const size_t q = (size_t)min(y >> 1, C.H - 1) * C.fpitch + min(x >> 1, C.W - 1);
+            ux = 2.0 * gld(reinterpret_cast<const double *>(C.ds[dir]))[q];
+            uy = 2.0 * gld(reinterpret_cast<const double *>(C.df[dir]))[q];
+        }
+        uint32_t gxp[WN][NP], gyp[WN][NP];
+        int hxx = 0, hxy = 0, hyy = 0, sax = 0, say = 0;
+        {
+            uint32_t op[WN + 2][NP], ar[WN + 2][(AB + 3) / 4];
+            load_rows<AB, WN + 2>(Ao, yp, y - LP - 1, x - LP - 1, ar);
+#pragma unroll
+            for (int r = 0; r < WN + 2; r++) {
+                odd_pairs<NP, 0>(ar[r], op[r]);
+                if (r >= 1 && r <= WN) gx_pairs<NP, 0>(ar[r], gxp[r - 1]);
             }
-            // doubled central-difference gradients G = 2 g of the window
-            // (integers) and the window's Ref values; 4 H and sum G A are
-            // exact integer sums
-            int gx[WN][WN], gy[WN][WN];
-            int hxx4 = 0, hxy4 = 0, hyy4 = 0, tx = 0, ty = 0;
 #pragma unroll
             for (int j = 0; j < WN; j++)
 #pragma unroll
-                for (int i = 0; i < WN; i++) {
-                    const int qy = clampi(y + j - P, 0, H - 1), qx = clampi(x + i - P, 0, W - 1);
-                    const ptrdiff_t o = (ptrdiff_t)qy * yp + qx;
-                    gx[j][i] = (int)A[o + 1] - (int)A[o - 1];
-                    gy[j][i] = (int)A[o + yp] - (int)A[o - yp];
-                    const int av = A[o];
-                    hxx4 += gx[j][i] * gx[j][i];
-                    hxy4 += gx[j][i] * gy[j][i];
-                    hyy4 += gy[j][i] * gy[j][i];
-                    tx += gx[j][i] * av;
-                    ty += gy[j][i] * av;
+                for (int k = 0; k < NP; k++) {
+                    gyp[j][k] = sub2(op[j + 2][k], op[j][k]);
+                    hxx = dot2(gxp[j][k], gxp[j][k], hxx);
+                    hxy = dot2(gxp[j][k], gyp[j][k], hxy);
+                    hyy = dot2(gyp[j][k], gyp[j][k], hyy);
+                    sax = dot2(gxp[j][k], op[j + 1][k], sax);
+                    say = dot2(gyp[j][k], op[j + 1][k], say);
                 }
-            const double hxx = eps + 0.25 * hxx4, hxy = 0.25 * hxy4, hyy = eps + 0.25 * hyy4;
-            const double idet = 1.0 / (hxx * hyy - hxy * hxy);
-            // the window's positions are clamped only near the border
-            const bool inner = x >= P && x + P <= W - 1 && y >= P && y + P <= H - 1;
-            for (int it = 0; it < K; it++) {
-                const double fux = floor(ux), fuy = floor(uy);
-                const double fx = ux - fux, fy = uy - fuy;
-                const int ix = (int)fux, iy = (int)fuy;
-                // S[b][a][c] = sum over the window of G_c(q) Tgt(q + (ix + a, iy + b)),
-                // with clamped target indices: the residual sum is their
-                // bilinear combination minus sum G A
-                int S[2][2][2] = {};
-                if (inner) {
-                    // target rows one at a time: row m serves window row m
-                    // (corner row 0) and window row m - 1 (corner row 1)
-                    int cols[WN + 1];
+        }
+        const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
+        const double idet = 1.0 / (Hxx * Hyy - Hxy * Hxy);
+        for (int it = 0; it < iters; it++) {
+            const double fux = floor(ux), fuy = floor(uy);
+            const double fx = ux - fux, fy = uy - fuy;
+            // |u| may exceed the int range only with a diverging step; the
+            // clamp keeps the block origin in the padded plane either way
+            const double cx = fmin(fmax(fux, -(double)(W + 2 * kPad)), (double)(W + 2 * kPad));
+            const double cy = fmin(fmax(fuy, -(double)(H + 2 * kPad)), (double)(H + 2 * kPad));
+            const int c0 = clampi(x - LP + (int)cx, -kPad, W - 1 + kPad - (WN + 1));
+            const int r0 = clampi(y - LP + (int)cy, -kPad, H - 1 + kPad - WN);
+            int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
+            uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
+            load_rows<WN + 2, WN + 1>(Bo, yp, r0, c0, tb);
 #pragma unroll
-                    for (int k = 0; k <= WN; k++) cols[k] = clampi(x - P + k + ix, 0, W - 1);
+            for (int r = 0; r <= WN; r++) {
+                uint32_t te[NP], to[NP];
+                tgt_pairs<NP, 0>(tb[r], te, to);
 #pragma unroll
-                    for (int m = 0; m <= WN; m++) {
-                        const ptrdiff_t rb = (ptrdiff_t)clampi(y - P + m + iy, 0, H - 1) * yp;
-                        int Bv[WN + 1];
-#pragma unroll
-                        for (int k = 0; k <= WN; k++) Bv[k] = B[rb + cols[k]];
-#pragma unroll
-                        for (int i = 0; i < WN; i++)
-#pragma unroll
-                            for (int a = 0; a < 2; a++) {
-                                if (m < WN) {
-                                    S[0][a][0] += gx[m][i] * Bv[i + a];
-                                    S[0][a][1] += gy[m][i] * Bv[i + a];
-                                }
-                                if (m > 0) {
-                                    S[1][a][0] += gx[m - 1][i] * Bv[i + a];
-                                    S[1][a][1] += gy[m - 1][i] * Bv[i + a];
-                                }
-                            }
+                for (int k = 0; k < NP; k++) {
+                    if (r < WN) {
+                        s00x = dot2(gxp[r][k], te[k], s00x);
+                        s01x = dot2(gxp[r][k], to[k], s01x);
+                        s00y = dot2(gyp[r][k], te[k], s00y);
+                        s01y = dot2(gyp[r][k], to[k], s01y);
                     }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < WN; j++) {
-                        const int qy = clampi(y + j - P, 0, H - 1);
-                        const ptrdiff_t r0 = (ptrdiff_t)clampi(qy + iy, 0, H - 1) * yp;
-                        const ptrdiff_t r1 = (ptrdiff_t)clampi(qy + iy + 1, 0, H - 1) * yp;
-#pragma unroll
-                        for (int i = 0; i < WN; i++) {
-                            const int qx = clampi(x + i - P, 0, W - 1);
-                            const int c0 = clampi(qx + ix, 0, W - 1), c1 = clampi(qx + ix + 1, 0, W - 1);
-                            const int v[2][2] = {{B[r0 + c0], B[r0 + c1]}, {B[r1 + c0], B[r1 + c1]}};
-#pragma unroll
-                            for (int b = 0; b < 2; b++)
-#pragma unroll
-                                for (int a = 0; a < 2; a++) {
-                                    S[b][a][0] += gx[j][i] * v[b][a];
-                                    S[b][a][1] += gy[j][i] * v[b][a];
-                                }
-                        }
+                    if (r > 0) {
+                        s10x = dot2(gxp[r - 1][k], te[k], s10x);
+                        s11x = dot2(gxp[r - 1][k], to[k], s11x);
+                        s10y = dot2(gyp[r - 1][k], te[k], s10y);
+                        s11y = dot2(gyp[r - 1][k], to[k], s11y);
                     }
                 }
-                const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
-                const double bx = 0.5 * (w00 * S[0][0][0] + w01 * S[0][1][0] + w10 * S[1][0][0] + w11 * S[1][1][0] - tx);
-                const double by = 0.5 * (w00 * S[0][0][1] + w01 * S[0][1][1] + w10 * S[1][0][1] + w11 * S[1][1][1] - ty);
-                ux -= (hyy * bx - hxy * by) * idet;
-                uy -= (hxx * by - hxy * bx) * idet;
             }
-            if (level0) {
-                const uint64_t v = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
-                gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(size_t)y * W + x] = v;
-            } else {
-                gst(reinterpret_cast<double *>(L.ds[dir]))[(size_t)y * L.fpitch + x] = ux;
-                gst(reinterpret_cast<double *>(L.df[dir]))[(size_t)y * L.fpitch + x] = uy;
-            }
+            // residual sums with the doubled gradient: G (Tgt~ - A)
+            const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
+            const double bx = 0.5 * (w00 * s00x + w01 * s01x + w10 * s10x + w11 * s11x - sax);
+            const double by = 0.5 * (w00 * s00y + w01 * s01y + w10 * s10y + w11 * s11y - say);
+            ux -= (Hyy * bx - Hxy * by) * idet;
+            uy -= (Hxx * by - Hxy * bx) * idet;
+        }
+        if (level0) {
+            const uint64_t v = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
+            gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(size_t)y * W + x] = v;
+        } else {
+            gst(reinterpret_cast<double *>(L.ds[dir]))[(size_t)y * L.fpitch + x] = ux;
+            gst(reinterpret_cast<double *>(L.df[dir]))[(size_t)y * L.fpitch + x] = uy;
         }
     }
 }
@@ -1554,16 +1655,38 @@ hipError_t launch_refine_border(const StripLv *lv0, const StripIO *io, Work w, L
     }
 }
 
-hipError_t launch_lk_level(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk, int th,
-                           int grid, bool level0, hipStream_t s)
+hipError_t launch_lk_border(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk, bool level0,
+                            hipStream_t s)
 {
-    const dim3 g(grid_for(w.total, grid)), b(64 * th);
+    const dim3 g(grid_for(w.total, 0)), b(kRowTW);
+    const double e = lk.eps;
     switch (lk.patch) {
-    case 1: hipLaunchKernelGGL(k_lk_level<1>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, th, lk.iters, (double)lk.eps, level0); break;
-    case 2: hipLaunchKernelGGL(k_lk_level<2>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, th, lk.iters, (double)lk.eps, level0); break;
-    default: hipLaunchKernelGGL(k_lk_level<3>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, th, lk.iters, (double)lk.eps, level0); break;
+    case 1: hipLaunchKernelGGL(k_lk_border<1>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, lk.iters, e, level0); break;
+    case 2: hipLaunchKernelGGL(k_lk_border<2>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, lk.iters, e, level0); break;
+    default: hipLaunchKernelGGL(k_lk_border<3>, g, b, 0, s, lv, lvc, io, w.prefix, w.n, w.total, lk.iters, e, level0); break;
     }
     return hipGetLastError();
+}
+
+template <int LP>
+static hipError_t lk_interior_th(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk,
+                                 int th, int grid, bool level0, hipStream_t s)
+{
+    const dim3 g(grid_for(w.total, grid));
+    const double e = lk.eps;
+    if (th == 2)
+        hipLaunchKernelGGL((k_lk_interior<LP, 2>), g, dim3(128), 0, s, lv, lvc, io, w.prefix, w.n, w.total, lk.iters, e, level0);
+    else
+        hipLaunchKernelGGL((k_lk_interior<LP, 4>), g, dim3(256), 0, s, lv, lvc, io, w.prefix, w.n, w.total, lk.iters, e, level0);
+    return hipGetLastError();
+}
+
+hipError_t launch_lk_interior(const StripLv *lv, const StripLv *lvc, const StripIO *io, Work w, LkParams lk, int th,
+                              int grid, bool level0, hipStream_t s)
+{
+    if (lk.patch == 1) return lk_interior_th<1>(lv, lvc, io, w, lk, th, grid, level0, s);
+    if (lk.patch == 2) return lk_interior_th<2>(lv, lvc, io, w, lk, th, grid, level0, s);
+    return lk_interior_th<3>(lv, lvc, io, w, lk, th, grid, level0, s);
 }
 
 hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s)
