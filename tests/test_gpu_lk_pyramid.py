@@ -111,10 +111,11 @@ def test_launch_shapes_give_identical_results(api):
     plan = api.Plan(p, max_strips=1, max_H=70, max_W=150)
     print("[gpu] classic LK launch shapes", flush=True)
     base = [t.clone() for t in plan.flow_bidirectional(dev(s.L), dev(s.R))]
-    for th in (1, 2, 4, 8):
+    # interior pixels run on the refinement's tiles (tile height 2 or 4)
+    for th in (2, 4):
         for grid in (0, 1, 3):
             for c in range(4):
-                plan.set_launch(2, c, th, grid)
+                plan.set_launch(4, c, th, grid)
             out = plan.flow_bidirectional(dev(s.L), dev(s.R))
             torch.cuda.synchronize()
             assert torch.equal(out[0], base[0]) and torch.equal(out[1], base[1])
