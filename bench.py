@@ -199,14 +199,14 @@ def run_lk_pyramid(dev, shapes, total_px, timed, log, steps, iters=4):
     plan.stitch(batch, use_graph=True)
     ms, _ = timed(lambda: plan.stitch(batch, use_graph=True), steps)
     prof = plan.profile(batch, reps=3)
-    # per level: the interior launch (search slot) and the border launch
-    # (refinement slot)
+    # per level: the interior launch (refinement slot) and the border
+    # launch (search slot)
     lvl = [prof[2][k] + prof[4][k] for k in range(6)]
-    l0 = prof[2][0]
+    l0 = prof[4][0]
     win = (2 * p.lk_patch + 1) ** 2
     inner = sum(max(h - 2 * p.lk_patch, 0) * max(w - 2 * p.lk_patch, 0) for h, w, _ in shapes)
     flops = 2.0 * inner * win * (6 + iters * 11)
-    log(f"classic LK pyramid: {ms:.3f} ms per panorama, level 0 interior {l0:.3f} ms, border {prof[4][0]:.3f} ms")
+    log(f"classic LK pyramid: {ms:.3f} ms per panorama, level 0 interior {l0:.3f} ms, border {prof[2][0]:.3f} ms")
     return {"workload": "the same panorama, flow by the classic coarse-to-fine Lucas-Kanade (6 levels, "
                         f"{iters} Gauss-Newton steps per level, 5x5 window, double) + blend, batched graph replay",
             "ms_per_panorama": round(ms, 4), "mpix_s": round(total_px / ms / 1e3, 1),

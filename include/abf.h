@@ -344,7 +344,9 @@ abf_status abf_set_launch(abf_plan *plan, int32_t stage, int32_t size_class, int
  * milliseconds per launch to ms_out[stage * 12 + level] (stage numbering
  * of abf_get_launch; 6 * 12 floats, host memory); the refinement (level 0
  * only) reports its interior launch in the level-0 slot and its border-pixel
- * launch in the level-1 slot. Synchronous. */
+ * launch in the level-1 slot. With flow_method 1 the refinement slots hold
+ * each level's interior launch (which uses the refinement's launch shapes)
+ * and the search slots each level's border-pixel launch. Synchronous. */
 abf_status abf_profile(abf_plan *plan, const abf_strip *strips, int32_t n, int32_t reps, float *ms_out,
                        void *hip_stream);
 

@@ -441,16 +441,17 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
         if (p.flow_method == 1) {
             // classic coarse-to-fine Lucas-Kanade: one launch per level,
             // timed in the search stage's slots
-            // (interior pixels in the search slots, border pixels in the
-            // refinement's)
+            // (interior pixels in the refinement's slots, whose launch
+            // shapes they use and the tuner sets; border pixels in the
+            // search slots)
             LkParams lk{p.lk_patch, p.lk_iters, p.lk_eps};
             for (int k = N - 1; k >= 0; k--) {
                 const int c = b.cls[k];
                 const StripLv *lvk = lv + (size_t)k * n, *lvc = k == N - 1 ? nullptr : lv + (size_t)(k + 1) * n;
-                TIMED(ST_SEARCH, k,
+                TIMED(ST_REFINE, k,
                       launch_lk_interior(lvk, lvc, io, work(ST_REFINE, k), lk, pl->launch[ST_REFINE][c].tile_h,
                                          grid_of(pl, ST_REFINE, c), k == 0, s));
-                TIMED(ST_REFINE, k, launch_lk_border(lvk, lvc, io, work(LIST_REFINE_BORDER, k), lk, k == 0, s));
+                TIMED(ST_SEARCH, k, launch_lk_border(lvk, lvc, io, work(LIST_REFINE_BORDER, k), lk, k == 0, s));
             }
         }
         for (int k = N - 1; k >= 0 && p.flow_method == 0; k--) {
