@@ -41,7 +41,7 @@ def test_default_params(lib):
     p = _abi.default_params()
     assert (p.levels, p.patch, p.radius, p.radius_coarse, p.prop_steps, p.median) == (6, 2, 2, 4, 2, 1)
     assert (p.lk_patch, p.lk_iters, p.lk_eps, p.k_sharp, p.k_flowmag, p.blend_mode) == (2, 2, 25.0, 10.0, 20.0, 0)
-    assert p.gain_comp == 1
+    assert p.gain_comp == 1 and p.flow_method == 0
 
 
 def test_defaults_match_oracle_and_api():
@@ -57,7 +57,7 @@ def test_defaults_match_oracle_and_api():
 @pytest.mark.parametrize("field,value,status", [
     ("levels", 0, _abi.E_INVALID), ("levels", 13, _abi.E_INVALID), ("patch", 0, _abi.E_INVALID),
     ("lk_eps", 0.0, _abi.E_INVALID), ("lk_eps", float("nan"), _abi.E_INVALID), ("blend_mode", 2, _abi.E_INVALID),
-    ("gain_comp", 2, _abi.E_INVALID),
+    ("gain_comp", 2, _abi.E_INVALID), ("flow_method", 2, _abi.E_INVALID), ("flow_method", -1, _abi.E_INVALID),
     ("patch", 3, _abi.E_UNSUPPORTED), ("radius", 5, _abi.E_UNSUPPORTED), ("median", 2, _abi.E_UNSUPPORTED),
 ])
 def test_create_plan_rejects_parameters(lib, field, value, status):
@@ -101,3 +101,14 @@ def test_strip_struct_layout():
     assert ctypes.sizeof(_abi.AbfParams) == 56 and _abi.AbfParams.flow_method.offset == 52
     P = _abi.AbfPhoto
     assert P.mask.offset == 8 and P.pitch.offset == 16 and P.side.offset == 24 and ctypes.sizeof(P) == 32
+
+
+def test_canvas_and_merge_reject_null_plans(lib):
+    assert lib.abf_canvas_workspace_bytes(None, 10, 10) == 0
+    assert lib.abf_merge_workspace_bytes(None, 10, 10) == 0
+    assert lib.abf_overlap_box(None, None, None, 4, 4, 4, None, None) == _abi.E_INVALID
+    assert lib.abf_canvas_blend(None, None, None, 4, 4, 4, None, 4, None, None, 4, None) == _abi.E_INVALID
+    box = (ctypes.c_int32 * 4)(0, 0, 0, 0)
+    assert lib.abf_composite_canvas(None, None, None, None, None, 4, 4, 12, 12, 4, None, None, box, 0, None, 4,
+                                    None, 12, None, None) == _abi.E_INVALID
+    assert lib.abf_merge_photos(None, None, 0, 4, 4, 4, None, 12, None, 12, None, None, None) == _abi.E_INVALID
