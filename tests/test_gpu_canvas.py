@@ -237,3 +237,13 @@ def test_canvas_limits_are_enforced(api):
         small.overlap_box(wide, wide)
     with pytest.raises(ValueError):
         small.canvas_blend(wide, wide)
+
+
+def test_distances_are_bitwise_repeatable(api):
+    mL, mR = synth.random_masks(12, 300, 500, blobs=8)
+    plan = plan_for(api, 300, 500)
+    print("[gpu] canvas distances twice", flush=True)
+    a = [t.clone() for t in plan.canvas_blend(dev(mL), dev(mR), distances=True)]
+    b = plan.canvas_blend(dev(mL), dev(mR), distances=True)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(a, b))

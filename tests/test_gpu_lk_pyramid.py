@@ -124,3 +124,13 @@ def test_launch_shapes_give_identical_results(api):
 def test_flow_method_is_validated(api):
     with pytest.raises(ValueError):
         api.Plan(dataclasses.replace(api.Params(), flow_method=2))
+
+
+def test_runs_are_bitwise_repeatable(api):
+    s = synth.make_random(6, 90, 170, max_ux=8, max_uy=2, occluder=True)
+    plan = api.Plan(api.Params(levels=4, flow_method=1, lk_iters=4), max_strips=1, max_H=90, max_W=170)
+    print("[gpu] classic LK twice", flush=True)
+    a = [t.clone() for t in plan.flow_bidirectional(dev(s.L), dev(s.R))]
+    b = plan.flow_bidirectional(dev(s.L), dev(s.R))
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])

@@ -111,3 +111,16 @@ def test_merge_box_beyond_plan_limits(api):
     plan = api.Plan(api.Params(levels=3), max_strips=1, max_H=16, max_W=16, canvas=(H, W))
     with pytest.raises(ValueError):
         plan.merge_photos(photos)
+
+
+def test_merge_is_bitwise_repeatable(api):
+    H, W = 140, 300
+    photos = _photos(5, H, W, 3)
+    plan = api.Plan(api.Params(levels=3), max_strips=1, max_H=H, max_W=W, canvas=(H, W))
+    print("[gpu] merge twice", flush=True)
+    a, ca, ba = plan.merge_photos(photos)
+    a = a.clone()
+    ca = ca.clone()
+    b, cb, bb = plan.merge_photos(photos)
+    torch.cuda.synchronize()
+    assert ba == bb and torch.equal(a, b) and torch.equal(ca, cb)
