@@ -30,7 +30,10 @@
  *   - A plan is bound to the device current at creation, and is not
  *     thread-safe: use one plan per stream.
  *   - Errors are returned as abf_status; no C++ exception crosses the ABI.
- *     abf_last_error() gives the text of the last failure of a plan.
+ *     abf_last_error() gives the text of the last failure of a plan. The
+ *     environment variable ABF_LOG (read once) writes a log to stderr:
+ *     1 = failures, plan and graph set-up, tuning choices, merge steps;
+ *     2 = also every batched call.
  */
 #ifndef ABF_H
 #define ABF_H

@@ -75,16 +75,38 @@ struct abf_plan {
 
 namespace {
 
+// Logging to stderr by the ABF_LOG environment variable (read once):
+// 0 (default) silent; 1 failures, plan and workspace set-up, graph
+// captures, tuning choices and merge steps; 2 also every batched call.
+int log_level()
+{
+    static const int level = [] {
+        const char *v = getenv("ABF_LOG");
+        return v ? atoi(v) : 0;
+    }();
+    return level;
+}
+
+void logf(int level, const char *fmt, ...)
+{
+    if (log_level() < level) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[abf] %s\n", buf);
+}
+
 abf_status fail(abf_plan *pl, abf_status st, const char *fmt, ...)
 {
-    if (pl) {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof(buf), fmt, ap);
-        va_end(ap);
-        pl->err = buf;
-    }
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (pl) pl->err = buf;
+    logf(1, "error %d: %s", (int)st, buf);
     return st;
 }
 
@@ -519,11 +541,13 @@ abf_status run(abf_plan *pl, const abf_strip *st, int n, bool flows, bool blend,
         pl->lv_host = b.lv;
         pl->last_n = n;
     }
+    logf(2, "run: %d strip(s), flows %d, blend %d, graph %d", n, (int)flows, (int)blend, (int)use_graph);
     if (!use_graph) return enqueue(pl, b, flows, blend, s);
 
     const std::string key = graph_key(pl, b, flows, blend);
     auto it = pl->graphs.find(key);
     if (it == pl->graphs.end()) {
+        logf(1, "capturing a graph for %d strip(s) (%zu cached)", n, pl->graphs.size());
         if (!pl->cap_stream) HIP_TRY(pl, hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
         // the tables were uploaded on `s`; the capture stream only records
         HIP_TRY(pl, hipStreamSynchronize(s));
@@ -599,11 +623,12 @@ abf_status abf_create_plan(const abf_params *params, int32_t max_strips, int64_t
     if (max_strips < 1 || max_pixels < 1 || max_H < 1 || max_W < 1) return ABF_E_INVALID;
     if ((int64_t)max_H * max_W > max_pixels) max_pixels = (int64_t)max_H * max_W;
     int dev = 0, count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return ABF_E_UNSUPPORTED;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(nullptr, ABF_E_UNSUPPORTED, "no device");
     if (hipGetDevice(&dev) != hipSuccess) return ABF_E_UNSUPPORTED;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return ABF_E_UNSUPPORTED;
-    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ABF_E_UNSUPPORTED;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, ABF_E_UNSUPPORTED, "device %d is %s, not gfx950", dev, prop.gcnArchName);
 
     abf_plan *pl = new abf_plan();
     pl->p = *params;
@@ -641,6 +666,9 @@ abf_status abf_create_plan(const abf_params *params, int32_t max_strips, int64_t
             fclose(f);
         }
     }
+    logf(1, "plan on device %d (%s): %d strips, %lld px, %d x %d, %d levels, flow method %d; workspace %zu bytes",
+         dev, prop.gcnArchName, max_strips, (long long)max_pixels, max_H, max_W, params->levels,
+         params->flow_method, abf_workspace_bytes(pl));
     *out = pl;
     return ABF_OK;
 }
@@ -821,6 +849,8 @@ abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hi
                     }
                 }
             plan->launch[stage][c] = best;
+            logf(1, "tune: stage %d, size class %d: tile height %d, grid %d (%.4f ms)", stage, c, best.tile_h,
+                 best.grid, best_ms);
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1060,6 +1090,8 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
         HIP_TRY(plan, hipMemcpyAsync(hb, dbox, sizeof(hb), hipMemcpyDeviceToHost, s));
         HIP_TRY(plan, hipStreamSynchronize(s));
         if (boxes) memcpy(boxes + 4 * i, hb, sizeof(hb));
+        logf(1, "merge photo %d (axis %d, side %d): overlap box %d %d %d x %d", i, p.axis, p.side, hb[0], hb[1],
+             hb[2], hb[3]);
         const bool any = hb[2] > 0 && hb[3] > 0;
         if (any) {
             abf_strip st{};

@@ -112,3 +112,22 @@ def test_canvas_and_merge_reject_null_plans(lib):
     assert lib.abf_composite_canvas(None, None, None, None, None, 4, 4, 12, 12, 4, None, None, box, 0, None, 4,
                                     None, 12, None, None) == _abi.E_INVALID
     assert lib.abf_merge_photos(None, None, 0, 4, 4, 4, None, 12, None, 12, None, None, None) == _abi.E_INVALID
+
+
+def test_log_to_stderr_by_environment(lib):
+    import subprocess
+    import sys
+
+    code = ("from paper_2006_01201_amd import _abi; "
+            "print(_abi.create_plan(_abi.default_params(), 1, 100, 10, 10)[0])")
+    env = dict(os.environ, ABF_LOG="1", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    quiet = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                           env={k: v for k, v in env.items() if k != "ABF_LOG"}, cwd=ROOT)
+    import torch
+
+    if torch.cuda.is_available():
+        assert "[abf] plan on device" in r.stderr
+    else:
+        assert "[abf] error 5: no device" in r.stderr and r.stdout.strip() == "5"
+    assert "[abf]" not in quiet.stderr
