@@ -6,7 +6,9 @@ strip with the per-strip calls. The oracle runs the whole path on every
 strip, so nothing is sampled: every luma level, raw search and
 propagated + median flow at every level bit for bit, the refined flows
 within 1e-2 px at every pixel, and the blend kernel at these sizes on the
-oracle's flows within 0.5/255."""
+oracle's flows within 0.5/255. The same panorama with the classic
+coarse-to-fine Lucas-Kanade is checked at every level with that method's
+bars, and the canvas composite on the 4000 x 2400 pair canvas."""
 import numpy as np
 import pytest
 import torch
@@ -81,13 +83,20 @@ def check_blend(plan, name, L, R, axis, op, o_lr, o_rl):
     assert np.abs(F8.astype(int) - o8.astype(int)).max() <= 1, name
 
 
-def test_full_panorama_batched(api, tmp_path, monkeypatch):
+@pytest.fixture(scope="module")
+def panorama():
+    shapes = synth.strip_shapes(2, 0)
+    print(f"[gpu] full panorama: {len(shapes)} strips, "
+          f"{sum(h * w for h, w, _ in shapes) / 1e6:.2f} Mpx, generating", flush=True)
+    return synth.make_config(2, 0)
+
+
+def test_full_panorama_batched(api, panorama, tmp_path, monkeypatch):
     monkeypatch.setenv("ABF_TUNE_CACHE", str(tmp_path / "tune.json"))
     cfg = 2
     shapes = synth.strip_shapes(cfg, 0)
     total = sum(h * w for h, w, _ in shapes)
-    print(f"[gpu] full panorama: {len(shapes)} strips, {total / 1e6:.2f} Mpx, generating", flush=True)
-    strips = synth.make_config(cfg, 0)
+    strips = panorama
     p = api.Params(levels=synth.LEVELS[cfg])
     op = o_params(p)
     plan = api.Plan(p, max_strips=len(shapes), max_pixels=total, max_H=max(h for h, _, _ in shapes),
@@ -125,3 +134,69 @@ def test_full_single_strip(api):
     views = gpu_levels(plan, 0, p.levels)
     o_lr, o_rl = check_flows(f"strip {H}x{W}", s.L, s.R, op, views, flr.cpu().numpy(), frl.cpu().numpy())
     check_blend(plan, f"strip {H}x{W}", s.L, s.R, s.axis, op, o_lr, o_rl)
+
+
+def test_full_panorama_classic_lk(api, panorama):
+    # flow method 1 as the benchmark runs it: 6 levels, 4 Gauss-Newton
+    # steps per level, one batch, graph replay; every level of every strip
+    # within the method's bars (1e-3 px, and 99.9 % within 1e-4 px)
+    strips = panorama
+    shapes = [(s.L.shape[0], s.L.shape[1]) for s in strips]
+    p = api.Params(levels=6, flow_method=1, lk_iters=4)
+    plan = api.Plan(p, max_strips=len(strips), max_pixels=sum(h * w for h, w in shapes),
+                    max_H=max(h for h, _ in shapes), max_W=max(w for _, w in shapes))
+    batch = plan.make_batch([(dev(s.L), dev(s.R), s.axis) for s in strips])
+    print("[gpu] full panorama, classic LK: batched graph replay", flush=True)
+    out = plan.stitch(batch, use_graph=True)
+    torch.cuda.synchronize()
+    gpu = []
+    for i in range(len(strips)):
+        lv = [[out[i]["flow_lr"].cpu().numpy()], [out[i]["flow_rl"].cpu().numpy()]]
+        for d in (0, 1):
+            for k in range(1, p.levels):
+                lv[d].append(plan.lk_level_flow(i, k, d).cpu().numpy())
+        gpu.append(lv)
+    op = oracle.Params(levels=6, lk_iters=4)
+    for i, s in enumerate(strips):
+        o = oracle.flow_lk_bidirectional(s.L, s.R, op)
+        worst = 0.0
+        for d in (0, 1):
+            for k in range(p.levels):
+                e = np.abs(gpu[i][d][k].astype(np.float64) - o[d][k]).max(axis=2)
+                worst = max(worst, e.max())
+                assert e.max() <= 1e-3, (i, d, k, e.max())
+                assert (e <= 1e-4).mean() >= 0.999, (i, d, k)
+        gpu[i] = None
+        print(f"classic LK strip {i} {s.L.shape[0]}x{s.L.shape[1]}: max |gpu - oracle| {worst:.3g} px", flush=True)
+
+
+def test_full_canvas_composite(api):
+    # the 4000 x 2400 pair canvas of the benchmark: box, the flows on the
+    # box crops, and Code 1 over the canvas on the oracle's flows and a
+    # given Blend map (eq. (1) over this canvas is checked pixel by pixel
+    # at sampled points in the canvas tests)
+    c = synth.make_canvas(0, 4000, 2400, holes=2)
+    H, W = c.mask_L.shape
+    p = api.Params(levels=6)
+    op = o_params(p)
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, canvas=(H, W))
+    print(f"[gpu] full canvas {H}x{W}", flush=True)
+    box = oracle.overlap_box(c.mask_L, c.mask_R)
+    assert plan.overlap_box(dev(c.mask_L), dev(c.mask_R)) == box
+    bx, by, bw, bh = box
+    Lc, Rc = c.L[by:by + bh, bx:bx + bw], c.R[by:by + bh, bx:bx + bw]
+    o_lr, o_rl = oracle.flow_bidirectional(Lc, Rc, op)
+    g_lr, g_rl = plan.flow_bidirectional(dev(Lc), dev(Rc))
+    torch.cuda.synchronize()
+    assert max(np.abs(g_lr.cpu().numpy() - o_lr).max(), np.abs(g_rl.cpu().numpy() - o_rl).max()) <= FLOW_TOL
+    f_lr, f_rl = o_lr.astype(np.float32), o_rl.astype(np.float32)
+    blend = synth.rng_for(116, 0, 0).uniform(0, 1, (H, W)).astype(np.float32)
+    F8, Ff = plan.composite_canvas(dev(c.L), dev(c.R), dev(c.mask_L), dev(c.mask_R), dev(f_lr), dev(f_rl), box,
+                                   axis=0, blend=dev(blend), f32=True)
+    torch.cuda.synchronize()
+    oF, o8 = oracle.composite(c.L, c.R, c.mask_L, c.mask_R, f_lr, f_rl, box, axis=0, blend=blend, params=op)
+    Ff, F8 = Ff.cpu().numpy(), F8.cpu().numpy()
+    assert np.abs(Ff - oF).max() <= F_TOL
+    safe = np.abs(oF - np.floor(oF) - 0.5) > F_TOL
+    assert np.array_equal(F8[safe], o8[safe])
+    assert np.abs(F8.astype(int) - o8.astype(int)).max() <= 1
