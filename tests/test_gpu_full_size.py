@@ -200,3 +200,32 @@ def test_full_canvas_composite(api):
     safe = np.abs(oF - np.floor(oF) - 0.5) > F_TOL
     assert np.array_equal(F8[safe], o8[safe])
     assert np.abs(F8.astype(int) - o8.astype(int)).max() <= 1
+
+
+def test_full_merge_equals_stepwise_calls(api):
+    # the benchmark's photo set (6 ring photos + top on a 4000 x 9000
+    # canvas, images generated on the GPU): the native merge equals the
+    # same steps issued one call at a time, bit for bit, and its coverage
+    # is the union of the photos' masks (a property at any size; every
+    # kind of step is checked against the oracle in the merge tests)
+    H, W = 4000, 9000
+    photos = synth.make_panorama_photos(0, H, W, n_ring=6, device="cuda")
+    p = api.Params(levels=6)
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, max_pixels=8 << 20, canvas=(H, W))
+    print(f"[gpu] full merge {H}x{W}, {len(photos)} photos", flush=True)
+    canvas, cov, boxes = plan.merge_photos(photos)
+    canvas, cov = canvas.clone(), cov.clone()
+    img0, m0 = photos[0][0], photos[0][1]
+    acc = img0 * (m0 > 0)[..., None]
+    c = (m0 > 0).to(torch.uint8)
+    for i, (img, m, axis, side) in enumerate(photos[1:], start=1):
+        L, R, mL, mR = (acc, img, c, m) if side == 0 else (img, acc, m, c)
+        box = plan.overlap_box(mL, mR)
+        assert box == boxes[i], i
+        bx, by, bw, bh = box
+        flr, frl = plan.flow_bidirectional(L[by:by + bh, bx:bx + bw], R[by:by + bh, bx:bx + bw])
+        acc = plan.composite_canvas(L, R, mL, mR, flr, frl, box, axis=axis)
+        c = torch.maximum(c, (m > 0).to(torch.uint8))
+    torch.cuda.synchronize()
+    assert torch.equal(canvas, acc)
+    assert torch.equal(cov, c)
