@@ -864,9 +864,11 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(const StripLv *__restrict
 // S(d) = sum g Tgt(q + d) are dot products of 16-bit pairs (v_dot2_i32_i16).
 // The bilinear sample is linear in its four corners, so the right-hand side
 // sum g (Tgt(q + u) - A) of a fractional u is the bilinear combination of
-// S(d) - sum g A over the corners d of the cell of u, formed in double with
-// the 2x2 solve. Window rows are padded to an even width with a zero
-// gradient, so the padding sample never contributes.
+// S(d) - sum g A over the corners d of the cell of u, formed in FP32 with
+// the 2x2 solve (the sums convert exactly; the combination, the solve and
+// the iterate round at 2^-24 relative, far below the flow tolerance: the
+// flow is stored as FP32 anyway). Window rows are padded to an even width
+// with a zero gradient, so the padding sample never contributes.
 //
 // A pixel whose window lies inside the image reads its Ref rows and its
 // (WN+1)^2 Tgt block from the padded planes; a pixel near the border (its
@@ -934,8 +936,47 @@ __device__ __forceinline__ void tgt_pairs(const uint32_t (&t)[NO], uint32_t (&e)
     if constexpr (K + 1 < NP) tgt_pairs<NP, K + 1>(t, e, o);
 }
 
+// The 2x2 solve of a refinement step, in FP32. Its inputs are integer
+// window sums (below 2^23 in magnitude for windows up to 5x5, so they
+// convert exactly); the determinant is Kahan's compensated ad - bc, since
+// it cancels where the window's gradients are nearly parallel. The entries
+// kept are those of H^-1 / 2 (the step is -H^-1 (b / 2), g doubled).
+struct RefineSolve {
+    float ixx, ixy, iyy;
+};
+__device__ __forceinline__ RefineSolve refine_solve(int hxx, int hxy, int hyy, float eps)
+{
+    const float Hxx = 0.25f * (float)hxx + eps, Hxy = 0.25f * (float)hxy, Hyy = 0.25f * (float)hyy + eps;
+    const float w = Hxy * Hxy;
+    const float det = fmaf(Hxx, Hyy, -w) + fmaf(-Hxy, Hxy, w);
+    const float hdet = 0.5f / det;
+    return {Hyy * hdet, Hxy * hdet, Hxx * hdet};
+}
+// sum over the window of g (Tgt(q + u) - A) from the corner correlations
+// S(d) of the cell of u (corner (a, b) at column offset a, row offset b)
+// and sum g A, with the bilinear weights of u's fraction
+__device__ __forceinline__ float corner_mix(int s00, int s01, int s10, int s11, int sa, float fx, float fy)
+{
+    const float t = fmaf(fx, (float)(s01 - s00), (float)(s00 - sa));
+    const float b = fmaf(fx, (float)(s11 - s10), (float)(s10 - sa));
+    return fmaf(fy, b - t, t);
+}
+// one Gauss-Newton update, each component clamped to within 1 px of the
+// integer flow
+__device__ __forceinline__ void refine_update(const RefineSolve &q, float bx, float by, int d0x, int d0y, float &ux,
+                                              float &uy)
+{
+    const float dx = fmaf(q.ixy, by, -q.ixx * bx);
+    const float dy = fmaf(q.ixy, bx, -q.iyy * by);
+    ux = fminf(fmaxf(ux + dx, (float)(d0x - 1)), (float)(d0x + 1));
+    uy = fminf(fmaxf(uy + dy, (float)(d0y - 1)), (float)(d0y + 1));
+}
+
+// Register budget: at most 80 VGPRs, so that 6 waves share a SIMD and hide
+// more of the row-load latency (the compiler fits it without spills; with
+// its own choice of 121 VGPRs, 4 waves, the level-0 launch took 15 % longer).
 template <int LP, int TH>
-__global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
+__global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
                                                     const int32_t *__restrict__ prefix, int n, int total, int iters,
                                                     float eps)
 {
@@ -986,21 +1027,18 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
                     say = dot2(gyp[j][k], op[j + 1][k], say);
                 }
         }
-        // the step is -H^-1 (b / 2): keep the entries of H^-1 / 2
-        const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
-        const double hdet = 0.5 / (Hxx * Hyy - Hxy * Hxy);
-        const double ixx = Hyy * hdet, ixy = Hxy * hdet, iyy = Hxx * hdet;
-        double ux = d0x, uy = d0y;
+        const RefineSolve q = refine_solve(hxx, hxy, hyy, eps);
+        float ux = (float)d0x, uy = (float)d0y;
         for (int it = 0; it < iters; it++) {
-            const double fux = floor(ux), fuy = floor(uy);
-            const double fx = ux - fux, fy = uy - fuy;
+            const float fux = floorf(ux), fuy = floorf(uy);
+            const float fx = ux - fux, fy = uy - fuy;
             // the (WN+1)^2 target block at the cell of u; a block beyond the
             // padded border lies wholly on one side of the image, where every
             // sample is the edge value, so its origin is clamped to the
             // padded range without changing any sample
             const int c0 = clampi(x - LP + (int)fux, -kPad, W - 1 + kPad - (WN + 1));
             const int r0 = clampi(y - LP + (int)fuy, -kPad, H - 1 + kPad - WN);
-            double bx, by;  // sum over the window of g (Tgt - A), g doubled
+            float bx, by;  // sum over the window of g (Tgt - A), g doubled
             if (it == 0) {
                 // the integer start: one corner
                 int sx = 0, sy = 0;
@@ -1016,8 +1054,8 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
                         sy = dot2(gyp[j][k], te[k], sy);
                     }
                 }
-                bx = (double)(sx - sax);
-                by = (double)(sy - say);
+                bx = (float)(sx - sax);
+                by = (float)(sy - say);
             } else {
                 int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
                 uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
@@ -1042,19 +1080,12 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
                         }
                     }
                 }
-                const double tx = (double)(s00x - sax) + fx * (double)(s01x - s00x);
-                const double bx1 = (double)(s10x - sax) + fx * (double)(s11x - s10x);
-                const double ty = (double)(s00y - say) + fx * (double)(s01y - s00y);
-                const double by1 = (double)(s10y - say) + fx * (double)(s11y - s10y);
-                bx = tx + fy * (bx1 - tx);
-                by = ty + fy * (by1 - ty);
+                bx = corner_mix(s00x, s01x, s10x, s11x, sax, fx, fy);
+                by = corner_mix(s00y, s01y, s10y, s11y, say, fx, fy);
             }
-            const double dx = ixy * by - ixx * bx;
-            const double dy = ixy * bx - iyy * by;
-            ux = fmin(fmax(ux + dx, (double)(d0x - 1)), (double)(d0x + 1));
-            uy = fmin(fmax(uy + dy, (double)(d0y - 1)), (double)(d0y + 1));
+            refine_update(q, bx, by, d0x, d0y, ux, uy);
         }
-        const uint64_t packed = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
+        const uint64_t packed = (uint64_t)__float_as_uint(ux) | ((uint64_t)__float_as_uint(uy) << 32);
         gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(uint32_t)(y * W + x)] = packed;
     }
 }
@@ -1172,13 +1203,11 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
                 say = dot2(gyp[j][k], av, say);
             }
         }
-        const double Hxx = 0.25 * hxx + eps, Hxy = 0.25 * hxy, Hyy = 0.25 * hyy + eps;
-        const double hdet = 0.5 / (Hxx * Hyy - Hxy * Hxy);
-        const double ixx = Hyy * hdet, ixy = Hxy * hdet, iyy = Hxx * hdet;
-        double ux = d0x, uy = d0y;
+        const RefineSolve q = refine_solve(hxx, hxy, hyy, eps);
+        float ux = (float)d0x, uy = (float)d0y;
         for (int it = 0; it < iters; it++) {
-            const double fux = floor(ux), fuy = floor(uy);
-            const double fx = ux - fux, fy = uy - fuy;
+            const float fux = floorf(ux), fuy = floorf(uy);
+            const float fx = ux - fux, fy = uy - fuy;
             // the Tgt run of a row: samples at qx[i] + ux, cell columns
             // qx[i] + floor(ux) (+ 1); a run beyond the padded border lies
             // wholly on one side of the image and is clamped to it unchanged
@@ -1214,17 +1243,10 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
                     s11y = dot2(gyp[j][k], ob, s11y);
                 }
             }
-            const double tx = (double)(s00x - sax) + fx * (double)(s01x - s00x);
-            const double bx1 = (double)(s10x - sax) + fx * (double)(s11x - s10x);
-            const double ty = (double)(s00y - say) + fx * (double)(s01y - s00y);
-            const double by1 = (double)(s10y - say) + fx * (double)(s11y - s10y);
-            const double bx = tx + fy * (bx1 - tx), by = ty + fy * (by1 - ty);
-            const double dx = ixy * by - ixx * bx;
-            const double dy = ixy * bx - iyy * by;
-            ux = fmin(fmax(ux + dx, (double)(d0x - 1)), (double)(d0x + 1));
-            uy = fmin(fmax(uy + dy, (double)(d0y - 1)), (double)(d0y + 1));
+            refine_update(q, corner_mix(s00x, s01x, s10x, s11x, sax, fx, fy),
+                          corner_mix(s00y, s01y, s10y, s11y, say, fx, fy), d0x, d0y, ux, uy);
         }
-        const uint64_t packed = (uint64_t)__float_as_uint((float)ux) | ((uint64_t)__float_as_uint((float)uy) << 32);
+        const uint64_t packed = (uint64_t)__float_as_uint(ux) | ((uint64_t)__float_as_uint(uy) << 32);
         gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(uint32_t)(y * W + x)] = packed;
     }
 }
@@ -1359,13 +1381,13 @@ __global__ __launch_bounds__(kRowTW) void k_lk_border(const StripLv *__restrict_
 // 4 H, sum G Ref and, per step, the four corner correlations of the target
 // block at the cell of u (its origin clamped to the padded range as in
 // k_refine), combined with the bilinear weights in double. The seed is
-// fractional, so every step takes the four corners; no clamp.
+// fractional, so every step takes the four corners; no clamp. Register
+// budget: at most 96 VGPRs (5 waves per SIMD; one value spilled), 4 %
+// faster than the compiler's own 105 at 4 waves.
 template <int LP, int TH>
-__global__ __launch_bounds__(64 * TH) void k_lk_interior(const StripLv *__restrict__ lv,
-                                                         const StripLv *__restrict__ lvc,
-                                                         const StripIO *__restrict__ io,
-                                                         const int32_t *__restrict__ prefix, int n, int total,
-                                                         int iters, double eps, bool level0)
+__global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_lk_interior(
+    const StripLv *__restrict__ lv, const StripLv *__restrict__ lvc, const StripIO *__restrict__ io,
+    const int32_t *__restrict__ prefix, int n, int total, int iters, double eps, bool level0)
 {
     constexpr int TW = kRefineTW;
     constexpr int WN = 2 * LP + 1;
