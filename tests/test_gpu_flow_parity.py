@@ -55,6 +55,9 @@ CASES = {
     "noise_tie_rich_40x72": lambda: (synth.random_levels(6, (40, 72, 3), 3), synth.random_levels(7, (40, 72, 3), 3),
                                      0, 3),
     "cfg1_rows_0_320": lambda: (*_crop(1, 0, slice(0, 320)), 6),
+    # every gradient parallel to (1, 1): each window's normal matrix is
+    # rank one plus eps I, the refinement's worst-conditioned case
+    "diagonal_edges_90x120": lambda: (*_diagonal_pair(90, 120, 2.4), 0, 3),
     # flows that carry every sample of a border tile past the image edge
     "off_edge_shift_48x77": lambda: (*_shift_pair(48, 77, 21, 3), 0, 3),
     "off_edge_shift_neg_37x70": lambda: (*_shift_pair(37, 70, -25, -6), 0, 3),
@@ -66,6 +69,23 @@ def _shift_pair(H, W, sx, sy):
     L = big[32:32 + H, 32:32 + W]
     R = big[32 + sy:32 + sy + H, 32 + sx:32 + sx + W]  # R(p) = L(p + s)
     return np.ascontiguousarray(L), np.ascontiguousarray(R)
+
+
+def _diagonal_pair(H, W, s):
+    # a texture of x + y only: random steps of 0..255 every 3 to 6 px,
+    # softened by a 3-tap box; R(p) = L(p + (s, 0)) by linear interpolation
+    r = synth.rng_for(123, H, W)
+    n = H + W + 64
+    steps = np.repeat(r.integers(0, 256, n), r.integers(3, 7, n))[:n + 8].astype(np.float64)
+    prof = np.convolve(steps, np.ones(3) / 3.0, mode="same")
+    t = np.arange(H)[:, None] + np.arange(W)[None, :] + 16.0
+    def at(u):
+        i = np.floor(u).astype(int)
+        f = u - i
+        return prof[i] * (1 - f) + prof[i + 1] * f
+    L = np.clip(np.rint(at(t)), 0, 255).astype(np.uint8)
+    R = np.clip(np.rint(at(t + s)), 0, 255).astype(np.uint8)
+    return np.repeat(L[..., None], 3, axis=2), np.repeat(R[..., None], 3, axis=2)
 
 
 def run_case(api, name, params=None):
