@@ -937,10 +937,11 @@ __device__ __forceinline__ void tgt_pairs(const uint32_t (&t)[NO], uint32_t (&e)
 }
 
 // The 2x2 solve of a refinement step, in FP32. Its inputs are integer
-// window sums (below 2^23 in magnitude for windows up to 5x5, so they
-// convert exactly); the determinant is Kahan's compensated ad - bc, since
-// it cancels where the window's gradients are nearly parallel. The entries
-// kept are those of H^-1 / 2 (the step is -H^-1 (b / 2), g doubled).
+// window sums (|g| <= 255, so below 2^23 in magnitude for every window up
+// to 7x7: they convert exactly); the determinant is Kahan's compensated
+// ad - bc, since it cancels where the window's gradients are nearly
+// parallel. The entries kept are those of H^-1 / 2 (the step is
+// -H^-1 (b / 2), g doubled).
 struct RefineSolve {
     float ixx, ixy, iyy;
 };
@@ -972,11 +973,12 @@ __device__ __forceinline__ void refine_update(const RefineSolve &q, float bx, fl
     uy = fminf(fmaxf(uy + dy, (float)(d0y - 1)), (float)(d0y + 1));
 }
 
-// Register budget: at most 80 VGPRs, so that 6 waves share a SIMD and hide
-// more of the row-load latency (the compiler fits it without spills; with
-// its own choice of 121 VGPRs, 4 waves, the level-0 launch took 15 % longer).
+// Register budget: for windows up to 5x5 at most 80 VGPRs, so that 6 waves
+// share a SIMD and hide more of the row-load latency (the compiler fits it
+// without spills; with its own choice of 121 VGPRs, 4 waves, the level-0
+// launch took 15 % longer); the 7x7 window keeps the compiler's budget.
 template <int LP, int TH>
-__global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
+__global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(LP <= 2 ? 6 : 1, 8))) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
                                                     const int32_t *__restrict__ prefix, int n, int total, int iters,
                                                     float eps)
 {
@@ -1382,10 +1384,11 @@ __global__ __launch_bounds__(kRowTW) void k_lk_border(const StripLv *__restrict_
 // block at the cell of u (its origin clamped to the padded range as in
 // k_refine), combined with the bilinear weights in double. The seed is
 // fractional, so every step takes the four corners; no clamp. Register
-// budget: at most 96 VGPRs (5 waves per SIMD; one value spilled), 4 %
-// faster than the compiler's own 105 at 4 waves.
+// budget for windows up to 5x5: at most 96 VGPRs (5 waves per SIMD; one
+// value spilled), 4 % faster than the compiler's own 105 at 4 waves; the
+// 7x7 window keeps the compiler's budget (capped, it would spill).
 template <int LP, int TH>
-__global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_lk_interior(
+__global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(LP <= 2 ? 5 : 1, 8))) void k_lk_interior(
     const StripLv *__restrict__ lv, const StripLv *__restrict__ lvc, const StripIO *__restrict__ io,
     const int32_t *__restrict__ prefix, int n, int total, int iters, double eps, bool level0)
 {

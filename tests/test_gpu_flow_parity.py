@@ -151,6 +151,43 @@ def test_flow_parity_param_grid(api, T, M, R):
     assert np.abs(flr.cpu().numpy() - o_lr).max() <= FLOW_TOL
 
 
+@pytest.mark.parametrize("kw", [dict(lk_patch=3, lk_iters=3), dict(lk_patch=1, lk_iters=4, lk_eps=4.0),
+                                dict(lk_iters=8, lk_eps=100.0), dict(lk_iters=0), dict(gain_comp=0)],
+                         ids=["window7_K3", "window3_K4_eps4", "K8_eps100", "K0", "no_exposure_step"])
+def test_flow_parity_refinement_params(api, kw):
+    # the refinement's other windows (3x3, 7x7), step counts (none, up to
+    # the maximum 8) and regularisations, and the path without the
+    # exposure step
+    L, R, axis, p, g_lr, g_rl, views = run_case(api, "occluder_130x197", dataclasses.replace(api.Params(), **kw))
+    o_lr, o_rl, lv = oracle.flow_bidirectional(L, R, o_params(p), levels_out=True)
+    for k in range(p.levels):
+        for d, tag in ((0, "lr"), (1, "rl")):
+            assert np.array_equal(views[(2, k, d)], lv["final_" + tag][k]), f"final {tag} level {k}"
+    assert np.abs(g_lr - o_lr).max() <= FLOW_TOL
+    assert np.abs(g_rl - o_rl).max() <= FLOW_TOL
+    if kw.get("lk_iters") == 0:
+        # no Gauss-Newton step: the refined flow is the integer flow
+        assert np.array_equal(g_lr, views[(2, 0, 0)].astype(np.float32))
+        assert np.array_equal(g_rl, views[(2, 0, 1)].astype(np.float32))
+
+
+@pytest.mark.parametrize("ks,kf", [(60.0, 80.0), (0.5, 0.0)], ids=["sharp", "flat"])
+def test_blend_softmax_parameters(api, ks, kf):
+    # a sharp softmax (exponents in the hundreds, nearly a hard switch) and
+    # a flat one without the flow-magnitude term
+    L, R, axis, levels = CASES["occluder_130x197"]()
+    H, W = L.shape[:2]
+    p = api.Params(levels=levels, k_sharp=ks, k_flowmag=kf)
+    op = o_params(p)
+    o_lr, o_rl = oracle.flow_bidirectional(L, R, op)
+    f_lr, f_rl = o_lr.astype(np.float32), o_rl.astype(np.float32)
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W)
+    print(f"[gpu] blend kS={ks} kF={kf}", flush=True)
+    F8, Ff = plan.blend_asymmetric(to_dev(L), to_dev(R), to_dev(f_lr), to_dev(f_rl), axis=axis, f32=True)
+    oF, _ = oracle.blend(L, R, f_lr, f_rl, axis=axis, params=op)
+    _check_blend(F8.cpu().numpy(), Ff.cpu().numpy(), oF)
+
+
 def _check_blend(F8, Ff, oF):
     assert np.abs(Ff - oF).max() <= F_TOL
     r = oF - np.floor(oF)
