@@ -1194,8 +1194,15 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
 #pragma unroll
             for (int k = 0; k < NP; k++) {
                 const uint32_t av = __builtin_amdgcn_perm(r[1][1], r[1][0], sA[k]);
-                gxp[j][k] = sub2(__builtin_amdgcn_perm(r[1][1], r[1][0], sR[k]),
-                                 __builtin_amdgcn_perm(r[1][1], r[1][0], sL[k]));
+                uint32_t right = __builtin_amdgcn_perm(r[1][1], r[1][0], sR[k]);
+                if constexpr (AB > 8) {
+                    // 7x7 window: the right tap of the last (half) pair can be
+                    // byte 8 of the run, beyond the 8 bytes one v_perm_b32
+                    // reaches; it is byte 4 of the next dword pair
+                    if (k == NP - 1 && qx[WN - 1] - qx[0] + 2 == 8)
+                        right = __builtin_amdgcn_perm(r[1][2], r[1][1], psel(4, -1));
+                }
+                gxp[j][k] = sub2(right, __builtin_amdgcn_perm(r[1][1], r[1][0], sL[k]));
                 gyp[j][k] = sub2(__builtin_amdgcn_perm(r[2][1], r[2][0], sA[k]),
                                  __builtin_amdgcn_perm(r[0][1], r[0][0], sA[k]));
                 hxx = dot2(gxp[j][k], gxp[j][k], hxx);

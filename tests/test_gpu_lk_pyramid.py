@@ -61,7 +61,7 @@ def _inputs(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("patch,iters", [(2, 4), (1, 2)])
+@pytest.mark.parametrize("patch,iters", [(2, 4), (1, 2), (3, 2)])
 def test_levels_match_oracle(api, name, patch, iters):
     L, R, levels = _inputs(name)
     H, W = L.shape[:2]
