@@ -151,6 +151,45 @@ def test_flow_parity_param_grid(api, T, M, R):
     assert np.abs(flr.cpu().numpy() - o_lr).max() <= FLOW_TOL
 
 
+@pytest.mark.parametrize("R,Rc", [(2, 2), (4, 4), (1, 4)])
+def test_flow_parity_patch3x3(api, R, Rc):
+    # 3x3 patches in the search and the propagation at every radius
+    L, R_img, _, _ = CASES["occluder_130x197"]()
+    H, W = L.shape[:2]
+    p = api.Params(levels=4, patch=1, radius=R, radius_coarse=Rc)
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W)
+    print(f"[gpu] 3x3 patches R={R} Rc={Rc}", flush=True)
+    flr, frl = plan.flow_bidirectional(to_dev(L), to_dev(R_img))
+    torch.cuda.synchronize()
+    o_lr, o_rl, lv = oracle.flow_bidirectional(L, R_img, o_params(p), levels_out=True)
+    for k in range(p.levels):
+        for d, tag in ((0, "lr"), (1, "rl")):
+            assert np.array_equal(plan.view(1, 0, k, d).cpu().numpy().astype(np.int32), lv["search_" + tag][k])
+            assert np.array_equal(plan.view(2, 0, k, d).cpu().numpy().astype(np.int32), lv["final_" + tag][k])
+    assert np.abs(flr.cpu().numpy() - o_lr).max() <= FLOW_TOL
+    assert np.abs(frl.cpu().numpy() - o_rl).max() <= FLOW_TOL
+
+
+@pytest.mark.parametrize("levels", [1, 8, 12])
+def test_flow_parity_pyramid_depths(api, levels):
+    # one level (the search at the coarse radius with no centre) and
+    # pyramids that reach 1 x 1 and repeat it up to the maximum depth
+    L, R, _, _ = CASES["ragged_37x53"]()
+    H, W = L.shape[:2]
+    p = api.Params(levels=levels)
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W)
+    print(f"[gpu] pyramid depth {levels}", flush=True)
+    flr, frl = plan.flow_bidirectional(to_dev(L), to_dev(R))
+    torch.cuda.synchronize()
+    o_lr, o_rl, lv = oracle.flow_bidirectional(L, R, o_params(p), levels_out=True)
+    for k in range(levels):
+        for d, tag in ((0, "lr"), (1, "rl")):
+            g = plan.view(2, 0, k, d).cpu().numpy().astype(np.int32)
+            assert np.array_equal(g, lv["final_" + tag][k]), f"final {tag} level {k}"
+    assert np.abs(flr.cpu().numpy() - o_lr).max() <= FLOW_TOL
+    assert np.abs(frl.cpu().numpy() - o_rl).max() <= FLOW_TOL
+
+
 @pytest.mark.parametrize("kw", [dict(lk_patch=3, lk_iters=3), dict(lk_patch=1, lk_iters=4, lk_eps=4.0),
                                 dict(lk_iters=8, lk_eps=100.0), dict(lk_iters=0), dict(gain_comp=0)],
                          ids=["window7_K3", "window3_K4_eps4", "K8_eps100", "K0", "no_exposure_step"])
