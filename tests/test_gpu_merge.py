@@ -124,3 +124,28 @@ def test_merge_is_bitwise_repeatable(api):
     b, cb, bb = plan.merge_photos(photos)
     torch.cuda.synchronize()
     assert ba == bb and torch.equal(a, b) and torch.equal(ca, cb)
+
+
+def test_merge_with_a_disjoint_photo(api):
+    # photo 1 does not touch the canvas merged so far (empty overlap box:
+    # no flows, Area1 and Area2 copied); photo 2 overlaps both
+    H, W = 100, 240
+    imgs = synth.make_panorama_photos(11, H, W, n_ring=3)
+    spans = [(0, 100), (140, 240), (60, 180)]
+    photos = []
+    for (img, _, _, _), (a, b) in zip(imgs, spans):
+        m = np.zeros((H, W), np.uint8)
+        m[:, a:b] = 1
+        photos.append((dev(img), dev(m), 0, 0))
+    plan = api.Plan(api.Params(levels=3), max_strips=1, max_H=H, max_W=W, canvas=(H, W))
+    print("[gpu] merge with a disjoint photo", flush=True)
+    canvas, cov, boxes = plan.merge_photos(photos)
+    torch.cuda.synchronize()
+    assert boxes[1] == (0, 0, 0, 0) and boxes[2][2] > 0
+    states, _, sboxes = _stepwise(plan, photos)
+    assert boxes == sboxes
+    assert torch.equal(canvas, states[-1][0]) and torch.equal(cov, states[-1][1])
+    # after the disjoint step the canvas is each photo on its own span
+    acc1 = states[1][0].cpu().numpy()
+    assert np.array_equal(acc1[:, 140:], imgs[1][0][:, 140:]) and np.array_equal(acc1[:, :100], imgs[0][0][:, :100])
+    assert (acc1[:, 100:140] == 0).all()
