@@ -534,6 +534,107 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
     }
 }
 
+// The same search for 5x5 patches with a 2 x 2 quad of pixels per thread
+// (x, x+1 at rows y, y+1 with y even): the four share the centre, one set
+// of 2R+6 target rows serves them, and for each candidate the sums of
+// rows y-1 .. y+2 (middle four columns, and the two outer columns on
+// their own) are shared, so the row y-2 and y+3 terms are all that
+// differ between the two rows of the quad: 18 v_sad_u8 per candidate for
+// four pixels instead of 30. A tile of TH rows (TH even) is TH/2 waves,
+// each a row pair of 128 columns; results are those of k_search.
+template <int R, int TH>
+__global__ __launch_bounds__(32 * TH) void k_search_quad(const StripLv *__restrict__ lv,
+                                                         const int32_t *__restrict__ prefix, int n, int total)
+{
+    constexpr int P = 2;
+    constexpr int NC = 2 * R + 1;          // candidates per axis
+    constexpr int NR = 2 * R + 2 * P + 2;  // target rows (both output rows)
+    constexpr int NB = 2 * R + 2 * P + 2;  // target bytes per row (both pixels)
+    constexpr int NBO = (NB + 3) / 4;
+    constexpr int RB = 2 * P + 2;          // reference bytes per row (both pixels)
+    static_assert(TH % 2 == 0, "row pairs");
+    const int lane = threadIdx.x & 63, wpair = threadIdx.x >> 6;
+    TILE_LOOP(total)
+    {
+        const int s = find_strip(prefix, n, t);
+        int local = t - prefix[s];
+        const StripLv &L = lv[s];
+        const int H = L.H, W = L.W, yp = L.ypitch;
+        const int ntx = ceil_div(W, kSearchTW), per_dir = ntx * ceil_div(H, TH);
+        const int dir = local / per_dir;
+        local -= dir * per_dir;
+        const int tyi = local / ntx;
+        const int x = (local - tyi * ntx) * kSearchTW + 2 * lane, y = tyi * TH + 2 * wpair;
+        if (x >= W || y >= H) continue;  // no barrier in this kernel
+        const uint8_t *ref = L.y[dir], *tgt = L.y[1 - dir];
+        int cx = 0, cy = 0;
+        if (L.dc[dir]) {
+            const uint32_t v = gld(L.dc[dir])[(size_t)min(y >> 1, L.Hc - 1) * L.fpitch_c + min(x >> 1, L.Wc - 1)];
+            cx = 2 * unpack_x(v);
+            cy = 2 * unpack_y(v);
+        }
+        // reference rows y-P .. y+1+P (row y+1 may be the first row past the
+        // image: its rows lie in the padded border), columns x-P .. x+1+P
+        uint32_t rr[2 * P + 2][(RB + 3) / 4];
+        load_rows<RB, 2 * P + 2>(plane_org(ref, yp), yp, y - P, x - P, rr);
+        const int c0 = x + cx - R - P, r0 = y + cy - R - P;
+        const bool inpad = c0 >= -kPad && c0 + NB - 1 <= W - 1 + kPad && r0 >= -kPad && r0 + NR - 1 <= H - 1 + kPad;
+        uint32_t tt[NR][NBO];
+        if (inpad) {
+            load_rows<NB, NR>(plane_org(tgt, yp), yp, r0, c0, tt);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NR; k++) load_row_clamped<NB>(tgt, H, W, yp, r0 + k, c0, tt[k]);
+        }
+        uint32_t rm[6], rl[6], rh[6];
+#pragma unroll
+        for (int r = 0; r < 6; r++) {
+            rm[r] = dword_at(rr[r], 1);
+            rl[r] = byte_at(rr[r], 0);
+            rh[r] = byte_at(rr[r], 5);
+        }
+        uint32_t b00 = 0xffffffffu, b01 = 0xffffffffu, b10 = 0xffffffffu, b11 = 0xffffffffu;
+#pragma unroll
+        for (int j = 0; j < NC; j++)
+#pragma unroll
+            for (int i = 0; i < NC; i++) {
+                uint32_t m = 0, l = 0, h = 0;
+#pragma unroll
+                for (int r = 1; r < 5; r++) {
+                    m = __builtin_amdgcn_sad_u8(rm[r], dword_at(tt[j + r], i + 1), m);
+                    l = __builtin_amdgcn_sad_u8(rl[r], byte_at(tt[j + r], i), l);
+                    h = __builtin_amdgcn_sad_u8(rh[r], byte_at(tt[j + r], i + 5), h);
+                }
+                const uint32_t m0 = __builtin_amdgcn_sad_u8(rm[0], dword_at(tt[j], i + 1), m);
+                const uint32_t m5 = __builtin_amdgcn_sad_u8(rm[5], dword_at(tt[j + 5], i + 1), m);
+                const uint32_t l0 = __builtin_amdgcn_sad_u8(rl[0], byte_at(tt[j], i), l);
+                const uint32_t l5 = __builtin_amdgcn_sad_u8(rl[5], byte_at(tt[j + 5], i), l);
+                const uint32_t h0 = __builtin_amdgcn_sad_u8(rh[0], byte_at(tt[j], i + 5), h);
+                const uint32_t h5 = __builtin_amdgcn_sad_u8(rh[5], byte_at(tt[j + 5], i + 5), h);
+                const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
+                b00 = min(b00, ((m0 + l0) << 11) + K);
+                b01 = min(b01, ((m0 + h0) << 11) + K);
+                b10 = min(b10, ((m5 + l5) << 11) + K);
+                b11 = min(b11, ((m5 + h5) << 11) + K);
+            }
+        const uint32_t best[2][2] = {{b00, b01}, {b10, b11}};
+#pragma unroll
+        for (int dy = 0; dy < 2; dy++) {
+            if (y + dy >= H) break;
+            auto out = gst(L.ds[dir] + (size_t)(y + dy) * L.fpitch + x);
+            auto cst = gst(L.cs[dir] + (size_t)(y + dy) * L.fpitch + x);
+#pragma unroll
+            for (int dx = 0; dx < 2; dx++) {
+                if (x + dx >= W) break;
+                const uint32_t b = best[dy][dx];
+                const int idx = (int)(b & 127u), jj = idx / NC, ii = idx - jj * NC;
+                out[dx] = pack16(cx + ii - R, cy + jj - R);
+                cst[dx] = (uint16_t)(b >> 11);
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- propagation
 // One Jacobi step per launch: each pixel keeps the lowest-cost vector among
 // its own and those of its left, right, upper and lower neighbours in the
@@ -1591,6 +1692,18 @@ template <int P, int R>
 static hipError_t search_th(const StripLv *lv, Work w, int th, int grid, hipStream_t s)
 {
     const int g = grid_for(w.total, grid);
+    if constexpr (P == 2 && R <= 2) {
+        // 5x5 patches, tiles of 2, 4 or 8 rows: a 2 x 2 quad per thread
+        switch (th) {
+        case 2: hipLaunchKernelGGL((k_search_quad<R, 2>), dim3(g), dim3(64), 0, s, lv, w.prefix, w.n, w.total);
+            return hipGetLastError();
+        case 4: hipLaunchKernelGGL((k_search_quad<R, 4>), dim3(g), dim3(128), 0, s, lv, w.prefix, w.n, w.total);
+            return hipGetLastError();
+        case 8: hipLaunchKernelGGL((k_search_quad<R, 8>), dim3(g), dim3(256), 0, s, lv, w.prefix, w.n, w.total);
+            return hipGetLastError();
+        default: break;
+        }
+    }
     switch (th) {
     case 1: hipLaunchKernelGGL((k_search<P, R, 1>), dim3(g), dim3(64), 0, s, lv, w.prefix, w.n, w.total); break;
     case 2: hipLaunchKernelGGL((k_search<P, R, 2>), dim3(g), dim3(128), 0, s, lv, w.prefix, w.n, w.total); break;
