@@ -1074,12 +1074,80 @@ __device__ __forceinline__ void refine_update(const RefineSolve &q, float bx, fl
     uy = fminf(fmaxf(uy + dy, (float)(d0y - 1)), (float)(d0y + 1));
 }
 
-// Register budget: for windows up to 5x5 at most 80 VGPRs, so that 6 waves
-// share a SIMD and hide more of the row-load latency (the compiler fits it
-// without spills; with its own choice of 121 VGPRs, 4 waves, the level-0
-// launch took 15 % longer); the 7x7 window keeps the compiler's budget.
+// `iters` Gauss-Newton steps of one interior pixel (x, y) from its integer
+// flow (d0x, d0y): its window rows are rows OFF .. OFF + WN - 1 of the
+// doubled-gradient pair arrays, sax / say its sums of g A. Returns the
+// refined flow as a packed float2.
+template <int LP, int OFF, int NRW>
+__device__ __forceinline__ uint64_t refine_steps(const uint32_t (&gxp)[NRW][LP + 1], const uint32_t (&gyp)[NRW][LP + 1],
+                                                 const uint8_t *Bo, int yp, int H, int W, int x, int y, int d0x,
+                                                 int d0y, int sax, int say, const RefineSolve &q, int iters)
+{
+    constexpr int WN = 2 * LP + 1, NP = LP + 1;
+    float ux = (float)d0x, uy = (float)d0y;
+    for (int it = 0; it < iters; it++) {
+        const float fux = floorf(ux), fuy = floorf(uy);
+        const float fx = ux - fux, fy = uy - fuy;
+        // the (WN+1)^2 target block at the cell of u; a block beyond the
+        // padded border lies wholly on one side of the image, where every
+        // sample is the edge value, so its origin is clamped to the
+        // padded range without changing any sample
+        const int c0 = clampi(x - LP + (int)fux, -kPad, W - 1 + kPad - (WN + 1));
+        const int r0 = clampi(y - LP + (int)fuy, -kPad, H - 1 + kPad - WN);
+        float bx, by;  // sum over the window of g (Tgt - A), g doubled
+        if (it == 0) {
+            // the integer start: one corner
+            int sx = 0, sy = 0;
+            uint32_t tb[WN][(WN + 1 + 3) / 4];
+            load_rows<WN + 1, WN>(Bo, yp, r0, c0, tb);
+#pragma unroll
+            for (int j = 0; j < WN; j++) {
+                uint32_t te[NP];
+                even_pairs<NP, 0>(tb[j], te);
+#pragma unroll
+                for (int k = 0; k < NP; k++) {
+                    sx = dot2(gxp[OFF + j][k], te[k], sx);
+                    sy = dot2(gyp[OFF + j][k], te[k], sy);
+                }
+            }
+            bx = (float)(sx - sax);
+            by = (float)(sy - say);
+        } else {
+            int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
+            uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
+            load_rows<WN + 2, WN + 1>(Bo, yp, r0, c0, tb);
+#pragma unroll
+            for (int r = 0; r <= WN; r++) {
+                uint32_t te[NP], to[NP];
+                tgt_pairs<NP, 0>(tb[r], te, to);
+#pragma unroll
+                for (int k = 0; k < NP; k++) {
+                    if (r < WN) {
+                        s00x = dot2(gxp[OFF + r][k], te[k], s00x);
+                        s01x = dot2(gxp[OFF + r][k], to[k], s01x);
+                        s00y = dot2(gyp[OFF + r][k], te[k], s00y);
+                        s01y = dot2(gyp[OFF + r][k], to[k], s01y);
+                    }
+                    if (r > 0) {
+                        s10x = dot2(gxp[OFF + r - 1][k], te[k], s10x);
+                        s11x = dot2(gxp[OFF + r - 1][k], to[k], s11x);
+                        s10y = dot2(gyp[OFF + r - 1][k], te[k], s10y);
+                        s11y = dot2(gyp[OFF + r - 1][k], to[k], s11y);
+                    }
+                }
+            }
+            bx = corner_mix(s00x, s01x, s10x, s11x, sax, fx, fy);
+            by = corner_mix(s00y, s01y, s10y, s11y, say, fx, fy);
+        }
+        refine_update(q, bx, by, d0x, d0y, ux, uy);
+    }
+    return (uint64_t)__float_as_uint(ux) | ((uint64_t)__float_as_uint(uy) << 32);
+}
+
+// One pixel per thread; used for the 7x7 window (windows up to 5x5 take
+// k_refine_pair below).
 template <int LP, int TH>
-__global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(LP <= 2 ? 6 : 1, 8))) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
+__global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ lv, const StripIO *__restrict__ io,
                                                     const int32_t *__restrict__ prefix, int n, int total, int iters,
                                                     float eps)
 {
@@ -1131,65 +1199,106 @@ __global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(LP <= 2
                 }
         }
         const RefineSolve q = refine_solve(hxx, hxy, hyy, eps);
-        float ux = (float)d0x, uy = (float)d0y;
-        for (int it = 0; it < iters; it++) {
-            const float fux = floorf(ux), fuy = floorf(uy);
-            const float fx = ux - fux, fy = uy - fuy;
-            // the (WN+1)^2 target block at the cell of u; a block beyond the
-            // padded border lies wholly on one side of the image, where every
-            // sample is the edge value, so its origin is clamped to the
-            // padded range without changing any sample
-            const int c0 = clampi(x - LP + (int)fux, -kPad, W - 1 + kPad - (WN + 1));
-            const int r0 = clampi(y - LP + (int)fuy, -kPad, H - 1 + kPad - WN);
-            float bx, by;  // sum over the window of g (Tgt - A), g doubled
-            if (it == 0) {
-                // the integer start: one corner
-                int sx = 0, sy = 0;
-                uint32_t tb[WN][(WN + 1 + 3) / 4];
-                load_rows<WN + 1, WN>(Bo, yp, r0, c0, tb);
-#pragma unroll
-                for (int j = 0; j < WN; j++) {
-                    uint32_t te[NP];
-                    even_pairs<NP, 0>(tb[j], te);
-#pragma unroll
-                    for (int k = 0; k < NP; k++) {
-                        sx = dot2(gxp[j][k], te[k], sx);
-                        sy = dot2(gyp[j][k], te[k], sy);
-                    }
-                }
-                bx = (float)(sx - sax);
-                by = (float)(sy - say);
-            } else {
-                int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
-                uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
-                load_rows<WN + 2, WN + 1>(Bo, yp, r0, c0, tb);
-#pragma unroll
-                for (int r = 0; r <= WN; r++) {
-                    uint32_t te[NP], to[NP];
-                    tgt_pairs<NP, 0>(tb[r], te, to);
-#pragma unroll
-                    for (int k = 0; k < NP; k++) {
-                        if (r < WN) {
-                            s00x = dot2(gxp[r][k], te[k], s00x);
-                            s01x = dot2(gxp[r][k], to[k], s01x);
-                            s00y = dot2(gyp[r][k], te[k], s00y);
-                            s01y = dot2(gyp[r][k], to[k], s01y);
-                        }
-                        if (r > 0) {
-                            s10x = dot2(gxp[r - 1][k], te[k], s10x);
-                            s11x = dot2(gxp[r - 1][k], to[k], s11x);
-                            s10y = dot2(gyp[r - 1][k], te[k], s10y);
-                            s11y = dot2(gyp[r - 1][k], to[k], s11y);
-                        }
-                    }
-                }
-                bx = corner_mix(s00x, s01x, s10x, s11x, sax, fx, fy);
-                by = corner_mix(s00y, s01y, s10y, s11y, say, fx, fy);
-            }
-            refine_update(q, bx, by, d0x, d0y, ux, uy);
-        }
-        const uint64_t packed = (uint64_t)__float_as_uint(ux) | ((uint64_t)__float_as_uint(uy) << 32);
+        const uint64_t packed = refine_steps<LP, 0, WN>(gxp, gyp, Bo, yp, H, W, x, y, d0x, d0y, sax, say, q, iters);
         gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(uint32_t)(y * W + x)] = packed;
+    }
+}
+
+// The interior refinement for windows up to 5x5 with a vertical pair of
+// pixels per thread ((x, y) and (x, y+1)): the two windows share WN - 1 of
+// their rows, so the Ref rows are loaded, the doubled gradients formed and
+// the row sums of 4 H and sum g A taken once for the shared rows (the
+// sums are exact integers, so the order of addition does not matter), and
+// each pixel adds its own first or last row. The Gauss-Newton steps are
+// those of k_refine, pixel by pixel. A tile of TH rows (TH even) is TH/2
+// waves, each a row pair; the results are those of k_refine. Register
+// budget: at most 128 VGPRs (4 waves per SIMD, no spills); capped at 96
+// (5 waves) it spilled and was slower.
+template <int LP, int TH>
+__global__ __launch_bounds__(32 * TH) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_refine_pair(
+    const StripLv *__restrict__ lv, const StripIO *__restrict__ io, const int32_t *__restrict__ prefix, int n,
+    int total, int iters, float eps)
+{
+    constexpr int TW = kRefineTW;
+    constexpr int WN = 2 * LP + 1;  // window width
+    constexpr int NP = LP + 1;      // 16-bit pairs per window row (the last one half padding)
+    constexpr int AB = WN + 2;      // Ref bytes per row (window + gradient taps)
+    static_assert(TH % 2 == 0 && LP <= 2, "row pairs, windows up to 5x5");
+    const int lane = threadIdx.x & 63, wpair = threadIdx.x >> 6;
+    TILE_LOOP(total)
+    {
+        const int s = find_strip(prefix, n, t);
+        int local = t - prefix[s];
+        const StripLv &L = lv[s];
+        const int H = L.H, W = L.W, yp = L.ypitch;
+        const RefineSplit sp = refine_split(H, W, TH, LP);
+        const int dir = local / sp.nint;
+        local -= dir * sp.nint;
+        const int ntx = ceil_div(sp.xhi - sp.xlo, TW);
+        const int tyi = local / ntx;
+        const int x = sp.xlo + (local - tyi * ntx) * TW + lane;
+        const int y = sp.ylo + tyi * TH + 2 * wpair;
+        if (x >= sp.xhi || y >= sp.yhi) continue;  // no barrier in this kernel
+        const bool two = y + 1 < sp.yhi;           // else row y + 1 is only read, in the padded plane
+        const uint8_t *Ao = plane_org(L.y[dir], yp), *Bo = plane_org(L.y[1 - dir], yp);
+        const auto df = gld(L.df[dir]);
+        const uint32_t dA = df[(uint32_t)(y * L.fpitch + x)];
+        const uint32_t dB = two ? df[(uint32_t)((y + 1) * L.fpitch + x)] : dA;
+
+        // doubled gradients of the WN + 1 window rows of the pair
+        uint32_t gxp[WN + 1][NP], gyp[WN + 1][NP];
+        int hA[5], hB[5];  // 4 Hxx, 4 Hxy, 4 Hyy, sum gx A, sum gy A of each pixel
+        {
+            uint32_t op[WN + 3][NP], ar[WN + 3][(AB + 3) / 4];
+            load_rows<AB, WN + 3>(Ao, yp, y - LP - 1, x - LP - 1, ar);
+#pragma unroll
+            for (int r = 0; r < WN + 3; r++) {
+                odd_pairs<NP, 0>(ar[r], op[r]);
+                if (r >= 1 && r <= WN + 1) gx_pairs<NP, 0>(ar[r], gxp[r - 1]);
+            }
+            int sh[5] = {0, 0, 0, 0, 0};  // rows 1 .. WN - 1, shared
+#pragma unroll
+            for (int j = 0; j <= WN; j++)
+#pragma unroll
+                for (int k = 0; k < NP; k++) gyp[j][k] = sub2(op[j + 2][k], op[j][k]);
+#pragma unroll
+            for (int j = 1; j < WN; j++)
+#pragma unroll
+                for (int k = 0; k < NP; k++) {
+                    sh[0] = dot2(gxp[j][k], gxp[j][k], sh[0]);
+                    sh[1] = dot2(gxp[j][k], gyp[j][k], sh[1]);
+                    sh[2] = dot2(gyp[j][k], gyp[j][k], sh[2]);
+                    sh[3] = dot2(gxp[j][k], op[j + 1][k], sh[3]);
+                    sh[4] = dot2(gyp[j][k], op[j + 1][k], sh[4]);
+                }
+#pragma unroll
+            for (int m = 0; m < 5; m++) hA[m] = hB[m] = sh[m];
+#pragma unroll
+            for (int k = 0; k < NP; k++) {
+                hA[0] = dot2(gxp[0][k], gxp[0][k], hA[0]);
+                hA[1] = dot2(gxp[0][k], gyp[0][k], hA[1]);
+                hA[2] = dot2(gyp[0][k], gyp[0][k], hA[2]);
+                hA[3] = dot2(gxp[0][k], op[1][k], hA[3]);
+                hA[4] = dot2(gyp[0][k], op[1][k], hA[4]);
+                hB[0] = dot2(gxp[WN][k], gxp[WN][k], hB[0]);
+                hB[1] = dot2(gxp[WN][k], gyp[WN][k], hB[1]);
+                hB[2] = dot2(gyp[WN][k], gyp[WN][k], hB[2]);
+                hB[3] = dot2(gxp[WN][k], op[WN + 1][k], hB[3]);
+                hB[4] = dot2(gyp[WN][k], op[WN + 1][k], hB[4]);
+            }
+        }
+        const auto out = gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]));
+        {
+            const RefineSolve q = refine_solve(hA[0], hA[1], hA[2], eps);
+            out[(uint32_t)(y * W + x)] = refine_steps<LP, 0, WN + 1>(gxp, gyp, Bo, yp, H, W, x, y, unpack_x(dA),
+                                                                     unpack_y(dA), hA[3], hA[4], q, iters);
+        }
+        if (two) {
+            const RefineSolve q = refine_solve(hB[0], hB[1], hB[2], eps);
+            out[(uint32_t)((y + 1) * W + x)] = refine_steps<LP, 1, WN + 1>(gxp, gyp, Bo, yp, H, W, x, y + 1,
+                                                                           unpack_x(dB), unpack_y(dB), hB[3], hB[4],
+                                                                           q, iters);
+        }
     }
 }
 
@@ -1762,13 +1871,24 @@ static hipError_t refine_lp(const StripLv *lv0, const StripIO *io, Work w, LkPar
 {
     if (w.total == 0) return hipSuccess;
     const int g = grid_for(w.total, grid);
-    if (th == 2)
-        hipLaunchKernelGGL((k_refine<LP, 2>), dim3(g), dim3(128), 0, s, lv0, io, w.prefix, w.n, w.total, lk.iters,
-                           lk.eps);
-    else
-        hipLaunchKernelGGL((k_refine<LP, 4>), dim3(g), dim3(256), 0, s, lv0, io, w.prefix, w.n, w.total, lk.iters,
-                           lk.eps);
-    return hipGetLastError();
+    if constexpr (LP <= 2) {
+        // vertical pixel pairs: TH / 2 waves per tile
+        if (th == 2)
+            hipLaunchKernelGGL((k_refine_pair<LP, 2>), dim3(g), dim3(64), 0, s, lv0, io, w.prefix, w.n, w.total,
+                               lk.iters, lk.eps);
+        else
+            hipLaunchKernelGGL((k_refine_pair<LP, 4>), dim3(g), dim3(128), 0, s, lv0, io, w.prefix, w.n, w.total,
+                               lk.iters, lk.eps);
+        return hipGetLastError();
+    } else {
+        if (th == 2)
+            hipLaunchKernelGGL((k_refine<LP, 2>), dim3(g), dim3(128), 0, s, lv0, io, w.prefix, w.n, w.total,
+                               lk.iters, lk.eps);
+        else
+            hipLaunchKernelGGL((k_refine<LP, 4>), dim3(g), dim3(256), 0, s, lv0, io, w.prefix, w.n, w.total,
+                               lk.iters, lk.eps);
+        return hipGetLastError();
+    }
 }
 
 hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid, hipStream_t s)
