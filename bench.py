@@ -46,7 +46,9 @@ def kernel_name(stage, level, p):
     if stage == 0:
         return "k_luma level 0" if level == 0 else "k_gain_prep + k_gain level 0"
     if stage == 4:
-        return "k_refine level 0" if level == 0 else "k_refine_border level 0"
+        if level != 0:
+            return "k_refine_border level 0"
+        return "k_refine_pair level 0" if p.lk_patch <= 2 else "k_refine level 0"
     if stage == 3:
         return f"k_prop ({p.prop_steps} steps + median) level {level}"
     return f"{KERNELS[stage]} level {level}"
