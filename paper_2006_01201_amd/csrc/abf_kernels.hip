@@ -1336,13 +1336,146 @@ __device__ __forceinline__ uint32_t psel(int b0, int b1)
     return (uint32_t)b0 | 0x0c00u | (b1 < 0 ? 0x0c0000u : (uint32_t)b1 << 16) | 0x0c000000u;
 }
 
+// The window of a border pixel: its clamped positions, the selectors that
+// gather them from row runs, and its doubled gradients as 16-bit pairs with
+// the exact sums 4 H and sum g A.
+template <int LP>
+struct BorderWin {
+    static constexpr int WN = 2 * LP + 1, NP = LP + 1;
+    int qx[WN], qy[WN];
+    uint32_t sE[NP], sO[NP];
+    uint32_t gxp[WN][NP], gyp[WN][NP];
+    int hxx, hxy, hyy, sax, say;
+};
+
+template <int LP>
+__device__ __forceinline__ void border_setup(const uint8_t *Ao, int yp, int H, int W, int x, int y, BorderWin<LP> &bw)
+{
+    constexpr int WN = 2 * LP + 1, NP = LP + 1, AB = WN + 2;
+#pragma unroll
+    for (int i = 0; i < WN; i++) {
+        bw.qx[i] = clampi(x + i - LP, 0, W - 1);
+        bw.qy[i] = clampi(y + i - LP, 0, H - 1);
+    }
+    // selectors: the Ref run starts at column qx[0] - 1, the Tgt run at
+    // the cell column of qx[0]
+    uint32_t sA[NP], sL[NP], sR[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const int i0 = 2 * k, i1 = 2 * k + 1;
+        const int c0 = bw.qx[i0] - bw.qx[0] + 1, c1 = i1 < WN ? bw.qx[i1] - bw.qx[0] + 1 : -1;
+        sA[k] = psel(c0, c1);
+        sL[k] = psel(c0 - 1, c1 < 0 ? -1 : c1 - 1);
+        sR[k] = psel(c0 + 1, c1 < 0 ? -1 : c1 + 1);
+        bw.sE[k] = psel(c0 - 1, c1 < 0 ? -1 : c1 - 1);
+        bw.sO[k] = psel(c0, c1);
+    }
+    int hxx = 0, hxy = 0, hyy = 0, sax = 0, say = 0;
+    // the 3 WN Ref rows (clamped rows - 1, 0, + 1 of each window row), all
+    // loads issued before the first is used
+    uint32_t rw[WN][3][1][RawRows<AB>::ND + 1];
+    int rs = 0;
+#pragma unroll
+    for (int j = 0; j < WN; j++)
+#pragma unroll
+        for (int d = 0; d < 3; d++) rs = issue_rows<AB, 1>(Ao, yp, bw.qy[j] + d - 1, bw.qx[0] - 1, rw[j][d]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < WN; j++) {
+        uint32_t r[3][(AB + 3) / 4];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            uint32_t rr[1][(AB + 3) / 4];
+            align_rows<AB, 1>(rw[j][d], rs, rr);
+#pragma unroll
+            for (int k = 0; k < (AB + 3) / 4; k++) r[d][k] = rr[0][k];
+        }
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const uint32_t av = __builtin_amdgcn_perm(r[1][1], r[1][0], sA[k]);
+            uint32_t right = __builtin_amdgcn_perm(r[1][1], r[1][0], sR[k]);
+            if constexpr (AB > 8) {
+                // 7x7 window: the right tap of the last (half) pair can be
+                // byte 8 of the run, beyond the 8 bytes one v_perm_b32
+                // reaches; it is byte 4 of the next dword pair
+                if (k == NP - 1 && bw.qx[WN - 1] - bw.qx[0] + 2 == 8)
+                    right = __builtin_amdgcn_perm(r[1][2], r[1][1], psel(4, -1));
+            }
+            bw.gxp[j][k] = sub2(right, __builtin_amdgcn_perm(r[1][1], r[1][0], sL[k]));
+            bw.gyp[j][k] = sub2(__builtin_amdgcn_perm(r[2][1], r[2][0], sA[k]),
+                                __builtin_amdgcn_perm(r[0][1], r[0][0], sA[k]));
+            hxx = dot2(bw.gxp[j][k], bw.gxp[j][k], hxx);
+            hxy = dot2(bw.gxp[j][k], bw.gyp[j][k], hxy);
+            hyy = dot2(bw.gyp[j][k], bw.gyp[j][k], hyy);
+            sax = dot2(bw.gxp[j][k], av, sax);
+            say = dot2(bw.gyp[j][k], av, say);
+        }
+    }
+    bw.hxx = hxx;
+    bw.hxy = hxy;
+    bw.hyy = hyy;
+    bw.sax = sax;
+    bw.say = say;
+}
+
+// The four corner correlations S(d) = sum g Tgt(q + d), d = (ix + a, iy + b),
+// of a border window (S[c][b][a], c = 0 for g_x, 1 for g_y), target indices
+// clamped to the image: the Tgt run of a row holds the samples at
+// qx[i] + ix (+ 1); a run beyond the padded border lies wholly on one side
+// of the image and is clamped to it unchanged.
+template <int LP>
+__device__ __forceinline__ void border_corners(const BorderWin<LP> &bw, const uint8_t *Bo, int yp, int H, int W, int ix,
+                                               int iy, int (&S)[2][2][2])
+{
+    constexpr int WN = 2 * LP + 1, NP = LP + 1;
+    const int c0 = clampi(bw.qx[0] + ix, -kPad, W - 1 + kPad - (WN + 1));
+    int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
+    // the 2 WN Tgt rows of the cells, all loads issued first
+    uint32_t tw[WN][2][1][RawRows<WN + 2>::ND + 1];
+    int ts = 0;
+#pragma unroll
+    for (int j = 0; j < WN; j++)
+#pragma unroll
+        for (int d = 0; d < 2; d++)
+            ts = issue_rows<WN + 2, 1>(Bo, yp, clampi(bw.qy[j] + iy + d, -kPad, H - 1 + kPad), c0, tw[j][d]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < WN; j++) {
+        uint32_t ta[1][(WN + 2 + 3) / 4], tb[1][(WN + 2 + 3) / 4];
+        align_rows<WN + 2, 1>(tw[j][0], ts, ta);
+        align_rows<WN + 2, 1>(tw[j][1], ts, tb);
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const uint32_t ea = __builtin_amdgcn_perm(ta[0][1], ta[0][0], bw.sE[k]);
+            const uint32_t oa = __builtin_amdgcn_perm(ta[0][1], ta[0][0], bw.sO[k]);
+            const uint32_t eb = __builtin_amdgcn_perm(tb[0][1], tb[0][0], bw.sE[k]);
+            const uint32_t ob = __builtin_amdgcn_perm(tb[0][1], tb[0][0], bw.sO[k]);
+            s00x = dot2(bw.gxp[j][k], ea, s00x);
+            s01x = dot2(bw.gxp[j][k], oa, s01x);
+            s10x = dot2(bw.gxp[j][k], eb, s10x);
+            s11x = dot2(bw.gxp[j][k], ob, s11x);
+            s00y = dot2(bw.gyp[j][k], ea, s00y);
+            s01y = dot2(bw.gyp[j][k], oa, s01y);
+            s10y = dot2(bw.gyp[j][k], eb, s10y);
+            s11y = dot2(bw.gyp[j][k], ob, s11y);
+        }
+    }
+    S[0][0][0] = s00x;
+    S[0][0][1] = s01x;
+    S[0][1][0] = s10x;
+    S[0][1][1] = s11x;
+    S[1][0][0] = s00y;
+    S[1][0][1] = s01y;
+    S[1][1][0] = s10y;
+    S[1][1][1] = s11y;
+}
+
 template <int LP>
 __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restrict__ lv,
                                                           const StripIO *__restrict__ io,
                                                           const int32_t *__restrict__ prefix, int n, int total,
                                                           int iters, float eps)
 {
-    constexpr int WN = 2 * LP + 1, NP = LP + 1, AB = WN + 2;
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -1360,110 +1493,18 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
         const uint8_t *Ao = plane_org(L.y[dir], yp), *Bo = plane_org(L.y[1 - dir], yp);
         const uint32_t d0 = gld(L.df[dir])[(uint32_t)(y * L.fpitch + x)];
         const int d0x = unpack_x(d0), d0y = unpack_y(d0);
-        int qx[WN], qy[WN];
-#pragma unroll
-        for (int i = 0; i < WN; i++) {
-            qx[i] = clampi(x + i - LP, 0, W - 1);
-            qy[i] = clampi(y + i - LP, 0, H - 1);
-        }
-        // selectors: the Ref run starts at column qx[0] - 1, the Tgt run at
-        // the cell column of qx[0]
-        uint32_t sA[NP], sL[NP], sR[NP], sE[NP], sO[NP];
-#pragma unroll
-        for (int k = 0; k < NP; k++) {
-            const int i0 = 2 * k, i1 = 2 * k + 1;
-            const int c0 = qx[i0] - qx[0] + 1, c1 = i1 < WN ? qx[i1] - qx[0] + 1 : -1;
-            sA[k] = psel(c0, c1);
-            sL[k] = psel(c0 - 1, c1 < 0 ? -1 : c1 - 1);
-            sR[k] = psel(c0 + 1, c1 < 0 ? -1 : c1 + 1);
-            sE[k] = psel(c0 - 1, c1 < 0 ? -1 : c1 - 1);
-            sO[k] = psel(c0, c1);
-        }
-        // doubled gradients at the clamped positions as 16-bit pairs
-        uint32_t gxp[WN][NP], gyp[WN][NP];
-        int hxx = 0, hxy = 0, hyy = 0, sax = 0, say = 0;
-        // the 3 WN Ref rows (clamped rows - 1, 0, + 1 of each window row), all
-        // loads issued before the first is used
-        uint32_t rw[WN][3][1][RawRows<AB>::ND + 1];
-        int rs = 0;
-#pragma unroll
-        for (int j = 0; j < WN; j++)
-#pragma unroll
-            for (int d = 0; d < 3; d++) rs = issue_rows<AB, 1>(Ao, yp, qy[j] + d - 1, qx[0] - 1, rw[j][d]);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int j = 0; j < WN; j++) {
-            uint32_t r[3][(AB + 3) / 4];
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                uint32_t rr[1][(AB + 3) / 4];
-                align_rows<AB, 1>(rw[j][d], rs, rr);
-#pragma unroll
-                for (int k = 0; k < (AB + 3) / 4; k++) r[d][k] = rr[0][k];
-            }
-#pragma unroll
-            for (int k = 0; k < NP; k++) {
-                const uint32_t av = __builtin_amdgcn_perm(r[1][1], r[1][0], sA[k]);
-                uint32_t right = __builtin_amdgcn_perm(r[1][1], r[1][0], sR[k]);
-                if constexpr (AB > 8) {
-                    // 7x7 window: the right tap of the last (half) pair can be
-                    // byte 8 of the run, beyond the 8 bytes one v_perm_b32
-                    // reaches; it is byte 4 of the next dword pair
-                    if (k == NP - 1 && qx[WN - 1] - qx[0] + 2 == 8)
-                        right = __builtin_amdgcn_perm(r[1][2], r[1][1], psel(4, -1));
-                }
-                gxp[j][k] = sub2(right, __builtin_amdgcn_perm(r[1][1], r[1][0], sL[k]));
-                gyp[j][k] = sub2(__builtin_amdgcn_perm(r[2][1], r[2][0], sA[k]),
-                                 __builtin_amdgcn_perm(r[0][1], r[0][0], sA[k]));
-                hxx = dot2(gxp[j][k], gxp[j][k], hxx);
-                hxy = dot2(gxp[j][k], gyp[j][k], hxy);
-                hyy = dot2(gyp[j][k], gyp[j][k], hyy);
-                sax = dot2(gxp[j][k], av, sax);
-                say = dot2(gyp[j][k], av, say);
-            }
-        }
-        const RefineSolve q = refine_solve(hxx, hxy, hyy, eps);
+        BorderWin<LP> bw;
+        border_setup<LP>(Ao, yp, H, W, x, y, bw);
+        const RefineSolve q = refine_solve(bw.hxx, bw.hxy, bw.hyy, eps);
         float ux = (float)d0x, uy = (float)d0y;
         for (int it = 0; it < iters; it++) {
             const float fux = floorf(ux), fuy = floorf(uy);
             const float fx = ux - fux, fy = uy - fuy;
-            // the Tgt run of a row: samples at qx[i] + ux, cell columns
-            // qx[i] + floor(ux) (+ 1); a run beyond the padded border lies
-            // wholly on one side of the image and is clamped to it unchanged
-            const int c0 = clampi(qx[0] + (int)fux, -kPad, W - 1 + kPad - (WN + 1));
-            int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
-            // the 2 WN Tgt rows of the cells, all loads issued first
-            uint32_t tw[WN][2][1][RawRows<WN + 2>::ND + 1];
-            int ts = 0;
-#pragma unroll
-            for (int j = 0; j < WN; j++)
-#pragma unroll
-                for (int d = 0; d < 2; d++)
-                    ts = issue_rows<WN + 2, 1>(Bo, yp, clampi(qy[j] + (int)fuy + d, -kPad, H - 1 + kPad), c0, tw[j][d]);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int j = 0; j < WN; j++) {
-                uint32_t ta[1][(WN + 2 + 3) / 4], tb[1][(WN + 2 + 3) / 4];
-                align_rows<WN + 2, 1>(tw[j][0], ts, ta);
-                align_rows<WN + 2, 1>(tw[j][1], ts, tb);
-#pragma unroll
-                for (int k = 0; k < NP; k++) {
-                    const uint32_t ea = __builtin_amdgcn_perm(ta[0][1], ta[0][0], sE[k]);
-                    const uint32_t oa = __builtin_amdgcn_perm(ta[0][1], ta[0][0], sO[k]);
-                    const uint32_t eb = __builtin_amdgcn_perm(tb[0][1], tb[0][0], sE[k]);
-                    const uint32_t ob = __builtin_amdgcn_perm(tb[0][1], tb[0][0], sO[k]);
-                    s00x = dot2(gxp[j][k], ea, s00x);
-                    s01x = dot2(gxp[j][k], oa, s01x);
-                    s10x = dot2(gxp[j][k], eb, s10x);
-                    s11x = dot2(gxp[j][k], ob, s11x);
-                    s00y = dot2(gyp[j][k], ea, s00y);
-                    s01y = dot2(gyp[j][k], oa, s01y);
-                    s10y = dot2(gyp[j][k], eb, s10y);
-                    s11y = dot2(gyp[j][k], ob, s11y);
-                }
-            }
-            refine_update(q, corner_mix(s00x, s01x, s10x, s11x, sax, fx, fy),
-                          corner_mix(s00y, s01y, s10y, s11y, say, fx, fy), d0x, d0y, ux, uy);
+            int S[2][2][2];
+            border_corners<LP>(bw, Bo, yp, H, W, (int)fux, (int)fuy, S);
+            refine_update(q, corner_mix(S[0][0][0], S[0][0][1], S[0][1][0], S[0][1][1], bw.sax, fx, fy),
+                          corner_mix(S[1][0][0], S[1][0][1], S[1][1][0], S[1][1][1], bw.say, fx, fy), d0x, d0y, ux,
+                          uy);
         }
         const uint64_t packed = (uint64_t)__float_as_uint(ux) | ((uint64_t)__float_as_uint(uy) << 32);
         gst(reinterpret_cast<uint64_t *>(io[s].flow[dir]))[(uint32_t)(y * W + x)] = packed;
@@ -1486,18 +1527,20 @@ __global__ __launch_bounds__(kRowTW) void k_refine_border(const StripLv *__restr
 // level's ds / df buffers (allocated with 8-byte entries for this method);
 // level 0 writes the caller's float32 flow. Interior pixels take
 // k_lk_interior (16-bit pair sums, as k_refine); the pixels within P of
-// the image edge, whose window positions repeat, take lk_pixel with
-// plain integer sums, one thread each.
+// the image edge, whose window positions repeat, take lk_border_pixel
+// (the row runs and gathers of k_refine_border), one thread each.
 
-// One pixel of the classic method (any pixel; the window positions and the
-// target indices are clamped as in the textbook form).
+// One border pixel of the classic method (its window positions repeat):
+// the clamped window and its exact sums as in k_refine_border, then K
+// Gauss-Newton steps from twice the coarser flow, with the corner
+// correlations of the cell of u at clamped target indices, combined with
+// the bilinear weights and solved in double.
 template <int P>
-__device__ __forceinline__ void lk_pixel(const StripLv &L, const StripLv *__restrict__ lvc, const StripIO *__restrict__ io,
-                                         int s, int dir, int x, int y, int K, double eps, bool level0)
+__device__ __forceinline__ void lk_border_pixel(const StripLv &L, const StripLv *__restrict__ lvc,
+                                                const StripIO *__restrict__ io, int s, int dir, int x, int y, int K,
+                                                double eps, bool level0)
 {
-    constexpr int WN = 2 * P + 1;
     const int H = L.H, W = L.W, yp = L.ypitch;
-    const auto A = gld(L.y[dir]), B = gld(L.y[1 - dir]);
     double ux = 0.0, uy = 0.0;
     if (lvc) {
         const StripLv &C = lvc[s];
@@ -1505,60 +1548,23 @@ __device__ __forceinline__ void lk_pixel(const StripLv &L, const StripLv *__rest
         ux = 2.0 * gld(reinterpret_cast<const double *>(C.ds[dir]))[q];
         uy = 2.0 * gld(reinterpret_cast<const double *>(C.df[dir]))[q];
     }
-    // doubled central-difference gradients G = 2 g of the window
-    // (integers) and the window's Ref values; 4 H and sum G A are
-    // exact integer sums
-    int gx[WN][WN], gy[WN][WN];
-    int hxx4 = 0, hxy4 = 0, hyy4 = 0, tx = 0, ty = 0;
-#pragma unroll
-    for (int j = 0; j < WN; j++)
-#pragma unroll
-        for (int i = 0; i < WN; i++) {
-            const int qy = clampi(y + j - P, 0, H - 1), qx = clampi(x + i - P, 0, W - 1);
-            const ptrdiff_t o = (ptrdiff_t)qy * yp + qx;
-            gx[j][i] = (int)A[o + 1] - (int)A[o - 1];
-            gy[j][i] = (int)A[o + yp] - (int)A[o - yp];
-            const int av = A[o];
-            hxx4 += gx[j][i] * gx[j][i];
-            hxy4 += gx[j][i] * gy[j][i];
-            hyy4 += gy[j][i] * gy[j][i];
-            tx += gx[j][i] * av;
-            ty += gy[j][i] * av;
-        }
-    const double hxx = eps + 0.25 * hxx4, hxy = 0.25 * hxy4, hyy = eps + 0.25 * hyy4;
+    BorderWin<P> bw;
+    border_setup<P>(plane_org(L.y[dir], yp), yp, H, W, x, y, bw);
+    const double hxx = eps + 0.25 * bw.hxx, hxy = 0.25 * bw.hxy, hyy = eps + 0.25 * bw.hyy;
     const double idet = 1.0 / (hxx * hyy - hxy * hxy);
+    const uint8_t *Bo = plane_org(L.y[1 - dir], yp);
     for (int it = 0; it < K; it++) {
         const double fux = floor(ux), fuy = floor(uy);
         const double fx = ux - fux, fy = uy - fuy;
-        const int ix = (int)fux, iy = (int)fuy;
-        // S[b][a][c] = sum over the window of G_c(q) Tgt(q + (ix + a, iy + b)),
-        // with clamped target indices: the residual sum is their
-        // bilinear combination minus sum G A
-        int S[2][2][2] = {};
-        {
-#pragma unroll
-            for (int j = 0; j < WN; j++) {
-                const int qy = clampi(y + j - P, 0, H - 1);
-                const ptrdiff_t r0 = (ptrdiff_t)clampi(qy + iy, 0, H - 1) * yp;
-                const ptrdiff_t r1 = (ptrdiff_t)clampi(qy + iy + 1, 0, H - 1) * yp;
-#pragma unroll
-                for (int i = 0; i < WN; i++) {
-                    const int qx = clampi(x + i - P, 0, W - 1);
-                    const int c0 = clampi(qx + ix, 0, W - 1), c1 = clampi(qx + ix + 1, 0, W - 1);
-                    const int v[2][2] = {{B[r0 + c0], B[r0 + c1]}, {B[r1 + c0], B[r1 + c1]}};
-#pragma unroll
-                    for (int b = 0; b < 2; b++)
-#pragma unroll
-                        for (int a = 0; a < 2; a++) {
-                            S[b][a][0] += gx[j][i] * v[b][a];
-                            S[b][a][1] += gy[j][i] * v[b][a];
-                        }
-                }
-            }
-        }
+        // a cell farther than the padded border reads edge values only, so
+        // the integer part is clamped before it is converted
+        const int ix = (int)fmin(fmax(fux, -(double)(W + 2 * kPad)), (double)(W + 2 * kPad));
+        const int iy = (int)fmin(fmax(fuy, -(double)(H + 2 * kPad)), (double)(H + 2 * kPad));
+        int S[2][2][2];
+        border_corners<P>(bw, Bo, yp, H, W, ix, iy, S);
         const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
-        const double bx = 0.5 * (w00 * S[0][0][0] + w01 * S[0][1][0] + w10 * S[1][0][0] + w11 * S[1][1][0] - tx);
-        const double by = 0.5 * (w00 * S[0][0][1] + w01 * S[0][1][1] + w10 * S[1][0][1] + w11 * S[1][1][1] - ty);
+        const double bx = 0.5 * (w00 * S[0][0][0] + w01 * S[0][0][1] + w10 * S[0][1][0] + w11 * S[0][1][1] - bw.sax);
+        const double by = 0.5 * (w00 * S[1][0][0] + w01 * S[1][0][1] + w10 * S[1][1][0] + w11 * S[1][1][1] - bw.say);
         ux -= (hyy * bx - hxy * by) * idet;
         uy -= (hxx * by - hxy * bx) * idet;
     }
@@ -1591,7 +1597,7 @@ __global__ __launch_bounds__(kRowTW) void k_lk_border(const StripLv *__restrict_
         if (b >= sp.nbp) continue;
         int x, y;
         border_pixel(sp, L.H, L.W, b, x, y);
-        lk_pixel<P>(L, lvc, io, s, dir, x, y, K, eps, level0);
+        lk_border_pixel<P>(L, lvc, io, s, dir, x, y, K, eps, level0);
     }
 }
 
