@@ -11,7 +11,7 @@
 // order-independent) converted to float afterwards.
 #include <hip/hip_runtime.h>
 
-#include "abf_internal.h"
+#include "abf_device.h"
 
 namespace abf {
 
@@ -51,8 +51,9 @@ __device__ __forceinline__ Bil bil_at(int x, int y, float ux, float uy, int H, i
 // value and position derivatives of channel c of a float HWC image
 __device__ __forceinline__ void bil_eval(const float *img, int W, const Bil &b, int c, float &v, float &dX, float &dY)
 {
-    const float v00 = img[3 * ((size_t)b.ya * W + b.xa) + c], v01 = img[3 * ((size_t)b.ya * W + b.xb) + c];
-    const float v10 = img[3 * ((size_t)b.yb * W + b.xa) + c], v11 = img[3 * ((size_t)b.yb * W + b.xb) + c];
+    const auto g = gld(img);
+    const float v00 = g[3 * ((size_t)b.ya * W + b.xa) + c], v01 = g[3 * ((size_t)b.ya * W + b.xb) + c];
+    const float v10 = g[3 * ((size_t)b.yb * W + b.xa) + c], v11 = g[3 * ((size_t)b.yb * W + b.xb) + c];
     const float top = v00 + b.fx * (v01 - v00), bot = v10 + b.fx * (v11 - v10);
     v = top + b.fy * (bot - top);
     dX = (1.f - b.fy) * (v01 - v00) + b.fy * (v11 - v10);
@@ -67,23 +68,29 @@ __device__ __forceinline__ void bil_scatter(float *g, unsigned long long *gfix, 
     scatter_add(g, gfix, 3 * ((size_t)b.yb * W + b.xb) + c, w * b.fy * b.fx);
 }
 
-// TV term at q for component m: s(q) and the forward differences
-__device__ __forceinline__ float tv_s(const float *u, int H, int W, int x, int y, int m, float eps, float &dx,
-                                      float &dy)
+// TV term at q for component m: s(q)^2 and the forward differences
+__device__ __forceinline__ float tv_s2(const float *u, int H, int W, int x, int y, int m, float eps, float &dx,
+                                       float &dy)
 {
+    const auto g = gld(u);
     const size_t q = (size_t)y * W + x;
-    const float c = u[2 * q + m];
-    dx = x < W - 1 ? u[2 * (q + 1) + m] - c : 0.f;
-    dy = y < H - 1 ? u[2 * (q + W) + m] - c : 0.f;
-    return sqrtf(dx * dx + dy * dy + eps * eps);
+    const float c = g[2 * q + m];
+    dx = x < W - 1 ? g[2 * (q + 1) + m] - c : 0.f;
+    dy = y < H - 1 ? g[2 * (q + W) + m] - c : 0.f;
+    return dx * dx + dy * dy + eps * eps;
 }
+
+// 1 / sqrt(v) for v > 0 (v_rsq_f32, within 1 ulp): the gradient's
+// quotients r / rho and d / s; the energy keeps the rounded square roots
+__device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
 
 // dE/du at p (photometric + lambda * TV); also returns the pixel's energy
 __device__ __forceinline__ void grad_u_at(const float *Ref, const float *Tgt, const float *u, int H, int W, int x,
                                           int y, float lambda, float eps, float &gx, float &gy, double &e)
 {
     const size_t p = (size_t)y * W + x;
-    const float ux = u[2 * p], uy = u[2 * p + 1];
+    const auto gu = gld(u), gr = gld(Ref);
+    const float ux = gu[2 * p], uy = gu[2 * p + 1];
     const Bil b = bil_at(x, y, ux, uy, H, W);
     gx = gy = 0.f;
     e = 0.0;
@@ -91,28 +98,28 @@ __device__ __forceinline__ void grad_u_at(const float *Ref, const float *Tgt, co
     for (int c = 0; c < 3; c++) {
         float v, dX, dY;
         bil_eval(Tgt, W, b, c, v, dX, dY);
-        const float r = v - Ref[3 * p + c];
-        const float rho = sqrtf(r * r + eps * eps);
-        const float d = r / rho;
-        e += rho;
+        const float r = v - gr[3 * p + c];
+        const float rho2 = r * r + eps * eps;
+        const float d = r * rsq(rho2);
+        e += sqrtf(rho2);
         gx = fmaf(d, dX, gx);
         gy = fmaf(d, dY, gy);
     }
 #pragma unroll
     for (int m = 0; m < 2; m++) {
         float dx, dy;
-        const float s = tv_s(u, H, W, x, y, m, eps, dx, dy);
-        e += (double)lambda * s;
-        float g = -(dx + dy) / s;
+        const float s2 = tv_s2(u, H, W, x, y, m, eps, dx, dy);
+        e += (double)lambda * sqrtf(s2);
+        float g = -(dx + dy) * rsq(s2);
         if (x > 0) {
             float ddx, ddy;
-            const float sl = tv_s(u, H, W, x - 1, y, m, eps, ddx, ddy);
-            g += ddx / sl;
+            const float sl2 = tv_s2(u, H, W, x - 1, y, m, eps, ddx, ddy);
+            g = fmaf(ddx, rsq(sl2), g);
         }
         if (y > 0) {
             float ddx, ddy;
-            const float su = tv_s(u, H, W, x, y - 1, m, eps, ddx, ddy);
-            g += ddy / su;
+            const float su2 = tv_s2(u, H, W, x, y - 1, m, eps, ddx, ddy);
+            g = fmaf(ddy, rsq(su2), g);
         }
         if (m == 0) gx = fmaf(lambda, g, gx);
         else gy = fmaf(lambda, g, gy);
@@ -200,8 +207,10 @@ __global__ __launch_bounds__(256) void k_energy_step(const float *__restrict__ R
         double e;
         grad_u_at(Ref, Tgt, u_in, H, W, x, y, lambda, eps, gx, gy, e);
         const float sx = fminf(fmaxf(eta * gx, -clip), clip), sy = fminf(fmaxf(eta * gy, -clip), clip);
-        u_out[2 * p] = u_in[2 * p] - sx;
-        u_out[2 * p + 1] = u_in[2 * p + 1] - sy;
+        const uint64_t w = gld(reinterpret_cast<const uint64_t *>(u_in))[p];
+        const float ax = __uint_as_float((uint32_t)w) - sx, ay = __uint_as_float((uint32_t)(w >> 32)) - sy;
+        gst(reinterpret_cast<uint64_t *>(u_out))[p] =
+            (uint64_t)__float_as_uint(ax) | ((uint64_t)__float_as_uint(ay) << 32);
     }
 }
 
@@ -353,8 +362,10 @@ __global__ __launch_bounds__(256) void k_energy_step_batch(const RefineDesc *__r
         double e;
         grad_u_at(r.Ref, r.Tgt, u_in, r.H, r.W, x, y, lambda, eps, gx, gy, e);
         const float sx = fminf(fmaxf(eta * gx, -clip), clip), sy = fminf(fmaxf(eta * gy, -clip), clip);
-        u_out[2 * p] = u_in[2 * p] - sx;
-        u_out[2 * p + 1] = u_in[2 * p + 1] - sy;
+        const uint64_t w = gld(reinterpret_cast<const uint64_t *>(u_in))[p];
+        const float ax = __uint_as_float((uint32_t)w) - sx, ay = __uint_as_float((uint32_t)(w >> 32)) - sy;
+        gst(reinterpret_cast<uint64_t *>(u_out))[p] =
+            (uint64_t)__float_as_uint(ax) | ((uint64_t)__float_as_uint(ay) << 32);
     }
 }
 
