@@ -75,7 +75,9 @@ typedef struct abf_params {
     int32_t gain_comp;     /* 1: before the pyramid, scale R's intensity by the ratio of the two
                               strips' intensity sums (16-bit fixed point: a = floor(2^16 sum(YL) /
                               sum(YR)), YR' = min(255, (YR a + 2^15) >> 16)) to remove a residual
-                              exposure gain left by pre-processing (Section III.B); 0: off */
+                              exposure gain left by pre-processing (Section III.B); 0: off, the
+                              default (colour correction is the caller's pre-processing, and with
+                              the step off a pure integer shift gives exactly that flow) */
     int32_t flow_method;   /* 0: integer patch search, propagation and median per level, then the
                               level-0 Lucas-Kanade refinement (the default); 1: the classic
                               coarse-to-fine Lucas-Kanade of Section III.C.1: at every level a

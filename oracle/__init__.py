@@ -46,7 +46,7 @@ class Params:
     k_sharp: float = 10.0  # kSoftmaxSharpness
     k_flowmag: float = 20.0  # kFlowMagCoef
     blend_mode: int = 0   # 0 softmax (Code 1), 1 linear
-    gain_comp: int = 1    # compensate R's intensity by the ratio of intensity sums
+    gain_comp: int = 0    # 1: compensate R's intensity by the ratio of intensity sums (off by default)
 
     @staticmethod
     def lean(**kw) -> "Params":

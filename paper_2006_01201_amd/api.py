@@ -33,7 +33,7 @@ class Params:
     k_sharp: float = 10.0
     k_flowmag: float = 20.0
     blend_mode: int = 0
-    gain_comp: int = 1
+    gain_comp: int = 0  # exposure step off: colour correction is the caller's pre-processing
     flow_method: int = 0  # 0: integer search + refinement; 1: classic coarse-to-fine Lucas-Kanade
 
     def to_c(self) -> _abi.AbfParams:

@@ -593,7 +593,7 @@ void abf_default_params(abf_params *p)
     p->k_sharp = 10.0f;
     p->k_flowmag = 20.0f;
     p->blend_mode = 0;
-    p->gain_comp = 1;
+    p->gain_comp = 0;
     p->flow_method = 0;
 }
 

@@ -41,7 +41,7 @@ def test_default_params(lib):
     p = _abi.default_params()
     assert (p.levels, p.patch, p.radius, p.radius_coarse, p.prop_steps, p.median) == (6, 2, 2, 4, 2, 1)
     assert (p.lk_patch, p.lk_iters, p.lk_eps, p.k_sharp, p.k_flowmag, p.blend_mode) == (2, 2, 25.0, 10.0, 20.0, 0)
-    assert p.gain_comp == 1 and p.flow_method == 0
+    assert p.gain_comp == 0 and p.flow_method == 0
 
 
 def test_defaults_match_oracle_and_api():

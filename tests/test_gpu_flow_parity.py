@@ -191,12 +191,12 @@ def test_flow_parity_pyramid_depths(api, levels):
 
 
 @pytest.mark.parametrize("kw", [dict(lk_patch=3, lk_iters=3), dict(lk_patch=1, lk_iters=4, lk_eps=4.0),
-                                dict(lk_iters=8, lk_eps=100.0), dict(lk_iters=0), dict(gain_comp=0)],
-                         ids=["window7_K3", "window3_K4_eps4", "K8_eps100", "K0", "no_exposure_step"])
+                                dict(lk_iters=8, lk_eps=100.0), dict(lk_iters=0), dict(gain_comp=1)],
+                         ids=["window7_K3", "window3_K4_eps4", "K8_eps100", "K0", "exposure_step"])
 def test_flow_parity_refinement_params(api, kw):
     # the refinement's other windows (3x3, 7x7), step counts (none, up to
-    # the maximum 8) and regularisations, and the path without the
-    # exposure step
+    # the maximum 8) and regularisations, and the path with the exposure
+    # step
     L, R, axis, p, g_lr, g_rl, views = run_case(api, "occluder_130x197", dataclasses.replace(api.Params(), **kw))
     o_lr, o_rl, lv = oracle.flow_bidirectional(L, R, o_params(p), levels_out=True)
     for k in range(p.levels):

@@ -97,7 +97,9 @@ def test_full_panorama_batched(api, panorama, tmp_path, monkeypatch):
     shapes = synth.strip_shapes(cfg, 0)
     total = sum(h * w for h, w, _ in shapes)
     strips = panorama
-    p = api.Params(levels=synth.LEVELS[cfg])
+    # the panorama's strips carry an exposure gain: the benchmark runs them
+    # with the exposure step, and so does this check
+    p = api.Params(levels=synth.LEVELS[cfg], gain_comp=1)
     op = o_params(p)
     plan = api.Plan(p, max_strips=len(shapes), max_pixels=total, max_H=max(h for h, _, _ in shapes),
                     max_W=max(w for _, w, _ in shapes))
@@ -142,7 +144,7 @@ def test_full_panorama_classic_lk(api, panorama):
     # within the method's bars (1e-3 px, and 99.9 % within 1e-4 px)
     strips = panorama
     shapes = [(s.L.shape[0], s.L.shape[1]) for s in strips]
-    p = api.Params(levels=6, flow_method=1, lk_iters=4)
+    p = api.Params(levels=6, flow_method=1, lk_iters=4, gain_comp=1)
     plan = api.Plan(p, max_strips=len(strips), max_pixels=sum(h * w for h, w in shapes),
                     max_H=max(h for h, _ in shapes), max_W=max(w for _, w in shapes))
     batch = plan.make_batch([(dev(s.L), dev(s.R), s.axis) for s in strips])
@@ -156,7 +158,7 @@ def test_full_panorama_classic_lk(api, panorama):
             for k in range(1, p.levels):
                 lv[d].append(plan.lk_level_flow(i, k, d).cpu().numpy())
         gpu.append(lv)
-    op = oracle.Params(levels=6, lk_iters=4)
+    op = oracle.Params(levels=6, lk_iters=4, gain_comp=1)
     for i, s in enumerate(strips):
         o = oracle.flow_lk_bidirectional(s.L, s.R, op)
         worst = 0.0
@@ -210,7 +212,7 @@ def test_full_merge_equals_stepwise_calls(api):
     # kind of step is checked against the oracle in the merge tests)
     H, W = 4000, 9000
     photos = synth.make_panorama_photos(0, H, W, n_ring=6, device="cuda")
-    p = api.Params(levels=6)
+    p = api.Params(levels=6, gain_comp=1)  # the photos carry exposure gains
     plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, max_pixels=8 << 20, canvas=(H, W))
     print(f"[gpu] full merge {H}x{W}, {len(photos)} photos", flush=True)
     canvas, cov, boxes = plan.merge_photos(photos)

@@ -229,6 +229,33 @@ def test_gradient_descent_lowers_energy(orc):
     assert np.all(hist >= 0)
 
 
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_descent_step_is_clipped(orc, sign):
+    # lambda = 0, Tgt a ramp in x (slope a per channel) and Ref a constant
+    # above (sign -1) or below (sign +1) every Tgt value: the residual keeps
+    # its sign, so dE/du_x = 3 a rho'(r) has the sign of the residual and
+    # |eta dE/du_x| = 50 * 3 * 0.005 ~ 0.75 > 0.25; every step is clipped to
+    # exactly 0.25 px against the gradient, and dE/du_y = 0 leaves u_y alone.
+    H, W, a = 8, 64, 0.005
+    xx = np.arange(W, dtype=np.float64)[None, :, None]
+    Tgt = np.broadcast_to(0.1 + a * xx, (H, W, 3)).copy()
+    Ref = np.full((H, W, 3), 0.95 if sign < 0 else 0.0)
+    u0 = np.zeros((H, W, 2))
+    u0[..., 0] = 10.0
+    u0[..., 1] = 0.3
+    steps = 6
+    u, hist = orc.refine_gd(Ref, Tgt, u0, steps=steps, eta=50.0, lam=0.0, eps=1e-3, clip=0.25)
+    # samples stay inside the ramp (x + 10 +- 1.5 within [0, W - 2])
+    inner = (slice(None), slice(2, W - 14))
+    assert (u[inner][..., 0] == 10.0 - sign * 0.25 * steps).all()
+    assert (u[..., 1] == 0.3).all()
+    # eta * |g| below the clip: the plain step eta * 3 a rho'(r), rho' = r / sqrt(r^2 + eps^2)
+    u, _ = orc.refine_gd(Ref, Tgt, u0, steps=1, eta=5.0, lam=0.0, eps=1e-3, clip=0.25)
+    r = 0.1 + a * (xx[0, :, 0] + 10.0) - Ref[0, 0, 0]
+    step = 5.0 * 3 * a * r / np.sqrt(r * r + 1e-6)
+    assert np.allclose(u[0, 2:W - 14, 0], 10.0 - step[2:W - 14], rtol=0, atol=1e-12)
+
+
 def test_blend_adjoint_matches_central_differences(orc):
     s = synth.make_random(13, 20, 24, float_out=True, max_ux=3, max_uy=1)
     L = s.L.astype(np.float64) * 255

@@ -280,6 +280,39 @@ def test_refine_diagonal_ramp_cross_term(orc):
     assert np.allclose(u[inner][..., 1], sy + 4.0 / 9.0, atol=1e-12)
 
 
+@pytest.mark.parametrize("side", [-1, 1])
+def test_refine_clamp_holds_one_pixel_from_the_seed(orc, side):
+    # A = 2x + 10, B(x) = A(x - s), seed 3 px from the answer: the first
+    # Gauss-Newton step moves by 3 * 100 / 125 = 2.4 px, past the +-1 px
+    # band around the seed, so the clamp holds it at seed +- 1; the second
+    # step (2 px off, a 1.6 px move) is clamped again. Without the clamp the
+    # two steps would end 0.12 px from s.
+    H, W, s = 32, 64, 3
+    A = _ramp(H, W, lambda x, y: 2 * x + 10 + 0 * y)
+    B = _ramp(H, W, lambda x, y: 2 * (x - s) + 10 + 0 * y)
+    D0 = np.zeros((H, W, 2), np.int32)
+    D0[..., 0] = s + 3 * side
+    u = orc.refine(A, B, D0, orc.Params())
+    inner = (slice(6, H - 6), slice(12, W - 12))
+    assert (u[inner][..., 0] == s + 2 * side).all()
+    assert (u[inner][..., 1] == 0.0).all()
+    # one step: the clamp binds after the first move as well
+    u1 = orc.refine(A, B, D0, orc.Params(lk_iters=1))
+    assert (u1[inner][..., 0] == s + 2 * side).all()
+
+
+def test_refine_clamp_on_the_vertical_component(orc):
+    H, W, s = 64, 32, -2
+    A = _ramp(H, W, lambda x, y: 2 * y + 20 + 0 * x)
+    B = _ramp(H, W, lambda x, y: 2 * (y - s) + 20 + 0 * x)
+    D0 = np.zeros((H, W, 2), np.int32)
+    D0[..., 1] = s - 3
+    u = orc.refine(A, B, D0, orc.Params())
+    inner = (slice(12, H - 12), slice(6, W - 6))
+    assert (u[inner][..., 1] == s - 2).all()
+    assert (u[inner][..., 0] == 0.0).all()
+
+
 def test_refine_keeps_exact_integer_flow(orc):
     L, R = _shifted_pair(12, 40, 40, 2, -1)
     yl, yr = orc.luma(L), orc.luma(R)
