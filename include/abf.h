@@ -17,7 +17,8 @@
  *     overlap); L and R are its two crops, OverlappedL and OverlappedR.
  *   - Images are RGB uint8, interleaved (HWC), rows `pitch` bytes apart
  *     (pitch >= 3 W). Flows are float32 H x W x 2, contiguous, (x, y) =
- *     (column, row) components.
+ *     (column, row) components, 8-byte aligned (each pixel's pair is one
+ *     64-bit access; ABF_E_INVALID otherwise).
  *   - Flow sense: Ref(p) ~ Tgt(p + u(p)). FlowRtoL has Ref = R and Tgt = L
  *     (R(p) ~ L(p + FlowRtoL(p))); FlowLtoR has Ref = L and Tgt = R.
  *   - axis 0: Area1 (only L) lies left of the strip and Area2 right of it;
@@ -189,15 +190,20 @@ abf_status abf_workspace_view(const abf_plan *plan, int32_t kind, int32_t strip,
  * dE/dRef, dE/dTgt (device, same shapes as u, Ref, Tgt; overwritten). The
  * derivative at an integer sample position is the right-hand one.
  * dE/dTgt is a bilinear scatter: with deterministic != 0 it is summed with
- * 64-bit fixed-point integer atomics (resolution 2^-40, |sums| < 2^23), so
- * the result does not depend on the order of the additions; otherwise with
- * float atomics. Scratch: 8 bytes per energy block and, if deterministic,
- * 24 bytes per pixel of the bound workspace (ABF_E_WORKSPACE if short). */
+ * 64-bit fixed-point integer atomics, so the result does not depend on the
+ * order of the additions; otherwise with float atomics. The fixed-point
+ * scale is a power of two, 2^(62 - e) with 3 H W < 2^e (|rho'| <= 1 bounds
+ * every pixel's sum by 3 H W), so no sum can overflow. eps^2 must be a normal float (eps >=
+ * 1.1e-19; ABF_E_INVALID otherwise). Scratch: 8 bytes per energy block
+ * and, if deterministic, 24 bytes per pixel of the bound workspace
+ * (ABF_E_WORKSPACE if short). */
 abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H,
                       int32_t W, float lambda, float eps, float *E_dev, float *g_u, float *g_Ref,
                       float *g_Tgt, int32_t deterministic, void *hip_stream);
 
-/* steps times u <- u - clip(eta * dE/du, -clip_px, clip_px) in place. */
+/* steps times u <- u - clip(eta * dE/du, -clip_px, clip_px) in place. u
+ * must be 8-byte aligned (each pixel's (x, y) is one 64-bit access) and
+ * eps^2 a normal float; ABF_E_INVALID otherwise. */
 abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, float *u, int32_t H,
                            int32_t W, int32_t steps, float eta, float lambda, float eps, float clip_px,
                            void *hip_stream);
@@ -213,24 +219,26 @@ typedef struct abf_refine_strip {
 
 /* abf_refine_flow over n strips at once (host array of descriptors): one
  * launch per descent step covers every strip. Results equal per-strip
- * abf_refine_flow calls bit for bit. Scratch: 8 bytes per pixel of the
- * workspace. */
+ * abf_refine_flow calls bit for bit (same argument rules). Scratch: 8
+ * bytes per pixel of the workspace. */
 abf_status abf_refine_strips(abf_plan *plan, const abf_refine_strip *strips, int32_t n, int32_t steps,
                              float eta, float lambda, float eps, float clip_px, void *hip_stream);
 
 /* Adjoint of Code 1 over float32 RGB images L, R (H x W x 3, contiguous;
  * any value scale): given g_F (float32 H x W x 3), writes the gradients
- * with respect to flow_LtoR, flow_RtoL (H x W x 2) and L, R (H x W x 3),
- * each nullable and overwritten. d|f|/df = f/|f| for f != 0 and 0 at 0;
- * a non-finite flow component is used as 0 and receives gradient 0. The
- * image gradients are bilinear scatters, summed with float atomics, or,
- * when the environment variable ABF_DETERMINISTIC is a non-zero integer,
- * with the order-independent fixed-point atomics of abf_energy (scratch:
- * 48 bytes per pixel of the workspace). */
+ * with respect to flow_LtoR, flow_RtoL (H x W x 2, 8-byte aligned) and
+ * L, R (H x W x 3), each nullable and overwritten. d|f|/df = f/|f| for
+ * f != 0 and 0 at 0; a non-finite flow component is used as 0 and
+ * receives gradient 0. The image gradients are bilinear scatters, summed
+ * with float atomics, or, with deterministic != 0, with order-independent
+ * 64-bit fixed-point atomics whose power-of-two scale, 2^(62 - e) with
+ * max |g_F| * 3 H W < 2^e (a bound on every sum; max |g_F| is taken on the
+ * device), cannot overflow at any value scale; g_F must then be finite.
+ * Scratch (deterministic only): 48 bytes per pixel of the workspace. */
 abf_status abf_blend_backward(abf_plan *plan, const float *L, const float *R, const float *flow_LtoR,
                               const float *flow_RtoL, const float *blend, int32_t axis, int32_t H,
                               int32_t W, const float *g_F, float *g_flow_LtoR, float *g_flow_RtoL,
-                              float *g_L, float *g_R, void *hip_stream);
+                              float *g_L, float *g_R, int32_t deterministic, void *hip_stream);
 
 /* Code 1 forward over float32 RGB images (the differentiable variant of
  * abf_blend_asymmetric): F (float32 H x W x 3). */

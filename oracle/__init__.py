@@ -65,6 +65,7 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     sig = {
         "orc_num_threads": (c_int, []),
+        "orc_set_num_threads": (None, [c_int]),
         "orc_luma": (None, [u8p, c_int, c_int, c_long, u8p]),
         "orc_pyr_down": (None, [u8p, c_int, c_int, u8p]),
         "orc_upsample": (None, [i32p, c_int, c_int, c_int, c_int, i32p]),
@@ -91,6 +92,7 @@ def _load():
         "orc_flow_lk_bidirectional": (None, [u8p, u8p, c_int, c_int, c_long, c_long, c_int, c_int, c_int, c_double,
                                              c_int, f64p, f64p]),
         "orc_canvas_dist2": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
+        "orc_canvas_dist2_rows": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
         "orc_canvas_blend": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, f64p]),
         "orc_overlap_box": (None, [u8p, u8p, c_long, c_int, c_int, i32p]),
         "orc_composite": (None, [f64p, f64p, u8p, u8p, c_long, c_int, c_int, f64p, f64p, i32p, c_int, f64p,
@@ -124,6 +126,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (for timing)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def level_sizes(H: int, W: int, N: int):
@@ -326,6 +333,23 @@ def canvas_dist2(mask_L, mask_R, points=None):
     d1, d2 = np.empty(n, np.int64), np.empty(n, np.int64)
     _load().orc_canvas_dist2(_p(mL, u8p), _p(mR, u8p), W, H, W, n, _p(xs, i32p), _p(ys, i32p), _p(d1, i64p),
                              _p(d2, i64p))
+    if points is None:
+        return d1.reshape(H, W), d2.reshape(H, W)
+    return d1, d2
+
+
+def canvas_dist2_rows(mask_L, mask_R, points=None):
+    """The squared distances of ``canvas_dist2`` in two stages (nearest
+    pixel of the area along every row, then the minimum over rows of
+    dy^2 + dx^2): the same values, fast enough for long lists of points on
+    large canvases."""
+    mL, mR = _u8(mask_L), _u8(mask_R)
+    H, W = mL.shape
+    xs, ys = _points(H, W, points)
+    n = xs.size
+    d1, d2 = np.empty(n, np.int64), np.empty(n, np.int64)
+    _load().orc_canvas_dist2_rows(_p(mL, u8p), _p(mR, u8p), W, H, W, n, _p(xs, i32p), _p(ys, i32p),
+                                  _p(d1, i64p), _p(d2, i64p))
     if points is None:
         return d1.reshape(H, W), d2.reshape(H, W)
     return d1, d2

@@ -53,6 +53,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads used by the parallel loops from now on (timing runs). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Flow, step 1: intensity image. The paper runs its flow on image
  * intensity (Section III.C.1); the integer luma weights are a reading. */
@@ -818,6 +828,54 @@ void orc_canvas_dist2(const uint8_t *mL, const uint8_t *mR, long pitch, int H, i
         d2_1[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 1);
         d2_2[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 2);
     }
+}
+
+/* The same squared distances in two stages, for long lists of points on
+ * large canvases: for every row v and column x, the distance along the
+ * row to the nearest pixel of the area in that row (g_v(x), none if the
+ * row has no such pixel); then the nearest pixel of the area to (x, y) is,
+ * for some row v, the nearest one in that row, so
+ * d^2(x, y) = min over v of (y - v)^2 + g_v(x)^2. */
+static void row_distances(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int a, int32_t *g)
+{
+#pragma omp parallel for
+    for (int v = 0; v < H; v++) {
+        int32_t *row = g + (long)v * W;
+        int last = -1;
+        for (int x = 0; x < W; x++) {
+            if (canvas_area(mL, mR, pitch, x, v) == a) last = x;
+            row[x] = last < 0 ? -1 : x - last;
+        }
+        last = -1;
+        for (int x = W - 1; x >= 0; x--) {
+            if (canvas_area(mL, mR, pitch, x, v) == a) last = x;
+            if (last >= 0 && (row[x] < 0 || last - x < row[x])) row[x] = last - x;
+        }
+    }
+}
+
+void orc_canvas_dist2_rows(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, long n,
+                           const int32_t *xs, const int32_t *ys, long long *d2_1, long long *d2_2)
+{
+    int32_t *g1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)H * W);
+    int32_t *g2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)H * W);
+    row_distances(mL, mR, pitch, H, W, 1, g1);
+    row_distances(mL, mR, pitch, H, W, 2, g2);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long i = 0; i < n; i++) {
+        const int x = xs[i], y = ys[i];
+        long long b1 = -1, b2 = -1;
+        for (int v = 0; v < H; v++) {
+            const long long dy2 = (long long)(y - v) * (y - v);
+            const int32_t a1 = g1[(long)v * W + x], a2 = g2[(long)v * W + x];
+            if (a1 >= 0 && (b1 < 0 || dy2 + (long long)a1 * a1 < b1)) b1 = dy2 + (long long)a1 * a1;
+            if (a2 >= 0 && (b2 < 0 || dy2 + (long long)a2 * a2 < b2)) b2 = dy2 + (long long)a2 * a2;
+        }
+        d2_1[i] = b1;
+        d2_2[i] = b2;
+    }
+    free(g1);
+    free(g2);
 }
 
 /* eq. (1) at n canvas points: 0 in Area1, 1 in Area2, 0.5 outside both

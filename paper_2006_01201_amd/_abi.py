@@ -60,7 +60,7 @@ _SIGS = {
                            c_vp]),
     "abf_refine_flow": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_f32, c_vp]),
     "abf_blend_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp,
-                                   c_vp, c_vp, c_vp]),
+                                   c_vp, c_vp, c_i32, c_vp]),
     "abf_blend_asymmetric_f32": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
     "abf_tune": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_vp]),
     "abf_get_launch": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
@@ -183,9 +183,10 @@ def refine_flow(plan, Ref, Tgt, u, H, W, steps, eta, lam, eps, clip_px, stream) 
     return load().abf_refine_flow(plan, Ref, Tgt, u, H, W, steps, eta, lam, eps, clip_px, stream)
 
 
-def blend_backward(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, g_F, g_flr, g_frl, g_L, g_R, stream) -> int:
+def blend_backward(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, g_F, g_flr, g_frl, g_L, g_R, deterministic,
+                   stream) -> int:
     return load().abf_blend_backward(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, g_F, g_flr, g_frl, g_L,
-                                     g_R, stream)
+                                     g_R, deterministic, stream)
 
 
 def blend_asymmetric_f32(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, F, stream) -> int:

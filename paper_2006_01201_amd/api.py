@@ -259,16 +259,18 @@ class Plan:
         _abi.check(st, self.h, "abf_blend_asymmetric_f32")
         return F
 
-    def blend_backward(self, L, R, flow_lr, flow_rl, g_F, blend=None, axis: int = 0):
+    def blend_backward(self, L, R, flow_lr, flow_rl, g_F, blend=None, axis: int = 0, deterministic: bool = False):
         """Adjoint of Code 1: (dF/dflow_LtoR, dF/dflow_RtoL, dF/dL, dF/dR)
-        contracted with g_F."""
+        contracted with g_F; ``deterministic`` sums the image gradients in
+        an order-independent fixed point (bitwise repeatable)."""
         H, W = L.shape[0], L.shape[1]
         out = [torch.empty((H, W, 2), dtype=torch.float32, device=L.device) for _ in range(2)]
         out += [torch.empty((H, W, 3), dtype=torch.float32, device=L.device) for _ in range(2)]
         st = _abi.blend_backward(self.h, _f32(L, (H, W, 3), "L"), _f32(R, (H, W, 3), "R"),
                                  _f32(flow_lr, (H, W, 2), "flow_LtoR"), _f32(flow_rl, (H, W, 2), "flow_RtoL"),
                                  _f32(blend, (H, W), "blend") if blend is not None else None, axis, H, W,
-                                 _f32(g_F, (H, W, 3), "g_F"), *[o.data_ptr() for o in out], _stream())
+                                 _f32(g_F, (H, W, 3), "g_F"), *[o.data_ptr() for o in out], int(deterministic),
+                                 _stream())
         _abi.check(st, self.h, "abf_blend_backward")
         return tuple(out)
 

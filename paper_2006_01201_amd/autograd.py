@@ -44,7 +44,9 @@ class AsymBlend(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gF):
         L, R, flr, frl = ctx.saved_tensors
-        g_lr, g_rl, gL, gR = ctx.plan.blend_backward(L, R, flr, frl, gF.contiguous(), ctx.blend, ctx.axis)
+        # deterministic scatter for the image gradients: repeatable gradients
+        g_lr, g_rl, gL, gR = ctx.plan.blend_backward(L, R, flr, frl, gF.contiguous(), ctx.blend, ctx.axis,
+                                                     deterministic=True)
         return None, gL, gR, g_lr, g_rl, None, None
 
 

@@ -19,12 +19,23 @@ namespace {
 
 __device__ __forceinline__ int clampg(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-constexpr double kFixScale = 1099511627776.0;  // 2^40
+// Deterministic scatters add v * scale, rounded, into 64-bit integers. The
+// scale is a power of two chosen per call from a bound B on the sum of the
+// magnitudes that can reach one pixel (so on every partial sum): 2^(62 - e)
+// with B < 2^e, so |sum| * scale < 2^62 never overflows, and each addend
+// keeps 62 bits below B. (B is at least 3 times the smallest float, so the
+// exponent stays far from the double range.)
+__host__ __device__ inline double fix_scale_for(double bound)
+{
+    int e = 0;
+    if (bound > 0.0) (void)frexp(bound, &e);  // bound < 2^e
+    return ldexp(1.0, 62 - e);
+}
 
-__device__ __forceinline__ void scatter_add(float *g, unsigned long long *gfix, size_t i, float v)
+__device__ __forceinline__ void scatter_add(float *g, unsigned long long *gfix, double scale, size_t i, float v)
 {
     if (gfix)
-        atomicAdd(gfix + i, (unsigned long long)(long long)llrint((double)v * kFixScale));
+        atomicAdd(gfix + i, (unsigned long long)(long long)llrint((double)v * scale));
     else
         atomicAdd(g + i, v);
 }
@@ -60,12 +71,13 @@ __device__ __forceinline__ void bil_eval(const float *img, int W, const Bil &b, 
     dY = (1.f - b.fx) * (v10 - v00) + b.fx * (v11 - v01);
 }
 
-__device__ __forceinline__ void bil_scatter(float *g, unsigned long long *gfix, int W, const Bil &b, int c, float w)
+__device__ __forceinline__ void bil_scatter(float *g, unsigned long long *gfix, double scale, int W, const Bil &b,
+                                            int c, float w)
 {
-    scatter_add(g, gfix, 3 * ((size_t)b.ya * W + b.xa) + c, w * (1.f - b.fy) * (1.f - b.fx));
-    scatter_add(g, gfix, 3 * ((size_t)b.ya * W + b.xb) + c, w * (1.f - b.fy) * b.fx);
-    scatter_add(g, gfix, 3 * ((size_t)b.yb * W + b.xa) + c, w * b.fy * (1.f - b.fx));
-    scatter_add(g, gfix, 3 * ((size_t)b.yb * W + b.xb) + c, w * b.fy * b.fx);
+    scatter_add(g, gfix, scale, 3 * ((size_t)b.ya * W + b.xa) + c, w * (1.f - b.fy) * (1.f - b.fx));
+    scatter_add(g, gfix, scale, 3 * ((size_t)b.ya * W + b.xb) + c, w * (1.f - b.fy) * b.fx);
+    scatter_add(g, gfix, scale, 3 * ((size_t)b.yb * W + b.xa) + c, w * b.fy * (1.f - b.fx));
+    scatter_add(g, gfix, scale, 3 * ((size_t)b.yb * W + b.xb) + c, w * b.fy * b.fx);
 }
 
 // TV term at q for component m: s(q)^2 and the forward differences
@@ -80,9 +92,15 @@ __device__ __forceinline__ float tv_s2(const float *u, int H, int W, int x, int 
     return dx * dx + dy * dy + eps * eps;
 }
 
-// 1 / sqrt(v) for v > 0 (v_rsq_f32, within 1 ulp): the gradient's
-// quotients r / rho and d / s; the energy keeps the rounded square roots
+// 1 / sqrt(v) for v >= FLT_MIN (v_rsq_f32, within 1 ulp; the entry points
+// reject an eps whose square is below FLT_MIN, so every argument is a
+// normal number): the gradient's quotients r / rho and d / s; the energy
+// keeps the rounded square roots
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+
+// rho'(r) = r / sqrt(r^2 + eps^2), the Charbonnier derivative (both the
+// flow gradient and the image gradients use this one form)
+__device__ __forceinline__ float charb_d(float r, float eps) { return r * rsq(r * r + eps * eps); }
 
 // dE/du at p (photometric + lambda * TV); also returns the pixel's energy
 __device__ __forceinline__ void grad_u_at(const float *Ref, const float *Tgt, const float *u, int H, int W, int x,
@@ -99,9 +117,8 @@ __device__ __forceinline__ void grad_u_at(const float *Ref, const float *Tgt, co
         float v, dX, dY;
         bil_eval(Tgt, W, b, c, v, dX, dY);
         const float r = v - gr[3 * p + c];
-        const float rho2 = r * r + eps * eps;
-        const float d = r * rsq(rho2);
-        e += sqrtf(rho2);
+        const float d = charb_d(r, eps);
+        e += sqrtf(r * r + eps * eps);
         gx = fmaf(d, dX, gx);
         gy = fmaf(d, dY, gy);
     }
@@ -131,7 +148,8 @@ constexpr int kEB = 256;
 __global__ __launch_bounds__(kEB) void k_energy(const float *__restrict__ Ref, const float *__restrict__ Tgt,
                                                 const float *__restrict__ u, int H, int W, float lambda, float eps,
                                                 double *__restrict__ partials, float *__restrict__ g_u,
-                                                float *__restrict__ g_ref, float *g_tgt, unsigned long long *g_fix)
+                                                float *__restrict__ g_ref, float *g_tgt, unsigned long long *g_fix,
+                                                double fix_scale)
 {
     __shared__ double red[kEB];
     const int64_t n = (int64_t)H * W;
@@ -152,10 +170,9 @@ __global__ __launch_bounds__(kEB) void k_energy(const float *__restrict__ Ref, c
             for (int c = 0; c < 3; c++) {
                 float v, dX, dY;
                 bil_eval(Tgt, W, b, c, v, dX, dY);
-                const float r = v - Ref[3 * p + c];
-                const float d = r / sqrtf(r * r + eps * eps);
+                const float d = charb_d(v - Ref[3 * p + c], eps);
                 if (g_ref) g_ref[3 * p + c] = -d;
-                if (g_tgt || g_fix) bil_scatter(g_tgt, g_fix, W, b, c, d);
+                if (g_tgt || g_fix) bil_scatter(g_tgt, g_fix, fix_scale, W, b, c, d);
             }
         }
     }
@@ -182,6 +199,11 @@ __global__ __launch_bounds__(kEB) void k_sum_partials(const double *__restrict__
     if (threadIdx.x == 0) *E = (float)red[0];
 }
 
+__global__ __launch_bounds__(64) void k_zero_u32(uint32_t *a)
+{
+    if (threadIdx.x == 0) *a = 0u;
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(float *a, unsigned long long *b, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -190,10 +212,28 @@ __global__ __launch_bounds__(256) void k_fill_zero(float *a, unsigned long long 
     }
 }
 
-__global__ __launch_bounds__(256) void k_fix_to_float(const unsigned long long *__restrict__ b, float *a, int64_t n)
+// scale: the fixed-point scale itself, or, with gmax, the scale for the
+// bound (largest |g_F|, as float bits) * fan
+__global__ __launch_bounds__(256) void k_fix_to_float(const unsigned long long *__restrict__ b, float *a, int64_t n,
+                                                      double scale, const uint32_t *__restrict__ gmax, double fan)
 {
+    if (gmax) scale = fix_scale_for((double)__uint_as_float(*gmax) * fan);
+    const double inv = 1.0 / scale;  // a power of two: exact
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        a[i] = (float)((double)(long long)b[i] / kFixScale);
+        a[i] = (float)((double)(long long)b[i] * inv);
+}
+
+// largest |v| over n floats, as float bits (an unsigned max of the bits of
+// non-negative floats orders them; the result does not depend on the
+// order); *out must start at 0
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ v, int64_t n, uint32_t *out)
+{
+    uint32_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = max(m, __float_as_uint(v[i]) & 0x7fffffffu);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
 }
 
 __global__ __launch_bounds__(256) void k_energy_step(const float *__restrict__ Ref, const float *__restrict__ Tgt,
@@ -289,9 +329,13 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const float *__restrict__ L, 
                                                    const float *__restrict__ blend, int axis, int H, int W,
                                                    BlendParams bp, const float *__restrict__ gF,
                                                    float *__restrict__ g_flr, float *__restrict__ g_frl, float *g_L,
-                                                   float *g_R, unsigned long long *fixL, unsigned long long *fixR)
+                                                   float *g_R, unsigned long long *fixL, unsigned long long *fixR,
+                                                   const uint32_t *__restrict__ gmax)
 {
     const int64_t n = (int64_t)H * W;
+    // every (pixel, channel) of g_F adds at most |g_F| (weights sL, sR and
+    // the bilinear weights are <= 1 and sum to <= 1) into an image gradient
+    const double scale = gmax ? fix_scale_for((double)__uint_as_float(*gmax) * 3.0 * (double)n) : 0.0;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
         const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
         const Setup s = code1_setup(x, y, H, W, axis, blend, flr, frl, bp);
@@ -308,8 +352,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const float *__restrict__ L, 
             gLy = fmaf(g * sL, lY, gLy);
             gRx = fmaf(g * sR, rX, gRx);
             gRy = fmaf(g * sR, rY, gRy);
-            if (g_L || fixL) bil_scatter(g_L, fixL, W, s.bl, c, g * sL);
-            if (g_R || fixR) bil_scatter(g_R, fixR, W, s.br, c, g * sR);
+            if (g_L || fixL) bil_scatter(g_L, fixL, scale, W, s.bl, c, g * sL);
+            if (g_R || fixR) bil_scatter(g_R, fixR, scale, W, s.br, c, g * sR);
         }
         const float t = (float)s.t;
         float grl_x = t * gLx, grl_y = t * gLy, glr_x = (1.f - t) * gRx, glr_y = (1.f - t) * gRy;
@@ -407,10 +451,15 @@ hipError_t launch_energy_full(const float *Ref, const float *Tgt, const float *u
     if (g_tgt) {
         hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, fix ? nullptr : g_tgt, fix, n3);
     }
+    // |rho'| <= 1 and the bilinear weights sum to 1: no pixel of dE/dTgt
+    // exceeds 3 H W in magnitude
+    const double scale = fix_scale_for((double)n3);
     hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kEB), 0, s, Ref, Tgt, u, H, W, lambda, eps, partials, g_u, g_ref,
-                       fix ? nullptr : g_tgt, g_tgt ? fix : nullptr);
+                       fix ? nullptr : g_tgt, g_tgt ? fix : nullptr, scale);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kEB), 0, s, partials, nb, E);
-    if (g_tgt && fix) hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fix, g_tgt, n3);
+    if (g_tgt && fix)
+        hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fix, g_tgt, n3, scale,
+                           (const uint32_t *)nullptr, 0.0);
     return hipGetLastError();
 }
 
@@ -449,16 +498,30 @@ hipError_t launch_blend_f32(const float *L, const float *R, const float *flr, co
 hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *flr, const float *frl,
                                  const float *blend, int axis, int H, int W, BlendParams bp, const float *gF,
                                  float *g_flr, float *g_frl, float *g_L, float *g_R, unsigned long long *fixL,
-                                 unsigned long long *fixR, hipStream_t s)
+                                 unsigned long long *fixR, uint32_t *gmax, hipStream_t s)
 {
     const int64_t n3 = (int64_t)H * W * 3;
-    if (g_L) hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, fixL ? nullptr : g_L, fixL, n3);
-    if (g_R) hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, fixR ? nullptr : g_R, fixR, n3);
+    const bool det = gmax && (g_L || g_R);
+    if (det) {
+        // the fixed-point scale follows the largest |g_F|, found on the device
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, gmax);
+        hipLaunchKernelGGL(k_absmax, dim3(blocks_for(n3, 256, 2048)), dim3(256), 0, s, gF, n3, gmax);
+    }
+    if (g_L) hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, det ? nullptr : g_L,
+                                det ? fixL : nullptr, n3);
+    if (g_R) hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n3)), dim3(256), 0, s, det ? nullptr : g_R,
+                                det ? fixR : nullptr, n3);
     hipLaunchKernelGGL(k_blend_bwd, dim3(blocks_for((int64_t)H * W)), dim3(256), 0, s, L, R, flr, frl, blend, axis,
-                       H, W, bp, gF, g_flr, g_frl, fixL ? nullptr : g_L, fixR ? nullptr : g_R, g_L ? fixL : nullptr,
-                       g_R ? fixR : nullptr);
-    if (g_L && fixL) hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fixL, g_L, n3);
-    if (g_R && fixR) hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fixR, g_R, n3);
+                       H, W, bp, gF, g_flr, g_frl, det ? nullptr : g_L, det ? nullptr : g_R,
+                       (det && g_L) ? fixL : nullptr, (det && g_R) ? fixR : nullptr,
+                       det ? (const uint32_t *)gmax : nullptr);
+    const double fan = 3.0 * (double)H * W;
+    if (det && g_L)
+        hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fixL, g_L, n3, 0.0,
+                           (const uint32_t *)gmax, fan);
+    if (det && g_R)
+        hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fixR, g_R, n3, 0.0,
+                           (const uint32_t *)gmax, fan);
     return hipGetLastError();
 }
 

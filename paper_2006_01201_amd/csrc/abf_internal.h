@@ -131,7 +131,8 @@ hipError_t launch_refine_batch(const RefineDesc *d, const int32_t *prefix, int n
                                float lambda, float eps, float clip, hipStream_t s);
 
 // differentiable path (float images); `fix` buffers (3 H W uint64) select
-// the deterministic fixed-point scatter, null selects float atomics
+// the deterministic fixed-point scatter, null selects float atomics (for
+// the Code 1 adjoint, `gmax` (one uint32) selects it)
 int energy_blocks(int H, int W);
 hipError_t launch_energy_full(const float *Ref, const float *Tgt, const float *u, int H, int W, float lambda,
                               float eps, double *partials, float *E, float *g_u, float *g_ref, float *g_tgt,
@@ -144,7 +145,7 @@ hipError_t launch_blend_f32(const float *L, const float *R, const float *flr, co
 hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *flr, const float *frl,
                                  const float *blend, int axis, int H, int W, BlendParams bp, const float *gF,
                                  float *g_flr, float *g_frl, float *g_L, float *g_R, unsigned long long *fixL,
-                                 unsigned long long *fixR, hipStream_t s);
+                                 unsigned long long *fixR, uint32_t *gmax, hipStream_t s);
 
 // ---------------------------------------------------------------------
 // Canvas compositing (defined in abf_canvas.hip). Canvases are at most

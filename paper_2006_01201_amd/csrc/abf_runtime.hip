@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -31,6 +32,9 @@ constexpr size_t kAlign = 256;
 constexpr int kSlots = 4;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// flows are read and written as one 64-bit (x, y) pair per pixel
+inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 struct Launch {
     int tile_h;
@@ -260,6 +264,8 @@ abf_status build_batch(abf_plan *pl, const abf_strip *st, int n, bool flows, boo
         const abf_strip &x = st[s];
         if (!x.L || !x.R || (blend && !x.F) || !x.flow_LtoR || !x.flow_RtoL)
             return fail(pl, ABF_E_INVALID, "strip %d: null pointer", s);
+        if (!aligned8(x.flow_LtoR) || !aligned8(x.flow_RtoL))
+            return fail(pl, ABF_E_INVALID, "strip %d: flows must be 8-byte aligned", s);
         if (x.H < 1 || x.W < 1) return fail(pl, ABF_E_SHAPE, "strip %d: size %d x %d", s, x.H, x.W);
         if (x.H > pl->max_H || x.W > pl->max_W)
             return fail(pl, ABF_E_SHAPE, "strip %d: %d x %d exceeds the plan's %d x %d", s, x.H, x.W, pl->max_H,
@@ -982,6 +988,8 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
         return fail(plan, ABF_E_SHAPE, "box {%d, %d, %d, %d} outside the %d x %d canvas", bx, by, bw, bh, H, W);
     const bool any = bw > 0 && bh > 0;
     if (any && (!flow_LtoR || !flow_RtoL)) return fail(plan, ABF_E_INVALID, "null flow");
+    if (any && (!aligned8(flow_LtoR) || !aligned8(flow_RtoL)))
+        return fail(plan, ABF_E_INVALID, "flows must be 8-byte aligned");
     if (blend && pitch_blend < W) return fail(plan, ABF_E_SHAPE, "blend pitch %d < W %d", pitch_blend, W);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     CanvasGeom g{};
@@ -1148,7 +1156,8 @@ abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const 
     if (!plan) return ABF_E_INVALID;
     if (!Ref || !Tgt || !u || !E_dev) return fail(plan, ABF_E_INVALID, "null pointer");
     if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
-    if (!(eps > 0.f) || !(lambda >= 0.f)) return fail(plan, ABF_E_INVALID, "eps must be > 0, lambda >= 0");
+    if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f))
+        return fail(plan, ABF_E_INVALID, "eps^2 must be a normal float (eps >= 1.1e-19), lambda >= 0");
     const size_t npart = align_up(sizeof(double) * energy_blocks(H, W), kAlign);
     const size_t nfix = (deterministic && g_Tgt) ? align_up(sizeof(uint64_t) * 3 * (size_t)H * W, kAlign) : 0;
     uint8_t *scr = nullptr;
@@ -1166,7 +1175,9 @@ abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, f
     if (!plan) return ABF_E_INVALID;
     if (!Ref || !Tgt || !u) return fail(plan, ABF_E_INVALID, "null pointer");
     if (H < 1 || W < 1 || steps < 0) return fail(plan, ABF_E_SHAPE, "size %d x %d, %d steps", H, W, steps);
-    if (!(eps > 0.f) || !(lambda >= 0.f) || !(clip_px >= 0.f)) return fail(plan, ABF_E_INVALID, "bad parameter");
+    if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f) || !(clip_px >= 0.f))
+        return fail(plan, ABF_E_INVALID, "bad parameter (eps^2 must be a normal float, lambda and clip >= 0)");
+    if (!aligned8(u)) return fail(plan, ABF_E_INVALID, "u must be 8-byte aligned");
     uint8_t *scr = nullptr;
     abf_status rc = grad_scratch(plan, sizeof(float) * 2 * (size_t)H * W, &scr);
     if (rc != ABF_OK) return rc;
@@ -1195,17 +1206,18 @@ abf_status abf_blend_asymmetric_f32(abf_plan *plan, const float *L, const float 
 abf_status abf_blend_backward(abf_plan *plan, const float *L, const float *R, const float *flow_LtoR,
                               const float *flow_RtoL, const float *blend, int32_t axis, int32_t H, int32_t W,
                               const float *g_F, float *g_flow_LtoR, float *g_flow_RtoL, float *g_L, float *g_R,
-                              void *hip_stream)
+                              int32_t deterministic, void *hip_stream)
 {
     if (!plan) return ABF_E_INVALID;
     if (!L || !R || !flow_LtoR || !flow_RtoL || !g_F) return fail(plan, ABF_E_INVALID, "null pointer");
     if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
     if (axis != 0 && axis != 1) return fail(plan, ABF_E_INVALID, "axis %d", axis);
-    const bool det = getenv("ABF_DETERMINISTIC") && atoi(getenv("ABF_DETERMINISTIC")) != 0;
+    if (!aligned8(flow_LtoR) || !aligned8(flow_RtoL)) return fail(plan, ABF_E_INVALID, "flows must be 8-byte aligned");
+    const bool det = deterministic != 0 && (g_L || g_R);
     const size_t nfix = align_up(sizeof(uint64_t) * 3 * (size_t)H * W, kAlign);
     uint8_t *scr = nullptr;
     if (det) {
-        abf_status rc = grad_scratch(plan, 2 * nfix, &scr);
+        abf_status rc = grad_scratch(plan, 2 * nfix + kAlign, &scr);
         if (rc != ABF_OK) return rc;
     }
     BlendParams bp{plan->p.k_sharp, plan->p.k_flowmag, plan->p.blend_mode};
@@ -1213,6 +1225,7 @@ abf_status abf_blend_backward(abf_plan *plan, const float *L, const float *R, co
                                         g_flow_RtoL, g_L, g_R,
                                         det ? reinterpret_cast<unsigned long long *>(scr) : nullptr,
                                         det ? reinterpret_cast<unsigned long long *>(scr + nfix) : nullptr,
+                                        det ? reinterpret_cast<uint32_t *>(scr + 2 * nfix) : nullptr,
                                         static_cast<hipStream_t>(hip_stream)));
     return ABF_OK;
 }
@@ -1253,7 +1266,8 @@ abf_status abf_refine_strips(abf_plan *plan, const abf_refine_strip *strips, int
     if (!plan) return ABF_E_INVALID;
     if (!strips || n < 1 || steps < 0) return fail(plan, ABF_E_INVALID, "bad arguments");
     if (n > plan->max_strips) return fail(plan, ABF_E_SHAPE, "%d strips exceed the plan's %d", n, plan->max_strips);
-    if (!(eps > 0.f) || !(lambda >= 0.f) || !(clip_px >= 0.f)) return fail(plan, ABF_E_INVALID, "bad parameter");
+    if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f) || !(clip_px >= 0.f))
+        return fail(plan, ABF_E_INVALID, "bad parameter (eps^2 must be a normal float, lambda and clip >= 0)");
     if (!plan->ws) return fail(plan, ABF_E_WORKSPACE, "no workspace bound");
     std::vector<RefineDesc> d(n);
     std::vector<int32_t> prefix(n + 1);
@@ -1262,6 +1276,7 @@ abf_status abf_refine_strips(abf_plan *plan, const abf_refine_strip *strips, int
     for (int i = 0; i < n; i++) {
         const abf_refine_strip &x = strips[i];
         if (!x.Ref || !x.Tgt || !x.u) return fail(plan, ABF_E_INVALID, "strip %d: null pointer", i);
+        if (!aligned8(x.u)) return fail(plan, ABF_E_INVALID, "strip %d: u must be 8-byte aligned", i);
         if (x.H < 1 || x.W < 1) return fail(plan, ABF_E_SHAPE, "strip %d: size %d x %d", i, x.H, x.W);
         d[i].Ref = x.Ref;
         d[i].Tgt = x.Tgt;

@@ -122,6 +122,43 @@ def test_large_canvas_sampled(api):
     assert (h2[a == 2] == 0).all() and (h2[a != 2] > 0).all()
 
 
+def test_large_canvas_full_rows_and_columns(api):
+    # the same 4000 x 2400 canvas: every pixel of 8 full rows and 8 full
+    # columns (51 200 points), through both Area1 islands inside the overlap
+    # and across the overlap box, against the oracle's exact distances
+    from scipy import ndimage
+
+    rng = synth.rng_for(113, 0, 0)
+    mL, mR = synth.canvas_masks(rng, 4000, 2400, 0.3, holes=2)
+    H, W = mL.shape
+    plan = plan_for(api, H, W)
+    print("[gpu] canvas distances 4000x2400, 8 full rows and 8 full columns", flush=True)
+    B, d1, d2 = plan.canvas_blend(dev(mL), dev(mR), distances=True)
+    torch.cuda.synchronize()
+    a = (mL > 0) + 2 * (mR > 0)
+    lab, n = ndimage.label(a == 1)
+    sizes = ndimage.sum(np.ones_like(lab), lab, range(1, n + 1))
+    islands = [k + 1 for k in np.argsort(sizes)[:-1]]  # every component but the main Area1
+    assert len(islands) >= 2
+    cents = ndimage.center_of_mass(np.ones_like(lab), lab, islands[:2])
+    bx, by, bw, bh = oracle.overlap_box(mL, mR)
+    rows = [int(c[0]) for c in cents] + [by + 1, by + bh - 2] + [by + bh * k // 5 for k in range(1, 5)]
+    cols = [int(c[1]) for c in cents] + [bx + 1, bx + bw - 2] + [bx + bw * k // 5 for k in range(1, 5)]
+    pts = np.concatenate([np.stack([np.arange(W), np.full(W, r)], 1) for r in rows] +
+                         [np.stack([np.full(H, c), np.arange(H)], 1) for c in cols])
+    o1, o2 = oracle.canvas_dist2_rows(mL, mR, pts)
+    g1 = d1.cpu().numpy()[pts[:, 1], pts[:, 0]].astype(np.int64)
+    g2 = d2.cpu().numpy()[pts[:, 1], pts[:, 0]].astype(np.int64)
+    assert np.array_equal(g1, o1)
+    assert np.array_equal(g2, o2)
+    # eq. (1) from the exact distances, at the Area3 points
+    on3 = a[pts[:, 1], pts[:, 0]] == 3
+    oB = np.sqrt(o1) / (np.sqrt(o1) + np.sqrt(o2))
+    gB = B.cpu().numpy()[pts[:, 1], pts[:, 0]].astype(np.float64)
+    assert np.abs(gB[on3] - oB[on3]).max() <= B_TOL
+    print(f"canvas rows {rows} columns {cols}: {len(pts)} points, {int(on3.sum())} in Area3, all equal", flush=True)
+
+
 def _check_F(F8, Ff, oF):
     assert np.abs(Ff - oF).max() <= F_TOL
     r = oF - np.floor(oF)

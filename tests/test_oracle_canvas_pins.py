@@ -30,6 +30,25 @@ def test_dist2_equals_scipy_edt(seed, H, W):
         assert np.array_equal(d, np.rint(e * e).astype(np.int64))
 
 
+@pytest.mark.parametrize("seed,H,W", [(1, 23, 41), (3, 17, 90), (4, 1, 57), (5, 49, 1), (11, 120, 77),
+                                      (12, 60, 50)])
+def test_two_stage_dist2_equals_scipy_edt_and_brute_force(seed, H, W):
+    mL, mR = synth.random_masks(seed, H, W, p_empty=0.3 if seed == 12 else 0.0)
+    a = areas(mL, mR)
+    r1, r2 = oracle.canvas_dist2_rows(mL, mR)
+    b1, b2 = oracle.canvas_dist2(mL, mR)
+    assert np.array_equal(r1, b1) and np.array_equal(r2, b2)
+    for k, d in ((1, r1), (2, r2)):
+        if (a == k).any():
+            e = ndimage.distance_transform_edt(a != k)
+            assert np.array_equal(d, np.rint(e * e).astype(np.int64))
+        else:
+            assert (d == -1).all()
+    pts = np.array([[0, 0], [W - 1, H - 1], [W // 2, H // 3]])
+    p1, p2 = oracle.canvas_dist2_rows(mL, mR, pts)
+    assert np.array_equal(p1, b1[pts[:, 1], pts[:, 0]]) and np.array_equal(p2, b2[pts[:, 1], pts[:, 0]])
+
+
 def test_dist2_points_equal_full_canvas():
     mL, mR = synth.random_masks(7, 30, 45)
     d1, d2 = oracle.canvas_dist2(mL, mR)
