@@ -108,7 +108,7 @@ typedef struct abf_strip {
 
 /* Fills the adopted defaults: N = 6, P = 2, R = 2, Rc = 4, T = 2, M = 1,
  * lk window 5 x 5, 2 iterations, eps 25, kSoftmaxSharpness 10,
- * kFlowMagCoef 20, softmax blend, exposure compensation on. */
+ * kFlowMagCoef 20, softmax blend, exposure step off, flow method 0. */
 void abf_default_params(abf_params *p);
 
 /* Creates a plan for batches of at most max_strips strips whose level-0
@@ -345,7 +345,7 @@ abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hi
  * propagation, refine, blend), level-size class 0..3; *tile_h and *grid
  * receive the tile height and persistent workgroups per CU (0 = one
  * workgroup per tile). abf_set_launch overrides it; valid tile heights:
- * search 1, 2, 4, 8; propagation 8, 16, 32; refine 2, 4; other stages 4
+ * search 1, 2, 4, 8; propagation 16, 32; refine 2, 4; other stages 4
  * (ABF_E_INVALID otherwise). */
 abf_status abf_get_launch(const abf_plan *plan, int32_t stage, int32_t size_class, int32_t *tile_h,
                           int32_t *grid);

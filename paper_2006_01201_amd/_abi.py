@@ -94,6 +94,11 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libabf.so is not built ({LIB_PATH}); run paper_2006_01201_amd/build.py "
                           "(or __graft_entry__.build()) first")
+    # torch ships its own HIP runtime under the same soname as the system's;
+    # whichever is loaded first serves the whole process. Loading torch first
+    # makes the library run on the runtime that owns torch's memory and
+    # streams, whatever the caller imported first.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

@@ -201,20 +201,13 @@ __host__ __device__ inline int tiles_pyr(int H, int W)
 }
 __host__ __device__ inline int tiles_search(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kSearchTW); }
 // fused propagation (T steps + median, halo h = T + M <= kPropMaxHalo):
-// 256 threads per tile of (kPropRW - 2h) x th outputs over a
-// kPropRW x (th + 2h) region; LDS per region pixel: two iterates and the
-// job index (4 B each), the carried cost (2 B), up to four job entries
-// (2 B each) and the step of its last change (1 B), plus the job counter
-constexpr int kPropThreads = 256;
+// one wave per tile of (kPropRW - 2h) x th outputs over a
+// kPropRW x (th + 2h) region held in registers (th = 16 or 32)
 constexpr int kPropRW = 64;
 constexpr int kPropMaxHalo = 5;
 __host__ __device__ inline int tiles_prop(int H, int W, int th, int h)
 {
     return 2 * ceil_div(H, th) * ceil_div(W, kPropRW - 2 * h);
-}
-__host__ __device__ inline size_t prop_lds_bytes(int h, int th)
-{
-    return (((size_t)kPropRW * (th + 2 * h) * 23 + 3) & ~(size_t)3) + 16;
 }
 // refine: tiles of 64 x th pixels over the interior rectangle (window
 // inside the image) per direction; the border band around it (per

@@ -147,7 +147,7 @@ bool valid_th(int stage, int th)
 {
     switch (stage) {
     case ST_SEARCH: return th == 1 || th == 2 || th == 4 || th == 8;
-    case ST_PROP: return th == 8 || th == 16 || th == 32;
+    case ST_PROP: return th == 16 || th == 32;
     case ST_REFINE: return th == 2 || th == 4;
     default: return th == 4;
     }
