@@ -264,7 +264,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
 CSRC = os.path.join(ROOT, "paper_2006_01201_amd", "csrc")
 # the sources whose change invalidates the recorded counters (kernels and
 # the runtime that shapes their launches)
-TRAFFIC_SOURCES = ("abf_kernels.hip", "abf_runtime.hip", "abf_internal.h", "abf_device.h")
+TRAFFIC_SOURCES = ("abf_kernels.hip", "abf_prop.hip", "abf_runtime.hip", "abf_internal.h", "abf_device.h", "abf_tiles.h")
 
 
 def source_digest():

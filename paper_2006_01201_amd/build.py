@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabf.so")
-SOURCES = ["abf_kernels.hip", "abf_runtime.hip", "abf_grad.hip", "abf_canvas.hip"]
+SOURCES = ["abf_kernels.hip", "abf_prop.hip", "abf_runtime.hip", "abf_grad.hip", "abf_canvas.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
