@@ -138,6 +138,27 @@ abf_status abf_flow_bidirectional(abf_plan *plan, const uint8_t *L, const uint8_
                                   int32_t W, int32_t pitch_L, int32_t pitch_R, float *flow_LtoR,
                                   float *flow_RtoL, void *hip_stream);
 
+/* Allocation-free variant of abf_flow_bidirectional, for callers that
+ * cannot allocate device memory (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same arguments, kernels and
+ * results; the flow path's scratch (pyramids, integer flows of every level,
+ * descriptor tables) lives in a static device array of
+ * ABF_NOALLOC_SCRATCH_BYTES per device, which the library holds from the
+ * first plan on that device until the process ends, instead of the plan's
+ * workspace (none need be bound). The call allocates no device memory
+ * (no hipMalloc or hipFree; the descriptor tables go through the plan's
+ * pinned staging, a host-to-device copy on hip_stream). ABF_E_WORKSPACE if
+ * the strip's layout exceeds the array (at 6 levels, strips up to about
+ * 2 Mpx fit). Every call on one device shares that device's array, which
+ * keeps the last call's contents (everything the path reads is written
+ * first in the same call): calls that overlap in time on one device (two
+ * streams, plans or threads) race and give wrong results, so order them on
+ * one stream. */
+#define ABF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+abf_status abf_flow_bidirectional_noalloc(abf_plan *plan, const uint8_t *L, const uint8_t *R, int32_t H,
+                                          int32_t W, int32_t pitch_L, int32_t pitch_R, float *flow_LtoR,
+                                          float *flow_RtoL, void *hip_stream);
+
 /* Code 1 with eq. (1) over one strip. Device pointers: L, R, flow_LtoR,
  * flow_RtoL, blend (nullable: eq. (1) for a rectangular strip,
  * Blend = (x+1)/(W+1) for axis 0, (y+1)/(H+1) for axis 1; otherwise a

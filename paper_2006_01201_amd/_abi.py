@@ -48,6 +48,7 @@ _SIGS = {
     "abf_workspace_bytes": (c_sz, [c_vp]),
     "abf_bind_workspace": (c_i32, [c_vp, c_vp, c_sz]),
     "abf_flow_bidirectional": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp]),
+    "abf_flow_bidirectional_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp]),
     "abf_blend_asymmetric": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32,
                                      c_vp, c_i32, c_vp, c_vp]),
     "abf_stitch_strips": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_i32, c_vp]),
@@ -149,6 +150,10 @@ def bind_workspace(plan, ptr: int, nbytes: int) -> int:
 
 def flow_bidirectional(plan, L, R, H, W, pitch_L, pitch_R, flow_LtoR, flow_RtoL, stream) -> int:
     return load().abf_flow_bidirectional(plan, L, R, H, W, pitch_L, pitch_R, flow_LtoR, flow_RtoL, stream)
+
+
+def flow_bidirectional_noalloc(plan, L, R, H, W, pitch_L, pitch_R, flow_LtoR, flow_RtoL, stream) -> int:
+    return load().abf_flow_bidirectional_noalloc(plan, L, R, H, W, pitch_L, pitch_R, flow_LtoR, flow_RtoL, stream)
 
 
 def blend_asymmetric(plan, L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, pitch_L, pitch_R, F, pitch_F, F_f32,

@@ -135,6 +135,21 @@ class Plan:
         _abi.check(st, self.h, "abf_flow_bidirectional")
         return flr, frl
 
+    def flow_bidirectional_noalloc(self, L: torch.Tensor, R: torch.Tensor, out):
+        """flow_bidirectional with the library's static scratch instead of
+        the workspace (abf_flow_bidirectional_noalloc); ``out`` = the two
+        caller-allocated flow tensors."""
+        H, W, pl = _img_u8(L, "L")
+        H2, W2, pr = _img_u8(R, "R")
+        if (H, W) != (H2, W2):
+            raise ValueError("L and R differ in size")
+        flr, frl = out
+        st = _abi.flow_bidirectional_noalloc(self.h, L.data_ptr(), R.data_ptr(), H, W, pl, pr,
+                                             _f32(flr, (H, W, 2), "flow_LtoR"), _f32(frl, (H, W, 2), "flow_RtoL"),
+                                             _stream())
+        _abi.check(st, self.h, "abf_flow_bidirectional_noalloc")
+        return flr, frl
+
     def blend_asymmetric(self, L, R, flow_lr, flow_rl, blend=None, axis: int = 0, f32: bool = False, out=None):
         """Code 1 over one strip; returns F (uint8 H x W x 3) and, if
         ``f32``, the unrounded composite (float32 H x W x 3)."""

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,8 @@ struct abf_plan {
     // graphs
     std::map<std::string, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;
+    // device address of the static scratch array on the plan's device
+    uint8_t *scratch = nullptr;
 };
 
 namespace {
@@ -579,6 +582,39 @@ abf_status run(abf_plan *pl, const abf_strip *st, int n, bool flows, bool blend,
 
 }  // namespace
 
+// ---------------------------------------------------------------------
+// Static scratch of the allocation-free flow entry point: a file-scope
+// device array (one copy per device, held until the process ends). In
+// host code its name is only a stand-in for the symbol; the device address
+// of each device's copy is looked up once per device with
+// hipGetSymbolAddress (at plan creation, with that device current) and
+// only that address is used.
+static __device__ __align__(256) uint8_t scratch[ABF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[kMaxDevices] = {};
+
+// Address of the current device's scratch (device `dev`), looked up once.
+abf_status scratch_address(int dev, uint8_t **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return ABF_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return ABF_E_DEVICE;
+        g_scratch[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch[dev];
+    return ABF_OK;
+}
+
+}  // namespace
+
 // =====================================================================
 // C ABI
 
@@ -636,7 +672,12 @@ abf_status abf_create_plan(const abf_params *params, int32_t max_strips, int64_t
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(nullptr, ABF_E_UNSUPPORTED, "device %d is %s, not gfx950", dev, prop.gcnArchName);
 
+    uint8_t *scr = nullptr;
+    if (scratch_address(dev, &scr) != ABF_OK)
+        return fail(nullptr, ABF_E_DEVICE, "hipGetSymbolAddress of the static scratch failed on device %d", dev);
+
     abf_plan *pl = new abf_plan();
+    pl->scratch = scr;
     pl->p = *params;
     pl->max_strips = max_strips;
     pl->max_pixels = max_pixels;
@@ -714,6 +755,39 @@ abf_status abf_flow_bidirectional(abf_plan *plan, const uint8_t *L, const uint8_
     st.flow_LtoR = flow_LtoR;
     st.flow_RtoL = flow_RtoL;
     return run(plan, &st, 1, true, false, false, static_cast<hipStream_t>(hip_stream));
+}
+
+abf_status abf_flow_bidirectional_noalloc(abf_plan *plan, const uint8_t *L, const uint8_t *R, int32_t H, int32_t W,
+                                          int32_t pitch_L, int32_t pitch_R, float *flow_LtoR, float *flow_RtoL,
+                                          void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!plan->scratch) return fail(plan, ABF_E_UNSUPPORTED, "no static scratch on the plan's device");
+    abf_strip st{};
+    st.L = L;
+    st.R = R;
+    st.H = H;
+    st.W = W;
+    st.pitch_L = pitch_L;
+    st.pitch_R = pitch_R;
+    st.flow_LtoR = flow_LtoR;
+    st.flow_RtoL = flow_RtoL;
+    // the flow path lays the strip out from the head of the static scratch
+    // instead of the bound workspace; the descriptor tables are always
+    // uploaded (another call may have overwritten the array since)
+    uint8_t *const ws = plan->ws;
+    const size_t ws_bytes = plan->ws_bytes;
+    plan->ws = plan->scratch;
+    plan->ws_bytes = ABF_NOALLOC_SCRATCH_BYTES;
+    plan->last_upload.clear();
+    abf_status rc = run(plan, &st, 1, true, false, false, static_cast<hipStream_t>(hip_stream));
+    plan->ws = ws;
+    plan->ws_bytes = ws_bytes;
+    plan->last_upload.clear();
+    if (rc == ABF_E_WORKSPACE)
+        rc = fail(plan, ABF_E_WORKSPACE, "a %d x %d strip needs more than the %zu bytes of static scratch", H, W,
+                  (size_t)ABF_NOALLOC_SCRATCH_BYTES);
+    return rc;
 }
 
 abf_status abf_blend_asymmetric(abf_plan *plan, const uint8_t *L, const uint8_t *R, const float *flow_LtoR,
