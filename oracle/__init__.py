@@ -91,11 +91,11 @@ def _load():
         "orc_flow_lk": (None, [u8p, u8p, c_int, c_int, c_int, c_int, c_int, c_double, f64p]),
         "orc_flow_lk_bidirectional": (None, [u8p, u8p, c_int, c_int, c_long, c_long, c_int, c_int, c_int, c_double,
                                              c_int, f64p, f64p]),
-        "orc_canvas_dist2": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
-        "orc_canvas_dist2_rows": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
-        "orc_canvas_blend": (None, [u8p, u8p, c_long, c_int, c_int, c_long, i32p, i32p, f64p]),
-        "orc_overlap_box": (None, [u8p, u8p, c_long, c_int, c_int, i32p]),
-        "orc_composite": (None, [f64p, f64p, u8p, u8p, c_long, c_int, c_int, f64p, f64p, i32p, c_int, f64p,
+        "orc_canvas_dist2": (None, [u8p, u8p, c_long, c_int, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
+        "orc_canvas_dist2_rows": (None, [u8p, u8p, c_long, c_int, c_int, c_int, c_long, i32p, i32p, i64p, i64p]),
+        "orc_canvas_blend": (None, [u8p, u8p, c_long, c_int, c_int, c_int, c_long, i32p, i32p, f64p]),
+        "orc_overlap_box": (None, [u8p, u8p, c_long, c_int, c_int, c_int, i32p]),
+        "orc_composite": (None, [f64p, f64p, u8p, u8p, c_long, c_int, c_int, c_int, f64p, f64p, i32p, c_int, f64p,
                                  c_double, c_double, c_int, f64p, u8p]),
     }
     for name, (res, args) in sig.items():
@@ -322,23 +322,25 @@ def _points(H, W, points):
     return _i32(pts[:, 0]), _i32(pts[:, 1])
 
 
-def canvas_dist2(mask_L, mask_R, points=None):
+def canvas_dist2(mask_L, mask_R, points=None, periodic: bool = False):
     """Squared distances (int64) from canvas points to the nearest Area1
     and Area2 pixel (-1 if that area is empty), by brute force. ``points``
-    is an (n, 2) array of (x, y); None = every pixel (returned H x W)."""
+    is an (n, 2) array of (x, y); None = every pixel (returned H x W).
+    ``periodic``: the canvas wraps in x (column offsets the shorter way
+    round)."""
     mL, mR = _u8(mask_L), _u8(mask_R)
     H, W = mL.shape
     xs, ys = _points(H, W, points)
     n = xs.size
     d1, d2 = np.empty(n, np.int64), np.empty(n, np.int64)
-    _load().orc_canvas_dist2(_p(mL, u8p), _p(mR, u8p), W, H, W, n, _p(xs, i32p), _p(ys, i32p), _p(d1, i64p),
-                             _p(d2, i64p))
+    _load().orc_canvas_dist2(_p(mL, u8p), _p(mR, u8p), W, H, W, int(periodic), n, _p(xs, i32p), _p(ys, i32p),
+                             _p(d1, i64p), _p(d2, i64p))
     if points is None:
         return d1.reshape(H, W), d2.reshape(H, W)
     return d1, d2
 
 
-def canvas_dist2_rows(mask_L, mask_R, points=None):
+def canvas_dist2_rows(mask_L, mask_R, points=None, periodic: bool = False):
     """The squared distances of ``canvas_dist2`` in two stages (nearest
     pixel of the area along every row, then the minimum over rows of
     dy^2 + dx^2): the same values, fast enough for long lists of points on
@@ -348,36 +350,39 @@ def canvas_dist2_rows(mask_L, mask_R, points=None):
     xs, ys = _points(H, W, points)
     n = xs.size
     d1, d2 = np.empty(n, np.int64), np.empty(n, np.int64)
-    _load().orc_canvas_dist2_rows(_p(mL, u8p), _p(mR, u8p), W, H, W, n, _p(xs, i32p), _p(ys, i32p),
-                                  _p(d1, i64p), _p(d2, i64p))
+    _load().orc_canvas_dist2_rows(_p(mL, u8p), _p(mR, u8p), W, H, W, int(periodic), n, _p(xs, i32p),
+                                  _p(ys, i32p), _p(d1, i64p), _p(d2, i64p))
     if points is None:
         return d1.reshape(H, W), d2.reshape(H, W)
     return d1, d2
 
 
-def canvas_blend(mask_L, mask_R, points=None):
+def canvas_blend(mask_L, mask_R, points=None, periodic: bool = False):
     """eq. (1) on a canvas (float64), at ``points`` or at every pixel."""
     mL, mR = _u8(mask_L), _u8(mask_R)
     H, W = mL.shape
     xs, ys = _points(H, W, points)
     out = np.empty(xs.size, np.float64)
-    _load().orc_canvas_blend(_p(mL, u8p), _p(mR, u8p), W, H, W, xs.size, _p(xs, i32p), _p(ys, i32p),
-                             _p(out, f64p))
+    _load().orc_canvas_blend(_p(mL, u8p), _p(mR, u8p), W, H, W, int(periodic), xs.size, _p(xs, i32p),
+                             _p(ys, i32p), _p(out, f64p))
     return out.reshape(H, W) if points is None else out
 
 
-def overlap_box(mask_L, mask_R):
-    """Bounding box of Area3 as (x, y, w, h); zeros if there is none."""
+def overlap_box(mask_L, mask_R, periodic: bool = False):
+    """Bounding box of Area3 as (x, y, w, h); zeros if there is none. On a
+    periodic canvas the shortest circular run of columns holding Area3
+    (x + w may exceed W)."""
     mL, mR = _u8(mask_L), _u8(mask_R)
     H, W = mL.shape
     box = np.zeros(4, np.int32)
-    _load().orc_overlap_box(_p(mL, u8p), _p(mR, u8p), W, H, W, _p(box, i32p))
+    _load().orc_overlap_box(_p(mL, u8p), _p(mR, u8p), W, H, W, int(periodic), _p(box, i32p))
     return tuple(int(v) for v in box)
 
 
-def composite(L, R, mask_L, mask_R, flow_lr, flow_rl, box, axis: int = 0, blend=None, params: Params = Params()):
-    """Code 1 over a canvas; flows cover the overlap box. Returns
-    (F float64 H x W x 3, F uint8)."""
+def composite(L, R, mask_L, mask_R, flow_lr, flow_rl, box, axis: int = 0, blend=None, params: Params = Params(),
+              periodic: bool = False):
+    """Code 1 over a canvas; flows cover the overlap box (on a periodic
+    canvas its columns wrap). Returns (F float64 H x W x 3, F uint8)."""
     Ld, Rd = _f64(L), _f64(R)
     mL, mR = _u8(mask_L), _u8(mask_R)
     H, W, _ = Ld.shape
@@ -386,7 +391,7 @@ def composite(L, R, mask_L, mask_R, flow_lr, flow_rl, box, axis: int = 0, blend=
     bx = _i32(box)
     F = np.empty((H, W, 3), np.float64)
     F8 = np.empty((H, W, 3), np.uint8)
-    _load().orc_composite(_p(Ld, f64p), _p(Rd, f64p), _p(mL, u8p), _p(mR, u8p), W, H, W, _p(flr, f64p),
+    _load().orc_composite(_p(Ld, f64p), _p(Rd, f64p), _p(mL, u8p), _p(mR, u8p), W, H, W, int(periodic), _p(flr, f64p),
                           _p(frl, f64p), _p(bx, i32p), axis, _p(b, f64p), params.k_sharp, params.k_flowmag,
                           params.blend_mode, _p(F, f64p), _p(F8, u8p))
     return F, F8

@@ -804,63 +804,88 @@ static int canvas_area(const uint8_t *mL, const uint8_t *mR, long pitch, int x, 
     return l && r ? 3 : (l ? 1 : (r ? 2 : 0));
 }
 
+/* Column offset between canvas columns u and x: |u - x|, or, on a
+ * periodic canvas (x wraps: column W - 1 neighbours column 0, as on a
+ * 360-degree panorama), the shorter way round, min(|u - x|, W - |u - x|). */
+static long long col_dist(int u, int x, int W, int periodic)
+{
+    long long d = u > x ? u - x : x - u;
+    if (periodic && W - d < d) d = W - d;
+    return d;
+}
+
 /* Squared Euclidean distance between the centre of (x, y) and the centre
  * of the nearest canvas pixel of area `a`, over every pixel of the canvas;
  * -1 when no pixel has that area. */
-static long long nearest_d2(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int x, int y, int a)
+static long long nearest_d2(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int x, int y, int a,
+                            int periodic)
 {
     long long best = -1;
     for (int v = 0; v < H; v++)
         for (int u = 0; u < W; u++) {
             if (canvas_area(mL, mR, pitch, u, v) != a) continue;
-            long long d = (long long)(u - x) * (u - x) + (long long)(v - y) * (v - y);
+            long long dx = col_dist(u, x, W, periodic);
+            long long d = dx * dx + (long long)(v - y) * (v - y);
             if (best < 0 || d < best) best = d;
         }
     return best;
 }
 
 /* Squared distances from n canvas points to Area1 (d2_1) and Area2 (d2_2). */
-void orc_canvas_dist2(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, long n, const int32_t *xs,
-                      const int32_t *ys, long long *d2_1, long long *d2_2)
+void orc_canvas_dist2(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int periodic, long n,
+                      const int32_t *xs, const int32_t *ys, long long *d2_1, long long *d2_2)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (long i = 0; i < n; i++) {
-        d2_1[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 1);
-        d2_2[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 2);
+        d2_1[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 1, periodic);
+        d2_2[i] = nearest_d2(mL, mR, pitch, H, W, xs[i], ys[i], 2, periodic);
     }
 }
 
 /* The same squared distances in two stages, for long lists of points on
  * large canvases: for every row v and column x, the distance along the
  * row to the nearest pixel of the area in that row (g_v(x), none if the
- * row has no such pixel); then the nearest pixel of the area to (x, y) is,
- * for some row v, the nearest one in that row, so
+ * row has no such pixel; measured the shorter way round on a periodic
+ * canvas); then the nearest pixel of the area to (x, y) is, for some row
+ * v, the nearest one in that row, so
  * d^2(x, y) = min over v of (y - v)^2 + g_v(x)^2. */
-static void row_distances(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int a, int32_t *g)
+static void row_distances(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int a, int periodic,
+                          int32_t *g)
 {
 #pragma omp parallel for
     for (int v = 0; v < H; v++) {
         int32_t *row = g + (long)v * W;
+        int first = -1, lastm = -1;  /* the row's first and last pixel of the area */
+        for (int x = 0; x < W; x++)
+            if (canvas_area(mL, mR, pitch, x, v) == a) {
+                if (first < 0) first = x;
+                lastm = x;
+            }
+        /* nearest member at or left of x; on a periodic canvas, with none,
+         * the row's last member reached leftwards across column 0 */
         int last = -1;
         for (int x = 0; x < W; x++) {
             if (canvas_area(mL, mR, pitch, x, v) == a) last = x;
-            row[x] = last < 0 ? -1 : x - last;
+            row[x] = last >= 0 ? x - last : (periodic && lastm >= 0 ? x + W - lastm : -1);
         }
+        /* nearest member at or right of x; with none, the first member
+         * reached rightwards across column W - 1 */
         last = -1;
         for (int x = W - 1; x >= 0; x--) {
             if (canvas_area(mL, mR, pitch, x, v) == a) last = x;
-            if (last >= 0 && (row[x] < 0 || last - x < row[x])) row[x] = last - x;
+            int d = last >= 0 ? last - x : (periodic && first >= 0 ? W - x + first : -1);
+            if (d >= 0 && (row[x] < 0 || d < row[x])) row[x] = d;
         }
     }
 }
 
-void orc_canvas_dist2_rows(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, long n,
+void orc_canvas_dist2_rows(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int periodic, long n,
                            const int32_t *xs, const int32_t *ys, long long *d2_1, long long *d2_2)
 {
     int32_t *g1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)H * W);
     int32_t *g2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)H * W);
-    row_distances(mL, mR, pitch, H, W, 1, g1);
-    row_distances(mL, mR, pitch, H, W, 2, g2);
+    row_distances(mL, mR, pitch, H, W, 1, periodic, g1);
+    row_distances(mL, mR, pitch, H, W, 2, periodic, g2);
 #pragma omp parallel for schedule(dynamic, 64)
     for (long i = 0; i < n; i++) {
         const int x = xs[i], y = ys[i];
@@ -882,8 +907,8 @@ void orc_canvas_dist2_rows(const uint8_t *mL, const uint8_t *mR, long pitch, int
  * images, Lmin / (Lmin + Rmin) in Area3 with Lmin / Rmin the distances to
  * Area1 / Area2. An empty Area1 is infinitely far (Blend 1), an empty
  * Area2 likewise (Blend 0); with both empty Area3 takes 0.5. */
-void orc_canvas_blend(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, long n, const int32_t *xs,
-                      const int32_t *ys, double *out)
+void orc_canvas_blend(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int periodic, long n,
+                      const int32_t *xs, const int32_t *ys, double *out)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (long i = 0; i < n; i++) {
@@ -895,8 +920,8 @@ void orc_canvas_blend(const uint8_t *mL, const uint8_t *mR, long pitch, int H, i
         } else if (a == 0) {
             out[i] = 0.5;
         } else {
-            long long d1 = nearest_d2(mL, mR, pitch, H, W, x, y, 1);
-            long long d2 = nearest_d2(mL, mR, pitch, H, W, x, y, 2);
+            long long d1 = nearest_d2(mL, mR, pitch, H, W, x, y, 1, periodic);
+            long long d2 = nearest_d2(mL, mR, pitch, H, W, x, y, 2, periodic);
             if (d1 < 0 && d2 < 0)
                 out[i] = 0.5;
             else if (d1 < 0)
@@ -911,13 +936,24 @@ void orc_canvas_blend(const uint8_t *mL, const uint8_t *mR, long pitch, int H, i
     }
 }
 
-/* Bounding box of Area3 as {x, y, width, height}; {0, 0, 0, 0} if empty. */
-void orc_overlap_box(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int32_t box[4])
+/* Bounding box of Area3 as {x, y, width, height}; {0, 0, 0, 0} if empty.
+ * Rows: the first to the last row holding an Area3 pixel. Columns: on a
+ * plain canvas the first to the last such column. On a periodic canvas the
+ * columns form a circle and the box is the shortest run of consecutive
+ * columns (wrapping past W - 1 to 0) that holds every Area3 column: it
+ * starts right after the longest run of columns without an Area3 pixel
+ * (of several longest, the one that starts at the smallest column; a run
+ * that wraps starts at its column nearest W - 1) and w = W minus that run's
+ * length, so x + w may exceed W; with no such run (every column holds an
+ * Area3 pixel) the box starts at 0 with w = W. */
+void orc_overlap_box(const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W, int periodic, int32_t box[4])
 {
     int x0 = W, y0 = H, x1 = -1, y1 = -1;
+    char *occ = (char *)calloc((size_t)W, 1);
     for (int y = 0; y < H; y++)
         for (int x = 0; x < W; x++)
             if (canvas_area(mL, mR, pitch, x, y) == 3) {
+                occ[x] = 1;
                 if (x < x0) x0 = x;
                 if (x > x1) x1 = x;
                 if (y < y0) y0 = y;
@@ -930,7 +966,29 @@ void orc_overlap_box(const uint8_t *mL, const uint8_t *mR, long pitch, int H, in
         box[1] = y0;
         box[2] = x1 - x0 + 1;
         box[3] = y1 - y0 + 1;
+        if (periodic) {
+            /* every run of empty columns, by its first column s (the column
+             * before it, circularly, holds an Area3 pixel) */
+            int best_s = -1, best_len = 0;
+            for (int s0 = 0; s0 < W; s0++) {
+                if (occ[s0] || !occ[(s0 + W - 1) % W]) continue;
+                int len = 0;
+                while (len < W && !occ[(s0 + len) % W]) len++;
+                if (len > best_len) {
+                    best_len = len;
+                    best_s = s0;
+                }
+            }
+            if (best_len == 0) {
+                box[0] = 0;
+                box[2] = W;
+            } else {
+                box[0] = (best_s + best_len) % W;
+                box[2] = W - best_len;
+            }
+        }
     }
+    free(occ);
 }
 
 /* Code 1 over a canvas. L, R: double H x W x 3 canvas images. The flows
@@ -942,7 +1000,7 @@ void orc_overlap_box(const uint8_t *mL, const uint8_t *mR, long pitch, int H, in
  * Area1 copies L, Area2 copies R, every other pixel (and an Area3 pixel
  * outside the box, which has no flow) is 0. */
 void orc_composite(const double *L, const double *R, const uint8_t *mL, const uint8_t *mR, long pitch, int H, int W,
-                   const double *flow_lr, const double *flow_rl, const int32_t box[4], int axis,
+                   int periodic, const double *flow_lr, const double *flow_rl, const int32_t box[4], int axis,
                    const double *blend, double kS, double kF, int mode, double *F, uint8_t *F8)
 {
     int bx = box[0], by = box[1], bw = box[2], bh = box[3];
@@ -956,16 +1014,18 @@ void orc_composite(const double *L, const double *R, const uint8_t *mL, const ui
         int32_t *xs = (int32_t *)malloc(sizeof(int32_t) * nb), *ys = (int32_t *)malloc(sizeof(int32_t) * nb);
         for (int y = 0; y < bh; y++)
             for (int x = 0; x < bw; x++) {
-                long q = (long)y * bw + x, p = (long)(y + by) * W + (x + bx);
+                /* crop column x is canvas column bx + x, modulo W on a periodic canvas */
+                int cx = (x + bx) % W;
+                long q = (long)y * bw + x, p = (long)(y + by) * W + cx;
                 for (int c = 0; c < 3; c++) {
                     Lc[3 * q + c] = L[3 * p + c];
                     Rc[3 * q + c] = R[3 * p + c];
                 }
-                xs[q] = x + bx;
+                xs[q] = cx;
                 ys[q] = y + by;
                 if (blend) Bc[q] = blend[p];
             }
-        if (!blend) orc_canvas_blend(mL, mR, pitch, H, W, nb, xs, ys, Bc);
+        if (!blend) orc_canvas_blend(mL, mR, pitch, H, W, periodic, nb, xs, ys, Bc);
         orc_blend(Lc, Rc, flow_lr, flow_rl, Bc, axis, bh, bw, kS, kF, mode, Fc, NULL);
         free(xs);
         free(ys);
@@ -974,7 +1034,9 @@ void orc_composite(const double *L, const double *R, const uint8_t *mL, const ui
         for (int x = 0; x < W; x++) {
             long p = (long)y * W + x;
             int a = canvas_area(mL, mR, pitch, x, y);
-            int inbox = x >= bx && x < bx + bw && y >= by && y < by + bh;
+            int xb = x - bx;
+            if (periodic && xb < 0) xb += W;
+            int inbox = xb >= 0 && xb < bw && y >= by && y < by + bh;
             for (int c = 0; c < 3; c++) {
                 double f = 0.0;
                 if (a == 1)
@@ -982,7 +1044,7 @@ void orc_composite(const double *L, const double *R, const uint8_t *mL, const ui
                 else if (a == 2)
                     f = R[3 * p + c];
                 else if (a == 3 && inbox)
-                    f = Fc[3 * ((long)(y - by) * bw + (x - bx)) + c];
+                    f = Fc[3 * ((long)(y - by) * bw + xb) + c];
                 F[3 * p + c] = f;
                 if (F8) {
                     double r = floor(f + 0.5);

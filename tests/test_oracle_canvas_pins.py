@@ -165,3 +165,132 @@ def test_composite_rectangular_overlap_equals_the_strip_blend(axis):
     # an explicit Blend map equal to eq. (1) gives the same composite
     G, G8 = oracle.composite(L, R, mL, mR, flr, frl, box, axis=axis, blend=oracle.canvas_blend(mL, mR))
     assert np.array_equal(G8, F8) and np.allclose(G, F, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Periodic canvas (a 360-degree panorama: column W - 1 neighbours column 0)
+
+
+@pytest.mark.parametrize("seed,H,W", [(21, 23, 41), (22, 40, 64), (23, 1, 57), (24, 33, 2), (25, 17, 90)])
+def test_periodic_dist2_equals_scipy_edt_on_three_tiles(seed, H, W):
+    # the periodic distance of a pixel is its plain distance in the middle
+    # copy of the canvas tiled three times along x (no nearest pixel is more
+    # than half a period away, so one copy on each side suffices)
+    mL, mR = synth.random_masks(seed, H, W)
+    a = areas(mL, mR)
+    d1, d2 = oracle.canvas_dist2(mL, mR, periodic=True)
+    r1, r2 = oracle.canvas_dist2_rows(mL, mR, periodic=True)
+    assert np.array_equal(r1, d1) and np.array_equal(r2, d2)
+    a3 = np.tile(a, (1, 3))
+    for k, d in ((1, d1), (2, d2)):
+        if not (a == k).any():
+            assert (d == -1).all()
+            continue
+        e = ndimage.distance_transform_edt(a3 != k)[:, W:2 * W]
+        assert np.array_equal(d, np.rint(e * e).astype(np.int64))
+    # never farther than the plain distance
+    p1, p2 = oracle.canvas_dist2(mL, mR)
+    assert ((d1 <= p1) | (p1 < 0)).all() and ((d2 <= p2) | (p2 < 0)).all()
+
+
+@pytest.mark.parametrize("shift", [1, 17, 40])
+def test_periodic_blend_commutes_with_rolling(shift):
+    H, W = 30, 53
+    mL, mR = synth.random_masks(26, H, W)
+    B = oracle.canvas_blend(mL, mR, periodic=True)
+    Br = oracle.canvas_blend(np.roll(mL, shift, 1), np.roll(mR, shift, 1), periodic=True)
+    assert np.array_equal(Br, np.roll(B, shift, 1))
+
+
+def _brute_circular_box(occ):
+    # the shortest run [x, x + w) (mod W) of columns holding every occupied
+    # column, by trying every start; of equally short runs, the one whose
+    # complementary empty run starts at the smallest column
+    W = occ.size
+    cols = np.flatnonzero(occ)
+    best = None
+    for x in range(W):
+        w = int(((cols - x) % W).max()) + 1
+        key = (w, (x + w) % W)
+        if best is None or key < best[0]:
+            best = (key, x, w)
+    return (0, W) if best[2] == W else (best[1], best[2])
+
+
+def test_periodic_box_tie_takes_the_first_empty_run():
+    # occupied columns 0 and 10 of 20: two empty runs of 9 columns, starting
+    # at 1 and at 11; the first is skipped, so the box runs from 10 over the
+    # wrap to 0
+    mL = np.zeros((3, 20), np.uint8)
+    mL[1, [0, 10]] = 1
+    assert oracle.overlap_box(mL, mL, periodic=True) == (10, 1, 11, 1)
+    assert _brute_circular_box(mL.any(0)) == (10, 11)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_periodic_box_is_the_shortest_circular_cover(seed):
+    rng = np.random.default_rng(seed)
+    H, W = 11, 37
+    mL = np.zeros((H, W), np.uint8)
+    mR = np.zeros((H, W), np.uint8)
+    occ = np.zeros(W, bool)
+    # two or three column clusters, one of them often across the wrap
+    for _ in range(int(rng.integers(1, 4))):
+        c0, n = int(rng.integers(0, W)), int(rng.integers(1, 9))
+        cols = (c0 + np.arange(n)) % W
+        r0 = int(rng.integers(0, H - 2))
+        mL[r0:r0 + 3, cols] = 1
+        mR[r0:r0 + 3, cols] = 1
+        occ[cols] = True
+    mL[:, :5] = 1  # Area1 elsewhere
+    x, y, w, h = oracle.overlap_box(mL, mR, periodic=True)
+    bx, bw = _brute_circular_box(occ)
+    assert (x, w) == (bx, bw)
+    rows = np.flatnonzero(((mL > 0) & (mR > 0)).any(1))
+    assert (y, h) == (rows[0], rows[-1] - rows[0] + 1)
+    # every Area3 pixel lies in the box, read modulo W
+    ys, xs = np.nonzero((mL > 0) & (mR > 0))
+    assert (((xs - x) % W) < w).all()
+
+
+def test_periodic_box_of_contiguous_columns_is_the_plain_box():
+    mL, mR = synth.random_masks(27, 25, 60)
+    mL[:, 50:] = 0
+    mR[:, :10] = 0
+    assert oracle.overlap_box(mL, mR, periodic=True) == oracle.overlap_box(mL, mR)
+    full = np.ones((4, 9), np.uint8)
+    assert oracle.overlap_box(full, full, periodic=True) == (0, 0, 9, 4)
+
+
+@pytest.mark.parametrize("shift", [9, 31])
+def test_periodic_composite_commutes_with_rolling(shift):
+    # Code 1 on a periodic canvas depends on columns only through their
+    # circular order: rolling every input (and the box) rolls the output,
+    # including a box that the roll makes wrap past column W - 1
+    H, W = 24, 48
+    rng = np.random.default_rng(28)
+    mL = np.zeros((H, W), np.uint8)
+    mR = np.zeros((H, W), np.uint8)
+    mL[:, :30] = 1
+    mR[:, 18:] = 1
+    mR[5:9, 22:26] = 0  # an Area1 island inside the overlap
+    L = rng.integers(0, 256, (H, W, 3)).astype(np.uint8)
+    R = rng.integers(0, 256, (H, W, 3)).astype(np.uint8)
+    box = oracle.overlap_box(mL, mR, periodic=True)
+    bx, by, bw, bh = box
+    flr = rng.uniform(-3, 3, (bh, bw, 2))
+    frl = rng.uniform(-3, 3, (bh, bw, 2))
+    F, F8 = oracle.composite(L, R, mL, mR, flr, frl, box, periodic=True)
+    rb = oracle.overlap_box(np.roll(mL, shift, 1), np.roll(mR, shift, 1), periodic=True)
+    assert rb == ((bx + shift) % W, by, bw, bh)
+    Fr, F8r = oracle.composite(np.roll(L, shift, 1), np.roll(R, shift, 1), np.roll(mL, shift, 1),
+                               np.roll(mR, shift, 1), flr, frl, rb, periodic=True)
+    assert np.array_equal(Fr, np.roll(F, shift, 1)) and np.array_equal(F8r, np.roll(F8, shift, 1))
+    # the box's Area3 part is the strip blend of the box crops (read modulo W)
+    cols = (rb[0] + np.arange(bw)) % W
+    Lc = np.roll(L, shift, 1)[by:by + bh][:, cols]
+    Rc = np.roll(R, shift, 1)[by:by + bh][:, cols]
+    Bc = oracle.canvas_blend(np.roll(mL, shift, 1), np.roll(mR, shift, 1), periodic=True)[by:by + bh][:, cols]
+    Fs, _ = oracle.blend(Lc, Rc, flr, frl, blend=Bc, axis=0)
+    a3 = ((np.roll(mL, shift, 1) > 0) & (np.roll(mR, shift, 1) > 0))[by:by + bh][:, cols]
+    assert np.array_equal(Fr[by:by + bh][:, cols][a3], Fs[a3])
