@@ -224,40 +224,76 @@ def run_lk_pyramid(dev, shapes, total_px, timed, log, steps, iters=4):
                        "peak": 78.6, "unit": "TFLOP/s", "frac": round(flops / l0 / 1e9 / 78.6, 4)}}
 
 
-def run_merge(p, log, reps):
-    """Repeated pairwise merging of one photo set on a 4000 x 9000 canvas:
-    6 ring photos left to right, then the top photo (7 photos, 6 seams of
-    the ring with overlaps U[480, 960] px and a ~600-row top band), images
+def run_merge(p, log, reps, n_stream=3):
+    """Repeated pairwise merging of photo sets on a 4000 x 9000 canvas, 6
+    ring photos left to right, then the top photo (7 photos, seams of the
+    ring with overlaps U[480, 960] px and a ~600-row top band), images
     generated on the GPU. One step = one whole merge (abf_merge_photos,
-    which reads every overlap box back to size the flows)."""
+    which reads every overlap box back to size the flows):
+      - planar: the ring does not close (the canvas does not wrap);
+      - closed ring: a 360-degree panorama (periodic canvas), whose last
+        ring photo closes the ring across the wrap in its step;
+      - stream: n_stream closed photo sets merged one after another
+        through one plan on one stream."""
     import torch
 
     from paper_2006_01201_amd import api, synth
 
-    t0 = time.time()
     H, W = 4000, 9000
-    photos = synth.make_panorama_photos(0, H, W, n_ring=6, device="cuda")
-    torch.cuda.synchronize()
-    log(f"merge: 7 photos on {H} x {W} generated in {time.time() - t0:.1f} s")
-    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, max_pixels=8 << 20, canvas=(H, W))
+    plan = api.Plan(p, max_strips=1, max_H=H, max_W=W, max_pixels=10 << 20, canvas=(H, W))
     out = torch.empty((H, W, 3), dtype=torch.uint8, device="cuda")
-    _, _, boxes = plan.merge_photos(photos, out=out)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    e0.record()
-    for _ in range(reps):
-        plan.merge_photos(photos, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - w0) * 1e3 / reps
-    ms = e0.elapsed_time(e1) / reps
-    log(f"merge: {ms:.3f} ms per panorama (wall {wall:.3f})")
-    return {"workload": f"{H} x {W} canvas, 7 photos (6 ring left to right + top), overlap boxes "
+
+    def timed_merge(photos, periodic):
+        _, _, boxes = plan.merge_photos(photos, out=out, periodic=periodic)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            plan.merge_photos(photos, out=out, periodic=periodic)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, (time.perf_counter() - w0) * 1e3 / reps, boxes
+
+    res = {}
+    for closed in (False, True):
+        t0 = time.time()
+        photos = synth.make_panorama_photos(0, H, W, n_ring=6, device="cuda", closed=closed)
+        torch.cuda.synchronize()
+        log(f"merge: 7 photos on {H} x {W} generated in {time.time() - t0:.1f} s (closed ring {closed})")
+        ms, wall, boxes = timed_merge(photos, closed)
+        log(f"merge: {ms:.3f} ms per panorama (wall {wall:.3f}), closed ring {closed}")
+        res["closed_ring" if closed else "planar"] = {
+            "workload": f"{H} x {W} canvas, 7 photos (6 ring left to right + top"
+                        f"{', the ring closing across the 360-degree wrap' if closed else ''}), overlap boxes "
                         f"{[list(b) for b in boxes[1:]]}, each step box + flows + eq. (1) + Code 1 over the canvas",
             "ms_per_panorama": round(ms, 3), "wall_ms_per_panorama": round(wall, 3),
             "canvas_mpix_s": round(H * W / ms / 1e3, 1)}
+        del photos
+    if n_stream:
+        sets = []
+        for k in range(n_stream):
+            sets.append(synth.make_panorama_photos(1 + k, H, W, n_ring=6, device="cuda", closed=True))
+        torch.cuda.synchronize()
+        for ph in sets:  # warm-up: graph-free, but the first call of a shape sets up buffers
+            plan.merge_photos(ph, out=out, periodic=True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        for ph in sets:
+            plan.merge_photos(ph, out=out, periodic=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n_stream
+        wall = (time.perf_counter() - w0) * 1e3 / n_stream
+        log(f"merge stream: {n_stream} closed photo sets, {ms:.3f} ms per panorama (wall {wall:.3f})")
+        res["stream"] = {"workload": f"{n_stream} closed 360-degree photo sets of 7 photos on {H} x {W}, merged one "
+                                     "after another through one plan on one stream",
+                         "ms_per_panorama": round(ms, 3), "wall_ms_per_panorama": round(wall, 3)}
+    return res
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")

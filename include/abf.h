@@ -285,23 +285,32 @@ size_t abf_canvas_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W);
 
 /* Bounding box of Area3, written as int32 {x, y, w, h} to `box` (device,
  * 4 entries); {0, 0, 0, 0} when no pixel is covered by both images.
- * Scratch: 8 bytes per canvas row. */
+ * periodic != 0: the canvas wraps in x (a 360-degree panorama, column
+ * W - 1 next to column 0), and the box's columns are the shortest circular
+ * run holding every Area3 column: it starts right after the longest run of
+ * columns without an Area3 pixel (of several, the one that starts at the
+ * smallest column) and has w = W minus that run's length, so x + w may
+ * exceed W (columns x .. x + w - 1 modulo W); every column holding Area3
+ * gives x = 0, w = W. Scratch: 8 bytes per canvas row (+ W / 8 bytes if
+ * periodic). */
 abf_status abf_overlap_box(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
-                           int32_t pitch_mask, int32_t *box, void *hip_stream);
+                           int32_t pitch_mask, int32_t periodic, int32_t *box, void *hip_stream);
 
 /* eq. (1) over the canvas: Blend (float32, rows pitch_blend floats apart)
  * is 0 on Area1, 1 on Area2, 0.5 outside both images, and on Area3
  * Lmin / (Lmin + Rmin), with Lmin / Rmin the Euclidean distances between
  * pixel centres to the nearest Area1 / Area2 pixel (exact: integer squared
- * distances, then the ratio in double, rounded to float). An empty Area1
- * gives 1 on Area3, an empty Area2 gives 0, both empty give 0.5.
+ * distances, then the ratio in double, rounded to float; on a periodic
+ * canvas the column offset is taken the shorter way round, min(|dx|,
+ * W - |dx|)). An empty Area1 gives 1 on Area3, an empty Area2 gives 0,
+ * both empty give 0.5.
  * If dist2_1 / dist2_2 are non-null (both or neither; int32, rows
  * pitch_dist apart), they receive the squared distances of every canvas
  * pixel to Area1 / Area2 (0 inside the area, -1 if the area is empty).
  * blend may be null when the distances are requested. */
 abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
-                            int32_t pitch_mask, float *blend, int32_t pitch_blend, int32_t *dist2_1,
-                            int32_t *dist2_2, int32_t pitch_dist, void *hip_stream);
+                            int32_t pitch_mask, int32_t periodic, float *blend, int32_t pitch_blend,
+                            int32_t *dist2_1, int32_t *dist2_2, int32_t pitch_dist, void *hip_stream);
 
 /* Code 1 over the canvas: F (uint8 RGB, rows pitch_F bytes apart) = L on
  * Area1, R on Area2, 0 outside both images; an Area3 pixel inside the box
@@ -312,17 +321,20 @@ abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t
  * (float32 canvas array, rows pitch_blend floats apart) or, if null,
  * computed by eq. (1) as in abf_canvas_blend. An Area3 pixel outside the
  * box has no flow and is written as 0. `box` is a host array {x, y, w, h}
- * inside the canvas (w or h 0: no Area3 pixel is blended). F_f32
+ * inside the canvas (w or h 0: no Area3 pixel is blended); with periodic
+ * != 0 its columns may wrap past W - 1 (x < W, w <= W: the strip's column
+ * c is canvas column x + c modulo W) and eq. (1) is periodic. F_f32
  * (nullable, H x W x 3 contiguous) receives the unrounded composite. */
 abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t *R, const uint8_t *mask_L,
                                 const uint8_t *mask_R, int32_t H, int32_t W, int32_t pitch_L, int32_t pitch_R,
-                                int32_t pitch_mask, const float *flow_LtoR, const float *flow_RtoL,
+                                int32_t pitch_mask, int32_t periodic, const float *flow_LtoR, const float *flow_RtoL,
                                 const int32_t *box, int32_t axis, const float *blend, int32_t pitch_blend,
                                 uint8_t *F, int32_t pitch_F, float *F_f32, void *hip_stream);
 
 /* ------------------------------------------------------------------ */
 /* Repeated pairwise merging (Sections I and III.A: the two-photo blend is
- * applied photo after photo until the set is merged). Every photo is given
+ * applied photo after photo until the set is merged; Fig. 1: a ring of
+ * photos around a vertical axis and a top photo). Every photo is given
  * on the common canvas H x W: image (RGB uint8, `pitch` bytes per row) and
  * coverage mask (uint8, nonzero = covered, pitch_mask bytes per row, the
  * same pitch for every mask and for `coverage`). Photo 0 starts the merged
@@ -347,12 +359,20 @@ typedef struct abf_photo {
 } abf_photo;
 
 /* Workspace bytes for merges on an H x W canvas (flows of the largest box
- * the plan admits kept beside the canvas passes' scratch). */
+ * the plan admits kept beside the canvas passes' scratch, and two box
+ * copies). */
 size_t abf_merge_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W);
 
+/* periodic != 0: the canvas is a 360-degree panorama that wraps in x; the
+ * boxes, eq. (1) and Code 1 of every step are periodic (as in
+ * abf_overlap_box, abf_canvas_blend and abf_composite_canvas), so the last
+ * ring photo, whose coverage reaches across column W - 1 to the first
+ * photo, closes the ring in its step (its box then wraps, and its flows are
+ * computed on contiguous copies of the box crops). */
 abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, int32_t H, int32_t W,
-                            int32_t pitch_mask, uint8_t *canvas, int32_t pitch_canvas, uint8_t *spare,
-                            int32_t pitch_spare, uint8_t *coverage, int32_t *boxes, void *hip_stream);
+                            int32_t pitch_mask, int32_t periodic, uint8_t *canvas, int32_t pitch_canvas,
+                            uint8_t *spare, int32_t pitch_spare, uint8_t *coverage, int32_t *boxes,
+                            void *hip_stream);
 
 /* ------------------------------------------------------------------ */
 /* Autotuning of launch shapes (never of results): times the candidate

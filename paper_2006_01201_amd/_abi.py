@@ -71,12 +71,13 @@ _SIGS = {
     "abf_profile": (c_i32, [c_vp, ctypes.POINTER(AbfStrip), c_i32, c_i32, ctypes.POINTER(c_f32), c_vp]),
     "abf_canvas_workspace_bytes": (c_sz, [c_vp, c_i32, c_i32]),
     "abf_merge_workspace_bytes": (c_sz, [c_vp, c_i32, c_i32]),
-    "abf_merge_photos": (c_i32, [c_vp, ctypes.POINTER(AbfPhoto), c_i32, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp, c_i32,
-                                 c_vp, ctypes.POINTER(c_i32), c_vp]),
-    "abf_overlap_box": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
-    "abf_canvas_blend": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32, c_vp]),
-    "abf_composite_canvas": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp,
-                                     ctypes.POINTER(c_i32), c_i32, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp]),
+    "abf_merge_photos": (c_i32, [c_vp, ctypes.POINTER(AbfPhoto), c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp,
+                                 c_i32, c_vp, ctypes.POINTER(c_i32), c_vp]),
+    "abf_overlap_box": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp]),
+    "abf_canvas_blend": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32,
+                                 c_vp]),
+    "abf_composite_canvas": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp,
+                                     c_vp, ctypes.POINTER(c_i32), c_i32, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp]),
 }
 
 MAX_LEVELS = 12
@@ -231,29 +232,30 @@ def canvas_workspace_bytes(plan, H, W) -> int:
     return load().abf_canvas_workspace_bytes(plan, H, W)
 
 
-def overlap_box(plan, mask_L, mask_R, H, W, pitch_mask, box, stream) -> int:
-    return load().abf_overlap_box(plan, mask_L, mask_R, H, W, pitch_mask, box, stream)
+def overlap_box(plan, mask_L, mask_R, H, W, pitch_mask, periodic, box, stream) -> int:
+    return load().abf_overlap_box(plan, mask_L, mask_R, H, W, pitch_mask, periodic, box, stream)
 
 
-def canvas_blend(plan, mask_L, mask_R, H, W, pitch_mask, blend, pitch_blend, dist2_1, dist2_2, pitch_dist,
+def canvas_blend(plan, mask_L, mask_R, H, W, pitch_mask, periodic, blend, pitch_blend, dist2_1, dist2_2, pitch_dist,
                  stream) -> int:
-    return load().abf_canvas_blend(plan, mask_L, mask_R, H, W, pitch_mask, blend, pitch_blend, dist2_1, dist2_2,
-                                   pitch_dist, stream)
+    return load().abf_canvas_blend(plan, mask_L, mask_R, H, W, pitch_mask, periodic, blend, pitch_blend, dist2_1,
+                                   dist2_2, pitch_dist, stream)
 
 
-def composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_mask, flow_LtoR, flow_RtoL, box,
-                     axis, blend, pitch_blend, F, pitch_F, F_f32, stream) -> int:
+def composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_mask, periodic, flow_LtoR, flow_RtoL,
+                     box, axis, blend, pitch_blend, F, pitch_F, F_f32, stream) -> int:
     b = (c_i32 * 4)(*box)
-    return load().abf_composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_mask, flow_LtoR,
-                                       flow_RtoL, b, axis, blend, pitch_blend, F, pitch_F, F_f32, stream)
+    return load().abf_composite_canvas(plan, L, R, mask_L, mask_R, H, W, pitch_L, pitch_R, pitch_mask, periodic,
+                                       flow_LtoR, flow_RtoL, b, axis, blend, pitch_blend, F, pitch_F, F_f32, stream)
 
 
 def merge_workspace_bytes(plan, H, W) -> int:
     return load().abf_merge_workspace_bytes(plan, H, W)
 
 
-def merge_photos(plan, photos, n, H, W, pitch_mask, canvas, pitch_canvas, spare, pitch_spare, coverage, stream):
+def merge_photos(plan, photos, n, H, W, pitch_mask, periodic, canvas, pitch_canvas, spare, pitch_spare, coverage,
+                 stream):
     boxes = (c_i32 * (4 * n))()
-    st = load().abf_merge_photos(plan, photos, n, H, W, pitch_mask, canvas, pitch_canvas, spare, pitch_spare,
-                                 coverage, boxes, stream)
+    st = load().abf_merge_photos(plan, photos, n, H, W, pitch_mask, periodic, canvas, pitch_canvas, spare,
+                                 pitch_spare, coverage, boxes, stream)
     return st, [tuple(boxes[4 * i:4 * i + 4]) for i in range(n)]

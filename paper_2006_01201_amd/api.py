@@ -291,21 +291,23 @@ class Plan:
 
     # -- inspection ------------------------------------------------------
     # -- canvas compositing (eq. (1) and Code 1 with general areas) ----
-    def overlap_box(self, mask_L, mask_R, out=None):
+    def overlap_box(self, mask_L, mask_R, out=None, periodic: bool = False):
         """Bounding box (x, y, w, h) of Area3: a host tuple (synchronises),
         or, with ``out`` (int32 CUDA tensor of 4), written there without
-        synchronising."""
+        synchronising. ``periodic``: the canvas wraps in x (a 360-degree
+        panorama) and the box's columns may run past W - 1 to 0."""
         H, W, pm = _mask(mask_L, "mask_L")
         if _mask(mask_R, "mask_R") != (H, W, pm):
             raise ValueError("mask_L and mask_R differ in shape or pitch")
         box = torch.empty(4, dtype=torch.int32, device=mask_L.device) if out is None else out
         if box.dtype != torch.int32 or box.numel() != 4 or not box.is_cuda or not box.is_contiguous():
             raise ValueError("out: expected a contiguous CUDA int32 tensor of 4")
-        st = _abi.overlap_box(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, box.data_ptr(), _stream())
+        st = _abi.overlap_box(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, int(periodic), box.data_ptr(),
+                              _stream())
         _abi.check(st, self.h, "abf_overlap_box")
         return box if out is not None else tuple(int(v) for v in box.cpu())
 
-    def canvas_blend(self, mask_L, mask_R, distances: bool = False, out=None):
+    def canvas_blend(self, mask_L, mask_R, distances: bool = False, out=None, periodic: bool = False):
         """eq. (1) over the canvas (float32 H x W, into ``out`` if given);
         with ``distances`` also the squared distances to Area1 and Area2
         (int32, -1 = empty)."""
@@ -317,14 +319,14 @@ class Plan:
         _f32(B, (H, W), "out")
         d1 = torch.empty((H, W), dtype=torch.int32, device=dev) if distances else None
         d2 = torch.empty((H, W), dtype=torch.int32, device=dev) if distances else None
-        st = _abi.canvas_blend(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, B.data_ptr(), W,
+        st = _abi.canvas_blend(self.h, mask_L.data_ptr(), mask_R.data_ptr(), H, W, pm, int(periodic), B.data_ptr(), W,
                                d1.data_ptr() if distances else None, d2.data_ptr() if distances else None, W,
                                _stream())
         _abi.check(st, self.h, "abf_canvas_blend")
         return (B, d1, d2) if distances else B
 
     def composite_canvas(self, L, R, mask_L, mask_R, flow_lr, flow_rl, box, axis: int = 0, blend=None,
-                         f32: bool = False, out=None):
+                         f32: bool = False, out=None, periodic: bool = False):
         """Code 1 over the canvas; flows cover the overlap ``box``. Returns
         F (uint8 H x W x 3) and, if ``f32``, the unrounded composite."""
         H, W, pl = _img_u8(L, "L")
@@ -346,7 +348,7 @@ class Plan:
                 raise ValueError("blend: expected a CUDA float32 (H, W) tensor with unit column stride")
             bp, pb = blend.data_ptr(), blend.stride(0)
         st = _abi.composite_canvas(self.h, L.data_ptr(), R.data_ptr(), mask_L.data_ptr(), mask_R.data_ptr(), H, W,
-                                   pl, pr, pm, fl, fr, (bx, by, bw, bh), axis, bp, pb, F.data_ptr(), pf,
+                                   pl, pr, pm, int(periodic), fl, fr, (bx, by, bw, bh), axis, bp, pb, F.data_ptr(), pf,
                                    Ff.data_ptr() if Ff is not None else None, _stream())
         _abi.check(st, self.h, "abf_composite_canvas")
         return (F, Ff) if f32 else F
@@ -363,11 +365,12 @@ class Plan:
         res = self.composite_canvas(L, R, mask_L, mask_R, flr, frl, box, axis=axis, f32=f32)
         return (*res, box, flr, frl) if f32 else (res, box, flr, frl)
 
-    def merge_photos(self, photos, out=None):
+    def merge_photos(self, photos, out=None, periodic: bool = False):
         """Repeated pairwise merging of photos placed on one canvas.
         ``photos``: list of (image uint8 H x W x 3, mask uint8 H x W, axis,
-        side), merged in list order (photo 0 starts the canvas). Returns
-        (canvas uint8 H x W x 3, coverage uint8 H x W, boxes)."""
+        side), merged in list order (photo 0 starts the canvas); with
+        ``periodic`` the canvas wraps in x and the ring closes across it.
+        Returns (canvas uint8 H x W x 3, coverage uint8 H x W, boxes)."""
         if not photos:
             raise ValueError("no photos")
         H, W, pm = _mask(photos[0][1], "mask")
@@ -384,8 +387,8 @@ class Plan:
         spare = torch.empty_like(canvas)
         cov = torch.empty((H, pm), dtype=torch.uint8, device=dev)[:, :W]
         _, _, pc = _img_u8(canvas, "out")
-        st, boxes = _abi.merge_photos(self.h, arr, len(photos), H, W, pm, canvas.data_ptr(), pc, spare.data_ptr(),
-                                      spare.stride(0), cov.data_ptr(), _stream())
+        st, boxes = _abi.merge_photos(self.h, arr, len(photos), H, W, pm, int(periodic), canvas.data_ptr(), pc,
+                                      spare.data_ptr(), spare.stride(0), cov.data_ptr(), _stream())
         _abi.check(st, self.h, "abf_merge_photos")
         return canvas, cov, boxes
 

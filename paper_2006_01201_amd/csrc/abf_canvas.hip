@@ -117,6 +117,12 @@ __global__ __launch_bounds__(kCanvasThreads) void k_canvas_rows(CanvasGeom a)
         tot[3][t] = v3;
         __syncthreads();
     }
+    // the row's last and first members of each area: on a periodic canvas a
+    // pixel with no member on one side reaches the other end's across the
+    // wrap
+    const int endA = tot[0][kCanvasThreads - 1], endB = tot[1][kCanvasThreads - 1];
+    const int begA = tot[2][0], begB = tot[3][0];
+    const bool wrap = a.periodic != 0;
     // exclusive carries per owned chunk, in place (each entry is read and
     // written by its owner only)
     int ca = t > 0 ? tot[0][t - 1] : -1, cb = t > 0 ? tot[1][t - 1] : -1;
@@ -153,8 +159,8 @@ __global__ __launch_bounds__(kCanvasThreads) void k_canvas_rows(CanvasGeom a)
             const int x = x0 + k;
             if ((bb >> k) & 1u) l1 = x;
             if ((bb >> (16 + k)) & 1u) l2 = x;
-            const uint32_t e1 = l1 >= 0 ? (uint32_t)(x - l1) : kInf16;
-            const uint32_t e2 = l2 >= 0 ? (uint32_t)(x - l2) : kInf16;
+            const uint32_t e1 = l1 >= 0 ? (uint32_t)(x - l1) : (wrap && endA >= 0 ? (uint32_t)(x + W - endA) : kInf16);
+            const uint32_t e2 = l2 >= 0 ? (uint32_t)(x - l2) : (wrap && endB >= 0 ? (uint32_t)(x + W - endB) : kInf16);
             d[k] = e1 | (e2 << 16);
         }
 #pragma unroll
@@ -162,8 +168,8 @@ __global__ __launch_bounds__(kCanvasThreads) void k_canvas_rows(CanvasGeom a)
             const int x = x0 + k;
             if ((bb >> k) & 1u) r1 = x;
             if ((bb >> (16 + k)) & 1u) r2 = x;
-            const uint32_t e1 = r1 != INF ? (uint32_t)(r1 - x) : kInf16;
-            const uint32_t e2 = r2 != INF ? (uint32_t)(r2 - x) : kInf16;
+            const uint32_t e1 = r1 != INF ? (uint32_t)(r1 - x) : (wrap && begA != INF ? (uint32_t)(W - x + begA) : kInf16);
+            const uint32_t e2 = r2 != INF ? (uint32_t)(r2 - x) : (wrap && begB != INF ? (uint32_t)(W - x + begB) : kInf16);
             d[k] = min(d[k] & 0xffffu, e1) | (min(d[k] >> 16, e2) << 16);
         }
         if (n == kCanvasChunk) {
@@ -377,11 +383,63 @@ __global__ __launch_bounds__(kCanvasThreads) void k_box_rows(const uint8_t *mL, 
     }
 }
 
+// Column occupancy of a periodic canvas: bit x of occ is set iff column x
+// holds an Area3 pixel. One thread per column walks the rows (consecutive
+// columns per wave: coalesced), stopping at the first Area3 pixel; a wave's
+// 64 bits are one ballot.
+__global__ __launch_bounds__(256) void k_box_cols(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W,
+                                                  uint32_t *occ)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    bool o = false;
+    if (x < W)
+        for (int y = 0; y < H && !o; y++) {
+            const size_t p = (size_t)y * pitchM + x;
+            o = gld(mL)[p] != 0 && gld(mR)[p] != 0;
+        }
+    const uint64_t b = __ballot(o);
+    const int lane = threadIdx.x & 63, w0 = (x - lane) >> 5, nw = (W + 31) >> 5;
+    if (lane == 0 && w0 < nw) gst(occ)[w0] = (uint32_t)b;
+    if (lane == 32 && w0 + 1 < nw) gst(occ)[w0 + 1] = (uint32_t)(b >> 32);
+}
+
+// Zero runs of one occupancy word (bits [0, vb) valid, column base): the
+// zeros before its first set bit (pz) and after its last (sz), and its
+// longest run strictly between two set bits (length il, first column is; of
+// equally long runs the first).
+struct OccWord {
+    int pz, sz, il, is;
+};
+__device__ __forceinline__ OccWord occ_word(uint32_t w, int vb, int base)
+{
+    OccWord r{vb, vb, 0, -1};
+    if (w == 0) return r;
+    r.pz = __builtin_ctz(w);
+    r.sz = vb - 1 - (31 - __builtin_clz(w));
+    int i = r.pz;
+    uint32_t rest = w & (w - 1);
+    while (rest) {
+        const int j = __builtin_ctz(rest);
+        if (j - i - 1 > r.il) {
+            r.il = j - i - 1;
+            r.is = base + i + 1;
+        }
+        i = j;
+        rest &= rest - 1;
+    }
+    return r;
+}
+
 // Merge of the row extents into {x, y, w, h} (zeros when no row has an
-// Area3 pixel); one workgroup.
-__global__ __launch_bounds__(1024) void k_box_fin(const int32_t *part, int H, int32_t *box)
+// Area3 pixel); one workgroup. With `occ` (a periodic canvas) the columns
+// are the shortest circular run that holds every Area3 column: it starts
+// right after the longest run of columns without one (of several, the one
+// that starts at the smallest column), and w = W minus that run's length.
+__global__ __launch_bounds__(1024) void k_box_fin(const int32_t *part, int H, int W, const uint32_t *occ,
+                                                  int32_t *box)
 {
     __shared__ int32_t s[4];
+    __shared__ OccWord ow[(kCanvasMaxDim + 31) / 32 + 1];
     if (threadIdx.x == 0) {
         s[0] = 0x7fffffff;
         s[1] = 0x7fffffff;
@@ -405,17 +463,72 @@ __global__ __launch_bounds__(1024) void k_box_fin(const int32_t *part, int H, in
         atomicMax(&s[2], x1);
         atomicMax(&s[3], y1);
     }
+    const int nw = (W + 31) >> 5;
+    if (occ)
+        for (int k = threadIdx.x; k < nw; k += blockDim.x)
+            ow[k] = occ_word(gld(occ)[k], k + 1 < nw ? 32 : W - 32 * k, 32 * k);
     __syncthreads();
     if (threadIdx.x == 0) {
         const bool e = s[2] < 0;
-        gst(box)[0] = e ? 0 : s[0];
+        int bx = s[0], bw = s[2] - s[0] + 1;
+        if (occ && !e) {
+            // s[0] and s[2] are the first and last Area3 columns; the run
+            // that wraps past W - 1 is weighed first when it starts at
+            // column 0 (it holds column 0 only), last otherwise
+            const int first = s[0], last = s[2];
+            int best_len = last == W - 1 ? first : 0, best_s = 0;
+            int prev = -1;  // last Area3 column seen
+            for (int k = 0; k < nw; k++) {
+                const OccWord o = ow[k];
+                const int vb = k + 1 < nw ? 32 : W - 32 * k;
+                if (o.pz == vb) continue;  // no Area3 column in the word
+                const int f = 32 * k + o.pz;
+                if (prev >= 0 && f - prev - 1 > best_len) {
+                    best_len = f - prev - 1;
+                    best_s = prev + 1;
+                }
+                if (o.il > best_len) {
+                    best_len = o.il;
+                    best_s = o.is;
+                }
+                prev = 32 * k + vb - 1 - o.sz;
+            }
+            if (last < W - 1 && W - 1 - last + first > best_len) {
+                best_len = W - 1 - last + first;
+                best_s = last + 1;
+            }
+            bx = best_len == 0 ? 0 : (best_s + best_len) % W;
+            bw = W - best_len;
+        }
+        gst(box)[0] = e ? 0 : bx;
         gst(box)[1] = e ? 0 : s[1];
-        gst(box)[2] = e ? 0 : s[2] - s[0] + 1;
+        gst(box)[2] = e ? 0 : bw;
         gst(box)[3] = e ? 0 : s[3] - s[1] + 1;
     }
 }
 
 // ------------------------------------------------------------- composite
+// Bilinear RGB sample at (x0 + fx, y0 + fy) of the box crop of a canvas
+// image whose box wraps past column W - 1: crop coordinates are clamped to
+// the crop, crop column c is canvas column bx + c modulo W. Byte loads.
+__device__ __forceinline__ void sample_box_wrap(const uint8_t *img, int pitch, int W, int bx, int by, int bw, int bh,
+                                                int x0, int y0, float fx, float fy, float out[3])
+{
+    int c0 = bx + clampi(x0, 0, bw - 1), c1 = bx + clampi(x0 + 1, 0, bw - 1);
+    if (c0 >= W) c0 -= W;
+    if (c1 >= W) c1 -= W;
+    const uint8_t *ra = img + (size_t)(by + clampi(y0, 0, bh - 1)) * pitch;
+    const uint8_t *rb = img + (size_t)(by + clampi(y0 + 1, 0, bh - 1)) * pitch;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const float a0 = gld(ra)[3 * c0 + c], a1 = gld(ra)[3 * c1 + c];
+        const float b0 = gld(rb)[3 * c0 + c], b1 = gld(rb)[3 * c1 + c];
+        const float top = a0 + fx * (a1 - a0);
+        const float bot = b0 + fx * (b1 - b0);
+        out[c] = top + fy * (bot - top);
+    }
+}
+
 // Code 1 over the canvas, one workgroup per kRowTW pixels of a row: Area1
 // copies L, Area2 copies R, Area3 inside the overlap box is warped and
 // blended as a strip pixel of the box (images and flows cropped to the
@@ -435,7 +548,9 @@ __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendPara
         const size_t pm = (size_t)y * o.pitchM + x;
         const int area = (gld(o.mL)[pm] != 0) + 2 * (gld(o.mR)[pm] != 0);
         if (o.cov) gst(o.cov)[pm] = area != 0;  // may be one of the masks: read above, by this thread only
-        const int xb = x - o.bx, yb = y - o.by;
+        int xb = x - o.bx;
+        if (o.periodic && xb < 0) xb += W;  // box columns wrap modulo W
+        const int yb = y - o.by;
         float f[3] = {0.f, 0.f, 0.f};
         if (area == 1 || area == 2) {
             const uint8_t *src = area == 1 ? o.L + (size_t)y * o.pitchL : o.R + (size_t)y * o.pitchR;
@@ -445,11 +560,16 @@ __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendPara
             const uint32_t p = (uint32_t)(yb * o.bw + xb);
             const double t = (double)gld(o.blend)[(size_t)y * o.pitchB + x];
             const PixBlend pb = blend_setup(xb, yb, t, p, o.inv_ext, o.flr, o.frl, bp);
-            const uint8_t *Lb = o.L + (size_t)o.by * o.pitchL + 3 * (size_t)o.bx;
-            const uint8_t *Rb = o.R + (size_t)o.by * o.pitchR + 3 * (size_t)o.bx;
             float cl[3], cr[3];
-            sample_u8(Lb, o.pitchL, o.bh, o.bw, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
-            sample_u8(Rb, o.pitchR, o.bh, o.bw, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
+            if (o.bx + o.bw <= W) {
+                const uint8_t *Lb = o.L + (size_t)o.by * o.pitchL + 3 * (size_t)o.bx;
+                const uint8_t *Rb = o.R + (size_t)o.by * o.pitchR + 3 * (size_t)o.bx;
+                sample_u8(Lb, o.pitchL, o.bh, o.bw, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
+                sample_u8(Rb, o.pitchR, o.bh, o.bw, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
+            } else {
+                sample_box_wrap(o.L, o.pitchL, W, o.bx, o.by, o.bw, o.bh, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
+                sample_box_wrap(o.R, o.pitchR, W, o.bx, o.by, o.bw, o.bh, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
+            }
             const float sR = 1.0f - pb.sL;
 #pragma unroll
             for (int c = 0; c < 3; c++) f[c] = pb.sL * cl[c] + sR * cr[c];
@@ -488,12 +608,37 @@ __global__ __launch_bounds__(256) void k_photo_init(const uint8_t *img, int pitc
     gst(cov)[(size_t)y * pitchC + x] = m ? 1 : 0;
 }
 
-// ------------------------------------------------------------- launchers
-hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *part,
-                              int32_t *box, hipStream_t s)
+// Box crop of an RGB canvas image whose columns wrap modulo W, into a
+// contiguous buffer (the input of the flow path for a box that wraps).
+__global__ __launch_bounds__(256) void k_gather_box(const uint8_t *img, int pitch, int W, int bx, int by, int bw,
+                                                    uint8_t *dst, int pitchD)
 {
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= bw) return;
+    int cx = bx + x;
+    if (cx >= W) cx -= W;
+    const uint8_t *src = img + (size_t)(by + y) * pitch + 3 * (size_t)cx;
+    uint8_t *d = dst + (size_t)y * pitchD + 3 * (size_t)x;
+#pragma unroll
+    for (int c = 0; c < 3; c++) gst(d)[c] = gld(src)[c];
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, bool periodic,
+                              int32_t *part, int32_t *box, hipStream_t s)
+{
+    uint32_t *occ = periodic ? reinterpret_cast<uint32_t *>(part + 2 * (size_t)H) : nullptr;
     hipLaunchKernelGGL(k_box_rows, dim3(H), dim3(kCanvasThreads), 0, s, mL, mR, pitchM, W, part);
-    hipLaunchKernelGGL(k_box_fin, dim3(1), dim3(1024), 0, s, part, H, box);
+    if (occ) hipLaunchKernelGGL(k_box_cols, dim3(ceil_div(W, 256)), dim3(256), 0, s, mL, mR, pitchM, H, W, occ);
+    hipLaunchKernelGGL(k_box_fin, dim3(1), dim3(1024), 0, s, part, H, W, occ, box);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_box(const uint8_t *img, int pitch, int W, int bx, int by, int bw, int bh, uint8_t *dst,
+                             int pitchD, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_box, dim3(ceil_div(bw, 256), bh), dim3(256), 0, s, img, pitch, W, bx, by, bw, dst,
+                       pitchD);
     return hipGetLastError();
 }
 

@@ -166,6 +166,8 @@ struct CanvasGeom {
     const uint8_t *mL, *mR;
     uint32_t *G, *M;
     int32_t pitchM, H, W, gpitch;
+    int32_t periodic;  // columns wrap (W - 1 neighbours 0): row distances the shorter way round
+    int32_t pad_;
 };
 __host__ __device__ inline int canvas_gpitch(int W) { return (W + 63) / 64 * 64; }
 
@@ -178,13 +180,19 @@ struct CompositeArgs {
     uint8_t *cov;             // union of the coverages (pitchM), or null
     int32_t pitchL, pitchR, pitchM, pitchB, pitchF;
     int32_t H, W, bx, by, bw, bh, axis;
-    int32_t pad_;
+    int32_t periodic;         // columns wrap: the box's columns are bx .. bx + bw - 1 modulo W
     double inv_ext;           // 1 / the box's extent across the seam
 };
 
-// part: 2 H int32 of scratch (row extents)
-hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, int32_t *part,
-                              int32_t *box, hipStream_t s);
+// part: scratch of 2 H int32 (row extents) + ceil(W / 32) uint32 (the
+// column occupancy of a periodic canvas)
+inline size_t overlap_box_scratch(int H, int W) { return sizeof(int32_t) * (2 * (size_t)H + (W + 31) / 32); }
+hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W, bool periodic,
+                              int32_t *part, int32_t *box, hipStream_t s);
+// copy of a box of an RGB canvas image whose columns wrap modulo W into a
+// contiguous bh x bw x 3 buffer (rows pitchD bytes apart)
+hipError_t launch_gather_box(const uint8_t *img, int pitch, int W, int bx, int by, int bw, int bh, uint8_t *dst,
+                             int pitchD, hipStream_t s);
 hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int32_t *d1, int32_t *d2, int pitchD,
                               hipStream_t s);
 hipError_t launch_composite(const CompositeArgs &o, BlendParams bp, hipStream_t s);

@@ -980,7 +980,7 @@ static size_t canvas_scratch(int H, int W)
 }
 
 static abf_status canvas_setup(abf_plan *plan, const uint8_t *mL, const uint8_t *mR, int32_t H, int32_t W,
-                               int32_t pitchM, CanvasGeom &g, float **bmap)
+                               int32_t pitchM, bool periodic, CanvasGeom &g, float **bmap)
 {
     if (!mL || !mR) return fail(plan, ABF_E_INVALID, "null mask");
     if (H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim)
@@ -1000,6 +1000,7 @@ static abf_status canvas_setup(abf_plan *plan, const uint8_t *mL, const uint8_t 
     g.H = H;
     g.W = W;
     g.gpitch = (int32_t)gp;
+    g.periodic = periodic ? 1 : 0;
     return ABF_OK;
 }
 
@@ -1012,7 +1013,7 @@ size_t abf_canvas_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W)
 }
 
 abf_status abf_overlap_box(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
-                           int32_t pitch_mask, int32_t *box, void *hip_stream)
+                           int32_t pitch_mask, int32_t periodic, int32_t *box, void *hip_stream)
 {
     if (!plan) return ABF_E_INVALID;
     if (!mask_L || !mask_R || !box) return fail(plan, ABF_E_INVALID, "null pointer");
@@ -1020,15 +1021,15 @@ abf_status abf_overlap_box(abf_plan *plan, const uint8_t *mask_L, const uint8_t 
         return fail(plan, ABF_E_SHAPE, "canvas %d x %d (1..%d per side)", H, W, kCanvasMaxDim);
     if (pitch_mask < W) return fail(plan, ABF_E_SHAPE, "mask pitch %d < W %d", pitch_mask, W);
     uint8_t *scr = nullptr;
-    abf_status rc = grad_scratch(plan, 2 * sizeof(int32_t) * (size_t)H, &scr);
+    abf_status rc = grad_scratch(plan, overlap_box_scratch(H, W), &scr);
     if (rc != ABF_OK) return rc;
-    HIP_TRY(plan, launch_overlap_box(mask_L, mask_R, pitch_mask, H, W, reinterpret_cast<int32_t *>(scr), box,
-                                     static_cast<hipStream_t>(hip_stream)));
+    HIP_TRY(plan, launch_overlap_box(mask_L, mask_R, pitch_mask, H, W, periodic != 0, reinterpret_cast<int32_t *>(scr),
+                                     box, static_cast<hipStream_t>(hip_stream)));
     return ABF_OK;
 }
 
 abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t *mask_R, int32_t H, int32_t W,
-                            int32_t pitch_mask, float *blend, int32_t pitch_blend, int32_t *dist2_1,
+                            int32_t pitch_mask, int32_t periodic, float *blend, int32_t pitch_blend, int32_t *dist2_1,
                             int32_t *dist2_2, int32_t pitch_dist, void *hip_stream)
 {
     if (!plan) return ABF_E_INVALID;
@@ -1039,7 +1040,7 @@ abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t
     if (dist2_1 && pitch_dist < W) return fail(plan, ABF_E_SHAPE, "distance pitch %d < W %d", pitch_dist, W);
     CanvasGeom g{};
     float *bmap = nullptr;
-    abf_status rc = canvas_setup(plan, mask_L, mask_R, H, W, pitch_mask, g, &bmap);
+    abf_status rc = canvas_setup(plan, mask_L, mask_R, H, W, pitch_mask, periodic != 0, g, &bmap);
     if (rc != ABF_OK) return rc;
     HIP_TRY(plan, launch_canvas_dist(g, blend, pitch_blend, dist2_1, dist2_2, pitch_dist,
                                      static_cast<hipStream_t>(hip_stream)));
@@ -1048,7 +1049,7 @@ abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t
 
 abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t *R, const uint8_t *mask_L,
                                 const uint8_t *mask_R, int32_t H, int32_t W, int32_t pitch_L, int32_t pitch_R,
-                                int32_t pitch_mask, const float *flow_LtoR, const float *flow_RtoL,
+                                int32_t pitch_mask, int32_t periodic, const float *flow_LtoR, const float *flow_RtoL,
                                 const int32_t *box, int32_t axis, const float *blend, int32_t pitch_blend,
                                 uint8_t *F, int32_t pitch_F, float *F_f32, void *hip_stream)
 {
@@ -1058,7 +1059,8 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
     if (pitch_L < 3 * W || pitch_R < 3 * W || pitch_F < 3 * W)
         return fail(plan, ABF_E_SHAPE, "image pitch smaller than 3 W");
     const int bx = box[0], by = box[1], bw = box[2], bh = box[3];
-    if (bx < 0 || by < 0 || bw < 0 || bh < 0 || bx + bw > W || by + bh > H)
+    // on a periodic canvas the box's columns may wrap past W - 1
+    if (bx < 0 || by < 0 || bw < 0 || bh < 0 || (periodic ? (bx >= W || bw > W) : bx + bw > W) || by + bh > H)
         return fail(plan, ABF_E_SHAPE, "box {%d, %d, %d, %d} outside the %d x %d canvas", bx, by, bw, bh, H, W);
     const bool any = bw > 0 && bh > 0;
     if (any && (!flow_LtoR || !flow_RtoL)) return fail(plan, ABF_E_INVALID, "null flow");
@@ -1068,7 +1070,7 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     CanvasGeom g{};
     float *bmap = nullptr;
-    abf_status rc = canvas_setup(plan, mask_L, mask_R, H, W, pitch_mask, g, &bmap);
+    abf_status rc = canvas_setup(plan, mask_L, mask_R, H, W, pitch_mask, periodic != 0, g, &bmap);
     if (rc != ABF_OK) return rc;
     CompositeArgs o{};
     o.blend = blend;
@@ -1097,6 +1099,7 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
     o.bw = any ? bw : 0;
     o.bh = any ? bh : 0;
     o.axis = axis;
+    o.periodic = periodic ? 1 : 0;
     o.inv_ext = any ? 1.0 / (double)(axis == 0 ? bw : bh) : 0.0;
     BlendParams bp{plan->p.k_sharp, plan->p.k_flowmag, plan->p.blend_mode};
     HIP_TRY(plan, launch_composite(o, bp, s));
@@ -1105,8 +1108,10 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
 
 // ------------------------------------------------------ photo merging
 // Workspace of a merge: [head][flow path's data region, or the canvas
-// passes' scratch, whichever is larger][FlowLtoR][FlowRtoL][box]. The
-// flows of a step must survive the canvas passes that follow them.
+// passes' scratch, whichever is larger][FlowLtoR][FlowRtoL][box + box
+// scratch][L crop][R crop]. The flows of a step must survive the canvas
+// passes that follow them; the crops (contiguous copies of a box that
+// wraps past the last column of a periodic canvas) feed the flow path.
 static size_t merge_tail(const abf_plan *plan, int H, int W)
 {
     const size_t a = data_bound(plan), b = canvas_scratch(H, W);
@@ -1117,15 +1122,18 @@ static size_t merge_flow_bytes(const abf_plan *plan)
     return align_up(2 * sizeof(float) * (size_t)plan->max_pixels, kAlign);
 }
 
+static size_t merge_box_bytes(int H, int W) { return align_up(4 * sizeof(int32_t) + overlap_box_scratch(H, W), kAlign); }
+static size_t merge_crop_bytes(const abf_plan *plan) { return align_up(3 * (size_t)plan->max_pixels, kAlign); }
+
 size_t abf_merge_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W)
 {
     if (!plan || H < 1 || W < 1 || H > kCanvasMaxDim || W > kCanvasMaxDim) return 0;
-    return merge_tail(plan, H, W) + 2 * merge_flow_bytes(plan) + kAlign;
+    return merge_tail(plan, H, W) + 2 * merge_flow_bytes(plan) + merge_box_bytes(H, W) + 2 * merge_crop_bytes(plan);
 }
 
 abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, int32_t H, int32_t W,
-                            int32_t pitch_mask, uint8_t *canvas, int32_t pitch_canvas, uint8_t *spare,
-                            int32_t pitch_spare, uint8_t *coverage, int32_t *boxes, void *hip_stream)
+                            int32_t pitch_mask, int32_t periodic, uint8_t *canvas, int32_t pitch_canvas,
+                            uint8_t *spare, int32_t pitch_spare, uint8_t *coverage, int32_t *boxes, void *hip_stream)
 {
     if (!plan) return ABF_E_INVALID;
     if (!photos || n < 1 || !canvas || !spare || !coverage) return fail(plan, ABF_E_INVALID, "null pointer or no photo");
@@ -1150,6 +1158,9 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
     float *flr = reinterpret_cast<float *>(tail);
     float *frl = reinterpret_cast<float *>(tail + merge_flow_bytes(plan));
     int32_t *dbox = reinterpret_cast<int32_t *>(tail + 2 * merge_flow_bytes(plan));
+    int32_t *bscr = dbox + 4;  // the box kernels' scratch
+    uint8_t *crop[2] = {tail + 2 * merge_flow_bytes(plan) + merge_box_bytes(H, W),
+                        tail + 2 * merge_flow_bytes(plan) + merge_box_bytes(H, W) + merge_crop_bytes(plan)};
     uint8_t *buf[2] = {canvas, spare};
     const int32_t pitch[2] = {pitch_canvas, pitch_spare};
     // the buffer that holds the canvas merged so far; chosen so that the
@@ -1166,8 +1177,7 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
         const int32_t pL = p.side == 0 ? pitch[cur] : p.pitch, pR = p.side == 0 ? p.pitch : pitch[cur];
         const uint8_t *mL = p.side == 0 ? coverage : p.mask, *mR = p.side == 0 ? p.mask : coverage;
         // the overlap box decides the size of the flow computation: read back
-        HIP_TRY(plan, launch_overlap_box(mL, mR, pitch_mask, H, W, reinterpret_cast<int32_t *>(plan->ws + plan->hdr_cap),
-                                         dbox, s));
+        HIP_TRY(plan, launch_overlap_box(mL, mR, pitch_mask, H, W, periodic != 0, bscr, dbox, s));
         int32_t hb[4];
         HIP_TRY(plan, hipMemcpyAsync(hb, dbox, sizeof(hb), hipMemcpyDeviceToHost, s));
         HIP_TRY(plan, hipStreamSynchronize(s));
@@ -1177,12 +1187,23 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
         const bool any = hb[2] > 0 && hb[3] > 0;
         if (any) {
             abf_strip st{};
-            st.L = L + (size_t)hb[1] * pL + 3 * (size_t)hb[0];
-            st.R = R + (size_t)hb[1] * pR + 3 * (size_t)hb[0];
+            if (hb[0] + hb[2] <= W) {
+                st.L = L + (size_t)hb[1] * pL + 3 * (size_t)hb[0];
+                st.R = R + (size_t)hb[1] * pR + 3 * (size_t)hb[0];
+                st.pitch_L = pL;
+                st.pitch_R = pR;
+            } else {
+                // a box across the wrap of a periodic canvas: flows of its contiguous copies
+                if ((int64_t)hb[2] * hb[3] > plan->max_pixels)
+                    return fail(plan, ABF_E_SHAPE, "merge box %d x %d exceeds the plan", hb[3], hb[2]);
+                HIP_TRY(plan, launch_gather_box(L, pL, W, hb[0], hb[1], hb[2], hb[3], crop[0], 3 * hb[2], s));
+                HIP_TRY(plan, launch_gather_box(R, pR, W, hb[0], hb[1], hb[2], hb[3], crop[1], 3 * hb[2], s));
+                st.L = crop[0];
+                st.R = crop[1];
+                st.pitch_L = st.pitch_R = 3 * hb[2];
+            }
             st.H = hb[3];
             st.W = hb[2];
-            st.pitch_L = pL;
-            st.pitch_R = pR;
             st.axis = p.axis;
             st.flow_LtoR = flr;
             st.flow_RtoL = frl;
@@ -1191,7 +1212,7 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
         }
         CanvasGeom g{};
         float *bmap = nullptr;
-        abf_status rc = canvas_setup(plan, mL, mR, H, W, pitch_mask, g, &bmap);
+        abf_status rc = canvas_setup(plan, mL, mR, H, W, pitch_mask, periodic != 0, g, &bmap);
         if (rc != ABF_OK) return rc;
         if (any) HIP_TRY(plan, launch_canvas_dist(g, bmap, g.gpitch, nullptr, nullptr, 0, s));
         CompositeArgs o{};
@@ -1215,6 +1236,7 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
         o.bw = any ? hb[2] : 0;
         o.bh = any ? hb[3] : 0;
         o.axis = p.axis;
+        o.periodic = periodic ? 1 : 0;
         o.inv_ext = any ? 1.0 / (double)(p.axis == 0 ? hb[2] : hb[3]) : 0.0;
         o.cov = coverage;  // coverage |= the photo's mask, in the same pass
         HIP_TRY(plan, launch_composite(o, bp, s));

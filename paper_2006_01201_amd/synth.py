@@ -49,7 +49,10 @@ class Texture:
     N_SIN = 24
     N_RECT = 60
 
-    def __init__(self, rng: np.random.Generator, H: int, W: int):
+    def __init__(self, rng: np.random.Generator, H: int, W: int, periodic: bool = False):
+        """``periodic``: the texture repeats along x with period W (a
+        360-degree panorama): every sinusoid makes a whole number of cycles
+        across W and rectangles wrap."""
         n_sin, n_rect = self.N_SIN, self.N_RECT
         self.amp = rng.uniform(6.0, 14.0, n_sin)
         self.freq = np.exp(rng.uniform(np.log(1.0 / 400.0), np.log(1.0 / 5.0), n_sin))
@@ -61,6 +64,18 @@ class Texture:
         rh = np.exp(rng.uniform(np.log(0.005), np.log(0.4), n_rect)) * H
         self.rects = np.stack([rx0, ry0, rx0 + rw, ry0 + rh], axis=1)
         self.offset = rng.uniform(-50.0, 50.0, (n_rect, 3))
+        self.period = float(W) if periodic else None
+        if periodic:
+            fx = np.rint(self.freq * np.cos(self.theta) * W) / W
+            fy = self.freq * np.sin(self.theta)
+            self.freq = np.hypot(fx, fy)
+            self.theta = np.arctan2(fy, fx)
+
+    def rect_mask(self, r, x, y):
+        x0, y0, x1, y1 = self.rects[r]
+        if self.period is None:
+            return (x >= x0) & (x < x1) & (y >= y0) & (y < y1)
+        return (np.mod(x - x0, self.period) < x1 - x0) & (y >= y0) & (y < y1)
 
     def __call__(self, x: np.ndarray, y: np.ndarray) -> np.ndarray:
         x = np.asarray(x, dtype=np.float64)
@@ -90,10 +105,9 @@ class Texture:
             xlo, xhi, ylo, yhi = x.min(), x.max(), y.min(), y.max()
             for r in range(len(self.rects)):
                 x0, y0, x1, y1 = self.rects[r]
-                if x1 <= xlo or x0 > xhi or y1 <= ylo or y0 > yhi:
+                if y1 <= ylo or y0 > yhi or (self.period is None and (x1 <= xlo or x0 > xhi)):
                     continue
-                m = (x >= x0) & (x < x1) & (y >= y0) & (y < y1)
-                out[m] += self.offset[r].astype(np.float32)
+                out[self.rect_mask(r, x, y)] += self.offset[r].astype(np.float32)
         return out
 
 
@@ -457,13 +471,35 @@ def random_masks(seed: int, H: int, W: int, blobs: int = 6, p_empty: float = 0.0
     return out[0], out[1]
 
 
-def panorama_masks(rng, H: int, W: int, n_ring: int, top: bool = True):
+def panorama_masks(rng, H: int, W: int, n_ring: int, top: bool = True, closed: bool = False):
     """Coverage of a photo set on a panorama canvas: n_ring photos side by
     side (seams running top to bottom, overlaps U[480, 960] x W / 9000
     wide, slanted and bowed edges) reaching from ~0.15 H (bowed) to the
     bottom, and, if ``top``, one photo over the full width from the top to
-    ~0.3 H (bowed): its seam with the ring is a band of ~0.15 H."""
+    ~0.3 H (bowed): its seam with the ring is a band of ~0.15 H. With
+    ``closed`` the canvas wraps in x and the ring is closed: one more seam
+    at column 0 (= W), which the first photo reaches leftwards and the last
+    one rightwards, across the wrap."""
     yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    if closed:
+        seams = [k * W / n_ring for k in range(n_ring)] + [float(W)]
+        ov = rng.uniform(480.0, 960.0, n_ring) * W / 9000.0
+        ov = np.append(ov, ov[0])
+        edges = []
+        for x, o in zip(seams, ov):
+            slope = rng.uniform(-0.02, 0.02) * W / max(H, 1) / n_ring
+            bow = rng.uniform(-0.1, 0.1) * o
+            edges.append((_edge(rng, H, x - o / 2, slope, bow), _edge(rng, H, x + o / 2, slope, bow)))
+        ring_top = _edge(rng, W, 0.15 * H, 0.0, rng.uniform(-0.02, 0.02) * H)
+        masks = []
+        for k in range(n_ring):
+            lo, hi = edges[k][0], edges[k + 1][1]  # photo k: from seam k's left edge to seam k + 1's right one
+            m = (np.mod(xx - lo[:, None], W) < (hi - lo)[:, None]) & (yy >= ring_top[None, :])
+            masks.append(m.astype(np.uint8))
+        if top:
+            bottom = _edge(rng, W, 0.30 * H, 0.0, rng.uniform(-0.02, 0.02) * H)
+            masks.append((yy <= bottom[None, :]).astype(np.uint8))
+        return masks
     seams = [(k + 1) * W / n_ring for k in range(n_ring - 1)]
     ov = rng.uniform(480.0, 960.0, len(seams)) * W / 9000.0
     lefts, rights = [np.zeros(H) - 1.0], []
@@ -482,7 +518,7 @@ def panorama_masks(rng, H: int, W: int, n_ring: int, top: bool = True):
 
 
 def make_panorama_photos(seed: int, H: int, W: int, n_ring: int = 6, top: bool = True, max_ux: float = 6.0,
-                         max_uy: float = 2.0, noise: float = 2.0, device=None):
+                         max_uy: float = 2.0, noise: float = 2.0, device=None, closed: bool = False):
     """A photo set placed on one H x W canvas (seed slot cfg = 120): one
     scene texture seen by every photo through its own smooth residual
     misalignment (|u| <= max_ux, max_uy px), exposure gain U[0.95, 1.05]
@@ -490,10 +526,12 @@ def make_panorama_photos(seed: int, H: int, W: int, n_ring: int = 6, top: bool =
     (image H x W x 3 uint8, mask H x W uint8, axis, side) in merge order:
     the ring left to right (axis 0, side 0), then the top photo (axis 1,
     side 1). Arrays are numpy, or torch tensors on ``device`` (evaluated
-    there)."""
-    rng = rng_for(120, seed, 0)
-    masks = panorama_masks(rng, H, W, n_ring, top)
-    tex = Texture(rng, H, W)
+    there). ``closed``: a 360-degree panorama (scene, misalignment fields
+    and coverage periodic in x; seed slot cfg = 121) whose last ring photo
+    overlaps the first across column W - 1 / 0."""
+    rng = rng_for(121 if closed else 120, seed, 0)
+    masks = panorama_masks(rng, H, W, n_ring, top, closed=closed)
+    tex = Texture(rng, H, W, periodic=closed)
     sigma = max(8.0, 0.05 * min(H, W))
     out = []
     for i, m in enumerate(masks):
@@ -552,7 +590,11 @@ def _texture_torch(tex: Texture, x, y):
     # would synchronise with the host once per rectangle)
     for r in range(len(tex.rects)):
         x0, y0, x1, y1 = tex.rects[r]
-        m = ((x >= x0) & (x < x1) & (y >= y0) & (y < y1)).float()
+        if tex.period is None:
+            m = (x >= x0) & (x < x1)
+        else:
+            m = torch.remainder(x - x0, tex.period) < x1 - x0
+        m = (m & (y >= y0) & (y < y1)).float()
         out += m[..., None] * torch.tensor(tex.offset[r], dtype=torch.float32, device=x.device)
     return out
 

@@ -106,12 +106,14 @@ def test_strip_struct_layout():
 def test_canvas_and_merge_reject_null_plans(lib):
     assert lib.abf_canvas_workspace_bytes(None, 10, 10) == 0
     assert lib.abf_merge_workspace_bytes(None, 10, 10) == 0
-    assert lib.abf_overlap_box(None, None, None, 4, 4, 4, None, None) == _abi.E_INVALID
-    assert lib.abf_canvas_blend(None, None, None, 4, 4, 4, None, 4, None, None, 4, None) == _abi.E_INVALID
-    box = (ctypes.c_int32 * 4)(0, 0, 0, 0)
-    assert lib.abf_composite_canvas(None, None, None, None, None, 4, 4, 12, 12, 4, None, None, box, 0, None, 4,
-                                    None, 12, None, None) == _abi.E_INVALID
-    assert lib.abf_merge_photos(None, None, 0, 4, 4, 4, None, 12, None, 12, None, None, None) == _abi.E_INVALID
+    for per in (0, 1):
+        assert lib.abf_overlap_box(None, None, None, 4, 4, 4, per, None, None) == _abi.E_INVALID
+        assert lib.abf_canvas_blend(None, None, None, 4, 4, 4, per, None, 4, None, None, 4, None) == _abi.E_INVALID
+        box = (ctypes.c_int32 * 4)(0, 0, 0, 0)
+        assert lib.abf_composite_canvas(None, None, None, None, None, 4, 4, 12, 12, 4, per, None, None, box, 0, None,
+                                        4, None, 12, None, None) == _abi.E_INVALID
+        assert lib.abf_merge_photos(None, None, 0, 4, 4, 4, per, None, 12, None, 12, None, None,
+                                    None) == _abi.E_INVALID
 
 
 def test_log_to_stderr_by_environment(lib):

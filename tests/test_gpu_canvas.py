@@ -284,3 +284,95 @@ def test_distances_are_bitwise_repeatable(api):
     b = plan.canvas_blend(dev(mL), dev(mR), distances=True)
     torch.cuda.synchronize()
     assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+# ----------------------------------------------------------------------------
+# Periodic canvas (360-degree panorama: column W - 1 next to column 0)
+
+
+def _wrapped_masks(seed, H, W):
+    # random blobs rolled so that shapes cross the wrap, plus column clusters
+    # of Area3 at both ends (the box wraps)
+    mL, mR = synth.random_masks(seed, H, W, blobs=5)
+    s = W // 3 + seed
+    mL, mR = np.roll(mL, s, 1), np.roll(mR, s, 1)
+    mL[H // 4:H // 2, :4] = 1
+    mR[H // 4:H // 2, :4] = 1
+    mL[H // 3:, W - 5:] = 1
+    mR[H // 3:, W - 5:] = 1
+    return mL, mR
+
+
+PERIODIC = {
+    "wrapped_40x71": lambda: _wrapped_masks(31, 40, 71),
+    "wrapped_97x130": lambda: _wrapped_masks(32, 97, 130),
+    "wrapped_1x90": lambda: _wrapped_masks(33, 1, 90),
+    "blobs_64x33": lambda: synth.random_masks(2, 64, 33),
+    "identical_30x30": lambda: (np.ones((30, 30), np.uint8), np.ones((30, 30), np.uint8)),
+    "ring_seam_90x360": lambda: (lambda ph: (ph[0][1] | ph[1][1], ph[2][1]))(
+        synth.make_panorama_photos(4, 90, 360, n_ring=3, closed=True)),
+}
+
+
+@pytest.mark.parametrize("name", list(PERIODIC))
+def test_periodic_box_distances_and_blend(api, name):
+    mL, mR = PERIODIC[name]()
+    H, W = mL.shape
+    plan = plan_for(api, H, W)
+    print(f"[gpu] periodic canvas distances {name}", flush=True)
+    dL, dR = dev(mL), dev(mR)
+    assert plan.overlap_box(dL, dR, periodic=True) == oracle.overlap_box(mL, mR, periodic=True)
+    B, d1, d2 = plan.canvas_blend(dL, dR, distances=True, periodic=True)
+    torch.cuda.synchronize()
+    o1, o2 = oracle.canvas_dist2(mL, mR, periodic=True)
+    assert np.array_equal(d1.cpu().numpy().astype(np.int64), o1)
+    assert np.array_equal(d2.cpu().numpy().astype(np.int64), o2)
+    oB = oracle.canvas_blend(mL, mR, periodic=True)
+    assert np.abs(B.cpu().numpy().astype(np.float64) - oB).max() <= B_TOL
+    B2 = plan.canvas_blend(dL, dR, periodic=True)
+    torch.cuda.synchronize()
+    assert torch.equal(B, B2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_periodic_box_of_column_clusters(api, seed):
+    # one to three column clusters of Area3, often across the wrap, on
+    # canvases whose widths are not multiples of the occupancy words
+    rng = np.random.default_rng(40 + seed)
+    H, W = 13, [37, 64, 100, 161, 33, 250][seed]
+    mL = np.zeros((H, W), np.uint8)
+    mR = np.zeros((H, W), np.uint8)
+    for _ in range(int(rng.integers(1, 4))):
+        c0, n = int(rng.integers(0, W)), int(rng.integers(1, 12))
+        cols = (c0 + np.arange(n)) % W
+        r0 = int(rng.integers(0, H - 3))
+        mL[r0:r0 + 3, cols] = 1
+        mR[r0:r0 + 3, cols] = 1
+    plan = plan_for(api, H, W)
+    print(f"[gpu] periodic box clusters {seed}", flush=True)
+    assert plan.overlap_box(dev(mL), dev(mR), periodic=True) == oracle.overlap_box(mL, mR, periodic=True)
+    assert plan.overlap_box(dev(mL), dev(mR)) == oracle.overlap_box(mL, mR)
+
+
+@pytest.mark.parametrize("mode", ["eq1", "user"])
+def test_periodic_composite_with_a_wrapped_box(api, mode):
+    # the last photo of a closed ring against the photos before it: Area3 at
+    # its left seam and across the wrap, one box over the wrap
+    H, W = 90, 360
+    ph = synth.make_panorama_photos(4, H, W, n_ring=3, closed=True)
+    mL = ph[0][1] | ph[1][1]
+    mR = ph[2][1]
+    L = np.where(ph[1][1][..., None] > 0, ph[1][0], ph[0][0])
+    R = ph[2][0]
+    box = oracle.overlap_box(mL, mR, periodic=True)
+    bx, by, bw, bh = box
+    assert bx + bw > W  # the box wraps
+    flr, frl = _flows(9, bh, bw, 5.0)
+    blend = synth.rng_for(116, 0, 0).uniform(0, 1, (H, W)).astype(np.float32) if mode == "user" else None
+    plan = plan_for(api, H, W)
+    print(f"[gpu] periodic composite {mode}", flush=True)
+    F8, Ff = plan.composite_canvas(dev(L), dev(R), dev(mL), dev(mR), dev(flr), dev(frl), box,
+                                   blend=None if blend is None else dev(blend), f32=True, periodic=True)
+    torch.cuda.synchronize()
+    oF, _ = oracle.composite(L, R, mL, mR, flr, frl, box, blend=blend, periodic=True)
+    _check_F(F8.cpu().numpy(), Ff.cpu().numpy(), oF)
