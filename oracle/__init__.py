@@ -287,6 +287,81 @@ def energy(Ref, Tgt, u, lam=0.05, eps=1e-3, grads: bool = True):
     return (E, gu, gr, gt) if grads else E
 
 
+# Multi-level energy: the energy summed over a float pyramid of the images
+# and the flow (an extension for gradient refinement; not in the paper).
+
+_BINOM = np.array([1.0, 4.0, 6.0, 4.0, 1.0])
+
+
+def pyr_down_float(x):
+    """One level of the float pyramid: the 5 x 5 binomial filter of the
+    luma pyramid (weights w_i w_j / 256) with clamped indices, without
+    rounding, decimated to ceil(H / 2) x ceil(W / 2); every channel of an
+    H x W (x C) array alike."""
+    x = np.asarray(x, dtype=np.float64)
+    H, W = x.shape[:2]
+    h, w = (H + 1) // 2, (W + 1) // 2
+    out = np.zeros((h, w) + x.shape[2:])
+    Y, X = 2 * np.arange(h), 2 * np.arange(w)
+    for j in range(5):
+        ry = np.clip(Y + j - 2, 0, H - 1)
+        for i in range(5):
+            rx = np.clip(X + i - 2, 0, W - 1)
+            out += (_BINOM[j] * _BINOM[i] / 256.0) * x[ry][:, rx]
+    return out
+
+
+def pyr_down_float_adjoint(g, shape):
+    """The transpose of ``pyr_down_float``: every coarse value g(Y, X) is
+    added back, with its weight, onto the fine pixels its taps read
+    (clamped taps pile up on the border pixels). ``shape``: the fine shape."""
+    g = np.asarray(g, dtype=np.float64)
+    H, W = shape[:2]
+    h, w = g.shape[:2]
+    out = np.zeros(tuple(shape))
+    Y, X = 2 * np.arange(h), 2 * np.arange(w)
+    for j in range(5):
+        ry = np.clip(Y + j - 2, 0, H - 1)
+        for i in range(5):
+            rx = np.clip(X + i - 2, 0, W - 1)
+            np.add.at(out, (ry[:, None], rx[None, :]), (_BINOM[j] * _BINOM[i] / 256.0) * g)
+    return out
+
+
+def energy_ms(Ref, Tgt, u, levels: int, lam=0.05, eps=1e-3, grads: bool = True):
+    """E_ms = sum over pyramid levels k = 0 .. levels - 1 of the energy of
+    level k (``energy``), with Ref_k, Tgt_k the images reduced k times by
+    ``pyr_down_float`` and u_k the flow reduced likewise and halved at each
+    reduction (displacements in level-k pixels). Gradients with respect to
+    the level-0 u, Ref and Tgt by the chain rule, coarse to fine:
+    G_k = g_k + (1/2 for u) pyr_down_float_adjoint(G_{k+1})."""
+    R, T, U = [_f64(Ref)], [_f64(Tgt)], [_f64(u)]
+    for _ in range(1, levels):
+        R.append(pyr_down_float(R[-1]))
+        T.append(pyr_down_float(T[-1]))
+        U.append(pyr_down_float(U[-1]) / 2.0)
+    res = [energy(R[k], T[k], U[k], lam, eps, grads=grads) for k in range(levels)]
+    if not grads:
+        return float(sum(res))
+    E = sum(r[0] for r in res)
+    Gu, Gr, Gt = res[-1][1], res[-1][2], res[-1][3]
+    for k in range(levels - 2, -1, -1):
+        Gu = res[k][1] + 0.5 * pyr_down_float_adjoint(Gu, U[k].shape)
+        Gr = res[k][2] + pyr_down_float_adjoint(Gr, R[k].shape)
+        Gt = res[k][3] + pyr_down_float_adjoint(Gt, T[k].shape)
+    return E, Gu, Gr, Gt
+
+
+def refine_gd_ms(Ref, Tgt, u, levels: int, steps=20, eta=0.5, lam=0.05, eps=1e-3, clip=0.25):
+    """Gradient descent on the multi-level energy, u <- u - clip(eta dE_ms/du,
+    +-clip) per component, ``steps`` times; returns the flow."""
+    u = _f64(u).copy()
+    for _ in range(steps):
+        _, gu, _, _ = energy_ms(Ref, Tgt, u, levels, lam, eps)
+        u -= np.clip(eta * gu, -clip, clip)
+    return u
+
+
 def refine_gd(Ref, Tgt, u, steps=50, eta=0.5, lam=0.05, eps=1e-3, clip=0.25):
     Ref, Tgt = _f64(Ref), _f64(Tgt)
     u = _f64(u).copy()
