@@ -229,6 +229,37 @@ abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, f
                            int32_t W, int32_t steps, float eta, float lambda, float eps, float clip_px,
                            void *hip_stream);
 
+/* Multi-level energy (an extension): E_ms = the sum over pyramid levels
+ * k = 0 .. levels - 1 of the energy of abf_energy at level k, where Ref_k
+ * and Tgt_k are the images reduced k times by the float pyramid (the 5 x 5
+ * binomial filter of the luma pyramid, weights w_i w_j / 256 with w = 1 4 6
+ * 4 1, clamped indices, no rounding, decimated to ceil(H / 2) x
+ * ceil(W / 2)) and u_k the flow reduced likewise and halved at each level
+ * (displacements in level-k pixels). Writes E_ms (one float, device) and,
+ * where non-null, its gradients with respect to the level-0 u, Ref, Tgt,
+ * carried from the coarse levels through the pyramid's adjoint (the
+ * transpose of filter and decimation). The pyramid levels are built in
+ * the workspace during the call and not kept: a later gradient call
+ * recomputes them from the level-0 inputs. deterministic as in abf_energy
+ * (the adjoint passes are gathers, order-independent). levels = 1 gives
+ * abf_energy's results. Scratch: about 11 bytes per level-0 pixel
+ * (22 with gradients), plus abf_energy's. levels 1..12, else
+ * ABF_E_INVALID. */
+abf_status abf_energy_ms(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H,
+                         int32_t W, int32_t levels, float lambda, float eps, float *E_dev, float *g_u,
+                         float *g_Ref, float *g_Tgt, int32_t deterministic, void *hip_stream);
+
+/* Workspace bytes for abf_energy_ms and abf_refine_flow_ms on an H x W
+ * image with `levels` levels (at least abf_workspace_bytes); 0 for bad
+ * arguments. */
+size_t abf_energy_ms_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W, int32_t levels);
+
+/* steps times u <- u - clip(eta * dE_ms/du, -clip_px, clip_px) in place
+ * (abf_refine_flow on the multi-level energy). */
+abf_status abf_refine_flow_ms(abf_plan *plan, const float *Ref, const float *Tgt, float *u, int32_t H,
+                              int32_t W, int32_t levels, int32_t steps, float eta, float lambda, float eps,
+                              float clip_px, void *hip_stream);
+
 /* One strip of a batched refinement (device pointers): float32 RGB Ref and
  * Tgt (H x W x 3) and the flow u (H x W x 2), refined in place. */
 typedef struct abf_refine_strip {

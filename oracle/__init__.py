@@ -318,14 +318,18 @@ def pyr_down_float_adjoint(g, shape):
     g = np.asarray(g, dtype=np.float64)
     H, W = shape[:2]
     h, w = g.shape[:2]
-    out = np.zeros(tuple(shape))
+    gc = g.reshape(h, w, -1)
+    out = np.zeros((H * W, gc.shape[2]))
     Y, X = 2 * np.arange(h), 2 * np.arange(w)
     for j in range(5):
         ry = np.clip(Y + j - 2, 0, H - 1)
         for i in range(5):
             rx = np.clip(X + i - 2, 0, W - 1)
-            np.add.at(out, (ry[:, None], rx[None, :]), (_BINOM[j] * _BINOM[i] / 256.0) * g)
-    return out
+            idx = (ry[:, None] * W + rx[None, :]).ravel()  # the fine pixel each coarse value's tap read
+            wt = _BINOM[j] * _BINOM[i] / 256.0
+            for c in range(gc.shape[2]):
+                out[:, c] += np.bincount(idx, weights=wt * gc[:, :, c].ravel(), minlength=H * W)
+    return out.reshape(tuple(shape))
 
 
 def energy_ms(Ref, Tgt, u, levels: int, lam=0.05, eps=1e-3, grads: bool = True):

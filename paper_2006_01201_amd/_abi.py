@@ -60,6 +60,11 @@ _SIGS = {
     "abf_energy": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp, c_i32,
                            c_vp]),
     "abf_refine_flow": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_f32, c_vp]),
+    "abf_energy_ms_workspace_bytes": (c_sz, [c_vp, c_i32, c_i32, c_i32]),
+    "abf_energy_ms": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp,
+                              c_i32, c_vp]),
+    "abf_refine_flow_ms": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_f32,
+                                   c_vp]),
     "abf_blend_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_i32, c_vp]),
     "abf_blend_asymmetric_f32": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
@@ -259,3 +264,16 @@ def merge_photos(plan, photos, n, H, W, pitch_mask, periodic, canvas, pitch_canv
     st = load().abf_merge_photos(plan, photos, n, H, W, pitch_mask, periodic, canvas, pitch_canvas, spare,
                                  pitch_spare, coverage, boxes, stream)
     return st, [tuple(boxes[4 * i:4 * i + 4]) for i in range(n)]
+
+
+def energy_ms(plan, Ref, Tgt, u, H, W, levels, lam, eps, E, g_u, g_Ref, g_Tgt, deterministic, stream) -> int:
+    return load().abf_energy_ms(plan, Ref, Tgt, u, H, W, levels, lam, eps, E, g_u, g_Ref, g_Tgt, deterministic,
+                                stream)
+
+
+def refine_flow_ms(plan, Ref, Tgt, u, H, W, levels, steps, eta, lam, eps, clip, stream) -> int:
+    return load().abf_refine_flow_ms(plan, Ref, Tgt, u, H, W, levels, steps, eta, lam, eps, clip, stream)
+
+
+def energy_ms_workspace_bytes(plan, H, W, levels) -> int:
+    return load().abf_energy_ms_workspace_bytes(plan, H, W, levels)

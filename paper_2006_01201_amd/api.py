@@ -101,11 +101,21 @@ class Plan:
         nbytes = _abi.workspace_bytes(h)
         if canvas is not None:
             nbytes = max(nbytes, _abi.canvas_workspace_bytes(h, *canvas), _abi.merge_workspace_bytes(h, *canvas))
+        self._bind(nbytes)
+
+    def _bind(self, nbytes: int):
+        """Allocates (torch) and binds a workspace of ``nbytes``."""
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
         self._ws_off = (-base) % 256
-        _abi.check(_abi.bind_workspace(h, base + self._ws_off, nbytes), h, "abf_bind_workspace")
+        _abi.check(_abi.bind_workspace(self.h, base + self._ws_off, nbytes), self.h, "abf_bind_workspace")
         self.workspace_bytes = nbytes
+
+    def _ensure_ms_workspace(self, H: int, W: int, levels: int):
+        need = _abi.energy_ms_workspace_bytes(self.h, H, W, levels)
+        if need > self.workspace_bytes:
+            torch.cuda.current_stream().synchronize()  # the old workspace may still be in use
+            self._bind(need)
 
     def close(self):
         if getattr(self, "h", None):
@@ -246,6 +256,36 @@ class Plan:
         st = _abi.refine_flow(self.h, _f32(ref, (H, W, 3), "ref"), _f32(tgt, (H, W, 3), "tgt"),
                               _f32(u, (H, W, 2), "u"), H, W, steps, eta, lam, eps, clip, _stream())
         _abi.check(st, self.h, "abf_refine_flow")
+        return u
+
+    def energy_ms(self, ref, tgt, u, levels: int, lam: float = 0.05, eps: float = 1e-3, grads: bool = True,
+                  deterministic: bool = False):
+        """The energy summed over ``levels`` levels of a float pyramid of
+        the images and the flow; returns E and, if ``grads``, its gradients
+        with respect to the level-0 u, ref and tgt (pyramid levels built
+        and dropped within the call)."""
+        H, W = u.shape[0], u.shape[1]
+        self._ensure_ms_workspace(H, W, levels)
+        E = torch.empty(1, dtype=torch.float32, device=u.device)
+        gu = torch.empty_like(u) if grads else None
+        gr = torch.empty_like(ref) if grads else None
+        gt = torch.empty_like(tgt) if grads else None
+        st = _abi.energy_ms(self.h, _f32(ref, (H, W, 3), "ref"), _f32(tgt, (H, W, 3), "tgt"),
+                            _f32(u, (H, W, 2), "u"), H, W, levels, lam, eps, E.data_ptr(),
+                            gu.data_ptr() if grads else None, gr.data_ptr() if grads else None,
+                            gt.data_ptr() if grads else None, int(deterministic), _stream())
+        _abi.check(st, self.h, "abf_energy_ms")
+        return (E, gu, gr, gt) if grads else E
+
+    def refine_flow_ms(self, ref, tgt, u, levels: int, steps: int = 20, eta: float = 0.5, lam: float = 0.05,
+                       eps: float = 1e-3, clip: float = 0.25):
+        """``steps`` gradient-descent steps on the multi-level energy, in
+        place on ``u``."""
+        H, W = u.shape[0], u.shape[1]
+        self._ensure_ms_workspace(H, W, levels)
+        st = _abi.refine_flow_ms(self.h, _f32(ref, (H, W, 3), "ref"), _f32(tgt, (H, W, 3), "tgt"),
+                                 _f32(u, (H, W, 2), "u"), H, W, levels, steps, eta, lam, eps, clip, _stream())
+        _abi.check(st, self.h, "abf_refine_flow_ms")
         return u
 
     def refine_strips(self, items, steps: int = 20, eta: float = 0.5, lam: float = 0.05, eps: float = 1e-3,

@@ -431,6 +431,111 @@ __global__ __launch_bounds__(256) void k_copy_back_batch(const RefineDesc *__res
     }
 }
 
+// --- multi-level energy: float pyramid and its adjoint ----------------
+// One level of the float pyramid of a C-channel HWC array: the 5 x 5
+// binomial filter (w_i w_j / 256, w = 1 4 6 4 1) with clamped indices,
+// decimated by 2, times `scale` (1 for images; 1/2 for a flow, whose
+// displacements halve with the pixels). One thread per output pixel.
+__device__ __forceinline__ float binom(int i) { return i == 2 ? 6.f : (i == 1 || i == 3) ? 4.f : 1.f; }
+
+template <int C>
+__global__ __launch_bounds__(256) void k_pyr_down_f32(const float *__restrict__ x, int H, int W, float *__restrict__ y,
+                                                      int h, int w, float scale)
+{
+    const int64_t n = (int64_t)h * w;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int Y = (int)(p / w), X = (int)(p - (int64_t)Y * w);
+        float acc[C] = {};
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            const int r = clampg(2 * Y + j - 2, 0, H - 1);
+            float row[C] = {};
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                const int c0 = clampg(2 * X + i - 2, 0, W - 1);
+                const float wi = binom(i);
+#pragma unroll
+                for (int c = 0; c < C; c++) row[c] = fmaf(wi, gld(x)[C * ((size_t)r * W + c0) + c], row[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < C; c++) acc[c] = fmaf(binom(j), row[c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < C; c++) gst(y)[C * p + c] = acc[c] * (scale / 256.f);
+    }
+}
+
+// The coarse indices X of a fine index x that k_pyr_down_f32's taps reach,
+// with the summed tap weights (clamped taps pile up on the border): at
+// most three, from X in [floor((x - 2) / 2), floor((x + 2) / 2)].
+struct Taps {
+    int n, X[3];
+    float w[3];
+};
+__device__ __forceinline__ Taps adj_taps(int x, int N, int n)
+{
+    Taps t;
+    t.n = 0;
+    const int lo = max(0, (x - 2) >> 1), hi = min(n - 1, (x + 2) >> 1);
+    for (int X = lo; X <= hi; X++) {
+        float s = 0.f;
+#pragma unroll
+        for (int i = 0; i < 5; i++)
+            if (clampg(2 * X + i - 2, 0, N - 1) == x) s += binom(i);
+        if (s != 0.f) {
+            t.X[t.n] = X;
+            t.w[t.n] = s;
+            t.n++;
+        }
+    }
+    return t;
+}
+
+// g += scale * adjoint(k_pyr_down_f32)(G): every fine pixel gathers the
+// coarse values its taps fed, with their weights (the transpose of the
+// filter and decimation). G: h x w x C, g: H x W x C.
+template <int C>
+__global__ __launch_bounds__(256) void k_pyr_adj_add_f32(const float *__restrict__ G, int h, int w,
+                                                         float *__restrict__ g, int H, int W, float scale)
+{
+    const int64_t n = (int64_t)H * W;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const Taps ty = adj_taps(y, H, h), tx = adj_taps(x, W, w);
+        float acc[C] = {};
+        for (int a = 0; a < ty.n; a++) {
+            float row[C] = {};
+            for (int b = 0; b < tx.n; b++) {
+#pragma unroll
+                for (int c = 0; c < C; c++)
+                    row[c] = fmaf(tx.w[b], gld(G)[C * ((size_t)ty.X[a] * w + tx.X[b]) + c], row[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < C; c++) acc[c] = fmaf(ty.w[a], row[c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < C; c++) g[C * p + c] = fmaf(acc[c], scale / 256.f, g[C * p + c]);
+    }
+}
+
+// E = the sum of the n per-level energies (in double)
+__global__ __launch_bounds__(64) void k_sum_levels(const float *__restrict__ El, int n, float *E)
+{
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < n; k++) s += (double)El[k];
+        *E = (float)s;
+    }
+}
+
+// u <- u - clip(eta g, -clip, clip), per component
+__global__ __launch_bounds__(256) void k_clip_step(float *__restrict__ u, const float *__restrict__ g, int64_t n,
+                                                   float eta, float clip)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        u[i] -= fminf(fmaxf(eta * g[i], -clip), clip);
+}
+
 inline int blocks_for(int64_t n, int per = 256, int cap = 65536)
 {
     int64_t b = (n + per - 1) / per;
@@ -460,6 +565,36 @@ hipError_t launch_energy_full(const float *Ref, const float *Tgt, const float *u
     if (g_tgt && fix)
         hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fix, g_tgt, n3, scale,
                            (const uint32_t *)nullptr, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyr_down_f32(const float *x, int C, int H, int W, float *y, float scale, hipStream_t s)
+{
+    const int h = (H + 1) / 2, w = (W + 1) / 2;
+    const dim3 g(blocks_for((int64_t)h * w));
+    if (C == 3) hipLaunchKernelGGL(k_pyr_down_f32<3>, g, dim3(256), 0, s, x, H, W, y, h, w, scale);
+    else hipLaunchKernelGGL(k_pyr_down_f32<2>, g, dim3(256), 0, s, x, H, W, y, h, w, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyr_adj_add_f32(const float *G, int C, int H, int W, float *g, float scale, hipStream_t s)
+{
+    const int h = (H + 1) / 2, w = (W + 1) / 2;
+    const dim3 gr(blocks_for((int64_t)H * W));
+    if (C == 3) hipLaunchKernelGGL(k_pyr_adj_add_f32<3>, gr, dim3(256), 0, s, G, h, w, g, H, W, scale);
+    else hipLaunchKernelGGL(k_pyr_adj_add_f32<2>, gr, dim3(256), 0, s, G, h, w, g, H, W, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_levels(const float *El, int n, float *E, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_levels, dim3(1), dim3(64), 0, s, El, n, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_clip_step(float *u, const float *g, int64_t n, float eta, float clip, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clip_step, dim3(blocks_for(n)), dim3(256), 0, s, u, g, n, eta, clip);
     return hipGetLastError();
 }
 

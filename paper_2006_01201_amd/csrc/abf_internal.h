@@ -140,6 +140,14 @@ hipError_t launch_energy_full(const float *Ref, const float *Tgt, const float *u
 hipError_t launch_energy_step(const float *Ref, const float *Tgt, const float *u_in, float *u_out, int H, int W,
                               float eta, float lambda, float eps, float clip, hipStream_t s);
 hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);
+// multi-level energy: one level of the float pyramid of a C-channel (2 or 3)
+// HWC array, times scale; g += scale * its adjoint applied to G (G holds the
+// coarse level of an H x W array); the sum of per-level energies; the
+// clipped descent update u -= clip(eta g)
+hipError_t launch_pyr_down_f32(const float *x, int C, int H, int W, float *y, float scale, hipStream_t s);
+hipError_t launch_pyr_adj_add_f32(const float *G, int C, int H, int W, float *g, float scale, hipStream_t s);
+hipError_t launch_sum_levels(const float *El, int n, float *E, hipStream_t s);
+hipError_t launch_clip_step(float *u, const float *g, int64_t n, float eta, float clip, hipStream_t s);
 hipError_t launch_blend_f32(const float *L, const float *R, const float *flr, const float *frl, const float *blend,
                             int axis, int H, int W, BlendParams bp, float *F, hipStream_t s);
 hipError_t launch_blend_bwd_full(const float *L, const float *R, const float *flr, const float *frl,

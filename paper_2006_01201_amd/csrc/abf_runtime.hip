@@ -1285,6 +1285,150 @@ abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, f
     return ABF_OK;
 }
 
+// ------------------------------------------------------ multi-level energy
+// Scratch of abf_energy_ms (in the workspace's data region): per level
+// k >= 1 the reduced Ref, Tgt (3 floats per pixel) and u (2) and, with
+// gradients, their gradients (8 floats per pixel); the per-level energies;
+// the energy partials; the fixed-point scatter of level 0's dE/dTgt.
+namespace {
+
+struct MsLayout {
+    int N = 0;
+    int h[kMaxLevels] = {}, w[kMaxLevels] = {};
+    size_t ref[kMaxLevels] = {}, tgt[kMaxLevels] = {}, u[kMaxLevels] = {};
+    size_t gu[kMaxLevels] = {}, gref[kMaxLevels] = {}, gtgt[kMaxLevels] = {};
+    size_t El = 0, partials = 0, fix = 0, gstep = 0, bytes = 0;
+};
+
+MsLayout ms_layout(int H, int W, int N, bool grads, bool fix, bool step)
+{
+    MsLayout L;
+    L.N = N;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b, kAlign);
+        return o;
+    };
+    for (int k = 0; k < N; k++) {
+        L.h[k] = k == 0 ? H : (L.h[k - 1] + 1) / 2;
+        L.w[k] = k == 0 ? W : (L.w[k - 1] + 1) / 2;
+        if (k == 0) continue;
+        const size_t px = (size_t)L.h[k] * L.w[k];
+        L.ref[k] = take(sizeof(float) * 3 * px);
+        L.tgt[k] = take(sizeof(float) * 3 * px);
+        L.u[k] = take(sizeof(float) * 2 * px);
+        if (grads) {
+            L.gu[k] = take(sizeof(float) * 2 * px);
+            L.gref[k] = take(sizeof(float) * 3 * px);
+            L.gtgt[k] = take(sizeof(float) * 3 * px);
+        }
+    }
+    L.El = take(sizeof(float) * (kMaxLevels + 1));  // per level, and the descent's energy
+    L.partials = take(sizeof(double) * (size_t)energy_blocks(H, W));
+    if (fix) L.fix = take(sizeof(unsigned long long) * 3 * (size_t)H * W);
+    if (step) L.gstep = take(sizeof(float) * 2 * (size_t)H * W);
+    L.bytes = off;
+    return L;
+}
+
+// The multi-level energy and, where the gradient pointers are non-null, its
+// gradients at level 0: the pyramids are built in the scratch, each level's
+// energy and gradients computed, and the coarse levels' gradients carried
+// to the finer ones through the pyramid's adjoint (1/2 for the flow),
+// coarsest first.
+abf_status energy_ms_run(abf_plan *plan, const MsLayout &L, uint8_t *scr, const float *Ref, const float *Tgt,
+                         const float *u, float lambda, float eps, float *E, float *g_u, float *g_ref, float *g_tgt,
+                         bool det, hipStream_t s)
+{
+    const int N = L.N;
+    auto F = [&](size_t o) { return reinterpret_cast<float *>(scr + o); };
+    const float *R[kMaxLevels], *T[kMaxLevels], *U[kMaxLevels];
+    R[0] = Ref;
+    T[0] = Tgt;
+    U[0] = u;
+    for (int k = 1; k < N; k++) {
+        HIP_TRY(plan, launch_pyr_down_f32(R[k - 1], 3, L.h[k - 1], L.w[k - 1], F(L.ref[k]), 1.f, s));
+        HIP_TRY(plan, launch_pyr_down_f32(T[k - 1], 3, L.h[k - 1], L.w[k - 1], F(L.tgt[k]), 1.f, s));
+        HIP_TRY(plan, launch_pyr_down_f32(U[k - 1], 2, L.h[k - 1], L.w[k - 1], F(L.u[k]), 0.5f, s));
+        R[k] = F(L.ref[k]);
+        T[k] = F(L.tgt[k]);
+        U[k] = F(L.u[k]);
+    }
+    double *partials = reinterpret_cast<double *>(scr + L.partials);
+    float *El = F(L.El);
+    unsigned long long *fix = det && g_tgt ? reinterpret_cast<unsigned long long *>(scr + L.fix) : nullptr;
+    for (int k = N - 1; k >= 0; k--) {
+        float *gu = k == 0 ? g_u : (g_u ? F(L.gu[k]) : nullptr);
+        float *gr = k == 0 ? g_ref : (g_ref ? F(L.gref[k]) : nullptr);
+        float *gt = k == 0 ? g_tgt : (g_tgt ? F(L.gtgt[k]) : nullptr);
+        HIP_TRY(plan, launch_energy_full(R[k], T[k], U[k], L.h[k], L.w[k], lambda, eps, partials, El + k, gu, gr, gt,
+                                         gt ? fix : nullptr, s));
+        if (k == N - 1) continue;
+        if (gu) HIP_TRY(plan, launch_pyr_adj_add_f32(F(L.gu[k + 1]), 2, L.h[k], L.w[k], gu, 0.5f, s));
+        if (gr) HIP_TRY(plan, launch_pyr_adj_add_f32(F(L.gref[k + 1]), 3, L.h[k], L.w[k], gr, 1.f, s));
+        if (gt) HIP_TRY(plan, launch_pyr_adj_add_f32(F(L.gtgt[k + 1]), 3, L.h[k], L.w[k], gt, 1.f, s));
+    }
+    HIP_TRY(plan, launch_sum_levels(El, N, E, s));
+    return ABF_OK;
+}
+
+}  // namespace
+
+size_t abf_energy_ms_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W, int32_t levels)
+{
+    if (!plan || H < 1 || W < 1 || levels < 1 || levels > kMaxLevels) return 0;
+    // gradients, the deterministic scatter and the descent's gradient: the
+    // most any call of the two entry points takes
+    const size_t need = plan->hdr_cap + ms_layout(H, W, levels, true, true, true).bytes;
+    const size_t base = abf_workspace_bytes(plan);
+    return need > base ? need : base;
+}
+
+abf_status abf_energy_ms(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H, int32_t W,
+                         int32_t levels, float lambda, float eps, float *E_dev, float *g_u, float *g_Ref, float *g_Tgt,
+                         int32_t deterministic, void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!Ref || !Tgt || !u || !E_dev) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (levels < 1 || levels > kMaxLevels) return fail(plan, ABF_E_INVALID, "levels %d (1..%d)", levels, kMaxLevels);
+    if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f))
+        return fail(plan, ABF_E_INVALID, "eps^2 must be a normal float (eps >= 1.1e-19), lambda >= 0");
+    const bool grads = g_u || g_Ref || g_Tgt;
+    const MsLayout L = ms_layout(H, W, levels, grads, deterministic && g_Tgt, false);
+    uint8_t *scr = nullptr;
+    abf_status rc = grad_scratch(plan, L.bytes, &scr);
+    if (rc != ABF_OK) return rc;
+    return energy_ms_run(plan, L, scr, Ref, Tgt, u, lambda, eps, E_dev, g_u, g_Ref, g_Tgt, deterministic != 0,
+                         static_cast<hipStream_t>(hip_stream));
+}
+
+abf_status abf_refine_flow_ms(abf_plan *plan, const float *Ref, const float *Tgt, float *u, int32_t H, int32_t W,
+                              int32_t levels, int32_t steps, float eta, float lambda, float eps, float clip_px,
+                              void *hip_stream)
+{
+    if (!plan) return ABF_E_INVALID;
+    if (!Ref || !Tgt || !u) return fail(plan, ABF_E_INVALID, "null pointer");
+    if (H < 1 || W < 1 || steps < 0) return fail(plan, ABF_E_SHAPE, "size %d x %d, %d steps", H, W, steps);
+    if (levels < 1 || levels > kMaxLevels) return fail(plan, ABF_E_INVALID, "levels %d (1..%d)", levels, kMaxLevels);
+    if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f) || !(clip_px >= 0.f))
+        return fail(plan, ABF_E_INVALID, "bad parameter (eps^2 must be a normal float, lambda and clip >= 0)");
+    const MsLayout L = ms_layout(H, W, levels, true, false, true);
+    uint8_t *scr = nullptr;
+    abf_status rc = grad_scratch(plan, L.bytes, &scr);
+    if (rc != ABF_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    float *g = reinterpret_cast<float *>(scr + L.gstep);
+    float *E = reinterpret_cast<float *>(scr + L.El) + kMaxLevels;  // the slot after the level energies
+    for (int k = 0; k < steps; k++) {
+        rc = energy_ms_run(plan, L, scr, Ref, Tgt, u, lambda, eps, E, g, nullptr, nullptr, false, s);
+        if (rc != ABF_OK) return rc;
+        HIP_TRY(plan, launch_clip_step(u, g, 2 * (int64_t)H * W, eta, clip_px, s));
+    }
+    return ABF_OK;
+}
+
 abf_status abf_blend_asymmetric_f32(abf_plan *plan, const float *L, const float *R, const float *flow_LtoR,
                                     const float *flow_RtoL, const float *blend, int32_t axis, int32_t H, int32_t W,
                                     float *F, void *hip_stream)
