@@ -24,10 +24,14 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p)
     return (__attribute__((address_space(1))) T *)(void *)p;
 }
 
-// Code 1 per pixel. The scalar chain (Blend, displacements, flow
-// magnitudes, softmax exponent difference) is evaluated in double so that
-// no FP32 coordinate or large exponent is formed; bilinear sampling and
-// the composite are FP32.
+// Code 1 per pixel. The displacements and their split into cell and
+// fraction, and the softmax exponents, are evaluated in double, so that no
+// FP32 coordinate or large exponent is formed; the flow magnitudes take a
+// float square root refined by one Newton step in double, the softmax
+// weight a hardware 2^x and reciprocal in float (errors far below the
+// blend tolerance: at most 5e-5 gray levels in a bound study with flows up
+// to 150 px and kSoftmaxSharpness 60 / kFlowMagCoef 80); bilinear sampling
+// and the composite are FP32.
 struct PixBlend {
     int lx, ly, rx, ry;      // integer cell corners of the L and R samples
     float lfx, lfy, rfx, rfy;
@@ -35,6 +39,16 @@ struct PixBlend {
 };
 
 __device__ __forceinline__ float finite0(float v) { return isfinite(v) ? v : 0.f; }
+
+// sqrt(m2) for a double m2 >= 0: float square root s, then
+// s + (m2 - s^2) / (2 s) in double (relative error ~1e-14)
+__device__ __forceinline__ double norm_from_sq(double m2)
+{
+    const float sf = __builtin_amdgcn_sqrtf((float)m2);
+    if (!(sf > 0.f)) return 0.0;
+    const double s = (double)sf;
+    return fma(fma(-s, s, m2), (double)(0.5f * __builtin_amdgcn_rcpf(sf)), s);
+}
 
 // (x, y): the pixel in the crop that the images and flows cover; t: its
 // Blend; p: its index in the flow arrays; inv_ext: 1 / the crop's extent
@@ -63,11 +77,13 @@ __device__ __forceinline__ PixBlend blend_setup(int x, int y, double t, uint32_t
     } else {
         // the exponents in double: with large flows both can be in the
         // hundreds and nearly equal, where FP32 rounding would move F
-        const double mrl = sqrt((double)frx * frx + (double)fry * fry) * inv_ext;
-        const double mlr = sqrt((double)flx * flx + (double)fly * fly) * inv_ext;
+        const double mrl = norm_from_sq((double)frx * frx + (double)fry * fry) * inv_ext;
+        const double mlr = norm_from_sq((double)flx * flx + (double)fly * fly) * inv_ext;
         const double zL = (double)bp.k_sharp * (1.0 - t) * (1.0 + (double)bp.k_flowmag * mrl);
         const double zR = (double)bp.k_sharp * t * (1.0 + (double)bp.k_flowmag * mlr);
-        r.sL = 1.0f / (1.0f + expf((float)(zR - zL)));
+        // 1 / (1 + e^d) with e^d = 2^(d log2 e); e^d = inf gives 0
+        const float e = __builtin_amdgcn_exp2f((float)(zR - zL) * 1.44269504f);
+        r.sL = __builtin_amdgcn_rcpf(1.0f + e);
     }
     return r;
 }
@@ -76,19 +92,24 @@ __device__ __forceinline__ PixBlend blend_setup(int x, int y, double t, uint32_t
 // clamp-to-edge indices. When the two corner pixels of a row are distinct
 // and the dwords around them lie inside the image data, each row's 6
 // bytes come from one aligned dwordx3 load; otherwise byte by byte.
+// Addresses are a uniform base plus 32-bit byte offsets (images up to
+// 4 GiB).
 __device__ __forceinline__ void sample_u8(const uint8_t *img, int pitch, int H, int W, int x0, int y0, float fx,
                                           float fy, float out[3])
 {
-    const uint8_t *ra = img + (size_t)clampi(y0, 0, H - 1) * pitch;
-    const uint8_t *rb = img + (size_t)clampi(y0 + 1, 0, H - 1) * pitch;
+    // offsets from the dword-aligned base below img; data = [lead, end)
+    const uint8_t *base = reinterpret_cast<const uint8_t *>((uintptr_t)img & ~(uintptr_t)3);
+    const uint32_t lead = (uint32_t)((uintptr_t)img & 3);
+    const uint32_t end = lead + (uint32_t)(H - 1) * (uint32_t)pitch + 3u * (uint32_t)W;
+    const uint32_t ra = lead + (uint32_t)clampi(y0, 0, H - 1) * (uint32_t)pitch;
+    const uint32_t rb = lead + (uint32_t)clampi(y0 + 1, 0, H - 1) * (uint32_t)pitch;
     float v[2][6];
-    const uintptr_t lo = (uintptr_t)img, hi = (uintptr_t)(img + (size_t)(H - 1) * pitch + 3 * (size_t)W);
-    const uintptr_t pa = (uintptr_t)(ra + 3 * x0), pb = (uintptr_t)(rb + 3 * x0);
-    const uintptr_t aa = pa & ~(uintptr_t)3, ab = pb & ~(uintptr_t)3;
-    if (x0 >= 0 && x0 + 1 <= W - 1 && aa >= lo && aa + 12 <= hi && ab >= lo && ab + 12 <= hi) {
-        const int s = (int)(pa - aa), t = (int)(pb - ab);
-        const auto qa = reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(aa);
-        const auto qb = reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(ab);
+    const uint32_t pa = ra + 3u * (uint32_t)x0, pb = rb + 3u * (uint32_t)x0;
+    const uint32_t aa = pa & ~3u, ab = pb & ~3u;
+    if (x0 >= 0 && x0 + 1 <= W - 1 && aa >= lead && aa + 12u <= end && ab >= lead && ab + 12u <= end) {
+        const uint32_t s = pa - aa, t = pb - ab;
+        const auto qa = gld(reinterpret_cast<const uint32_t *>(base + aa));
+        const auto qb = gld(reinterpret_cast<const uint32_t *>(base + ab));
         const uint32_t a0 = qa[0], a1 = qa[1], a2 = qa[2], b0 = qb[0], b1 = qb[1], b2 = qb[2];
         const uint32_t ua = __builtin_amdgcn_alignbyte(a1, a0, s), wa = __builtin_amdgcn_alignbyte(a2, a1, s);
         const uint32_t ub = __builtin_amdgcn_alignbyte(b1, b0, t), wb = __builtin_amdgcn_alignbyte(b2, b1, t);
@@ -103,13 +124,14 @@ __device__ __forceinline__ void sample_u8(const uint8_t *img, int pitch, int H, 
             v[1][4 + c] = (float)((wb >> (8 * c)) & 0xffu);
         }
     } else {
-        const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+        const uint32_t xa = 3u * (uint32_t)clampi(x0, 0, W - 1), xb = 3u * (uint32_t)clampi(x0 + 1, 0, W - 1);
+        const auto g = gld(base);
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            v[0][c] = ra[3 * xa + c];
-            v[0][3 + c] = ra[3 * xb + c];
-            v[1][c] = rb[3 * xa + c];
-            v[1][3 + c] = rb[3 * xb + c];
+            v[0][c] = g[ra + xa + c];
+            v[0][3 + c] = g[ra + xb + c];
+            v[1][c] = g[rb + xa + c];
+            v[1][3 + c] = g[rb + xb + c];
         }
     }
 #pragma unroll

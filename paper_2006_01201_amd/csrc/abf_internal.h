@@ -109,7 +109,8 @@ hipError_t launch_prop(const StripLv *lv, Work w, int patch, int steps, int medi
 // refine: interior tiles and, separately, the border pixels
 hipError_t launch_refine(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, int th, int grid, hipStream_t s);
 hipError_t launch_refine_border(const StripLv *lv0, const StripIO *io, Work w, LkParams lk, hipStream_t s);
-hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s);
+// blend: px (1, 2 or 4) pixels per thread, px * kRowTW per tile
+hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int px, int grid, hipStream_t s);
 // classic coarse-to-fine Lucas-Kanade, one level (flow method 1): the
 // border pixels on the refinement's border list of the level and the
 // interior pixels (exact pair sums) on its refinement tiles (th 2 or 4);
@@ -248,6 +249,6 @@ __host__ __device__ inline int tiles_refine_border(int H, int W, int lp)
 {
     return 2 * ceil_div(refine_split(H, W, 1, lp).nbp, kRowTW);
 }
-__host__ __device__ inline int tiles_blend(int H, int W) { return H * ceil_div(W, kRowTW); }
+__host__ __device__ inline int tiles_blend(int H, int W, int px) { return H * ceil_div(W, px * kRowTW); }
 
 }  // namespace abf

@@ -1243,14 +1243,18 @@ __global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(LP <= 2
 }
 
 // ----------------------------------------------------------------- blend
-// One workgroup per segment of kRowTW pixels of a row. The uint8 output of
-// the segment is staged in LDS at the byte alignment of its destination, so
-// that the segment is written with aligned dword stores (bytes only at its
-// two ends).
+// One workgroup per segment of PX * kRowTW pixels of a row (PX pixels per
+// thread, kRowTW apart, so that every pixel's loads are coalesced across
+// the workgroup and a thread has PX pixels' loads to overlap). The uint8
+// output of the segment is staged in LDS at the byte alignment of its
+// destination, so that the segment is written with aligned dword stores
+// (bytes only at its two ends).
+template <int PX>
 __global__ __launch_bounds__(kRowTW) void k_blend(const StripIO *__restrict__ io, const int32_t *__restrict__ prefix,
                                                   int n, int total, BlendParams bp)
 {
-    __shared__ uint32_t stage[(3 * kRowTW + 8) / 4];
+    constexpr int TW = PX * kRowTW;
+    __shared__ uint32_t stage[(3 * TW + 8) / 4];
     uint8_t *sb = reinterpret_cast<uint8_t *>(stage);
     TILE_LOOP(total)
     {
@@ -1258,27 +1262,31 @@ __global__ __launch_bounds__(kRowTW) void k_blend(const StripIO *__restrict__ io
         const int local = t - prefix[s];
         const StripIO &o = io[s];
         const int W = o.W, H = o.H;
-        const int segs = ceil_div(W, kRowTW);
+        const int segs = ceil_div(W, TW);
         const int y = local / segs;
-        const int xs = (local - y * segs) * kRowTW;
-        const int npx = min(kRowTW, W - xs);
-        const int x = xs + (int)threadIdx.x;
+        const int xs = (local - y * segs) * TW;
+        const int npx = min(TW, W - xs);
         uint8_t *const seg = o.F + (size_t)y * o.pitchF + 3 * (size_t)xs;  // first output byte of the segment
         const int off = (int)((uintptr_t)seg & 3);
-        if (x < W) {
-            const uint32_t p = (uint32_t)(y * W + x);
-            const double bl = o.blend ? (double)gld(o.blend)[p] : (double)((o.axis == 0 ? x : y) + 1) * o.inv_ext1;
-            const PixBlend pb = blend_setup(x, y, bl, p, o.inv_ext, o.flow[0], o.flow[1], bp);
-            float cl[3], cr[3];
-            sample_u8(o.L, o.pitchL, H, W, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
-            sample_u8(o.R, o.pitchR, H, W, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
-            const float sR = 1.0f - pb.sL;
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const float f = pb.sL * cl[c] + sR * cr[c];
-                const float r = floorf(f + 0.5f);
-                sb[off + 3 * threadIdx.x + c] = (uint8_t)fminf(fmaxf(r, 0.f), 255.f);
-                if (o.Ff32) gst(o.Ff32)[3 * ((size_t)y * W + x) + c] = f;
+        for (int k = 0; k < PX; k++) {
+            const int i = k * kRowTW + (int)threadIdx.x, x = xs + i;
+            if (x < W) {
+                const uint32_t p = (uint32_t)(y * W + x);
+                const double bl =
+                    o.blend ? (double)gld(o.blend)[p] : (double)((o.axis == 0 ? x : y) + 1) * o.inv_ext1;
+                const PixBlend pb = blend_setup(x, y, bl, p, o.inv_ext, o.flow[0], o.flow[1], bp);
+                float cl[3], cr[3];
+                sample_u8(o.L, o.pitchL, H, W, pb.lx, pb.ly, pb.lfx, pb.lfy, cl);
+                sample_u8(o.R, o.pitchR, H, W, pb.rx, pb.ry, pb.rfx, pb.rfy, cr);
+                const float sR = 1.0f - pb.sL;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const float f = pb.sL * cl[c] + sR * cr[c];
+                    const float r = floorf(f + 0.5f);
+                    sb[off + 3 * i + c] = (uint8_t)fminf(fmaxf(r, 0.f), 255.f);
+                    if (o.Ff32) gst(o.Ff32)[3 * ((size_t)y * W + x) + c] = f;
+                }
             }
         }
         __syncthreads();
@@ -1457,9 +1465,15 @@ hipError_t launch_lk_interior(const StripLv *lv, const StripLv *lvc, const Strip
     return lk_interior_th<3>(lv, lvc, io, w, lk, th, grid, level0, s);
 }
 
-hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int grid, hipStream_t s)
+hipError_t launch_blend(const StripIO *io, Work w, BlendParams bp, int px, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_blend, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, w.prefix, w.n, w.total, bp);
+    const dim3 g(grid_for(w.total, grid)), b(kRowTW);
+    switch (px) {
+    case 1: hipLaunchKernelGGL(k_blend<1>, g, b, 0, s, io, w.prefix, w.n, w.total, bp); break;
+    case 2: hipLaunchKernelGGL(k_blend<2>, g, b, 0, s, io, w.prefix, w.n, w.total, bp); break;
+    case 4: hipLaunchKernelGGL(k_blend<4>, g, b, 0, s, io, w.prefix, w.n, w.total, bp); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -152,6 +152,7 @@ bool valid_th(int stage, int th)
     case ST_SEARCH: return th == 1 || th == 2 || th == 4 || th == 8;
     case ST_PROP: return th == 16 || th == 32;
     case ST_REFINE: return th == 2 || th == 4;
+    case ST_BLEND: return th == 1 || th == 2 || th == 4;  // pixels per thread
     default: return th == 4;
     }
 }
@@ -239,7 +240,7 @@ int stage_tiles(const abf_plan *pl, int stage, int cls, int H, int W)
     case ST_PROP: return tiles_prop(H, W, th, pl->p.prop_steps + pl->p.median);
     case ST_REFINE: return tiles_refine(H, W, th, pl->p.lk_patch);
     case LIST_REFINE_BORDER: return tiles_refine_border(H, W, pl->p.lk_patch);
-    default: return tiles_blend(H, W);
+    default: return tiles_blend(H, W, th);
     }
 }
 
@@ -508,7 +509,9 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
     }
     if (blend) {
         BlendParams bp{p.k_sharp, p.k_flowmag, p.blend_mode};
-        TIMED(ST_BLEND, 0, launch_blend(io, work(ST_BLEND, 0), bp, grid_of(pl, ST_BLEND, b.cls[0]), s));
+        TIMED(ST_BLEND, 0,
+              launch_blend(io, work(ST_BLEND, 0), bp, pl->launch[ST_BLEND][b.cls[0]].tile_h,
+                           grid_of(pl, ST_BLEND, b.cls[0]), s));
     }
 #undef TIMED
     return ABF_OK;
