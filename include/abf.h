@@ -408,9 +408,12 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
 /* ------------------------------------------------------------------ */
 /* Autotuning of launch shapes (never of results): times the candidate
  * tile heights and persistent grid sizes of each stage on the batch
- * `strips` and keeps the fastest per (stage, level-size class). Writes
- * the choice to the JSON file named by the ABF_TUNE_CACHE environment
- * variable if set. Runs synchronously. */
+ * `strips` and keeps the fastest per (stage, level-size class). Each
+ * candidate is timed by event pairs around the launches of that stage and
+ * class alone (best of three eager passes after a warm-up pass); classes
+ * with no launch in the batch keep their shapes. Writes the choice to the
+ * JSON file named by the ABF_TUNE_CACHE environment variable if set. Runs
+ * synchronously. */
 abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hip_stream);
 
 /* Current launch choice, for tests: stage 0..5 (luma, pyramid, search,

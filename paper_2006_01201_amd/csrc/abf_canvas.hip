@@ -351,12 +351,16 @@ __global__ __launch_bounds__(256) void k_canvas_dist(CanvasGeom a, float *blend,
 // ------------------------------------------------------------ overlap box
 // One workgroup per row: the extent {x0, x1} of the row's Area3 pixels
 // ({INT_MAX, -1} if none) into part[2 y], part[2 y + 1]. Each thread reads 16 consecutive
-// columns of both masks with all loads in flight at once.
+// columns of both masks with all loads in flight at once. With `occ` (a
+// periodic canvas) the first workgroup also clears the nw column-occupancy
+// words that k_box_cols then fills.
 __global__ __launch_bounds__(kCanvasThreads) void k_box_rows(const uint8_t *mL, const uint8_t *mR, int pitchM, int W,
-                                                             int32_t *part)
+                                                             int32_t *part, uint32_t *occ, int nw)
 {
     __shared__ int32_t s[2];
     const int y = blockIdx.x;
+    if (occ && y == 0)
+        for (int i = threadIdx.x; i < nw; i += kCanvasThreads) gst(occ)[i] = 0u;
     if (threadIdx.x == 0) {
         s[0] = 0x7fffffff;
         s[1] = -1;
@@ -384,23 +388,24 @@ __global__ __launch_bounds__(kCanvasThreads) void k_box_rows(const uint8_t *mL, 
 }
 
 // Column occupancy of a periodic canvas: bit x of occ is set iff column x
-// holds an Area3 pixel. One thread per column walks the rows (consecutive
-// columns per wave: coalesced), stopping at the first Area3 pixel; a wave's
-// 64 bits are one ballot.
+// holds an Area3 pixel. A thread takes one 16-column chunk over a band of
+// kBoxBand rows (grid: chunks x bands) and ORs the chunk's Area3 bits of
+// those rows into its occupancy word (cleared by k_box_rows).
+constexpr int kBoxBand = 32;
 __global__ __launch_bounds__(256) void k_box_cols(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W,
                                                   uint32_t *occ)
 {
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    bool o = false;
-    if (x < W)
-        for (int y = 0; y < H && !o; y++) {
-            const size_t p = (size_t)y * pitchM + x;
-            o = gld(mL)[p] != 0 && gld(mR)[p] != 0;
-        }
-    const uint64_t b = __ballot(o);
-    const int lane = threadIdx.x & 63, w0 = (x - lane) >> 5, nw = (W + 31) >> 5;
-    if (lane == 0 && w0 < nw) gst(occ)[w0] = (uint32_t)b;
-    if (lane == 32 && w0 + 1 < nw) gst(occ)[w0 + 1] = (uint32_t)(b >> 32);
+    const int x0 = (blockIdx.x * 256 + (int)threadIdx.x) * kCanvasChunk;
+    if (x0 >= W) return;
+    const int n = min(kCanvasChunk, W - x0);
+    const int y0 = blockIdx.y * kBoxBand, y1 = min(H, y0 + kBoxBand);
+    uint32_t m = 0;
+    for (int y = y0; y < y1; y++) {
+        const size_t r = (size_t)y * pitchM;
+        m |= chunk_nz(mL + r, x0, n) & chunk_nz(mR + r, x0, n);
+    }
+    static_assert(32 % kCanvasChunk == 0, "a chunk lies in one occupancy word");
+    if (m) atomicOr(occ + (x0 >> 5), m << (x0 & 31));
 }
 
 // Zero runs of one occupancy word (bits [0, vb) valid, column base): the
@@ -628,8 +633,11 @@ hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, 
                               int32_t *part, int32_t *box, hipStream_t s)
 {
     uint32_t *occ = periodic ? reinterpret_cast<uint32_t *>(part + 2 * (size_t)H) : nullptr;
-    hipLaunchKernelGGL(k_box_rows, dim3(H), dim3(kCanvasThreads), 0, s, mL, mR, pitchM, W, part);
-    if (occ) hipLaunchKernelGGL(k_box_cols, dim3(ceil_div(W, 256)), dim3(256), 0, s, mL, mR, pitchM, H, W, occ);
+    hipLaunchKernelGGL(k_box_rows, dim3(H), dim3(kCanvasThreads), 0, s, mL, mR, pitchM, W, part, occ,
+                       ceil_div(W, 32));
+    if (occ)
+        hipLaunchKernelGGL(k_box_cols, dim3(ceil_div(W, 256 * kCanvasChunk), ceil_div(H, kBoxBand)), dim3(256), 0, s,
+                           mL, mR, pitchM, H, W, occ);
     hipLaunchKernelGGL(k_box_fin, dim3(1), dim3(1024), 0, s, part, H, W, occ, box);
     return hipGetLastError();
 }

@@ -887,56 +887,88 @@ abf_status abf_set_launch(abf_plan *plan, int32_t stage, int32_t size_class, int
     return ABF_OK;
 }
 
+// Size class of the launch that an event pair of enqueue() times, or -1
+// when that launch takes no shape from the launch table (the refinement's
+// border launch, the classic Lucas-Kanade border launches in the search
+// slots).
+int slot_class(const abf_plan *pl, const Batch &b, int stage, int k)
+{
+    switch (stage) {
+    case ST_LUMA:
+    case ST_BLEND: return b.cls[0];
+    case ST_REFINE: return pl->p.flow_method == 1 ? b.cls[k] : (k == 0 ? b.cls[0] : -1);
+    case ST_SEARCH: return pl->p.flow_method == 1 ? -1 : b.cls[k];
+    default: return b.cls[k];
+    }
+}
+
 abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hip_stream)
 {
     if (!plan || !strips || n < 1) return ABF_E_INVALID;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    hipEvent_t e0, e1;
-    HIP_TRY(plan, hipEventCreate(&e0));
-    HIP_TRY(plan, hipEventCreate(&e1));
-    auto timed = [&](float &ms) -> abf_status {
-        abf_status rc = run(plan, strips, n, true, true, false, s);  // warm
+    // One eager pass with an event pair around every launch; `ms` receives
+    // the summed time of the launches of (stage, size class) `want`, or,
+    // with want.first < 0, `seen` the (stage, class) pairs that occur.
+    bool seen[kStages][kSizeClasses] = {};
+    auto pass = [&](std::pair<int, int> want, float &ms) -> abf_status {
+        Batch b;  // the tile lists depend on the launch table
+        abf_status rc = build_batch(plan, strips, n, true, true, b);
         if (rc != ABF_OK) return rc;
-        float best = 1e30f;
-        for (int r = 0; r < 3; r++) {
-            HIP_TRY(plan, hipEventRecord(e0, s));
-            rc = run(plan, strips, n, true, true, false, s);
-            if (rc != ABF_OK) return rc;
-            HIP_TRY(plan, hipEventRecord(e1, s));
-            HIP_TRY(plan, hipEventSynchronize(e1));
-            float t = 0;
-            HIP_TRY(plan, hipEventElapsedTime(&t, e0, e1));
-            best = std::min(best, t);
+        rc = upload(plan, b, s);
+        if (rc != ABF_OK) return rc;
+        Prof prof;
+        rc = enqueue(plan, b, true, true, s, &prof);
+        const hipError_t e = hipStreamSynchronize(s);
+        ms = 0.f;
+        for (size_t i = 0; i + 1 < prof.ev.size() && rc == ABF_OK && e == hipSuccess; i += 2) {
+            const int stg = prof.tag[i / 2].first, c = slot_class(plan, b, stg, prof.tag[i / 2].second);
+            if (c < 0) continue;
+            if (want.first < 0) {
+                seen[stg][c] = true;
+                continue;
+            }
+            float t = 0.f;
+            if (stg == want.first && c == want.second &&
+                hipEventElapsedTime(&t, prof.ev[i], prof.ev[i + 1]) == hipSuccess)
+                ms += t;
         }
-        ms = best;
+        for (hipEvent_t ev : prof.ev) (void)hipEventDestroy(ev);
+        if (rc != ABF_OK) return rc;
+        if (e != hipSuccess) return hip_fail(plan, e, "hipStreamSynchronize");
+        plan->lv_host = b.lv;
+        plan->last_n = n;
         return ABF_OK;
     };
+    float unused = 0.f;
+    abf_status rc = pass({-1, -1}, unused);
     static const int grids[] = {0, 1, 2, 4, 8};
-    abf_status rc = ABF_OK;
     for (int stage = 0; stage < kStages && rc == ABF_OK; stage++)
         for (int c = 0; c < kSizeClasses && rc == ABF_OK; c++) {
-            std::vector<int> ths;
-            for (int th : {1, 2, 4, 8, 16, 32})
-                if (valid_th(stage, th)) ths.push_back(th);
+            if (!seen[stage][c]) continue;
             Launch best = plan->launch[stage][c];
             float best_ms = 1e30f;
-            for (int th : ths)
+            for (int th : {1, 2, 4, 8, 16, 32}) {
+                if (!valid_th(stage, th)) continue;
                 for (int g : grids) {
                     plan->launch[stage][c] = {th, g};
-                    float ms = 0;
-                    rc = timed(ms);
+                    float ms = 1e30f;
+                    for (int r = 0; r < 4 && rc == ABF_OK; r++) {  // the first pass warms up
+                        float t = 0.f;
+                        rc = pass({stage, c}, t);
+                        if (r > 0) ms = std::min(ms, t);
+                    }
                     if (rc != ABF_OK) break;
                     if (ms < best_ms * 0.99f) {
                         best_ms = ms;
                         best = plan->launch[stage][c];
                     }
                 }
+                if (rc != ABF_OK) break;
+            }
             plan->launch[stage][c] = best;
             logf(1, "tune: stage %d, size class %d: tile height %d, grid %d (%.4f ms)", stage, c, best.tile_h,
                  best.grid, best_ms);
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc != ABF_OK) return rc;
     const char *cache = getenv("ABF_TUNE_CACHE");
     if (cache) {
