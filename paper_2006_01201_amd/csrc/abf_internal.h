@@ -219,7 +219,7 @@ __host__ __device__ inline int tiles_pyr(int H, int W)
 __host__ __device__ inline int tiles_search(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kSearchTW); }
 // fused propagation (T steps + median, halo h = T + M <= kPropMaxHalo):
 // one wave per tile of (kPropRW - 2h) x th outputs over a
-// kPropRW x (th + 2h) region held in registers (th = 16 or 32)
+// kPropRW x (th + 2h) region held in registers (th = 8, 16 or 32)
 constexpr int kPropRW = 64;
 constexpr int kPropMaxHalo = 5;
 __host__ __device__ inline int tiles_prop(int H, int W, int th, int h)

@@ -150,7 +150,7 @@ bool valid_th(int stage, int th)
 {
     switch (stage) {
     case ST_SEARCH: return th == 1 || th == 2 || th == 4 || th == 8;
-    case ST_PROP: return th == 16 || th == 32;
+    case ST_PROP: return th == 8 || th == 16 || th == 32;
     case ST_REFINE: return th == 2 || th == 4;
     case ST_BLEND: return th == 1 || th == 2 || th == 4;  // pixels per thread
     default: return th == 4;
