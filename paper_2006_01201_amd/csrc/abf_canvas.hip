@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kCanvasThreads) void k_box_rows(const uint8_t *mL, 
 // holds an Area3 pixel. A thread takes one 16-column chunk over a band of
 // kBoxBand rows (grid: chunks x bands) and ORs the chunk's Area3 bits of
 // those rows into its occupancy word (cleared by k_box_rows).
-constexpr int kBoxBand = 32;
+constexpr int kBoxBand = 8;
 __global__ __launch_bounds__(256) void k_box_cols(const uint8_t *mL, const uint8_t *mR, int pitchM, int H, int W,
                                                   uint32_t *occ)
 {
