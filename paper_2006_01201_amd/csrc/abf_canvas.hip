@@ -185,9 +185,9 @@ __global__ __launch_bounds__(kCanvasThreads) void k_canvas_rows(CanvasGeom a)
 }
 
 // Minimum of g over each block of kCanvasBH rows of a column, per area.
-__global__ __launch_bounds__(kCanvasThreads) void k_canvas_colmin(CanvasGeom a)
+__global__ __launch_bounds__(kCanvasThreads) void k_canvas_colmin(CanvasGeom a, int x0)
 {
-    const int x = blockIdx.x * kCanvasThreads + threadIdx.x, b = blockIdx.y;
+    const int x = x0 + blockIdx.x * kCanvasThreads + threadIdx.x, b = blockIdx.y;
     if (x >= a.W) return;
     const int r0 = b * kCanvasBH, r1 = min(r0 + kCanvasBH, a.H);
     uint32_t m1 = kInf16, m2 = kInf16;
@@ -247,14 +247,14 @@ __device__ __forceinline__ void eval_rows(const uint32_t (*rows)[64], int lane, 
 }
 
 __global__ __launch_bounds__(256) void k_canvas_dist(CanvasGeom a, float *blend, int pitchB, int32_t *d1, int32_t *d2,
-                                                     int pitchD)
+                                                     int pitchD, int tx0, int tb0)
 {
     __shared__ uint32_t own[kCanvasBH][64];
     __shared__ uint32_t nbr[2][kCanvasBH][64];  // staged block above / below
     __shared__ uint32_t nbm[2][64];             // and its block minima
     __shared__ uint32_t flags[2][4];            // by window parity: a window may end without a barrier
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int x = blockIdx.x * 64 + lane, b0 = blockIdx.y, y0 = b0 * kCanvasBH;
+    const int x = (tx0 + (int)blockIdx.x) * 64 + lane, b0 = tb0 + (int)blockIdx.y, y0 = b0 * kCanvasBH;
     const int H = a.H, nb = ceil_div(H, kCanvasBH);
     const bool inx = x < a.W;
     const bool all = d1 != nullptr;
@@ -651,13 +651,24 @@ hipError_t launch_gather_box(const uint8_t *img, int pitch, int W, int bx, int b
 }
 
 hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int32_t *d1, int32_t *d2, int pitchD,
-                              hipStream_t s)
+                              const int32_t *box, hipStream_t s)
 {
+    // tiles of 64 columns x kCanvasBH rows: all of them, or those that meet
+    // the box (every column of a box across the wrap of a periodic canvas)
+    int tx0 = 0, ntx = ceil_div(a.W, 64), tb0 = 0, ntb = ceil_div(a.H, kCanvasBH);
+    if (box && box[2] > 0 && box[3] > 0) {
+        if (box[0] + box[2] <= a.W) {
+            tx0 = box[0] / 64;
+            ntx = ceil_div(box[0] + box[2], 64) - tx0;
+        }
+        tb0 = box[1] / kCanvasBH;
+        ntb = ceil_div(box[1] + box[3], kCanvasBH) - tb0;
+    }
     hipLaunchKernelGGL(k_canvas_rows, dim3(a.H), dim3(kCanvasThreads), 0, s, a);
-    hipLaunchKernelGGL(k_canvas_colmin, dim3(ceil_div(a.W, kCanvasThreads), ceil_div(a.H, kCanvasBH)),
-                       dim3(kCanvasThreads), 0, s, a);
-    hipLaunchKernelGGL(k_canvas_dist, dim3(ceil_div(a.W, 64), ceil_div(a.H, kCanvasBH)), dim3(256), 0, s, a, blend,
-                       pitchB, d1, d2, pitchD);
+    hipLaunchKernelGGL(k_canvas_colmin, dim3(ceil_div(min(ntx * 64, a.W - tx0 * 64), kCanvasThreads),
+                                             ceil_div(a.H, kCanvasBH)),
+                       dim3(kCanvasThreads), 0, s, a, tx0 * 64);
+    hipLaunchKernelGGL(k_canvas_dist, dim3(ntx, ntb), dim3(256), 0, s, a, blend, pitchB, d1, d2, pitchD, tx0, tb0);
     return hipGetLastError();
 }
 

@@ -202,8 +202,12 @@ hipError_t launch_overlap_box(const uint8_t *mL, const uint8_t *mR, int pitchM, 
 // contiguous bh x bw x 3 buffer (rows pitchD bytes apart)
 hipError_t launch_gather_box(const uint8_t *img, int pitch, int W, int bx, int by, int bw, int bh, uint8_t *dst,
                              int pitchD, hipStream_t s);
+// eq. (1) distances and Blend over the canvas, or (box = {x, y, w, h}, not
+// null) over the 64 x 16 tiles that meet the box (all columns if the box
+// crosses the wrap of a periodic canvas): the composite reads Blend only
+// inside the box
 hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int32_t *d1, int32_t *d2, int pitchD,
-                              hipStream_t s);
+                              const int32_t *box, hipStream_t s);
 hipError_t launch_composite(const CompositeArgs &o, BlendParams bp, hipStream_t s);
 hipError_t launch_photo_init(const uint8_t *img, int pitchI, const uint8_t *mask, int pitchM, int H, int W,
                              uint8_t *dst, int pitchD, uint8_t *cov, int pitchC, hipStream_t s);

@@ -1077,7 +1077,7 @@ abf_status abf_canvas_blend(abf_plan *plan, const uint8_t *mask_L, const uint8_t
     float *bmap = nullptr;
     abf_status rc = canvas_setup(plan, mask_L, mask_R, H, W, pitch_mask, periodic != 0, g, &bmap);
     if (rc != ABF_OK) return rc;
-    HIP_TRY(plan, launch_canvas_dist(g, blend, pitch_blend, dist2_1, dist2_2, pitch_dist,
+    HIP_TRY(plan, launch_canvas_dist(g, blend, pitch_blend, dist2_1, dist2_2, pitch_dist, nullptr,
                                      static_cast<hipStream_t>(hip_stream)));
     return ABF_OK;
 }
@@ -1111,7 +1111,7 @@ abf_status abf_composite_canvas(abf_plan *plan, const uint8_t *L, const uint8_t 
     o.blend = blend;
     o.pitchB = pitch_blend;
     if (!blend && any) {
-        HIP_TRY(plan, launch_canvas_dist(g, bmap, g.gpitch, nullptr, nullptr, 0, s));
+        HIP_TRY(plan, launch_canvas_dist(g, bmap, g.gpitch, nullptr, nullptr, 0, box, s));
         o.blend = bmap;
         o.pitchB = g.gpitch;
     }
@@ -1249,7 +1249,7 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
         float *bmap = nullptr;
         abf_status rc = canvas_setup(plan, mL, mR, H, W, pitch_mask, periodic != 0, g, &bmap);
         if (rc != ABF_OK) return rc;
-        if (any) HIP_TRY(plan, launch_canvas_dist(g, bmap, g.gpitch, nullptr, nullptr, 0, s));
+        if (any) HIP_TRY(plan, launch_canvas_dist(g, bmap, g.gpitch, nullptr, nullptr, 0, hb, s));
         CompositeArgs o{};
         o.L = L;
         o.R = R;
