@@ -206,7 +206,9 @@ abf_status abf_workspace_view(const abf_plan *plan, int32_t kind, int32_t strip,
  *   E = sum_p sum_c rho(Tgt~_c(p + u(p)) - Ref_c(p))
  *     + lambda * sum_p sum_m sqrt((dx u_m)^2 + (dy u_m)^2 + eps^2),
  * rho(r) = sqrt(r^2 + eps^2), Tgt~ bilinear with clamped indices, forward
- * differences that are 0 at the last column / row.
+ * differences that are 0 at the last column / row. Sizes: 1 <= H, W and
+ * 3 H W < 2^32 for this and every float-image call below (ABF_E_SHAPE
+ * otherwise).
  * abf_energy writes E (one float, device) and, where non-null, dE/du,
  * dE/dRef, dE/dTgt (device, same shapes as u, Ref, Tgt; overwritten). The
  * derivative at an integer sample position is the right-hand one.

@@ -59,16 +59,49 @@ __device__ __forceinline__ Bil bil_at(int x, int y, float ux, float uy, int H, i
     return b;
 }
 
-// value and position derivatives of channel c of a float HWC image
+// value and position derivatives of channel c of a float HWC image (32-bit
+// element offsets: the entry points admit images of 3 H W < 2^32 floats)
 __device__ __forceinline__ void bil_eval(const float *img, int W, const Bil &b, int c, float &v, float &dX, float &dY)
 {
     const auto g = gld(img);
-    const float v00 = g[3 * ((size_t)b.ya * W + b.xa) + c], v01 = g[3 * ((size_t)b.ya * W + b.xb) + c];
-    const float v10 = g[3 * ((size_t)b.yb * W + b.xa) + c], v11 = g[3 * ((size_t)b.yb * W + b.xb) + c];
+    const uint32_t ra = (uint32_t)b.ya * (uint32_t)W, rb = (uint32_t)b.yb * (uint32_t)W;
+    const uint32_t xa = (uint32_t)b.xa, xb = (uint32_t)b.xb, cc = (uint32_t)c;
+    const float v00 = g[3u * (ra + xa) + cc], v01 = g[3u * (ra + xb) + cc];
+    const float v10 = g[3u * (rb + xa) + cc], v11 = g[3u * (rb + xb) + cc];
     const float top = v00 + b.fx * (v01 - v00), bot = v10 + b.fx * (v11 - v10);
     v = top + b.fy * (bot - top);
     dX = (1.f - b.fy) * (v01 - v00) + b.fy * (v11 - v10);
     dY = (1.f - b.fx) * (v10 - v00) + b.fx * (v11 - v01);
+}
+
+// bil_eval for all three channels: each corner's three floats from one
+// base address (merged loads)
+__device__ __forceinline__ void bil_eval3(const float *img, int W, const Bil &b, float (&v)[3], float (&dX)[3],
+                                          float (&dY)[3])
+{
+    const auto g = gld(img);
+    const uint32_t ra = (uint32_t)b.ya * (uint32_t)W, rb = (uint32_t)b.yb * (uint32_t)W;
+    const auto p00 = g + 3u * (ra + (uint32_t)b.xa), p01 = g + 3u * (ra + (uint32_t)b.xb);
+    const auto p10 = g + 3u * (rb + (uint32_t)b.xa), p11 = g + 3u * (rb + (uint32_t)b.xb);
+    float c00[3], c01[3], c10[3], c11[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        c00[c] = p00[c];
+        c01[c] = p01[c];
+        c10[c] = p10[c];
+        c11[c] = p11[c];
+    }
+    // d/dX = the row differences lerped by fy; d/dY = bot - top, which
+    // equals (1 - fx)(v10 - v00) + fx (v11 - v01)
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const float d0 = c01[c] - c00[c], d1 = c11[c] - c10[c];
+        const float top = fmaf(b.fx, d0, c00[c]), bot = fmaf(b.fx, d1, c10[c]);
+        const float bt = bot - top;
+        v[c] = fmaf(b.fy, bt, top);
+        dX[c] = fmaf(b.fy, d1 - d0, d0);
+        dY[c] = bt;
+    }
 }
 
 __device__ __forceinline__ void bil_scatter(float *g, unsigned long long *gfix, double scale, int W, const Bil &b,
@@ -78,18 +111,6 @@ __device__ __forceinline__ void bil_scatter(float *g, unsigned long long *gfix, 
     scatter_add(g, gfix, scale, 3 * ((size_t)b.ya * W + b.xb) + c, w * (1.f - b.fy) * b.fx);
     scatter_add(g, gfix, scale, 3 * ((size_t)b.yb * W + b.xa) + c, w * b.fy * (1.f - b.fx));
     scatter_add(g, gfix, scale, 3 * ((size_t)b.yb * W + b.xb) + c, w * b.fy * b.fx);
-}
-
-// TV term at q for component m: s(q)^2 and the forward differences
-__device__ __forceinline__ float tv_s2(const float *u, int H, int W, int x, int y, int m, float eps, float &dx,
-                                       float &dy)
-{
-    const auto g = gld(u);
-    const size_t q = (size_t)y * W + x;
-    const float c = g[2 * q + m];
-    dx = x < W - 1 ? g[2 * (q + 1) + m] - c : 0.f;
-    dy = y < H - 1 ? g[2 * (q + W) + m] - c : 0.f;
-    return dx * dx + dy * dy + eps * eps;
 }
 
 // 1 / sqrt(v) for v >= FLT_MIN (v_rsq_f32, within 1 ulp; the entry points
@@ -102,40 +123,58 @@ __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v);
 // flow gradient and the image gradients use this one form)
 __device__ __forceinline__ float charb_d(float r, float eps) { return r * rsq(r * r + eps * eps); }
 
-// dE/du at p (photometric + lambda * TV); also returns the pixel's energy
+// dE/du at p (photometric + lambda * TV); also returns the pixel's energy.
+// The flow is read as float pairs at p and at its neighbours p +- 1,
+// p +- W, p - 1 + W and p + 1 - W (32-bit element offsets: 3 H W < 2^32).
 __device__ __forceinline__ void grad_u_at(const float *Ref, const float *Tgt, const float *u, int H, int W, int x,
                                           int y, float lambda, float eps, float &gx, float &gy, double &e)
 {
-    const size_t p = (size_t)y * W + x;
-    const auto gu = gld(u), gr = gld(Ref);
-    const float ux = gu[2 * p], uy = gu[2 * p + 1];
-    const Bil b = bil_at(x, y, ux, uy, H, W);
+    const uint32_t p = (uint32_t)y * (uint32_t)W + (uint32_t)x, w = (uint32_t)W;
+    const auto gr = gld(Ref);
+    const auto g2 = gld(reinterpret_cast<const uint64_t *>(u));
+    auto pair = [&](uint32_t i) {
+        const uint64_t v = g2[i];
+        return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+    };
+    const float2 c = pair(p);
+    const Bil b = bil_at(x, y, c.x, c.y, H, W);
     gx = gy = 0.f;
     e = 0.0;
+    float v[3], dX[3], dY[3];
+    bil_eval3(Tgt, W, b, v, dX, dY);
+    const auto rp = gr + 3u * p;
+    const float rv[3] = {rp[0], rp[1], rp[2]};
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        float v, dX, dY;
-        bil_eval(Tgt, W, b, c, v, dX, dY);
-        const float r = v - gr[3 * p + c];
+    for (int k = 0; k < 3; k++) {
+        const float r = v[k] - rv[k];
         const float d = charb_d(r, eps);
         e += sqrtf(r * r + eps * eps);
-        gx = fmaf(d, dX, gx);
-        gy = fmaf(d, dY, gy);
+        gx = fmaf(d, dX[k], gx);
+        gy = fmaf(d, dY[k], gy);
     }
+    // TV: s(q)^2 = dx^2 + dy^2 + eps^2 with forward differences (0 past the
+    // last column / row) at q = p, p - 1 and p - W
+    const bool xr = x < W - 1, yd = y < H - 1, xl = x > 0, yu = y > 0;
+    const float2 rt = xr ? pair(p + 1) : c, dn = yd ? pair(p + w) : c;
+    const float2 lf = xl ? pair(p - 1) : c, ld = xl && yd ? pair(p - 1 + w) : c;
+    const float2 up = yu ? pair(p - w) : c, ur = yu && xr ? pair(p + 1 - w) : c;
 #pragma unroll
     for (int m = 0; m < 2; m++) {
-        float dx, dy;
-        const float s2 = tv_s2(u, H, W, x, y, m, eps, dx, dy);
+        const float cm = m ? c.y : c.x;
+        const float dx = xr ? (m ? rt.y : rt.x) - cm : 0.f, dy = yd ? (m ? dn.y : dn.x) - cm : 0.f;
+        const float s2 = dx * dx + dy * dy + eps * eps;
         e += (double)lambda * sqrtf(s2);
         float g = -(dx + dy) * rsq(s2);
-        if (x > 0) {
-            float ddx, ddy;
-            const float sl2 = tv_s2(u, H, W, x - 1, y, m, eps, ddx, ddy);
+        if (xl) {
+            const float lm = m ? lf.y : lf.x;
+            const float ddx = cm - lm, ddy = yd ? (m ? ld.y : ld.x) - lm : 0.f;
+            const float sl2 = ddx * ddx + ddy * ddy + eps * eps;
             g = fmaf(ddx, rsq(sl2), g);
         }
-        if (y > 0) {
-            float ddx, ddy;
-            const float su2 = tv_s2(u, H, W, x, y - 1, m, eps, ddx, ddy);
+        if (yu) {
+            const float um = m ? up.y : up.x;
+            const float ddx = xr ? (m ? ur.y : ur.x) - um : 0.f, ddy = cm - um;
+            const float su2 = ddx * ddx + ddy * ddy + eps * eps;
             g = fmaf(ddy, rsq(su2), g);
         }
         if (m == 0) gx = fmaf(lambda, g, gx);
@@ -152,10 +191,10 @@ __global__ __launch_bounds__(kEB) void k_energy(const float *__restrict__ Ref, c
                                                 double fix_scale)
 {
     __shared__ double red[kEB];
-    const int64_t n = (int64_t)H * W;
+    const uint32_t n = (uint32_t)H * (uint32_t)W;
     double acc = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * kEB + threadIdx.x; p < n; p += (int64_t)gridDim.x * kEB) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    for (uint32_t p = blockIdx.x * (uint32_t)kEB + threadIdx.x; p < n; p += gridDim.x * (uint32_t)kEB) {
+        const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * (uint32_t)W);
         float gx, gy;
         double e;
         grad_u_at(Ref, Tgt, u, H, W, x, y, lambda, eps, gx, gy, e);
@@ -240,9 +279,9 @@ __global__ __launch_bounds__(256) void k_energy_step(const float *__restrict__ R
                                                      const float *__restrict__ u_in, float *__restrict__ u_out, int H,
                                                      int W, float eta, float lambda, float eps, float clip)
 {
-    const int64_t n = (int64_t)H * W;
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    const uint32_t n = (uint32_t)H * (uint32_t)W;
+    for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n; p += gridDim.x * 256u) {
+        const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * (uint32_t)W);
         float gx, gy;
         double e;
         grad_u_at(Ref, Tgt, u_in, H, W, x, y, lambda, eps, gx, gy, e);
@@ -397,9 +436,9 @@ __global__ __launch_bounds__(256) void k_energy_step_batch(const RefineDesc *__r
             else hi = mid - 1;
         }
         const RefineDesc &r = d[lo];
-        const int64_t p = (int64_t)(t - prefix[lo]) * 256 + threadIdx.x;
-        if (p >= (int64_t)r.H * r.W) continue;
-        const int y = (int)(p / r.W), x = (int)(p - (int64_t)y * r.W);
+        const uint32_t p = (uint32_t)(t - prefix[lo]) * 256u + threadIdx.x;
+        if (p >= (uint32_t)r.H * (uint32_t)r.W) continue;
+        const int y = (int)(p / (uint32_t)r.W), x = (int)(p - (uint32_t)y * (uint32_t)r.W);
         const float *u_in = r.u[in];
         float *u_out = r.u[1 - in];
         float gx, gy;

@@ -1280,13 +1280,19 @@ abf_status abf_merge_photos(abf_plan *plan, const abf_photo *photos, int32_t n, 
     return ABF_OK;
 }
 
+// float images of the descent and Code 1 extensions: 32-bit element offsets
+static bool float_image_ok(int32_t H, int32_t W)
+{
+    return H >= 1 && W >= 1 && 3 * (uint64_t)H * (uint64_t)W <= (uint64_t)UINT32_MAX;
+}
+
 abf_status abf_energy(abf_plan *plan, const float *Ref, const float *Tgt, const float *u, int32_t H, int32_t W,
                       float lambda, float eps, float *E_dev, float *g_u, float *g_Ref, float *g_Tgt,
                       int32_t deterministic, void *hip_stream)
 {
     if (!plan) return ABF_E_INVALID;
     if (!Ref || !Tgt || !u || !E_dev) return fail(plan, ABF_E_INVALID, "null pointer");
-    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (!float_image_ok(H, W)) return fail(plan, ABF_E_SHAPE, "size %d x %d (1 <= H, W; 3 H W < 2^32)", H, W);
     if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f))
         return fail(plan, ABF_E_INVALID, "eps^2 must be a normal float (eps >= 1.1e-19), lambda >= 0");
     const size_t npart = align_up(sizeof(double) * energy_blocks(H, W), kAlign);
@@ -1305,7 +1311,8 @@ abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, f
 {
     if (!plan) return ABF_E_INVALID;
     if (!Ref || !Tgt || !u) return fail(plan, ABF_E_INVALID, "null pointer");
-    if (H < 1 || W < 1 || steps < 0) return fail(plan, ABF_E_SHAPE, "size %d x %d, %d steps", H, W, steps);
+    if (!float_image_ok(H, W) || steps < 0)
+        return fail(plan, ABF_E_SHAPE, "size %d x %d (1 <= H, W; 3 H W < 2^32), %d steps", H, W, steps);
     if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f) || !(clip_px >= 0.f))
         return fail(plan, ABF_E_INVALID, "bad parameter (eps^2 must be a normal float, lambda and clip >= 0)");
     if (!aligned8(u)) return fail(plan, ABF_E_INVALID, "u must be 8-byte aligned");
@@ -1426,7 +1433,7 @@ abf_status abf_energy_ms(abf_plan *plan, const float *Ref, const float *Tgt, con
 {
     if (!plan) return ABF_E_INVALID;
     if (!Ref || !Tgt || !u || !E_dev) return fail(plan, ABF_E_INVALID, "null pointer");
-    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (!float_image_ok(H, W)) return fail(plan, ABF_E_SHAPE, "size %d x %d (1 <= H, W; 3 H W < 2^32)", H, W);
     if (levels < 1 || levels > kMaxLevels) return fail(plan, ABF_E_INVALID, "levels %d (1..%d)", levels, kMaxLevels);
     if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f))
         return fail(plan, ABF_E_INVALID, "eps^2 must be a normal float (eps >= 1.1e-19), lambda >= 0");
@@ -1445,7 +1452,8 @@ abf_status abf_refine_flow_ms(abf_plan *plan, const float *Ref, const float *Tgt
 {
     if (!plan) return ABF_E_INVALID;
     if (!Ref || !Tgt || !u) return fail(plan, ABF_E_INVALID, "null pointer");
-    if (H < 1 || W < 1 || steps < 0) return fail(plan, ABF_E_SHAPE, "size %d x %d, %d steps", H, W, steps);
+    if (!float_image_ok(H, W) || steps < 0)
+        return fail(plan, ABF_E_SHAPE, "size %d x %d (1 <= H, W; 3 H W < 2^32), %d steps", H, W, steps);
     if (levels < 1 || levels > kMaxLevels) return fail(plan, ABF_E_INVALID, "levels %d (1..%d)", levels, kMaxLevels);
     if (!(eps * eps >= FLT_MIN) || !(lambda >= 0.f) || !(clip_px >= 0.f))
         return fail(plan, ABF_E_INVALID, "bad parameter (eps^2 must be a normal float, lambda and clip >= 0)");
@@ -1470,7 +1478,7 @@ abf_status abf_blend_asymmetric_f32(abf_plan *plan, const float *L, const float 
 {
     if (!plan) return ABF_E_INVALID;
     if (!L || !R || !flow_LtoR || !flow_RtoL || !F) return fail(plan, ABF_E_INVALID, "null pointer");
-    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (!float_image_ok(H, W)) return fail(plan, ABF_E_SHAPE, "size %d x %d (1 <= H, W; 3 H W < 2^32)", H, W);
     if (axis != 0 && axis != 1) return fail(plan, ABF_E_INVALID, "axis %d", axis);
     BlendParams bp{plan->p.k_sharp, plan->p.k_flowmag, plan->p.blend_mode};
     HIP_TRY(plan, launch_blend_f32(L, R, flow_LtoR, flow_RtoL, blend, axis, H, W, bp, F,
@@ -1485,7 +1493,7 @@ abf_status abf_blend_backward(abf_plan *plan, const float *L, const float *R, co
 {
     if (!plan) return ABF_E_INVALID;
     if (!L || !R || !flow_LtoR || !flow_RtoL || !g_F) return fail(plan, ABF_E_INVALID, "null pointer");
-    if (H < 1 || W < 1) return fail(plan, ABF_E_SHAPE, "size %d x %d", H, W);
+    if (!float_image_ok(H, W)) return fail(plan, ABF_E_SHAPE, "size %d x %d (1 <= H, W; 3 H W < 2^32)", H, W);
     if (axis != 0 && axis != 1) return fail(plan, ABF_E_INVALID, "axis %d", axis);
     if (!aligned8(flow_LtoR) || !aligned8(flow_RtoL)) return fail(plan, ABF_E_INVALID, "flows must be 8-byte aligned");
     const bool det = deterministic != 0 && (g_L || g_R);
@@ -1552,7 +1560,8 @@ abf_status abf_refine_strips(abf_plan *plan, const abf_refine_strip *strips, int
         const abf_refine_strip &x = strips[i];
         if (!x.Ref || !x.Tgt || !x.u) return fail(plan, ABF_E_INVALID, "strip %d: null pointer", i);
         if (!aligned8(x.u)) return fail(plan, ABF_E_INVALID, "strip %d: u must be 8-byte aligned", i);
-        if (x.H < 1 || x.W < 1) return fail(plan, ABF_E_SHAPE, "strip %d: size %d x %d", i, x.H, x.W);
+        if (!float_image_ok(x.H, x.W))
+            return fail(plan, ABF_E_SHAPE, "strip %d: size %d x %d (1 <= H, W; 3 H W < 2^32)", i, x.H, x.W);
         d[i].Ref = x.Ref;
         d[i].Tgt = x.Tgt;
         d[i].u[0] = x.u;
