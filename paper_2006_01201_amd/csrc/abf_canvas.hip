@@ -534,28 +534,33 @@ __device__ __forceinline__ void sample_box_wrap(const uint8_t *img, int pitch, i
     }
 }
 
-// Code 1 over the canvas, one workgroup per kRowTW pixels of a row: Area1
+// Code 1 over the canvas, one workgroup per PX kRowTW pixels of a row: Area1
 // copies L, Area2 copies R, Area3 inside the overlap box is warped and
 // blended as a strip pixel of the box (images and flows cropped to the
 // box), everything else is 0. With `cov` (a photo merge), the union of the
 // two coverages is written there (pitch of the masks). The uint8 output is staged in LDS at the
 // byte alignment of its destination and written with aligned dwords.
+template <int PX>
 __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendParams bp)
 {
-    __shared__ uint32_t stage[(3 * kRowTW + 8) / 4];
+    constexpr int TW = PX * kRowTW;  // pixels of a row segment; a thread takes PX of them, kRowTW apart
+    __shared__ uint32_t stage[(3 * TW + 8) / 4];
     uint8_t *sb = reinterpret_cast<uint8_t *>(stage);
-    const int W = o.W, segs = ceil_div(W, kRowTW);
-    const int y = blockIdx.x / segs, xs = (blockIdx.x - y * segs) * kRowTW;
-    const int npx = min(kRowTW, W - xs), x = xs + (int)threadIdx.x;
+    const int W = o.W, segs = ceil_div(W, TW);
+    const int y = blockIdx.x / segs, xs = (blockIdx.x - y * segs) * TW;
+    const int npx = min(TW, W - xs);
     uint8_t *const seg = o.F + (size_t)y * o.pitchF + 3 * (size_t)xs;
     const int off = (int)((uintptr_t)seg & 3);
-    if (x < W) {
+    const int yb = y - o.by;
+#pragma unroll
+    for (int k = 0; k < PX; k++) {
+        const int i = k * kRowTW + (int)threadIdx.x, x = xs + i;
+        if (x >= W) break;
         const size_t pm = (size_t)y * o.pitchM + x;
         const int area = (gld(o.mL)[pm] != 0) + 2 * (gld(o.mR)[pm] != 0);
         if (o.cov) gst(o.cov)[pm] = area != 0;  // may be one of the masks: read above, by this thread only
         int xb = x - o.bx;
         if (o.periodic && xb < 0) xb += W;  // box columns wrap modulo W
-        const int yb = y - o.by;
         float f[3] = {0.f, 0.f, 0.f};
         if (area == 1 || area == 2) {
             const uint8_t *src = area == 1 ? o.L + (size_t)y * o.pitchL : o.R + (size_t)y * o.pitchR;
@@ -582,7 +587,7 @@ __global__ __launch_bounds__(kRowTW) void k_composite(CompositeArgs o, BlendPara
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             const float r = floorf(f[c] + 0.5f);
-            sb[off + 3 * threadIdx.x + c] = (uint8_t)fminf(fmaxf(r, 0.f), 255.f);
+            sb[off + 3 * i + c] = (uint8_t)fminf(fmaxf(r, 0.f), 255.f);
             if (o.Ff32) gst(o.Ff32)[3 * ((size_t)y * W + x) + c] = f[c];
         }
     }
@@ -682,7 +687,8 @@ hipError_t launch_photo_init(const uint8_t *img, int pitchI, const uint8_t *mask
 
 hipError_t launch_composite(const CompositeArgs &o, BlendParams bp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_composite, dim3(o.H * ceil_div(o.W, kRowTW)), dim3(kRowTW), 0, s, o, bp);
+    constexpr int PX = 4;
+    hipLaunchKernelGGL(k_composite<PX>, dim3(o.H * ceil_div(o.W, PX * kRowTW)), dim3(kRowTW), 0, s, o, bp);
     return hipGetLastError();
 }
 
