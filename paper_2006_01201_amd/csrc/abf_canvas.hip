@@ -149,7 +149,8 @@ __global__ __launch_bounds__(kCanvasThreads) void k_canvas_rows(CanvasGeom a)
     }
     __syncthreads();
     uint32_t *const orow = a.G + (size_t)y * a.gpitch;
-    for (int c = t; c < nC; c += kCanvasThreads) {
+    const int cend = min(nC, ceil_div(a.gx1, kCanvasChunk));
+    for (int c = a.gx0 / kCanvasChunk + t; c < cend; c += kCanvasThreads) {
         const uint32_t bb = bits[c];
         const int x0 = c * kCanvasChunk, n = min(kCanvasChunk, W - x0);
         int l1 = lastA[c], l2 = lastB[c], r1 = firstA[c], r2 = firstB[c];
@@ -669,7 +670,10 @@ hipError_t launch_canvas_dist(const CanvasGeom &a, float *blend, int pitchB, int
         tb0 = box[1] / kCanvasBH;
         ntb = ceil_div(box[1] + box[3], kCanvasBH) - tb0;
     }
-    hipLaunchKernelGGL(k_canvas_rows, dim3(a.H), dim3(kCanvasThreads), 0, s, a);
+    CanvasGeom r = a;  // G only in the columns that the tiles read
+    r.gx0 = tx0 * 64;
+    r.gx1 = min(a.W, (tx0 + ntx) * 64);
+    hipLaunchKernelGGL(k_canvas_rows, dim3(a.H), dim3(kCanvasThreads), 0, s, r);
     hipLaunchKernelGGL(k_canvas_colmin, dim3(ceil_div(min(ntx * 64, a.W - tx0 * 64), kCanvasThreads),
                                              ceil_div(a.H, kCanvasBH)),
                        dim3(kCanvasThreads), 0, s, a, tx0 * 64);

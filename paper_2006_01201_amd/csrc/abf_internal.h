@@ -176,6 +176,7 @@ struct CanvasGeom {
     uint32_t *G, *M;
     int32_t pitchM, H, W, gpitch;
     int32_t periodic;  // columns wrap (W - 1 neighbours 0): row distances the shorter way round
+    int32_t gx0, gx1;  // columns [gx0, gx1) of G that are written (every row is scanned whole)
     int32_t pad_;
 };
 __host__ __device__ inline int canvas_gpitch(int W) { return (W + 63) / 64 * 64; }

@@ -1036,6 +1036,8 @@ static abf_status canvas_setup(abf_plan *plan, const uint8_t *mL, const uint8_t 
     g.W = W;
     g.gpitch = (int32_t)gp;
     g.periodic = periodic ? 1 : 0;
+    g.gx0 = 0;
+    g.gx1 = W;
     return ABF_OK;
 }
 
