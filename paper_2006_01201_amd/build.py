@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "libabf.so")
 SOURCES = ["abf_kernels.hip", "abf_prop.hip", "abf_runtime.hip", "abf_grad.hip", "abf_canvas.hip"]
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

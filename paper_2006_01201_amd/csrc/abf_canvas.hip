@@ -19,6 +19,7 @@
 //      k^2 + m^2, so it is skipped when that bound reaches the best value
 //      found, and the search ends in a direction once k^2 does.
 #include "abf_device.h"
+#include "abf_tiles.h"
 
 namespace abf {
 
@@ -444,15 +445,8 @@ __device__ __forceinline__ OccWord occ_word(uint32_t w, int vb, int base)
 __global__ __launch_bounds__(1024) void k_box_fin(const int32_t *part, int H, int W, const uint32_t *occ,
                                                   int32_t *box)
 {
-    __shared__ int32_t s[4];
+    __shared__ int32_t red[4 * 16];
     __shared__ OccWord ow[(kCanvasMaxDim + 31) / 32 + 1];
-    if (threadIdx.x == 0) {
-        s[0] = 0x7fffffff;
-        s[1] = 0x7fffffff;
-        s[2] = -1;
-        s[3] = -1;
-    }
-    __syncthreads();
     int x0 = 0x7fffffff, y0 = 0x7fffffff, x1 = -1, y1 = -1;
     for (int y = threadIdx.x; y < H; y += blockDim.x) {
         const int32_t ex = gld(part)[2 * y], ey = gld(part)[2 * y + 1];
@@ -463,12 +457,8 @@ __global__ __launch_bounds__(1024) void k_box_fin(const int32_t *part, int H, in
             y1 = max(y1, y);
         }
     }
-    if (x1 >= 0) {
-        atomicMin(&s[0], x0);
-        atomicMin(&s[1], y0);
-        atomicMax(&s[2], x1);
-        atomicMax(&s[3], y1);
-    }
+    wg_minmax4<1024>(x0, y0, x1, y1, red);  // over the workgroup (every thread gets the result)
+    const int s[4] = {x0, y0, x1, y1};
     const int nw = (W + 31) >> 5;
     if (occ)
         for (int k = threadIdx.x; k < nw; k += blockDim.x)

@@ -1334,6 +1334,7 @@ abf_status abf_refine_flow(abf_plan *plan, const float *Ref, const float *Tgt, f
 // k >= 1 the reduced Ref, Tgt (3 floats per pixel) and u (2) and, with
 // gradients, their gradients (8 floats per pixel); the per-level energies;
 // the energy partials; the fixed-point scatter of level 0's dE/dTgt.
+extern "C++" {  // helpers with C++ types inside the C-ABI block
 namespace {
 
 struct MsLayout {
@@ -1418,6 +1419,7 @@ abf_status energy_ms_run(abf_plan *plan, const MsLayout &L, uint8_t *scr, const 
 }
 
 }  // namespace
+}  // extern "C++"
 
 size_t abf_energy_ms_workspace_bytes(const abf_plan *plan, int32_t H, int32_t W, int32_t levels)
 {
