@@ -86,7 +86,7 @@ struct BlendParams {
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // search tiles: 128 x TH pixels (64 threads per row, two pixels each);
-// refine: 64 x TH; propagation: (64 - 2h) x TH outputs, TH = 8, 16 or 32; luma, exposure step and blend:
+// refine: 64 x TH; propagation: (64 - 2h) x TH outputs, TH = 8, 10, 16 or 32; luma, exposure step and blend:
 // 256 pixels of one row; pyramid: 256 x 4 output pixels (4 per thread). Luma, exposure
 // and pyramid tiles cover the padded planes.
 constexpr int kSearchTW = 128;
@@ -224,7 +224,7 @@ __host__ __device__ inline int tiles_pyr(int H, int W)
 __host__ __device__ inline int tiles_search(int H, int W, int th) { return 2 * ceil_div(H, th) * ceil_div(W, kSearchTW); }
 // fused propagation (T steps + median, halo h = T + M <= kPropMaxHalo):
 // one wave per tile of (kPropRW - 2h) x th outputs over a
-// kPropRW x (th + 2h) region held in registers (th = 8, 16 or 32)
+// kPropRW x (th + 2h) region held in registers (th = 8, 10, 16 or 32)
 constexpr int kPropRW = 64;
 constexpr int kPropMaxHalo = 5;
 __host__ __device__ inline int tiles_prop(int H, int W, int th, int h)

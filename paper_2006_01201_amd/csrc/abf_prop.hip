@@ -345,6 +345,7 @@ template <int P>
 static hipError_t prop_th(const StripLv *lv, Work w, int steps, int median, int th, int grid, hipStream_t s)
 {
     if (th == 8) return prop_h<P, 8>(lv, w, steps, median, grid, s);
+    if (th == 10) return prop_h<P, 10>(lv, w, steps, median, grid, s);
     if (th == 16) return prop_h<P, 16>(lv, w, steps, median, grid, s);
     if (th == 32) return prop_h<P, 32>(lv, w, steps, median, grid, s);
     return hipErrorInvalidValue;
