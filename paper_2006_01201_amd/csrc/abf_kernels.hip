@@ -341,6 +341,7 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                     const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
                     best0 = min(best0, (s0 << 11) + K);
                     best1 = min(best1, (s1 << 11) + K);
+                    asm volatile("" : "+v"(best0), "+v"(best1));  // min chains in candidate order
                 }
         } else {
             uint32_t r0m[3], r1m[3];
@@ -362,6 +363,7 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                     const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
                     best0 = min(best0, (s0 << 11) + K);
                     best1 = min(best1, (s1 << 11) + K);
+                    asm volatile("" : "+v"(best0), "+v"(best1));  // min chains in candidate order
                 }
         }
         auto out = gst(L.ds[dir] + (size_t)y * L.fpitch + x);
@@ -439,29 +441,43 @@ __global__ __launch_bounds__(32 * TH) void k_search_quad(const StripLv *__restri
             rh[r] = byte_at(rr[r], 5);
         }
         uint32_t b00 = 0xffffffffu, b01 = 0xffffffffu, b10 = 0xffffffffu, b11 = 0xffffffffu;
+        // candidate column i outer: the target words and bytes at column
+        // offset i are formed once per row and serve all NC candidate rows
+        // (the order of the candidates does not matter: ties are in the key)
 #pragma unroll
-        for (int j = 0; j < NC; j++)
+        for (int i = 0; i < NC; i++) {
+            uint32_t tm[NR], tl[NR], th[NR];
 #pragma unroll
-            for (int i = 0; i < NC; i++) {
+            for (int q = 0; q < NR; q++) {
+                tm[q] = dword_at(tt[q], i + 1);
+                tl[q] = byte_at(tt[q], i);
+                th[q] = byte_at(tt[q], i + 5);
+            }
+#pragma unroll
+            for (int j = 0; j < NC; j++) {
                 uint32_t m = 0, l = 0, h = 0;
 #pragma unroll
                 for (int r = 1; r < 5; r++) {
-                    m = __builtin_amdgcn_sad_u8(rm[r], dword_at(tt[j + r], i + 1), m);
-                    l = __builtin_amdgcn_sad_u8(rl[r], byte_at(tt[j + r], i), l);
-                    h = __builtin_amdgcn_sad_u8(rh[r], byte_at(tt[j + r], i + 5), h);
+                    m = __builtin_amdgcn_sad_u8(rm[r], tm[j + r], m);
+                    l = __builtin_amdgcn_sad_u8(rl[r], tl[j + r], l);
+                    h = __builtin_amdgcn_sad_u8(rh[r], th[j + r], h);
                 }
-                const uint32_t m0 = __builtin_amdgcn_sad_u8(rm[0], dword_at(tt[j], i + 1), m);
-                const uint32_t m5 = __builtin_amdgcn_sad_u8(rm[5], dword_at(tt[j + 5], i + 1), m);
-                const uint32_t l0 = __builtin_amdgcn_sad_u8(rl[0], byte_at(tt[j], i), l);
-                const uint32_t l5 = __builtin_amdgcn_sad_u8(rl[5], byte_at(tt[j + 5], i), l);
-                const uint32_t h0 = __builtin_amdgcn_sad_u8(rh[0], byte_at(tt[j], i + 5), h);
-                const uint32_t h5 = __builtin_amdgcn_sad_u8(rh[5], byte_at(tt[j + 5], i + 5), h);
+                const uint32_t m0 = __builtin_amdgcn_sad_u8(rm[0], tm[j], m);
+                const uint32_t m5 = __builtin_amdgcn_sad_u8(rm[5], tm[j + 5], m);
+                const uint32_t l0 = __builtin_amdgcn_sad_u8(rl[0], tl[j], l);
+                const uint32_t l5 = __builtin_amdgcn_sad_u8(rl[5], tl[j + 5], l);
+                const uint32_t h0 = __builtin_amdgcn_sad_u8(rh[0], th[j], h);
+                const uint32_t h5 = __builtin_amdgcn_sad_u8(rh[5], th[j + 5], h);
                 const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
                 b00 = min(b00, ((m0 + l0) << 11) + K);
                 b01 = min(b01, ((m0 + h0) << 11) + K);
                 b10 = min(b10, ((m5 + l5) << 11) + K);
                 b11 = min(b11, ((m5 + h5) << 11) + K);
+                // keep the min chains in candidate order (a reassociated
+                // tree would hold every candidate's key at once)
+                asm volatile("" : "+v"(b00), "+v"(b01), "+v"(b10), "+v"(b11));
             }
+        }
         const uint32_t best[2][2] = {{b00, b01}, {b10, b11}};
 #pragma unroll
         for (int dy = 0; dy < 2; dy++) {
