@@ -325,24 +325,34 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                 rl[r] = byte_at(rr[r], 0);
                 rh[r] = byte_at(rr[r], 5);
             }
+            // candidate columns outer: each column offset's target words are
+            // formed once per row
 #pragma unroll
-            for (int j = 0; j < NC; j++)
+            for (int i = 0; i < NC; i++) {
+                uint32_t tm[NR], tl[NR], th[NR];
 #pragma unroll
-                for (int i = 0; i < NC; i++) {
+                for (int q = 0; q < NR; q++) {
+                    tm[q] = dword_at(tt[q], i + 1);
+                    tl[q] = byte_at(tt[q], i);
+                    th[q] = byte_at(tt[q], i + 5);
+                }
+#pragma unroll
+                for (int j = 0; j < NC; j++) {
                     uint32_t m = 0;
 #pragma unroll
-                    for (int r = 0; r < 5; r++) m = __builtin_amdgcn_sad_u8(rm[r], dword_at(tt[j + r], i + 1), m);
+                    for (int r = 0; r < 5; r++) m = __builtin_amdgcn_sad_u8(rm[r], tm[j + r], m);
                     uint32_t s0 = m, s1 = m;
 #pragma unroll
                     for (int r = 0; r < 5; r++) {
-                        s0 = __builtin_amdgcn_sad_u8(rl[r], byte_at(tt[j + r], i), s0);
-                        s1 = __builtin_amdgcn_sad_u8(rh[r], byte_at(tt[j + r], i + 5), s1);
+                        s0 = __builtin_amdgcn_sad_u8(rl[r], tl[j + r], s0);
+                        s1 = __builtin_amdgcn_sad_u8(rh[r], th[j + r], s1);
                     }
                     const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
                     best0 = min(best0, (s0 << 11) + K);
                     best1 = min(best1, (s1 << 11) + K);
                     asm volatile("" : "+v"(best0), "+v"(best1));  // min chains in candidate order
                 }
+            }
         } else {
             uint32_t r0m[3], r1m[3];
 #pragma unroll
@@ -351,20 +361,27 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                 r1m[r] = rr[r][0] >> 8;
             }
 #pragma unroll
-            for (int j = 0; j < NC; j++)
+            for (int i = 0; i < NC; i++) {
+                uint32_t t0[NR], t1[NR];
 #pragma unroll
-                for (int i = 0; i < NC; i++) {
+                for (int q = 0; q < NR; q++) {
+                    t0[q] = dword_at(tt[q], i) & 0x00ffffffu;
+                    t1[q] = dword_at(tt[q], i + 1) & 0x00ffffffu;
+                }
+#pragma unroll
+                for (int j = 0; j < NC; j++) {
                     uint32_t s0 = 0, s1 = 0;
 #pragma unroll
                     for (int r = 0; r < 3; r++) {
-                        s0 = __builtin_amdgcn_sad_u8(r0m[r], dword_at(tt[j + r], i) & 0x00ffffffu, s0);
-                        s1 = __builtin_amdgcn_sad_u8(r1m[r], dword_at(tt[j + r], i + 1) & 0x00ffffffu, s1);
+                        s0 = __builtin_amdgcn_sad_u8(r0m[r], t0[j + r], s0);
+                        s1 = __builtin_amdgcn_sad_u8(r1m[r], t1[j + r], s1);
                     }
                     const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
                     best0 = min(best0, (s0 << 11) + K);
                     best1 = min(best1, (s1 << 11) + K);
                     asm volatile("" : "+v"(best0), "+v"(best1));  // min chains in candidate order
                 }
+            }
         }
         auto out = gst(L.ds[dir] + (size_t)y * L.fpitch + x);
         auto cst = gst(L.cs[dir] + (size_t)y * L.fpitch + x);
