@@ -634,6 +634,37 @@ __device__ __forceinline__ void refine_update(const RefineSolve &q, float bx, fl
     uy = fminf(fmaxf(uy + dy, (float)(d0y - 1)), (float)(d0y + 1));
 }
 
+// Corner correlations of target rows R0 .. R0 + NR - 1 of a window (tb
+// holds them): row r adds to S(0, 0), S(1, 0) against window row r and to
+// S(0, 1), S(1, 1) against window row r - 1 (x, y components), in row order.
+template <int LP, int OFF, int NRW, int R0, int NR, int NBT>
+__device__ __forceinline__ void corner_rows(const uint32_t (&gxp)[NRW][LP + 1], const uint32_t (&gyp)[NRW][LP + 1],
+                                            const uint32_t (&tb)[NR][NBT], int (&sc)[8])
+{
+    constexpr int WN = 2 * LP + 1, NP = LP + 1;
+#pragma unroll
+    for (int i = 0; i < NR; i++) {
+        const int r = R0 + i;
+        uint32_t te[NP], to[NP];
+        tgt_pairs<NP, 0>(tb[i], te, to);
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            if (r < WN) {
+                sc[0] = dot2(gxp[OFF + r][k], te[k], sc[0]);
+                sc[1] = dot2(gxp[OFF + r][k], to[k], sc[1]);
+                sc[4] = dot2(gyp[OFF + r][k], te[k], sc[4]);
+                sc[5] = dot2(gyp[OFF + r][k], to[k], sc[5]);
+            }
+            if (r > 0) {
+                sc[2] = dot2(gxp[OFF + r - 1][k], te[k], sc[2]);
+                sc[3] = dot2(gxp[OFF + r - 1][k], to[k], sc[3]);
+                sc[6] = dot2(gyp[OFF + r - 1][k], te[k], sc[6]);
+                sc[7] = dot2(gyp[OFF + r - 1][k], to[k], sc[7]);
+            }
+        }
+    }
+}
+
 // `iters` Gauss-Newton steps of one interior pixel (x, y) from its integer
 // flow (d0x, d0y): its window rows are rows OFF .. OFF + WN - 1 of the
 // doubled-gradient pair arrays, sax / say its sums of g A. Returns the
@@ -673,31 +704,23 @@ __device__ __forceinline__ uint64_t refine_steps(const uint32_t (&gxp)[NRW][LP +
             bx = (float)(sx - sax);
             by = (float)(sy - say);
         } else {
-            int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
-            uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
-            load_rows<WN + 2, WN + 1>(Bo, yp, r0, c0, tb);
-#pragma unroll
-            for (int r = 0; r <= WN; r++) {
-                uint32_t te[NP], to[NP];
-                tgt_pairs<NP, 0>(tb[r], te, to);
-#pragma unroll
-                for (int k = 0; k < NP; k++) {
-                    if (r < WN) {
-                        s00x = dot2(gxp[OFF + r][k], te[k], s00x);
-                        s01x = dot2(gxp[OFF + r][k], to[k], s01x);
-                        s00y = dot2(gyp[OFF + r][k], te[k], s00y);
-                        s01y = dot2(gyp[OFF + r][k], to[k], s01y);
-                    }
-                    if (r > 0) {
-                        s10x = dot2(gxp[OFF + r - 1][k], te[k], s10x);
-                        s11x = dot2(gxp[OFF + r - 1][k], to[k], s11x);
-                        s10y = dot2(gyp[OFF + r - 1][k], te[k], s10y);
-                        s11y = dot2(gyp[OFF + r - 1][k], to[k], s11y);
-                    }
-                }
+            // the WN + 1 target rows in two halves, each loaded and used
+            // before the next is issued (fewer live registers)
+            int sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // s00x s01x s10x s11x s00y s01y s10y s11y
+            constexpr int H1 = (WN + 1) / 2, H2 = WN + 1 - H1, NBT = (WN + 2 + 3) / 4;
+            {
+                uint32_t tb[H1][NBT];
+                load_rows<WN + 2, H1>(Bo, yp, r0, c0, tb);
+                corner_rows<LP, OFF, NRW, 0, H1>(gxp, gyp, tb, sc);
             }
-            bx = corner_mix(s00x, s01x, s10x, s11x, sax, fx, fy);
-            by = corner_mix(s00y, s01y, s10y, s11y, say, fx, fy);
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                uint32_t tb[H2][NBT];
+                load_rows<WN + 2, H2>(Bo, yp, r0 + H1, c0, tb);
+                corner_rows<LP, OFF, NRW, H1, H2>(gxp, gyp, tb, sc);
+            }
+            bx = corner_mix(sc[0], sc[1], sc[2], sc[3], sax, fx, fy);
+            by = corner_mix(sc[4], sc[5], sc[6], sc[7], say, fx, fy);
         }
         refine_update(q, bx, by, d0x, d0y, ux, uy);
     }
@@ -775,7 +798,7 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
 // budget: at most 128 VGPRs (4 waves per SIMD, no spills); capped at 96
 // (5 waves) it spilled and was slower.
 template <int LP, int TH>
-__global__ __launch_bounds__(32 * TH) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_refine_pair(
+__global__ __launch_bounds__(32 * TH) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_refine_pair(
     const StripLv *__restrict__ lv, const StripIO *__restrict__ io, const int32_t *__restrict__ prefix, int n,
     int total, int iters, float eps)
 {
