@@ -795,8 +795,8 @@ __global__ __launch_bounds__(64 * TH) void k_refine(const StripLv *__restrict__ 
 // each pixel adds its own first or last row. The Gauss-Newton steps are
 // those of k_refine, pixel by pixel. A tile of TH rows (TH even) is TH/2
 // waves, each a row pair; the results are those of k_refine. Register
-// budget: at most 128 VGPRs (4 waves per SIMD, no spills); capped at 96
-// (5 waves) it spilled and was slower.
+// budget: 96 VGPRs (5 waves per SIMD, no spills, with the fractional
+// step's target rows loaded in two halves); at 80 (6 waves) it spills.
 template <int LP, int TH>
 __global__ __launch_bounds__(32 * TH) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_refine_pair(
     const StripLv *__restrict__ lv, const StripIO *__restrict__ io, const int32_t *__restrict__ prefix, int n,
