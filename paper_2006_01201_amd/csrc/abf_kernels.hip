@@ -1258,33 +1258,25 @@ __global__ __launch_bounds__(64 * TH) __attribute__((amdgpu_waves_per_eu(LP <= 2
             const double cy = fmin(fmax(fuy, -(double)(H + 2 * kPad)), (double)(H + 2 * kPad));
             const int c0 = clampi(x - LP + (int)cx, -kPad, W - 1 + kPad - (WN + 1));
             const int r0 = clampi(y - LP + (int)cy, -kPad, H - 1 + kPad - WN);
-            int s00x = 0, s01x = 0, s10x = 0, s11x = 0, s00y = 0, s01y = 0, s10y = 0, s11y = 0;
-            uint32_t tb[WN + 1][(WN + 2 + 3) / 4];
-            load_rows<WN + 2, WN + 1>(Bo, yp, r0, c0, tb);
-#pragma unroll
-            for (int r = 0; r <= WN; r++) {
-                uint32_t te[NP], to[NP];
-                tgt_pairs<NP, 0>(tb[r], te, to);
-#pragma unroll
-                for (int k = 0; k < NP; k++) {
-                    if (r < WN) {
-                        s00x = dot2(gxp[r][k], te[k], s00x);
-                        s01x = dot2(gxp[r][k], to[k], s01x);
-                        s00y = dot2(gyp[r][k], te[k], s00y);
-                        s01y = dot2(gyp[r][k], to[k], s01y);
-                    }
-                    if (r > 0) {
-                        s10x = dot2(gxp[r - 1][k], te[k], s10x);
-                        s11x = dot2(gxp[r - 1][k], to[k], s11x);
-                        s10y = dot2(gyp[r - 1][k], te[k], s10y);
-                        s11y = dot2(gyp[r - 1][k], to[k], s11y);
-                    }
-                }
+            // the WN + 1 target rows in two halves, each loaded and used
+            // before the next is issued (fewer live registers)
+            int sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // s00x s01x s10x s11x s00y s01y s10y s11y
+            constexpr int H1 = (WN + 1) / 2, H2 = WN + 1 - H1, NBT = (WN + 2 + 3) / 4;
+            {
+                uint32_t tb[H1][NBT];
+                load_rows<WN + 2, H1>(Bo, yp, r0, c0, tb);
+                corner_rows<LP, 0, WN, 0, H1>(gxp, gyp, tb, sc);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                uint32_t tb[H2][NBT];
+                load_rows<WN + 2, H2>(Bo, yp, r0 + H1, c0, tb);
+                corner_rows<LP, 0, WN, H1, H2>(gxp, gyp, tb, sc);
             }
             // residual sums with the doubled gradient: G (Tgt~ - A)
             const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
-            const double bx = 0.5 * (w00 * s00x + w01 * s01x + w10 * s10x + w11 * s11x - sax);
-            const double by = 0.5 * (w00 * s00y + w01 * s01y + w10 * s10y + w11 * s11y - say);
+            const double bx = 0.5 * (w00 * sc[0] + w01 * sc[1] + w10 * sc[2] + w11 * sc[3] - sax);
+            const double by = 0.5 * (w00 * sc[4] + w01 * sc[5] + w10 * sc[6] + w11 * sc[7] - say);
             ux -= (Hyy * bx - Hxy * by) * idet;
             uy -= (Hxx * by - Hxy * bx) * idet;
         }
