@@ -99,7 +99,8 @@ constexpr int kPyrTH = 4;
 // Kernel launchers (defined in abf_kernels.hip). Each returns the HIP
 // error of the launch. `grid` = 0 launches one workgroup per tile;
 // otherwise that many persistent workgroups loop over the tiles.
-hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s);
+// sums: also the luma sums of the exposure step
+hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, bool sums, hipStream_t s);
 hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s);
 hipError_t launch_gain(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s);
 hipError_t launch_pyr(const StripLv *lv, Work w, int grid, hipStream_t s);

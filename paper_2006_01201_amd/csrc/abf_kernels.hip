@@ -63,10 +63,12 @@ __device__ __forceinline__ void luma4(const uint8_t *p, uintptr_t lo, uintptr_t 
 
 // A thread makes four outputs of a padded row; a group wholly in the left
 // or right border repeats the edge pixel's luma.
+// With SUMS (the exposure step on) it also adds the strip's luma sums.
+template <bool SUMS>
 __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
                                               const int32_t *__restrict__ prefix, int n, int total)
 {
-    __shared__ unsigned long long red[2][4];
+    __shared__ uint32_t red[2][4];
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
         const int px = (local - py * segs) * kLumaTW + 4 * (int)threadIdx.x;  // first of 4 padded columns
         const int y = py - kPad, x = px - kPad;
         const int cy = clampi(y, 0, H - 1);
-        unsigned long long sl = 0, sr = 0;
+        uint32_t sl = 0, sr = 0;  // at most 4 x 255 per thread, 261120 per workgroup
         if (px < W + 2 * kPad) {
             const StripIO &o = io[s];
             const uint8_t *rl = o.L + (size_t)cy * o.pitchL;
@@ -108,20 +110,21 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
                 (uint32_t)yl[0] | ((uint32_t)yl[1] << 8) | ((uint32_t)yl[2] << 16) | ((uint32_t)yl[3] << 24);
             gst(reinterpret_cast<uint32_t *>(lv[s].y[1] + off))[0] =
                 (uint32_t)yr[0] | ((uint32_t)yr[1] << 8) | ((uint32_t)yr[2] << 16) | ((uint32_t)yr[3] << 24);
-            if (y == cy) {
+            if (SUMS && y == cy) {
 #pragma unroll
                 for (int k = 0; k < 4; k++)
                     if (x + k >= 0 && x + k < W) {
-                        sl += (unsigned long long)yl[k];
-                        sr += (unsigned long long)yr[k];
+                        sl += (uint32_t)yl[k];
+                        sr += (uint32_t)yr[k];
                     }
             }
         }
+        if constexpr (!SUMS) continue;
         // workgroup sum, one atomic per image
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
-            sl += __shfl_xor(sl, m, 64);
-            sr += __shfl_xor(sr, m, 64);
+            sl += (uint32_t)__shfl_xor((int)sl, m, 64);
+            sr += (uint32_t)__shfl_xor((int)sr, m, 64);
         }
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
@@ -130,8 +133,8 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned long long a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-            const unsigned long long b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+            const unsigned long long a = (unsigned long long)red[0][0] + red[0][1] + red[0][2] + red[0][3];
+            const unsigned long long b = (unsigned long long)red[1][0] + red[1][1] + red[1][2] + red[1][3];
             const int slot = (int)(blockIdx.x % kSumSlots);
             if (a) atomicAdd(&io[s].sums[slot], a);
             if (b) atomicAdd(&io[s].sums[kSumSlots + slot], b);
@@ -1355,9 +1358,14 @@ __global__ __launch_bounds__(kRowTW) void k_blend(const StripIO *__restrict__ io
 }
 
 // ------------------------------------------------------------- launchers
-hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s)
+hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, bool sums, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_luma, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n, w.total);
+    if (sums)
+        hipLaunchKernelGGL(k_luma<true>, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n,
+                           w.total);
+    else
+        hipLaunchKernelGGL(k_luma<false>, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n,
+                           w.total);
     return hipGetLastError();
 }
 

@@ -464,8 +464,8 @@ abf_status enqueue(abf_plan *pl, const Batch &b, bool flows, bool blend, hipStre
         HIP_TRY(pl, mark(stg, k));       \
     } while (0)
     if (flows) {
-        HIP_TRY(pl, launch_zero_sums(io, n, s));
-        TIMED(ST_LUMA, 0, launch_luma(io, lv, work(ST_LUMA, 0), grid_of(pl, ST_LUMA, b.cls[0]), s));
+        if (p.gain_comp) HIP_TRY(pl, launch_zero_sums(io, n, s));  // the exposure step's sums
+        TIMED(ST_LUMA, 0, launch_luma(io, lv, work(ST_LUMA, 0), grid_of(pl, ST_LUMA, b.cls[0]), p.gain_comp != 0, s));
         if (p.gain_comp)
             TIMED(ST_LUMA, 1, launch_gain(io, lv, work(ST_LUMA, 0), grid_of(pl, ST_LUMA, b.cls[0]), s));
         for (int k = 1; k < N; k++)
