@@ -162,6 +162,7 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
             }
         }
 
+        uint64_t chg = ~0ull;  // bit q: some pixel of region row q changed in the last step
         auto step = [&](int st, auto first) {
             constexpr bool FIRST = decltype(first)::value;
             const bool xact = xin && rx >= st && rx < 64 - st;
@@ -174,6 +175,11 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
                 rowbase[q] = J;
                 const int y = gy0 + q;
                 if (q < st || q >= RB - st || y < 0 || y >= H) continue;  // uniform
+                if (!FIRST && ((chg >> (q - 1)) & 7ull) == 0) {
+                    // no pixel of rows q - 1 .. q + 1 changed: no candidate can win
+                    m[q] &= kPmCost | kPmChg;
+                    continue;
+                }
                 const uint32_t c0 = v[q], c1 = from_left(v[q], 0u), c2 = from_right(v[q], 0u), c3 = v[q - 1],
                                c4 = v[q + 1];
                 const bool oku = xact && y > 0, okd = xact && y < H - 1;
@@ -263,6 +269,7 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
             }
             // apply the winners (Jacobi: every row reads the previous iterate)
             uint32_t up = v[0];
+            chg = 0;
 #pragma unroll
             for (int q = 1; q < RB - 1; q++) {
                 const uint32_t old = v[q];
@@ -272,6 +279,7 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
                     const uint32_t bk = (m[q] >> kPmWin) & 7u;
                     v[q] = bk == 0 ? old : bk == 1 ? cl : bk == 2 ? cr : bk == 3 ? up : v[q + 1];
                     m[q] = (m[q] & kPmCost) | (bk ? kPmChg : 0u);
+                    if (__ballot(bk != 0)) chg |= 1ull << q;
                 }
                 up = old;
             }
