@@ -79,7 +79,7 @@ def test_same_image_zero_flow_returns_it(orc):
 
 def test_warp_direction_and_scaling(orc):
     # linear weights, Blend = 1/2 everywhere: L is displaced by
-    # FlowRtoL * Blend and R by FlowLtoR * (1 - Blend) (Code 1, lines 9-13)
+    # FlowRtoL * Blend and R by FlowLtoR * (1 - Blend) (the warp of Code 1)
     L, R = _imgs(5, 32, 48)
     H, W, _ = L.shape
     frl = np.zeros((H, W, 2))
@@ -94,8 +94,8 @@ def test_warp_direction_and_scaling(orc):
 
 
 def test_softmax_matches_literal_code1(orc):
-    # constant colours, so only the weights matter; Code 1 lines 15-21
-    # written literally with exp (fine at these magnitudes)
+    # constant colours, so only the weights matter; the softmax weights of
+    # Code 1 written out with exp (fine at these magnitudes)
     H, W = 3, 50
     a, b = 40.0, 200.0
     L = np.full((H, W, 3), a)
