@@ -489,6 +489,19 @@ def run_cfg3(p6, timed, timed_each, log):
     e1 = np.hypot(*(u_after - st.flow_rl_gt).transpose(2, 0, 1))[sl][st.valid_rl[sl]]
     E0 = float(plan.energy(ref, tgt, u0, grads=False).item())
     E1 = float(plan.energy(ref, tgt, torch.from_numpy(u_after).cuda(), grads=False).item())
+    # the multi-level energy (6 levels of a float pyramid of the images and
+    # the flow): energy with all three gradients, and 20 descent steps on it
+    plan.energy_ms(ref, tgt, u0, 6, grads=True)
+    ms_ems = timed_each(lambda: plan.energy_ms(ref, tgt, u0, 6, grads=True), 20)
+
+    def ms20():
+        u.copy_(u0)
+        plan.refine_flow_ms(ref, tgt, u, 6, steps=20)
+
+    ms_ms20 = timed_each(ms20, 10)
+    e2 = np.hypot(*(u.cpu().numpy() - st.flow_rl_gt).transpose(2, 0, 1))[sl][st.valid_rl[sl]]
+    log(f"cfg3 multi-level energy: E + gradients {ms_ems['median']:.3f} ms, 20 steps {ms_ms20['median']:.3f} ms, "
+        f"EPE(RtoL) median {np.median(e0):.4f} -> {np.median(e2):.4f} px")
     log(f"cfg3: search {ms_flow['median']:.3f} ms, 50 steps {ms_ref['median']:.3f} ms, EPE(RtoL) median "
         f"{np.median(e0):.4f} -> {np.median(e1):.4f} px")
     plan.close()
@@ -497,6 +510,8 @@ def run_cfg3(p6, timed, timed_each, log):
             "ms_search": ms_flow, "ms_50_steps": ms_ref,
             "mpix_steps_s": round(H * W * 50 / ms_ref["median"] / 1e3, 1),
             "energy_before_after": [round(E0, 3), round(E1, 3)],
+            "multi_level": {"levels": 6, "ms_energy_and_gradients": ms_ems, "ms_20_steps": ms_ms20,
+                            "epe_rtol_after_median_px": round(float(np.median(e2)), 4)},
             "epe_rtol_before": {"median_px": round(float(np.median(e0)), 4), "mean_px": round(float(e0.mean()), 4)},
             "epe_rtol_after": {"median_px": round(float(np.median(e1)), 4), "mean_px": round(float(e1.mean()), 4)},
             "epe_both_search": before}
