@@ -215,6 +215,7 @@ __global__ __launch_bounds__(kEB) void k_energy(const float *__restrict__ Ref, c
             }
         }
     }
+    if (!partials) return;  // gradients only (uniform)
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = kEB / 2; s > 0; s >>= 1) {
@@ -600,7 +601,7 @@ hipError_t launch_energy_full(const float *Ref, const float *Tgt, const float *u
     const double scale = fix_scale_for((double)n3);
     hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kEB), 0, s, Ref, Tgt, u, H, W, lambda, eps, partials, g_u, g_ref,
                        fix ? nullptr : g_tgt, g_tgt ? fix : nullptr, scale);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kEB), 0, s, partials, nb, E);
+    if (partials) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kEB), 0, s, partials, nb, E);
     if (g_tgt && fix)
         hipLaunchKernelGGL(k_fix_to_float, dim3(blocks_for(n3)), dim3(256), 0, s, fix, g_tgt, n3, scale,
                            (const uint32_t *)nullptr, 0.0);

@@ -1382,9 +1382,11 @@ MsLayout ms_layout(int H, int W, int N, bool grads, bool fix, bool step)
 // energy and gradients computed, and the coarse levels' gradients carried
 // to the finer ones through the pyramid's adjoint (1/2 for the flow),
 // coarsest first.
+// With images_ready the image pyramids are already in the scratch (a
+// descent builds them once); with E null only the gradients are formed.
 abf_status energy_ms_run(abf_plan *plan, const MsLayout &L, uint8_t *scr, const float *Ref, const float *Tgt,
                          const float *u, float lambda, float eps, float *E, float *g_u, float *g_ref, float *g_tgt,
-                         bool det, hipStream_t s)
+                         bool det, hipStream_t s, bool images_ready = false)
 {
     const int N = L.N;
     auto F = [&](size_t o) { return reinterpret_cast<float *>(scr + o); };
@@ -1393,14 +1395,16 @@ abf_status energy_ms_run(abf_plan *plan, const MsLayout &L, uint8_t *scr, const 
     T[0] = Tgt;
     U[0] = u;
     for (int k = 1; k < N; k++) {
-        HIP_TRY(plan, launch_pyr_down_f32(R[k - 1], 3, L.h[k - 1], L.w[k - 1], F(L.ref[k]), 1.f, s));
-        HIP_TRY(plan, launch_pyr_down_f32(T[k - 1], 3, L.h[k - 1], L.w[k - 1], F(L.tgt[k]), 1.f, s));
+        if (!images_ready) {
+            HIP_TRY(plan, launch_pyr_down_f32(R[k - 1], 3, L.h[k - 1], L.w[k - 1], F(L.ref[k]), 1.f, s));
+            HIP_TRY(plan, launch_pyr_down_f32(T[k - 1], 3, L.h[k - 1], L.w[k - 1], F(L.tgt[k]), 1.f, s));
+        }
         HIP_TRY(plan, launch_pyr_down_f32(U[k - 1], 2, L.h[k - 1], L.w[k - 1], F(L.u[k]), 0.5f, s));
         R[k] = F(L.ref[k]);
         T[k] = F(L.tgt[k]);
         U[k] = F(L.u[k]);
     }
-    double *partials = reinterpret_cast<double *>(scr + L.partials);
+    double *partials = E ? reinterpret_cast<double *>(scr + L.partials) : nullptr;
     float *El = F(L.El);
     unsigned long long *fix = det && g_tgt ? reinterpret_cast<unsigned long long *>(scr + L.fix) : nullptr;
     for (int k = N - 1; k >= 0; k--) {
@@ -1414,7 +1418,7 @@ abf_status energy_ms_run(abf_plan *plan, const MsLayout &L, uint8_t *scr, const 
         if (gr) HIP_TRY(plan, launch_pyr_adj_add_f32(F(L.gref[k + 1]), 3, L.h[k], L.w[k], gr, 1.f, s));
         if (gt) HIP_TRY(plan, launch_pyr_adj_add_f32(F(L.gtgt[k + 1]), 3, L.h[k], L.w[k], gt, 1.f, s));
     }
-    HIP_TRY(plan, launch_sum_levels(El, N, E, s));
+    if (E) HIP_TRY(plan, launch_sum_levels(El, N, E, s));
     return ABF_OK;
 }
 
@@ -1467,9 +1471,9 @@ abf_status abf_refine_flow_ms(abf_plan *plan, const float *Ref, const float *Tgt
     if (rc != ABF_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     float *g = reinterpret_cast<float *>(scr + L.gstep);
-    float *E = reinterpret_cast<float *>(scr + L.El) + kMaxLevels;  // the slot after the level energies
     for (int k = 0; k < steps; k++) {
-        rc = energy_ms_run(plan, L, scr, Ref, Tgt, u, lambda, eps, E, g, nullptr, nullptr, false, s);
+        // gradients only; the image pyramids are built by the first step
+        rc = energy_ms_run(plan, L, scr, Ref, Tgt, u, lambda, eps, nullptr, g, nullptr, nullptr, false, s, k > 0);
         if (rc != ABF_OK) return rc;
         HIP_TRY(plan, launch_clip_step(u, g, 2 * (int64_t)H * W, eta, clip_px, s));
     }
