@@ -166,9 +166,12 @@ __global__ __launch_bounds__(64) void k_gain_prep(const StripIO *__restrict__ io
 // Exposure step: R's padded luma plane scaled by a = floor(2^16 sum(YL) /
 // sum(YR)) (made by k_gain_prep): YR' = min(255, (YR a + 2^15) >> 16);
 // all-zero YR is kept (a = 2^16).
-__global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
-                                              const int32_t *__restrict__ prefix, int n, int total)
+__global__ __launch_bounds__(64) void k_gain(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
+                                             const int32_t *__restrict__ prefix, int n, int total)
 {
+    // a wave per luma tile (kLumaTW padded columns of a row): four dwords
+    // per lane, kLumaTW / 4 / 64 = 4 apart
+    static_assert(kLumaTW == 4 * 64 * 4, "four dwords per lane");
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -176,18 +179,23 @@ __global__ __launch_bounds__(256) void k_gain(const StripIO *__restrict__ io, co
         const int W = lv[s].W;
         const int segs = ceil_div(W + 2 * kPad, kLumaTW);
         const int py = local / segs;
-        const int px = (local - py * segs) * kLumaTW + 4 * (int)threadIdx.x;
-        if (px >= W + 2 * kPad) continue;
+        const int px0 = (local - py * segs) * kLumaTW;
         const uint32_t a = (uint32_t)gld(io[s].sums)[kSumGain];
-        const auto p = gst(reinterpret_cast<uint32_t *>(lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch + (px - kPad)));
-        const uint32_t v = p[0];
-        uint32_t o = 0;
+        const auto row = gst(reinterpret_cast<uint32_t *>(lv[s].y[1] + (ptrdiff_t)(py - kPad) * lv[s].ypitch +
+                                                          (px0 - kPad)));
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const uint32_t g = (((v >> (8 * k)) & 0xffu) * a + (1u << 15)) >> 16;
-            o |= (g > 255u ? 255u : g) << (8 * k);
+        for (int j = 0; j < 4; j++) {
+            const int i = (int)threadIdx.x + 64 * j;  // dword of the tile
+            if (px0 + 4 * i >= W + 2 * kPad) break;
+            const uint32_t v = row[i];
+            uint32_t o = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t g = (((v >> (8 * k)) & 0xffu) * a + (1u << 15)) >> 16;
+                o |= (g > 255u ? 255u : g) << (8 * k);
+            }
+            row[i] = o;
         }
-        p[0] = o;
     }
 }
 
@@ -1378,7 +1386,7 @@ hipError_t launch_zero_sums(const StripIO *io, int n, hipStream_t s)
 hipError_t launch_gain(const StripIO *io, const StripLv *lv0, Work w, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gain_prep, dim3(w.n), dim3(64), 0, s, io);
-    hipLaunchKernelGGL(k_gain, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n, w.total);
+    hipLaunchKernelGGL(k_gain, dim3(grid_for(w.total, grid)), dim3(64), 0, s, io, lv0, w.prefix, w.n, w.total);
     return hipGetLastError();
 }
 
