@@ -61,14 +61,16 @@ __device__ __forceinline__ void luma4(const uint8_t *p, uintptr_t lo, uintptr_t 
     }
 }
 
-// A thread makes four outputs of a padded row; a group wholly in the left
-// or right border repeats the edge pixel's luma.
-// With SUMS (the exposure step on) it also adds the strip's luma sums.
+// Outputs of a padded row in groups of four; a group wholly in the left or
+// right border repeats the edge pixel's luma. With SUMS (the exposure step
+// on) it also adds the strip's luma sums.
 template <bool SUMS>
-__global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
-                                              const int32_t *__restrict__ prefix, int n, int total)
+__global__ __launch_bounds__(64) void k_luma(const StripIO *__restrict__ io, const StripLv *__restrict__ lv,
+                                             const int32_t *__restrict__ prefix, int n, int total)
 {
-    __shared__ uint32_t red[2][4];
+    // a wave per tile of kLumaTW padded columns of a row: lane l takes the
+    // groups of four columns l, l + 64, l + 128, l + 192
+    static_assert(kLumaTW == 4 * 64 * 4, "four groups per lane");
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -76,18 +78,24 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
         const int W = lv[s].W, H = lv[s].H;
         const int segs = ceil_div(W + 2 * kPad, kLumaTW);
         const int py = local / segs;
-        const int px = (local - py * segs) * kLumaTW + 4 * (int)threadIdx.x;  // first of 4 padded columns
-        const int y = py - kPad, x = px - kPad;
+        const int px0 = (local - py * segs) * kLumaTW;
+        const int y = py - kPad;
         const int cy = clampi(y, 0, H - 1);
-        uint32_t sl = 0, sr = 0;  // at most 4 x 255 per thread, 261120 per workgroup
-        if (px < W + 2 * kPad) {
-            const StripIO &o = io[s];
-            const uint8_t *rl = o.L + (size_t)cy * o.pitchL;
-            const uint8_t *rr = o.R + (size_t)cy * o.pitchR;
+        const StripIO &o = io[s];
+        const uint8_t *rl = o.L + (size_t)cy * o.pitchL;
+        const uint8_t *rr = o.R + (size_t)cy * o.pitchR;
+        const uintptr_t endL = (uintptr_t)(o.L + (size_t)(H - 1) * o.pitchL + 3 * (size_t)W);
+        const uintptr_t endR = (uintptr_t)(o.R + (size_t)(H - 1) * o.pitchR + 3 * (size_t)W);
+        uint32_t sl = 0, sr = 0;  // at most 16 x 255 per lane, 261120 per wave
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int px = px0 + 4 * ((int)threadIdx.x + 64 * j);  // first of 4 padded columns
+            if (px >= W + 2 * kPad) break;
+            const int x = px - kPad;
             int yl[4], yr[4];
             if (x >= 0 && x + 3 <= W - 1) {
-                luma4(rl + 3 * x, (uintptr_t)o.L, (uintptr_t)(o.L + (size_t)(H - 1) * o.pitchL + 3 * (size_t)W), yl);
-                luma4(rr + 3 * x, (uintptr_t)o.R, (uintptr_t)(o.R + (size_t)(H - 1) * o.pitchR + 3 * (size_t)W), yr);
+                luma4(rl + 3 * x, (uintptr_t)o.L, endL, yl);
+                luma4(rr + 3 * x, (uintptr_t)o.R, endR, yr);
             } else if (x + 3 < 0 || x > W - 1) {
                 const int cx = x < 0 ? 0 : W - 1;
                 const int vl = luma_of(rl[3 * cx], rl[3 * cx + 1], rl[3 * cx + 2]);
@@ -119,27 +127,19 @@ __global__ __launch_bounds__(256) void k_luma(const StripIO *__restrict__ io, co
                     }
             }
         }
-        if constexpr (!SUMS) continue;
-        // workgroup sum, one atomic per image
+        if constexpr (SUMS) {
+            // wave sum, one atomic per image into the tile's slot
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            sl += (uint32_t)__shfl_xor((int)sl, m, 64);
-            sr += (uint32_t)__shfl_xor((int)sr, m, 64);
+            for (int m = 32; m >= 1; m >>= 1) {
+                sl += (uint32_t)__shfl_xor((int)sl, m, 64);
+                sr += (uint32_t)__shfl_xor((int)sr, m, 64);
+            }
+            if (threadIdx.x == 0) {
+                const int slot = (int)(blockIdx.x % kSumSlots);
+                if (sl) atomicAdd(&io[s].sums[slot], (unsigned long long)sl);
+                if (sr) atomicAdd(&io[s].sums[kSumSlots + slot], (unsigned long long)sr);
+            }
         }
-        const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) {
-            red[0][w] = sl;
-            red[1][w] = sr;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned long long a = (unsigned long long)red[0][0] + red[0][1] + red[0][2] + red[0][3];
-            const unsigned long long b = (unsigned long long)red[1][0] + red[1][1] + red[1][2] + red[1][3];
-            const int slot = (int)(blockIdx.x % kSumSlots);
-            if (a) atomicAdd(&io[s].sums[slot], a);
-            if (b) atomicAdd(&io[s].sums[kSumSlots + slot], b);
-        }
-        __syncthreads();
     }
 }
 
@@ -1369,10 +1369,10 @@ __global__ __launch_bounds__(kRowTW) void k_blend(const StripIO *__restrict__ io
 hipError_t launch_luma(const StripIO *io, const StripLv *lv0, Work w, int grid, bool sums, hipStream_t s)
 {
     if (sums)
-        hipLaunchKernelGGL(k_luma<true>, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n,
+        hipLaunchKernelGGL(k_luma<true>, dim3(grid_for(w.total, grid)), dim3(64), 0, s, io, lv0, w.prefix, w.n,
                            w.total);
     else
-        hipLaunchKernelGGL(k_luma<false>, dim3(grid_for(w.total, grid)), dim3(256), 0, s, io, lv0, w.prefix, w.n,
+        hipLaunchKernelGGL(k_luma<false>, dim3(grid_for(w.total, grid)), dim3(64), 0, s, io, lv0, w.prefix, w.n,
                            w.total);
     return hipGetLastError();
 }
