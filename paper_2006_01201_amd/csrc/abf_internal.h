@@ -93,7 +93,7 @@ constexpr int kSearchTW = 128;
 constexpr int kRefineTW = 64;
 constexpr int kRowTW = 256;
 constexpr int kPyrTW = 256;
-constexpr int kPyrTH = 4;
+constexpr int kPyrTH = 8;  // a wave per two output rows
 
 // ---------------------------------------------------------------------
 // Kernel launchers (defined in abf_kernels.hip). Each returns the HIP

@@ -204,10 +204,11 @@ __global__ __launch_bounds__(64) void k_gain(const StripIO *__restrict__ io, con
 // even positions, clamped borders, rounding (s + 128) >> 8. Outputs cover
 // the padded plane (a border pixel takes the value at the nearest image
 // pixel); the taps of an image pixel stay inside the finer plane's border.
-// A thread makes four horizontally adjacent outputs: inside the image it
-// reads the 11 input bytes of each of the 5 rows as aligned dwords and
-// forms the horizontal taps with byte dot products; a group wholly in the
-// left or right border repeats the edge output.
+// A thread makes four horizontally adjacent outputs in each of two
+// consecutive rows: inside the image it reads the 11 input bytes of each of
+// the 7 source rows of the pair (3 shared) as aligned dwords and forms the
+// horizontal taps once per source row with byte dot products; a group
+// wholly in the left or right border repeats the edge output.
 __device__ __forceinline__ uint32_t pyr_one(const uint8_t *src, int pf, int x, int y)
 {
     constexpr int w5[5] = {1, 4, 6, 4, 1};
@@ -228,6 +229,20 @@ __global__ __launch_bounds__(256) void k_pyr(const StripLv *__restrict__ lv, con
 {
     constexpr uint32_t W4 = 0x04060401u;  // taps 1 4 6 4 on bytes 0..3
     constexpr int w5[5] = {1, 4, 6, 4, 1};
+    static_assert(kPyrTH == 8, "a wave takes two output rows");
+    // horizontal taps of the four outputs of one source row (bytes 2k .. 2k+4)
+    auto hsum = [&](const uint32_t (&r)[3], uint32_t (&hs)[4]) {
+        const uint32_t d1 = __builtin_amdgcn_alignbyte(r[1], r[0], 2);
+        const uint32_t d3 = __builtin_amdgcn_alignbyte(r[2], r[1], 2);
+        hs[0] = __builtin_amdgcn_udot4(r[0], W4, (r[1] >> 0) & 0xffu, false);
+        hs[1] = __builtin_amdgcn_udot4(d1, W4, (r[1] >> 16) & 0xffu, false);
+        hs[2] = __builtin_amdgcn_udot4(r[1], W4, (r[2] >> 0) & 0xffu, false);
+        hs[3] = __builtin_amdgcn_udot4(d3, W4, (r[2] >> 16) & 0xffu, false);
+    };
+    auto pack = [](const uint32_t (&acc)[4]) {
+        return ((acc[0] + 128) >> 8) | (((acc[1] + 128) >> 8) << 8) | (((acc[2] + 128) >> 8) << 16) |
+               (((acc[3] + 128) >> 8) << 24);
+    };
     TILE_LOOP(total)
     {
         const int s = find_strip(prefix, n, t);
@@ -239,41 +254,63 @@ __global__ __launch_bounds__(256) void k_pyr(const StripLv *__restrict__ lv, con
         const int tx = ceil_div(L.W + 2 * kPad, kPyrTW);
         const int ty = local / tx;
         const int px = (local - ty * tx) * kPyrTW + 4 * (int)(threadIdx.x & 63);
-        const int py = ty * kPyrTH + (int)(threadIdx.x >> 6);
-        if (px >= L.W + 2 * kPad || py >= L.H + 2 * kPad) continue;  // no barrier in this kernel
-        const int x0 = px - kPad, y = clampi(py - kPad, 0, L.H - 1);
+        const int py = ty * kPyrTH + 2 * (int)(threadIdx.x >> 6);  // the first of two output rows
+        const int Hp = L.H + 2 * kPad;
+        if (px >= L.W + 2 * kPad || py >= Hp) continue;  // no barrier in this kernel
+        const bool two = py + 1 < Hp;
+        const int x0 = px - kPad, ya = clampi(py - kPad, 0, L.H - 1), yb = clampi(py + 1 - kPad, 0, L.H - 1);
         const uint8_t *src = L.yfine[img];
         const int pf = L.ypitch_f;
-        uint32_t out;
+        uint32_t oa, ob;
         if (x0 >= 0 && x0 + 3 <= L.W - 1) {
-            uint32_t r[5][3];
-            load_rows<11, 5>(plane_org(src, pf), pf, 2 * y - 2, 2 * x0 - 2, r);
-            uint32_t acc[4] = {0, 0, 0, 0};
+            if (yb == ya + 1) {
+                // source rows 2 ya - 2 .. 2 ya + 4: the two outputs share three
+                uint32_t r[7][3];
+                load_rows<11, 7>(plane_org(src, pf), pf, 2 * ya - 2, 2 * x0 - 2, r);
+                uint32_t acc_a[4] = {0, 0, 0, 0}, acc_b[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int j = 0; j < 5; j++) {
-                // output k takes bytes 2k .. 2k+4 of the row
-                const uint32_t d1 = __builtin_amdgcn_alignbyte(r[j][1], r[j][0], 2);
-                const uint32_t d3 = __builtin_amdgcn_alignbyte(r[j][2], r[j][1], 2);
-                const uint32_t hs0 = __builtin_amdgcn_udot4(r[j][0], W4, (r[j][1] >> 0) & 0xffu, false);
-                const uint32_t hs1 = __builtin_amdgcn_udot4(d1, W4, (r[j][1] >> 16) & 0xffu, false);
-                const uint32_t hs2 = __builtin_amdgcn_udot4(r[j][1], W4, (r[j][2] >> 0) & 0xffu, false);
-                const uint32_t hs3 = __builtin_amdgcn_udot4(d3, W4, (r[j][2] >> 16) & 0xffu, false);
-                acc[0] += w5[j] * hs0;
-                acc[1] += w5[j] * hs1;
-                acc[2] += w5[j] * hs2;
-                acc[3] += w5[j] * hs3;
+                for (int j = 0; j < 7; j++) {
+                    uint32_t hs[4];
+                    hsum(r[j], hs);
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        if (j < 5) acc_a[k] += w5[j] * hs[k];
+                        if (j >= 2) acc_b[k] += w5[j - 2] * hs[k];
+                    }
+                }
+                oa = pack(acc_a);
+                ob = pack(acc_b);
+            } else {
+                uint32_t r[5][3];
+                load_rows<11, 5>(plane_org(src, pf), pf, 2 * ya - 2, 2 * x0 - 2, r);
+                uint32_t acc[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < 5; j++) {
+                    uint32_t hs[4];
+                    hsum(r[j], hs);
+#pragma unroll
+                    for (int k = 0; k < 4; k++) acc[k] += w5[j] * hs[k];
+                }
+                oa = pack(acc);
+                ob = oa;  // both rows clamp to the same image row
             }
-            out = ((acc[0] + 128) >> 8) | (((acc[1] + 128) >> 8) << 8) | (((acc[2] + 128) >> 8) << 16) |
-                  (((acc[3] + 128) >> 8) << 24);
         } else if (x0 + 3 < 0 || x0 > L.W - 1) {
-            out = pyr_one(src, pf, x0 < 0 ? 0 : L.W - 1, y) * 0x01010101u;
+            const int cx = x0 < 0 ? 0 : L.W - 1;
+            oa = pyr_one(src, pf, cx, ya) * 0x01010101u;
+            ob = yb == ya ? oa : pyr_one(src, pf, cx, yb) * 0x01010101u;
         } else {
-            out = 0;
+            oa = ob = 0;
 #pragma unroll
-            for (int k = 0; k < 4; k++) out |= pyr_one(src, pf, clampi(x0 + k, 0, L.W - 1), y) << (8 * k);
+            for (int k = 0; k < 4; k++) {
+                const int cx = clampi(x0 + k, 0, L.W - 1);
+                oa |= pyr_one(src, pf, cx, ya) << (8 * k);
+                ob |= pyr_one(src, pf, cx, yb) << (8 * k);
+            }
         }
         // padded rows are 64-byte aligned and px is a multiple of 4
-        gst(reinterpret_cast<uint32_t *>(L.y[img] + (ptrdiff_t)(py - kPad) * L.ypitch + x0))[0] = out;
+        uint8_t *const orow = L.y[img] + (ptrdiff_t)(py - kPad) * L.ypitch + x0;
+        gst(reinterpret_cast<uint32_t *>(orow))[0] = oa;
+        if (two) gst(reinterpret_cast<uint32_t *>(orow + L.ypitch))[0] = ob;
     }
 }
 
