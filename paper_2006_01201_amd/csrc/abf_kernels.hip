@@ -18,7 +18,7 @@
 //
 // The integer stages are bit-exact by construction (integer arithmetic,
 // fixed candidate order, Jacobi updates into separate buffers). Patch
-// costs use v_sad_u8 on byte-packed dwords.
+// costs use the byte-SAD instructions on byte-packed dwords.
 #include "abf_tiles.h"
 
 namespace abf {
@@ -320,8 +320,10 @@ __global__ __launch_bounds__(256) void k_pyr(const StripLv *__restrict__ lv, con
 // they share the centre (the coarser flow is upsampled by replication),
 // so one set of target rows serves both and, for P = 2, the middle four
 // columns of every row cost are shared. Key of a candidate:
-// (cost << 11) | (L1 offset << 7) | enumeration index, so one unsigned min
-// gives the lexicographic winner.
+// (cost << 16) | (L1 offset << 7) | enumeration index, so one unsigned min
+// gives the lexicographic winner. The sums run in v_sad_hi_u8, which adds
+// each |difference| at bit 16, with the chain started at the candidate's
+// tie bits: the last SAD leaves the key itself.
 template <int P, int R, int TH>
 __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ lv,
                                                     const int32_t *__restrict__ prefix, int n, int total)
@@ -386,18 +388,18 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                 }
 #pragma unroll
                 for (int j = 0; j < NC; j++) {
-                    uint32_t m = 0;
+                    const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
+                    uint32_t m = K;
 #pragma unroll
-                    for (int r = 0; r < 5; r++) m = __builtin_amdgcn_sad_u8(rm[r], tm[j + r], m);
+                    for (int r = 0; r < 5; r++) m = __builtin_amdgcn_sad_hi_u8(rm[r], tm[j + r], m);
                     uint32_t s0 = m, s1 = m;
 #pragma unroll
                     for (int r = 0; r < 5; r++) {
-                        s0 = __builtin_amdgcn_sad_u8(rl[r], tl[j + r], s0);
-                        s1 = __builtin_amdgcn_sad_u8(rh[r], th[j + r], s1);
+                        s0 = __builtin_amdgcn_sad_hi_u8(rl[r], tl[j + r], s0);
+                        s1 = __builtin_amdgcn_sad_hi_u8(rh[r], th[j + r], s1);
                     }
-                    const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
-                    best0 = min(best0, (s0 << 11) + K);
-                    best1 = min(best1, (s1 << 11) + K);
+                    best0 = min(best0, s0);
+                    best1 = min(best1, s1);
                     asm volatile("" : "+v"(best0), "+v"(best1));  // min chains in candidate order
                 }
             }
@@ -418,15 +420,15 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
                 }
 #pragma unroll
                 for (int j = 0; j < NC; j++) {
-                    uint32_t s0 = 0, s1 = 0;
+                    const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
+                    uint32_t s0 = K, s1 = K;
 #pragma unroll
                     for (int r = 0; r < 3; r++) {
-                        s0 = __builtin_amdgcn_sad_u8(r0m[r], t0[j + r], s0);
-                        s1 = __builtin_amdgcn_sad_u8(r1m[r], t1[j + r], s1);
+                        s0 = __builtin_amdgcn_sad_hi_u8(r0m[r], t0[j + r], s0);
+                        s1 = __builtin_amdgcn_sad_hi_u8(r1m[r], t1[j + r], s1);
                     }
-                    const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
-                    best0 = min(best0, (s0 << 11) + K);
-                    best1 = min(best1, (s1 << 11) + K);
+                    best0 = min(best0, s0);
+                    best1 = min(best1, s1);
                     asm volatile("" : "+v"(best0), "+v"(best1));  // min chains in candidate order
                 }
             }
@@ -436,12 +438,12 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
         {
             const int idx = (int)(best0 & 127u), j = idx / NC, i = idx - j * NC;
             out[0] = pack16(cx + i - R, cy + j - R);
-            cst[0] = (uint16_t)(best0 >> 11);
+            cst[0] = (uint16_t)(best0 >> 16);
         }
         if (x + 1 < W) {
             const int idx = (int)(best1 & 127u), j = idx / NC, i = idx - j * NC;
             out[1] = pack16(cx + i - R, cy + j - R);
-            cst[1] = (uint16_t)(best1 >> 11);
+            cst[1] = (uint16_t)(best1 >> 16);
         }
     }
 }
@@ -451,7 +453,7 @@ __global__ __launch_bounds__(64 * TH) void k_search(const StripLv *__restrict__ 
 // of 2R+6 target rows serves them, and for each candidate the sums of
 // rows y-1 .. y+2 (middle four columns, and the two outer columns on
 // their own) are shared, so the row y-2 and y+3 terms are all that
-// differ between the two rows of the quad: 18 v_sad_u8 per candidate for
+// differ between the two rows of the quad: 18 byte SADs per candidate for
 // four pixels instead of 30. A tile of TH rows (TH even) is TH/2 waves,
 // each a row pair of 128 columns; results are those of k_search.
 template <int R, int TH>
@@ -520,24 +522,27 @@ __global__ __launch_bounds__(32 * TH) void k_search_quad(const StripLv *__restri
             }
 #pragma unroll
             for (int j = 0; j < NC; j++) {
-                uint32_t m = 0, l = 0, h = 0;
+                // the sums accumulate in the upper 16 bits (v_sad_hi_u8), and the
+                // outer-column chains start at the tie key, so that m + l is
+                // already the candidate's key (cost << 16) | K
+                const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
+                uint32_t m = 0, l = K, h = K;
 #pragma unroll
                 for (int r = 1; r < 5; r++) {
-                    m = __builtin_amdgcn_sad_u8(rm[r], tm[j + r], m);
-                    l = __builtin_amdgcn_sad_u8(rl[r], tl[j + r], l);
-                    h = __builtin_amdgcn_sad_u8(rh[r], th[j + r], h);
+                    m = __builtin_amdgcn_sad_hi_u8(rm[r], tm[j + r], m);
+                    l = __builtin_amdgcn_sad_hi_u8(rl[r], tl[j + r], l);
+                    h = __builtin_amdgcn_sad_hi_u8(rh[r], th[j + r], h);
                 }
-                const uint32_t m0 = __builtin_amdgcn_sad_u8(rm[0], tm[j], m);
-                const uint32_t m5 = __builtin_amdgcn_sad_u8(rm[5], tm[j + 5], m);
-                const uint32_t l0 = __builtin_amdgcn_sad_u8(rl[0], tl[j], l);
-                const uint32_t l5 = __builtin_amdgcn_sad_u8(rl[5], tl[j + 5], l);
-                const uint32_t h0 = __builtin_amdgcn_sad_u8(rh[0], th[j], h);
-                const uint32_t h5 = __builtin_amdgcn_sad_u8(rh[5], th[j + 5], h);
-                const uint32_t K = ((uint32_t)(abs(i - R) + abs(j - R)) << 7) | (uint32_t)(j * NC + i);
-                b00 = min(b00, ((m0 + l0) << 11) + K);
-                b01 = min(b01, ((m0 + h0) << 11) + K);
-                b10 = min(b10, ((m5 + l5) << 11) + K);
-                b11 = min(b11, ((m5 + h5) << 11) + K);
+                const uint32_t m0 = __builtin_amdgcn_sad_hi_u8(rm[0], tm[j], m);
+                const uint32_t m5 = __builtin_amdgcn_sad_hi_u8(rm[5], tm[j + 5], m);
+                const uint32_t l0 = __builtin_amdgcn_sad_hi_u8(rl[0], tl[j], l);
+                const uint32_t l5 = __builtin_amdgcn_sad_hi_u8(rl[5], tl[j + 5], l);
+                const uint32_t h0 = __builtin_amdgcn_sad_hi_u8(rh[0], th[j], h);
+                const uint32_t h5 = __builtin_amdgcn_sad_hi_u8(rh[5], th[j + 5], h);
+                b00 = min(b00, m0 + l0);
+                b01 = min(b01, m0 + h0);
+                b10 = min(b10, m5 + l5);
+                b11 = min(b11, m5 + h5);
                 // keep the min chains in candidate order (a reassociated
                 // tree would hold every candidate's key at once)
                 asm volatile("" : "+v"(b00), "+v"(b01), "+v"(b10), "+v"(b11));
@@ -555,7 +560,7 @@ __global__ __launch_bounds__(32 * TH) void k_search_quad(const StripLv *__restri
                 const uint32_t b = best[dy][dx];
                 const int idx = (int)(b & 127u), jj = idx / NC, ii = idx - jj * NC;
                 out[dx] = pack16(cx + ii - R, cy + jj - R);
-                cst[dx] = (uint16_t)(b >> 11);
+                cst[dx] = (uint16_t)(b >> 16);
             }
         }
     }
