@@ -27,7 +27,8 @@ namespace abf {
 // cost, and the pixel's own cost is carried, so a candidate is costed only
 // if it can win:
 //  - step 1: not if it lies in the pixel's search window (the search took
-//    the minimum over that window);
+//    the minimum over that window), so never the two neighbours in the
+//    pixel's 2 x 2 cell of the coarser level, which share that window;
 //  - step t > 1: not if that neighbour did not change in step t - 1 (the
 //    pixel already weighed that vector and holds one at most as costly);
 //  - never if it equals an earlier candidate (same cost, loses the tie).
@@ -36,13 +37,14 @@ namespace abf {
 // per lane, and read back by each pixel in candidate order, so the result
 // does not depend on the packing; a list longer than the LDS ring is
 // processed in passes.
+template <int NBITS>
 __device__ __forceinline__ int wave_prefix(uint32_t c, int &total)
 {
-    // exclusive prefix sum over the wave of c (0..7) and the wave total
+    // exclusive prefix sum over the wave of c (below 2^NBITS) and the wave total
     int pre = 0;
     total = 0;
 #pragma unroll
-    for (int b = 0; b < 3; b++) {
+    for (int b = 0; b < NBITS; b++) {
         const uint64_t m = __ballot((c >> b) & 1u);
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
         pre += below << b;
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
                                              int n, int total, int T)
 {
     constexpr int RB = TB + 2 * HB, OW = 64 - 2 * HB;
+    static_assert(TB % 2 == 0, "even tile heights: a region row's parity of y is fixed");
     constexpr int NCEN = (RB + (HB & 1) + 1) / 2;  // coarse rows under the region
     __shared__ uint2 jobs[kPropCap];               // (candidate vector, row << 6 | lane), then its cost
     const int M = HB - T;
@@ -180,33 +183,49 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
                     m[q] &= kPmCost | kPmChg;
                     continue;
                 }
-                const uint32_t c0 = v[q], c1 = from_left(v[q], 0u), c2 = from_right(v[q], 0u), c3 = v[q - 1],
-                               c4 = v[q + 1];
+                // lane shifts outside any divergent code (a DPP read of an inactive
+                // lane returns the fallback value)
+                const uint32_t c0 = v[q], c1 = from_left(c0, 0u), c2 = from_right(c0, 0u);
                 const bool oku = xact && y > 0, okd = xact && y < H - 1;
-                bool n1 = okl & (c1 != c0);
-                bool n2 = okr & (c2 != c0) & !(okl & (c2 == c1));
-                bool n3 = oku & (c3 != c0) & !(okl & (c3 == c1)) & !(okr & (c3 == c2));
-                bool n4 = okd & (c4 != c0) & !(okl & (c4 == c1)) & !(okr & (c4 == c2)) & !(oku & (c4 == c3));
+                uint32_t need;
+                int wt, pre;
                 if constexpr (FIRST) {
+                    // A neighbour in the pixel's 2 x 2 cell of the coarser level has
+                    // the pixel's search window, which holds its vector: only the
+                    // neighbour across each edge of the cell can win, the left one at
+                    // even x, the right one at odd x, the upper one at even y, the
+                    // lower one at odd y (y's parity is fixed per region row: gy0 has
+                    // HB's parity). An earlier candidate it duplicates is either that
+                    // other horizontal neighbour (in the window, so this one is too)
+                    // or the horizontal candidate. need: bit 0 horizontal, bit 1
+                    // vertical.
+                    const bool ev = (x & 1) == 0, yev = ((q + HB) & 1) == 0;
+                    const uint32_t ch = ev ? c1 : c2;
+                    const uint32_t cv = yev ? v[q - 1] : v[q + 1];
+                    const bool okh = ev ? okl : okr, okv = yev ? oku : okd;
                     const uint32_t ce = cen[(q + (HB & 1)) >> 1];
                     const int cx = unpack_x(ce) * 2, cy = unpack_y(ce) * 2;
                     const uint32_t w = (uint32_t)(2 * R);
                     auto out = [&](uint32_t c) {
                         return ((uint32_t)(unpack_x(c) - cx + R) > w) || ((uint32_t)(unpack_y(c) - cy + R) > w);
                     };
-                    n1 &= out(c1);
-                    n2 &= out(c2);
-                    n3 &= out(c3);
-                    n4 &= out(c4);
+                    const bool nh = okh & (ch != c0) & out(ch);
+                    const bool nv = okv & (cv != c0) & !(okh & (cv == ch)) & out(cv);
+                    need = (nh ? 1u : 0u) | (nv ? 2u : 0u);
+                    pre = wave_prefix<2>(__popc(need), wt);
                 } else {
+                    const uint32_t c3 = v[q - 1], c4 = v[q + 1];
+                    bool n1 = okl & (c1 != c0);
+                    bool n2 = okr & (c2 != c0) & !(okl & (c2 == c1));
+                    bool n3 = oku & (c3 != c0) & !(okl & (c3 == c1)) & !(okr & (c3 == c2));
+                    bool n4 = okd & (c4 != c0) & !(okl & (c4 == c1)) & !(okr & (c4 == c2)) & !(oku & (c4 == c3));
                     n1 &= (from_left(m[q], 0u) & kPmChg) != 0;
                     n2 &= (from_right(m[q], 0u) & kPmChg) != 0;
                     n3 &= (m[q - 1] & kPmChg) != 0;
                     n4 &= (m[q + 1] & kPmChg) != 0;
+                    need = (n1 ? 1u : 0u) | (n2 ? 2u : 0u) | (n3 ? 4u : 0u) | (n4 ? 8u : 0u);
+                    pre = wave_prefix<3>(__popc(need), wt);
                 }
-                const uint32_t need = (n1 ? 1u : 0u) | (n2 ? 2u : 0u) | (n3 ? 4u : 0u) | (n4 ? 8u : 0u);
-                int wt;
-                const int pre = wave_prefix(__popc(need), wt);
                 m[q] = (m[q] & (kPmCost | kPmChg)) | need << kPmNeed | (uint32_t)pre << kPmPre;
                 J += wt;
             }
@@ -217,17 +236,27 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
                     const int y = gy0 + q;
                     if (q < st || q >= RB - st || y < 0 || y >= H) continue;  // uniform
                     const uint32_t cl = from_left(v[q], 1u), cr = from_right(v[q], 1u);
-                    const uint32_t need = (m[q] >> kPmNeed) & 15u;
+                    const uint32_t need = (m[q] >> kPmNeed) & (FIRST ? 3u : 15u);
                     if (need) {
                         int j = rowbase[q] + (int)((m[q] >> kPmPre) & 0xffu) - base;
                         const uint32_t pos = (uint32_t)(q << 6 | rx);
-#pragma unroll
-                        for (int k = 0; k < 4; k++)
-                            if (need & (1u << k)) {
-                                if (j >= 0 && j < kPropCap)
-                                    jobs[j] = make_uint2(k == 0 ? cl : k == 1 ? cr : k == 2 ? v[q - 1] : v[q + 1], pos);
+                        if constexpr (FIRST) {
+                            const bool ev = (x & 1) == 0, yev = ((q + HB) & 1) == 0;
+                            const uint32_t ch = ev ? cl : cr;
+                            if (need & 1u) {
+                                if (j >= 0 && j < kPropCap) jobs[j] = make_uint2(ch, pos);
                                 j++;
                             }
+                            if ((need & 2u) && j >= 0 && j < kPropCap) jobs[j] = make_uint2(yev ? v[q - 1] : v[q + 1], pos);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < 4; k++)
+                                if (need & (1u << k)) {
+                                    if (j >= 0 && j < kPropCap)
+                                        jobs[j] = make_uint2(k == 0 ? cl : k == 1 ? cr : k == 2 ? v[q - 1] : v[q + 1], pos);
+                                    j++;
+                                }
+                        }
                     }
                 }
                 __syncthreads();
@@ -246,22 +275,30 @@ __global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, con
                 for (int q = 1; q < RB - 1; q++) {
                     const int y = gy0 + q;
                     if (q < st || q >= RB - st || y < 0 || y >= H) continue;  // uniform
-                    const uint32_t need = (m[q] >> kPmNeed) & 15u;
+                    const uint32_t need = (m[q] >> kPmNeed) & (FIRST ? 3u : 15u);
                     if (need) {
                         int j = rowbase[q] + (int)((m[q] >> kPmPre) & 0xffu) - base;
                         uint32_t bc = m[q] & kPmCost, bk = (m[q] >> kPmWin) & 7u;
-#pragma unroll
-                        for (int k = 0; k < 4; k++)
-                            if (need & (1u << k)) {
-                                if (j >= 0 && j < kPropCap) {
-                                    const uint32_t c = jobs[j].x;
-                                    if (c < bc) {
-                                        bc = c;
-                                        bk = (uint32_t)(k + 1);
-                                    }
+                        // winner codes: 1 left, 2 right, 3 up, 4 down
+                        auto take = [&](uint32_t code) {
+                            if (j >= 0 && j < kPropCap) {
+                                const uint32_t c = jobs[j].x;
+                                if (c < bc) {
+                                    bc = c;
+                                    bk = code;
                                 }
-                                j++;
                             }
+                            j++;
+                        };
+                        if constexpr (FIRST) {
+                            const bool ev = (x & 1) == 0, yev = ((q + HB) & 1) == 0;
+                            if (need & 1u) take(ev ? 1u : 2u);
+                            if (need & 2u) take(yev ? 3u : 4u);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < 4; k++)
+                                if (need & (1u << k)) take((uint32_t)(k + 1));
+                        }
                         m[q] = (m[q] & ~(kPmCost | 7u << kPmWin)) | bc | bk << kPmWin;
                     }
                 }
