@@ -113,7 +113,9 @@ def test_search_ties_prefer_centre_then_l1(orc):
 
 
 # ------------------------------------------------------- propagation
-def brute_propagate_step(ref, tgt, D, P):
+def brute_propagate_step(ref, tgt, D, P, allowed=None):
+    # allowed: optional (5, H, W) mask of the candidates (own, left, right,
+    # up, down) a pixel may take
     H, W = ref.shape
     yy, xx = np.mgrid[0:H, 0:W]
     nbs = [(0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)]
@@ -123,6 +125,8 @@ def brute_propagate_step(ref, tgt, D, P):
     for k, (ox, oy) in enumerate(nbs):
         qx, qy = xx + ox, yy + oy
         ok = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+        if allowed is not None:
+            ok &= allowed[k]
         d = D[np.clip(qy, 0, H - 1), np.clip(qx, 0, W - 1)].astype(np.int64)
         c = np.zeros((H, W), np.int64)
         for b in range(-P, P + 1):
@@ -160,6 +164,29 @@ def test_propagate_never_increases_cost(orc):
         return c0
 
     assert (cost(D2) <= cost(D)).all()
+
+
+@pytest.mark.parametrize("seed,levels,shape", [(0, 3, (11, 15)), (1, 256, (12, 17)), (2, 6, (9, 9)), (3, 2, (13, 10))])
+def test_first_step_needs_only_neighbours_across_the_coarse_cell(orc, seed, levels, shape):
+    # After the search around the upsampled coarser flow, a neighbour in the
+    # pixel's own 2 x 2 cell has the pixel's search window, and the search
+    # took the minimum over it, so the first propagation step is unchanged
+    # when each pixel weighs only the neighbour across each edge of its cell:
+    # left at even x, right at odd x, up at even y, down at odd y. Odd sizes
+    # leave a last coarse row / column that covers one fine row / column.
+    H, W = shape
+    ref = synth.random_levels(seed + 20, shape, levels)
+    tgt = synth.random_levels(seed + 70, shape, levels)
+    Hc, Wc = (H + 1) // 2, (W + 1) // 2
+    Dc = synth.rng_for(107, seed, 0).integers(-2, 3, size=(Hc, Wc, 2)).astype(np.int32)
+    D, _ = orc.search(ref, tgt, orc.upsample(Dc, H, W), P=2, R=2)
+    yy, xx = np.mgrid[0:H, 0:W]
+    allowed = np.stack([np.ones((H, W), bool), xx % 2 == 0, xx % 2 == 1, yy % 2 == 0, yy % 2 == 1])
+    full = brute_propagate_step(ref, tgt, D, 2)
+    assert np.array_equal(brute_propagate_step(ref, tgt, D, 2, allowed), full)
+    assert np.array_equal(orc.propagate(ref, tgt, D, P=2, T=1), full)
+    # and some pixels do change in the step, so the restriction is exercised
+    assert (full != D).any()
 
 
 # ------------------------------------------------------------ median
