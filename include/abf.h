@@ -422,7 +422,7 @@ abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hi
  * propagation, refine, blend), level-size class 0..3; *tile_h and *grid
  * receive the tile height and persistent workgroups per CU (0 = one
  * workgroup per tile). abf_set_launch overrides it; valid tile heights:
- * search 1, 2, 4, 8; propagation 8, 10, 16, 32; refine 2, 4; blend 1, 2, 4 (pixels per
+ * search 1, 2, 4, 8; propagation 8, 10, 12, 16, 32; refine 2, 4; blend 1, 2, 4 (pixels per
  * thread); other stages 4
  * (ABF_E_INVALID otherwise). */
 abf_status abf_get_launch(const abf_plan *plan, int32_t stage, int32_t size_class, int32_t *tile_h,

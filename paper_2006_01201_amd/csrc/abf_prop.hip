@@ -117,9 +117,12 @@ constexpr uint32_t kPmCost = 0x1fffu, kPmChg = 1u << 13;
 constexpr int kPmNeed = 14, kPmPre = 18, kPmWin = 26;
 constexpr int kPropCap = 512;  // job records in LDS per pass
 
+// Regions of up to 18 rows are held to 128 VGPRs (4 waves per SIMD): the
+// 12-row tile of 2 steps and the median needs 135 unconstrained and fits
+// without spills under the cap (larger regions would spill).
 template <int P, int TB, int HB>
-__global__ __launch_bounds__(64) void k_prop(const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix,
-                                             int n, int total, int T)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TB + 2 * HB <= 18 ? 4 : 1, 8))) void k_prop(
+    const StripLv *__restrict__ lv, const int32_t *__restrict__ prefix, int n, int total, int T)
 {
     constexpr int RB = TB + 2 * HB, OW = 64 - 2 * HB;
     static_assert(TB % 2 == 0, "even tile heights: a region row's parity of y is fixed");
@@ -391,6 +394,7 @@ static hipError_t prop_th(const StripLv *lv, Work w, int steps, int median, int 
 {
     if (th == 8) return prop_h<P, 8>(lv, w, steps, median, grid, s);
     if (th == 10) return prop_h<P, 10>(lv, w, steps, median, grid, s);
+    if (th == 12) return prop_h<P, 12>(lv, w, steps, median, grid, s);
     if (th == 16) return prop_h<P, 16>(lv, w, steps, median, grid, s);
     if (th == 32) return prop_h<P, 32>(lv, w, steps, median, grid, s);
     return hipErrorInvalidValue;

@@ -150,7 +150,7 @@ bool valid_th(int stage, int th)
 {
     switch (stage) {
     case ST_SEARCH: return th == 1 || th == 2 || th == 4 || th == 8;
-    case ST_PROP: return th == 8 || th == 10 || th == 16 || th == 32;
+    case ST_PROP: return th == 8 || th == 10 || th == 12 || th == 16 || th == 32;
     case ST_REFINE: return th == 2 || th == 4;
     case ST_BLEND: return th == 1 || th == 2 || th == 4;  // pixels per thread
     default: return th == 4;
@@ -947,7 +947,7 @@ abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hi
             if (!seen[stage][c]) continue;
             Launch best = plan->launch[stage][c];
             float best_ms = 1e30f;
-            for (int th : {1, 2, 4, 8, 10, 16, 32}) {
+            for (int th : {1, 2, 4, 8, 10, 12, 16, 32}) {
                 if (!valid_th(stage, th)) continue;
                 for (int g : grids) {
                     plan->launch[stage][c] = {th, g};

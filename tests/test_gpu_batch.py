@@ -107,7 +107,7 @@ def test_every_launch_shape_gives_identical_results(api):
     print("[gpu] launch shape invariance", flush=True)
     ref = plan.stitch_strips(strips, use_graph=False, f32=True)
     torch.cuda.synchronize()
-    ths = {2: (1, 2, 4, 8), 3: (8, 10, 16, 32), 4: (2, 4), 5: (1, 2, 4)}
+    ths = {2: (1, 2, 4, 8), 3: (8, 10, 12, 16, 32), 4: (2, 4), 5: (1, 2, 4)}
     for stage in range(6):
         for th in ths.get(stage, (4,)):
             for grid in (0, 1, 3):
