@@ -941,7 +941,7 @@ abf_status abf_tune(abf_plan *plan, const abf_strip *strips, int32_t n, void *hi
     };
     float unused = 0.f;
     abf_status rc = pass({-1, -1}, unused);
-    static const int grids[] = {0, 1, 2, 4, 8};
+    static const int grids[] = {0, 1, 2, 4, 5, 6, 8};  // 0: a workgroup per tile, else per CU
     for (int stage = 0; stage < kStages && rc == ABF_OK; stage++)
         for (int c = 0; c < kSizeClasses && rc == ABF_OK; c++) {
             if (!seen[stage][c]) continue;
